@@ -1,0 +1,175 @@
+/*
+ * dsweep -- diagonal-sweeping source-transfer domain decomposition for the
+ * PML-truncated Helmholtz equation, on one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Every pointer argument ending in "_dev" is device memory owned by
+ * the caller; every pointer ending in "_host" is host memory owned by the
+ * caller.  The plan owns everything it allocates (factors, coefficient arrays,
+ * sweep and Krylov workspaces) and frees it in dsd_destroy.
+ *
+ * Layouts.
+ *   Global grid: the physical cells n[0] x n[1] (x n[2]) plus `pml` cells on
+ *   every side, N_g = prod_a (n[a] + 2 pml) cells, x fastest.  A batch of
+ *   complex vectors is [nrhs][N_g], complex values interleaved (re, im) in
+ *   FP64 (complex128).  This is torch's (nrhs, ny, nx) complex128 layout.
+ *   The medium is m = 1/c^2 on the physical cells only, FP64, x fastest; the
+ *   library extends it into the PML by clamping.
+ *   Right-hand sides are J-scaled sources on the global grid (equal to the
+ *   source itself wherever the source lies inside the physical box).
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ * ordered on that stream.  Calls that return host values (iteration counts,
+ * residuals, the misfit) synchronise the stream before returning; the others
+ * are asynchronous.
+ *
+ * Errors.  0 = success.  Negative codes are errors; outputs are then
+ * unspecified.  DSD_NOT_CONVERGED (> 0) means outputs, iteration counts and
+ * residuals are valid but the tolerance was not met.  dsd_strerror() gives a
+ * message for any code; dsd_last_error_detail() adds context (which
+ * subdomain, which check) for the last failing call of this thread.
+ */
+#ifndef DSWEEP_H
+#define DSWEEP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DSD_OK = 0,
+  DSD_NOT_CONVERGED = 1,
+  DSD_EINVAL = -1,     /* bad shape, overlap < 3, a part smaller than the overlap ... */
+  DSD_ENOMEM = -2,     /* device allocation failed                                    */
+  DSD_EHIP = -3,       /* HIP runtime error                                           */
+  DSD_EPIVOT = -4,     /* zero pivot in a subdomain factorisation                     */
+  DSD_ENOTFINITE = -5  /* NaN/Inf in a residual norm                                  */
+};
+
+enum { DSD_C64 = 1, DSD_C128 = 2 };   /* precision of factors and sweeps */
+
+typedef struct dsd_plan dsd_plan;     /* opaque */
+
+typedef struct {
+  int dim;               /* 2 or 3                                                     */
+  int n[3];              /* physical cells per axis (n[2] ignored in 2D)               */
+  double h;              /* cell size                                                  */
+  int pml;               /* PML cells, global and around every subdomain               */
+  int overlap;           /* overlap d in cells, >= 3                                   */
+  int parts[3];          /* subdomains per axis (N_x, N_y[, N_z])                     */
+  double sigma0_delta;   /* S in sigma(t) = (S/W) (t/W)^2, W = pml*h; 60 if <= 0       */
+  int precision;         /* DSD_C64 or DSD_C128                                        */
+  int max_rhs;           /* largest batch any later call will pass                     */
+  int rhs_per_group;     /* RHS handled by one workgroup in the subdomain solves;
+                            0 = let the library choose                                 */
+} dsd_params;
+
+/*
+ * Build a plan: checkerboard partition and extended subdomains (Section 2.1),
+ * assembly of every subdomain's J-scaled PML operator with the shifted profile
+ * (eq. (eq:PML), (eq:PMLprofile)), and the factorisation of every subdomain
+ * problem (the factorisation phase of sweeping methods, Section 1) as a
+ * block-tridiagonal LDL^T whose diagonal Schur blocks are stored inverted.
+ *   m_dev : [prod n] FP64, m = 1/c^2 on physical cells.  Read during the call.
+ *   omega : angular frequency.
+ * Returns DSD_EINVAL for an invalid partition, DSD_EPIVOT if a Schur block is
+ * singular (the subdomain index is in dsd_last_error_detail()).
+ */
+int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
+                    void* stream, dsd_plan** out);
+
+void dsd_destroy(dsd_plan* plan);
+
+/* Sizes of a plan (host outputs; any pointer may be NULL). */
+int dsd_plan_info(const dsd_plan* plan, long long* n_global, int* n_subdomains,
+                  long long* factor_bytes, long long* workspace_bytes);
+
+/* Local grid of subdomain `sub` (lexicographic index, x part fastest):
+ * dims[3] = local cells per axis, g0[3] = global array index of its first cell
+ * per axis (local PML cells included). */
+int dsd_subdomain_grid(const dsd_plan* plan, int sub, int* dims, int* g0);
+
+/*
+ * Solve one subdomain's local PML problem L_sub u = r (the local solve of
+ * Algorithms 3.1 / 4.1) with the plan's factors.
+ *   r_dev, u_dev : [nrhs][N_loc] complex128 on the subdomain's local grid
+ *                  (x fastest).  Computed in the plan precision.
+ */
+int dsd_local_solve(dsd_plan* plan, int sub, const double* r_dev, double* u_dev, int nrhs,
+                    void* stream);
+
+/*
+ * One application of the diagonal-sweeping DDM (Algorithm 3.1 in 2D, 4.1 in
+ * 3D): 2^dim sweeps; in every step all subdomains of the anti-diagonal are
+ * solved in one batched launch, the source-transfer operator Psi passes the
+ * cutoff-weighted sources to the neighbours (Section 2.2) routed by Rules
+ * 3.1/3.2 (4.1/4.2), and u_DDM = sum beta_{0;ij} u_ij (eq. (eq:sumdiag2D),
+ * (eq:sumdiag3D)) is accumulated in FP64.
+ *   f_dev, u_dev : [nrhs][N_g] complex128; nrhs <= max_rhs.
+ */
+int dsd_sweep_apply(dsd_plan* plan, const double* f_dev, double* u_dev, int nrhs, void* stream);
+
+/* y = M x with the FP64 J-scaled global operator (5/7-point, Section 5).
+ *   x_dev, y_dev : [nrhs][N_g] complex128, must not alias. */
+int dsd_apply_operator(dsd_plan* plan, const double* x_dev, double* y_dev, int nrhs,
+                       void* stream);
+
+/*
+ * Solve M x = b by flexible GMRES (FP64: residual, Gram-Schmidt, solution
+ * update) right-preconditioned by dsd_sweep_apply in the plan precision
+ * (Remark 1 of Section 4; stopping rule of Section 5.2).  Restarting from the
+ * current iterate with the true FP64 residual is the iterative refinement of
+ * the complex64 path.
+ *   b_dev, x_dev  : [nrhs][N_g] complex128 (x is overwritten; x0 = 0).
+ *   tol           : stop when ||b - M x|| / ||b|| <= tol (true residual), per RHS.
+ *   maxit         : cap on preconditioner applications per RHS.
+ *   restart       : Krylov vectors kept before a restart (<= 0: library default).
+ *   iters_host    : [nrhs] preconditioner applications used per RHS (may be NULL).
+ *   relres_host   : [nrhs] final true relative residual per RHS (may be NULL).
+ * Returns DSD_NOT_CONVERGED if some RHS missed tol within maxit.
+ */
+int dsd_gmres_solve(dsd_plan* plan, const double* b_dev, double* x_dev, int nrhs, double tol,
+                    int maxit, int restart, int* iters_host, double* relres_host, void* stream);
+
+/* Solve the adjoint system M^H x = b with the same factors; M is complex
+ * symmetric, so x = conj(M^{-1} conj(b)).  Arguments as dsd_gmres_solve. */
+int dsd_adjoint_solve(dsd_plan* plan, const double* b_dev, double* x_dev, int nrhs, double tol,
+                      int maxit, int restart, int* iters_host, double* relres_host,
+                      void* stream);
+
+/*
+ * Full-waveform-inversion misfit and gradient for the plan's medium (the
+ * multi-RHS application motivating Remark 2 of Section 4):
+ *   J(m) = 1/2 sum_s || P u_s - d_s ||^2,   M(m) u_s = f_s,
+ *   dJ/dm = -omega^2 Re sum_s conj(lam_s) J u_s  (transposed through the clamp
+ *   extension onto the physical cells),  M^H lam_s = P^T (P u_s - d_s).
+ *   f_dev      : [nsrc][N_g] complex128 sources (J-scaled).
+ *   rec_dev    : [nrec] int64 global flat indices of the receiver cells.
+ *   dobs_dev   : [nsrc][nrec] complex128 observed data.
+ *   grad_dev   : [prod n] FP64 gradient w.r.t. m on physical cells (output).
+ *   misfit_host: J (output).
+ *   u_dev      : optional [nsrc][N_g] complex128 output of the forward fields (may be NULL).
+ */
+int dsd_fwi_gradient(dsd_plan* plan, const double* f_dev, int nsrc, const long long* rec_dev,
+                     int nrec, const double* dobs_dev, double tol, int maxit, double* grad_dev,
+                     double* misfit_host, double* u_dev, void* stream);
+
+/* Forward modelling only: d = P u_s for every source (complex128 [nsrc][nrec]). */
+int dsd_fwi_forward(dsd_plan* plan, const double* f_dev, int nsrc, const long long* rec_dev,
+                    int nrec, double tol, int maxit, double* d_dev, void* stream);
+
+const char* dsd_strerror(int code);
+const char* dsd_last_error_detail(void);
+
+/* Kernel timing hooks for measurement: accumulated device time (ms) of the
+ * subdomain-solve kernels and their launch count since the last reset, and the
+ * algorithmic bytes those launches had to move (factor blocks once per RHS
+ * group sharing them, plus the vectors).  Timing uses HIP events on the plan's
+ * stream and is active only while enabled. */
+int dsd_timing_enable(dsd_plan* plan, int on);
+int dsd_timing_read(dsd_plan* plan, double* solve_ms, long long* solve_launches,
+                    double* solve_bytes, double* other_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSWEEP_H */

@@ -1,0 +1,903 @@
+// dsweep kernels for gfx950.
+//
+// Conventions: cells are indexed x fastest; a subdomain's local vectors for a
+// batch of RHS are [rhs][cell] blocks of length nloc inside pools laid out by
+// SubDesc::vec_off (times the plan's max RHS); complex values are interleaved.
+#include "kernels.hpp"
+
+namespace dsd {
+
+static inline unsigned cdiv_u(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// ============================================================================
+// a1: J-scaled coefficients of the 5/7-point PML operator on a list of grids.
+// Face coefficient along axis a: prod_{b != a} s_b(centre) / s_a(face) / h^2;
+// diagonal: minus the six (four) face coefficients plus omega^2 m prod_b s_b.
+// ============================================================================
+__global__ void k_assemble(Problem P, const AxisGrid* grids, const long long* offs, int ngrids,
+                           const double* m, cpx<double>* diag, cpx<double>* cx,
+                           cpx<double>* cy, cpx<double>* cz) {
+  const int gi = blockIdx.y;
+  const AxisGrid* ax = grids + 3 * gi;
+  const long long ncell = (long long)ax[0].n * ax[1].n * ax[2].n;
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int ix = (int)(c % ax[0].n);
+  const long long r = c / ax[0].n;
+  const int iy = (int)(r % ax[1].n);
+  const int iz = (int)(r / ax[1].n);
+  const int gx = ax[0].g0 + ix, gy = ax[1].g0 + iy, gz = ax[2].g0 + iz;
+  const double h = P.h;
+  const double inv_h2 = 1.0 / (h * h);
+  auto s_at = [&](int a, double xphys) { return stretch(xphys, ax[a].lo, ax[a].hi, P); };
+  const cpx<double> one = mk(1.0, 0.0);
+  cpx<double> sxc = s_at(0, (gx - P.pml + 0.5) * h), sxl = s_at(0, (gx - P.pml) * h),
+              sxh = s_at(0, (gx - P.pml + 1.0) * h);
+  cpx<double> syc = s_at(1, (gy - P.pml + 0.5) * h), syl = s_at(1, (gy - P.pml) * h),
+              syh = s_at(1, (gy - P.pml + 1.0) * h);
+  cpx<double> szc = one, szl = one, szh = one;
+  if (P.dim == 3) {
+    szc = s_at(2, (gz - P.pml + 0.5) * h);
+    szl = s_at(2, (gz - P.pml) * h);
+    szh = s_at(2, (gz - P.pml + 1.0) * h);
+  }
+  // medium: clamp to the grid's undamped box, then to the physical cells
+  auto clampi = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
+  const int px = clampi(gx, ax[0].clo, ax[0].chi) - P.pml;
+  const int py = clampi(gy, ax[1].clo, ax[1].chi) - P.pml;
+  const int pz = P.dim == 3 ? clampi(gz, ax[2].clo, ax[2].chi) - P.pml : 0;
+  const double mm = m[((long long)pz * P.n[1] + py) * P.n[0] + px];
+
+  const cpx<double> oyz = syc * szc, oxz = sxc * szc, oxy = sxc * syc;
+  const cpx<double> axh = inv_h2 * cdiv(oyz, sxh), axl = inv_h2 * cdiv(oyz, sxl);
+  const cpx<double> ayh = inv_h2 * cdiv(oxz, syh), ayl = inv_h2 * cdiv(oxz, syl);
+  cpx<double> dg = -(axh + axl + ayh + ayl);
+  cpx<double> azh = mk(0.0, 0.0);
+  if (P.dim == 3) {
+    azh = inv_h2 * cdiv(oxy, szh);
+    const cpx<double> azl = inv_h2 * cdiv(oxy, szl);
+    dg = dg - (azh + azl);
+  }
+  dg = dg + (P.omega * P.omega * mm) * (oxy * szc);
+  const long long o = offs[gi] + c;
+  diag[o] = dg;
+  cx[o] = axh;
+  cy[o] = ayh;
+  cz[o] = azh;
+}
+
+void launch_assemble(const Problem& P, const AxisGrid* d_grids, const long long* d_offs, int ngrids,
+                     long long max_cells, const double* d_m, cpx<double>* diag, cpx<double>* cx,
+                     cpx<double>* cy, cpx<double>* cz, hipStream_t s) {
+  dim3 grid(cdiv_u(max_cells, 256), ngrids);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, P, d_grids, d_offs, ngrids, d_m, diag, cx,
+                     cy, cz);
+}
+
+template <typename T>
+__global__ void k_convert(const cpx<double>* src, cpx<T>* dst, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = cvt<T>(src[i]);
+}
+template <typename T>
+void launch_convert(const cpx<double>* src, cpx<T>* dst, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_convert<T>, dim3(cdiv_u(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+
+// ============================================================================
+// a2: factorisation.  Local operator in natural order is block tridiagonal
+// with blocks A_k (one x-line in 2D, one xy-plane in 3D) and diagonal
+// couplings C_k (the +y / +z face coefficients of block k).  Two chains of
+// Schur complements run towards the middle block:
+//   top    S_k = A_k - C_{k-1} S_{k-1}^{-1} C_{k-1}
+//   bottom T_k = A_k - C_k T_{k+1}^{-1} C_k
+//   middle M   = A_m - C_{m-1} S_{m-1}^{-1} C_{m-1} - C_m T_{m+1}^{-1} C_m
+// formed and inverted in FP64, stored (rounded) in the plan precision.
+// ============================================================================
+__device__ inline cpx<double> block_entry(const SubDesc& S, int dim, int k, int i, int j,
+                                          const cpx<double>* diag, const cpx<double>* cx,
+                                          const cpx<double>* cy) {
+  const long long base = S.coef_off + (long long)k * S.nb;
+  if (i == j) return diag[base + i];
+  if (dim == 2) {
+    if (j == i + 1) return cx[base + i];
+    if (i == j + 1) return cx[base + j];
+    return mk(0.0, 0.0);
+  }
+  const int nx = S.dims[0];
+  if (j == i + 1 && (i % nx) != nx - 1) return cx[base + i];
+  if (i == j + 1 && (j % nx) != nx - 1) return cx[base + j];
+  if (j == i + nx) return cy[base + i];
+  if (i == j + nx) return cy[base + j];
+  return mk(0.0, 0.0);
+}
+
+__global__ void k_schur(Problem P, const SubDesc* subs, const FactorJob* jobs,
+                        const cpx<double>* diag, const cpx<double>* cx, const cpx<double>* cy,
+                        const cpx<double>* cz, cpx<double>* scratch) {
+  const FactorJob J = jobs[blockIdx.y];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nb * nb) return;
+  const int j = (int)(e / nb), i = (int)(e - (long long)j * nb);  // column-major
+  const cpx<double>* cpl = P.dim == 2 ? cy : cz;
+  cpx<double> v = block_entry(S, P.dim, J.k, i, j, diag, cx, cy);
+  if (J.cp_blk >= 0) {
+    const long long cb = S.coef_off + (long long)J.cp_blk * nb;
+    v = v - (cpl[cb + i] * scratch[J.prev + e]) * cpl[cb + j];
+  }
+  if (J.cq_blk >= 0) {
+    const long long cb = S.coef_off + (long long)J.cq_blk * nb;
+    v = v - (cpl[cb + i] * scratch[J.prev2 + e]) * cpl[cb + j];
+  }
+  scratch[J.cur + e] = v;
+}
+
+void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jobs, int njobs,
+                  int max_nb, const cpx<double>* diag, const cpx<double>* cx,
+                  const cpx<double>* cy, const cpx<double>* cz, cpx<double>* scratch,
+                  hipStream_t s) {
+  if (njobs <= 0) return;
+  dim3 grid(cdiv_u((long long)max_nb * max_nb, 256), njobs);
+  hipLaunchKernelGGL(k_schur, grid, dim3(256), 0, s, P, d_subs, d_jobs, diag, cx, cy, cz,
+                     scratch);
+}
+
+// In-place Gauss-Jordan inversion with partial (row) pivoting of the FP64
+// column-major nb x nb matrix at scratch[cur]; one workgroup per job.  The
+// inverse is then rounded into the factor slot of block k.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_invert(const SubDesc* subs, const FactorJob* jobs,
+                                                 cpx<double>* scratch, cpx<T>* fac, int* err,
+                                                 int* pivbuf, int max_nb) {
+  const FactorJob J = jobs[blockIdx.x];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  cpx<double>* a = scratch + J.cur;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* rowj = tcol + nb;
+  int* piv = pivbuf + (long long)blockIdx.x * max_nb;
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ int s_p;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
+  int bad = 0;
+  for (int j = 0; j < nb; ++j) {
+    // pivot: largest |a_ij| for i >= j (ties: smallest i)
+    double bv = -1.0;
+    int bi = nb;
+    for (int i = j + tid; i < nb; i += bs) {
+      double v = abs2(a[(long long)j * nb + i]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ov = __shfl_down(bv, o, 64);
+      int oi = __shfl_down(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double v = red_v[0];
+      int p = red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
+      if (!(v > 0.0)) { bad = 1; p = j; }
+      s_p = p;
+      piv[j] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j) {
+      for (int c = tid; c < nb; c += bs) {
+        cpx<double> t0 = a[(long long)c * nb + j];
+        a[(long long)c * nb + j] = a[(long long)c * nb + p];
+        a[(long long)c * nb + p] = t0;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += bs) tcol[i] = a[(long long)j * nb + i];
+    __syncthreads();
+    const cpx<double> piv_v = tcol[j];
+    const cpx<double> pinv = (abs2(piv_v) > 0.0) ? cdiv(mk(1.0, 0.0), piv_v) : mk(0.0, 0.0);
+    for (int c = tid; c < nb; c += bs)
+      rowj[c] = (c == j) ? pinv : a[(long long)c * nb + j] * pinv;
+    __syncthreads();
+    const long long ne = (long long)nb * nb;
+    for (long long e = tid; e < ne; e += bs) {
+      const int c = (int)(e / nb), i = (int)(e - (long long)c * nb);
+      if (i == j) a[e] = rowj[c];
+      else if (c == j) a[e] = -(tcol[i] * pinv);
+      else a[e] = a[e] - tcol[i] * rowj[c];
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, in reverse order
+  for (int j = nb - 1; j >= 0; --j) {
+    const int p = piv[j];
+    if (p != j) {
+      for (int i = tid; i < nb; i += bs) {
+        cpx<double> t0 = a[(long long)j * nb + i];
+        a[(long long)j * nb + i] = a[(long long)p * nb + i];
+        a[(long long)p * nb + i] = t0;
+      }
+    }
+    __syncthreads();
+  }
+  cpx<T>* out = fac + S.fac_off + (long long)J.k * nb * nb;
+  const long long ne = (long long)nb * nb;
+  for (long long e = tid; e < ne; e += bs) out[e] = cvt<T>(a[e]);
+  if (tid == 0 && bad) err[blockIdx.x] = J.sub + 1;
+}
+
+template <typename T>
+void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
+                   cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s) {
+  if (njobs <= 0) return;
+  size_t lds = (size_t)max_nb * 2 * sizeof(cpx<double>);
+  hipLaunchKernelGGL(k_invert<T>, dim3(njobs), dim3(1024), lds, s, d_subs, d_jobs, scratch, fac,
+                     d_err, d_piv, max_nb);
+}
+
+// ============================================================================
+// a3: subdomain solves.  With B_k the stored inverse Schur blocks and c_k the
+// coupling of blocks k and k+1:
+//   forward top    y_k = r_k - c_{k-1} w_{k-1},  w_k = B_k y_k        (k < m)
+//   forward bottom y_k = r_k - c_k w_{k+1},      w_k = B_k y_k        (k > m)
+//   middle         x_m = B_m (r_m - c_{m-1} w_{m-1} - c_m w_{m+1})
+//   backward top    x_k = w_k - B_k (c_k x_{k+1})                      (k < m)
+//   backward bottom x_k = w_k - B_k (c_{k-1} x_{k-1})                  (k > m)
+// One workgroup runs one chain (subdomain, half) for KG right-hand sides;
+// block steps are dense matrix x (nb x KG) products with B_k read once per
+// workgroup in coalesced columns.  Workgroups of the same chain (different
+// RHS groups) are placed on the same XCD so that B_k is shared through L2.
+// ============================================================================
+template <typename T, int KG>
+__global__ __launch_bounds__(256) void k_chain(int phase, const SubDesc* subs, const int2* jobs,
+                                               int njobs, int G, int nrhs, int kmax,
+                                               const cpx<T>* fac, const cpx<T>* cpl,
+                                               const cpx<T>* rpool, cpx<T>* xpool) {
+  const int total = gridDim.x;
+  const int per = total >> 3;
+  const int b = blockIdx.x;
+  const int L = (b & 7) * per + (b >> 3);
+  const int job = L / G, g = L - (L / G) * G;
+  if (job >= njobs) return;
+  const int2 jb = jobs[job];
+  const SubDesc S = subs[jb.x];
+  const int half = jb.y;
+  const int nb = S.nb, nblk = S.nblk, mid = S.mid;
+  const long long nloc = S.nloc;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* yin = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* prev = yin + (long long)nb * KG;
+  const cpx<T>* R = rpool + S.vec_off * kmax;
+  cpx<T>* X = xpool + S.vec_off * kmax;
+  const cpx<T>* C = cpl + S.coef_off;
+  const cpx<T>* F = fac + S.fac_off;
+  const int tid = threadIdx.x;
+  const cpx<T> zero = mk((T)0, (T)0);
+  int rr[KG];
+#pragma unroll
+  for (int q = 0; q < KG; ++q) rr[q] = g * KG + q;
+
+  auto matvec_rows = [&](int k, int mode) {
+    // mode 0: out = B y ; mode 1: out = w_k - B y (w_k read from X)
+    const cpx<T>* B = F + (long long)k * nb * nb;
+    for (int i = tid; i < nb; i += 256) {
+      cpx<T> acc[KG];
+#pragma unroll
+      for (int q = 0; q < KG; ++q) acc[q] = zero;
+      int j = 0;
+      for (; j + 4 <= nb; j += 4) {
+        cpx<T> b0 = B[(long long)(j + 0) * nb + i];
+        cpx<T> b1 = B[(long long)(j + 1) * nb + i];
+        cpx<T> b2 = B[(long long)(j + 2) * nb + i];
+        cpx<T> b3 = B[(long long)(j + 3) * nb + i];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          fma_acc(acc[q], b0, yin[q * nb + j + 0]);
+          fma_acc(acc[q], b1, yin[q * nb + j + 1]);
+          fma_acc(acc[q], b2, yin[q * nb + j + 2]);
+          fma_acc(acc[q], b3, yin[q * nb + j + 3]);
+        }
+      }
+      for (; j < nb; ++j) {
+        cpx<T> b0 = B[(long long)j * nb + i];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) fma_acc(acc[q], b0, yin[q * nb + j]);
+      }
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        cpx<T> out = acc[q];
+        const long long o = (long long)rr[q] * nloc + (long long)k * nb + i;
+        if (mode == 1) out = (rr[q] < nrhs ? X[o] : zero) - out;
+        prev[q * nb + i] = out;
+        if (rr[q] < nrhs) X[o] = out;
+      }
+    }
+  };
+
+  if (phase == 0) {
+    const int nsteps = half == 0 ? mid : (nblk - 1 - mid);
+    for (int t = 0; t < nsteps; ++t) {
+      const int k = half == 0 ? t : nblk - 1 - t;
+      for (int idx = tid; idx < nb * KG; idx += 256) {
+        const int q = idx / nb, i = idx - (idx / nb) * nb;
+        cpx<T> y = rr[q] < nrhs ? R[(long long)rr[q] * nloc + (long long)k * nb + i] : zero;
+        if (t > 0) {
+          const cpx<T> c = half == 0 ? C[(long long)(k - 1) * nb + i] : C[(long long)k * nb + i];
+          y = y - c * prev[q * nb + i];
+        }
+        yin[q * nb + i] = y;
+      }
+      __syncthreads();
+      matvec_rows(k, 0);
+      __syncthreads();
+    }
+  } else if (phase == 1) {
+    const int k = mid;
+    for (int idx = tid; idx < nb * KG; idx += 256) {
+      const int q = idx / nb, i = idx - (idx / nb) * nb;
+      cpx<T> y = zero;
+      if (rr[q] < nrhs) {
+        const long long ro = (long long)rr[q] * nloc;
+        y = R[ro + (long long)k * nb + i];
+        if (k > 0) y = y - C[(long long)(k - 1) * nb + i] * X[ro + (long long)(k - 1) * nb + i];
+        if (k < nblk - 1) y = y - C[(long long)k * nb + i] * X[ro + (long long)(k + 1) * nb + i];
+      }
+      yin[q * nb + i] = y;
+    }
+    __syncthreads();
+    matvec_rows(k, 0);
+  } else {
+    const int nsteps = half == 0 ? mid : (nblk - 1 - mid);
+    for (int t = 0; t < nsteps; ++t) {
+      const int k = half == 0 ? mid - 1 - t : mid + 1 + t;
+      const int kn = half == 0 ? k + 1 : k - 1;          // already-solved neighbour
+      const int cb = half == 0 ? k : k - 1;              // coupling block index
+      for (int idx = tid; idx < nb * KG; idx += 256) {
+        const int q = idx / nb, i = idx - (idx / nb) * nb;
+        cpx<T> xn;
+        if (t == 0) xn = rr[q] < nrhs ? X[(long long)rr[q] * nloc + (long long)kn * nb + i] : zero;
+        else xn = prev[q * nb + i];
+        yin[q * nb + i] = C[(long long)cb * nb + i] * xn;
+      }
+      __syncthreads();
+      matvec_rows(k, 1);
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T, int KG>
+static void launch_chain_kg(int phase, const SubDesc* d_subs, const int2* d_jobs, int njobs,
+                            int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                            const cpx<T>* rpool, cpx<T>* xpool, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  long long total = (long long)njobs * G;
+  total = (total + 7) / 8 * 8;
+  const size_t lds = (size_t)2 * max_nb * KG * sizeof(cpx<T>);
+  hipLaunchKernelGGL((k_chain<T, KG>), dim3((unsigned)total), dim3(256), lds, s, phase, d_subs,
+                     d_jobs, njobs, G, nrhs, kmax, fac, cpl, rpool, xpool);
+}
+
+template <typename T>
+void launch_chain(int kg, int phase, const SubDesc* d_subs, const int2* d_jobs, int njobs,
+                  int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                  const cpx<T>* rpool, cpx<T>* xpool, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0) return;
+  switch (kg) {
+    case 1: launch_chain_kg<T, 1>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
+    case 2: launch_chain_kg<T, 2>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
+    case 4: launch_chain_kg<T, 4>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
+    default: launch_chain_kg<T, 8>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
+  }
+}
+
+// ============================================================================
+// a4: local right-hand sides.  init: r^1 = f on own cells (first sweep), 0
+// otherwise.  pull: every receiver cell sums, in a fixed edge order, the
+// transferred sources Psi_t(v) = -M_sender(beta_t v) of the edges whose box
+// holds it; each cell is written by exactly one thread (no atomics).
+// ============================================================================
+template <typename T>
+__global__ void k_init_rhs(Problem P, const SubDesc* subs, const int* members, int first_sweep,
+                           int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool) {
+  const SubDesc S = subs[members[blockIdx.z]];
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= S.nloc || r >= nrhs) return;
+  cpx<T> v = mk((T)0, (T)0);
+  if (first_sweep) {
+    const int ix = (int)(c % S.dims[0]);
+    const long long q = c / S.dims[0];
+    const int iy = (int)(q % S.dims[1]);
+    const int iz = (int)(q / S.dims[1]);
+    const int g[3] = {S.ax[0].g0 + ix, S.ax[1].g0 + iy, S.ax[2].g0 + iz};
+    bool own = true;
+    for (int a = 0; a < P.dim; ++a) own = own && g[a] >= S.pt[a].o0 && g[a] < S.pt[a].o1;
+    if (own) {
+      const long long gf = ((long long)g[2] * P.ng[1] + g[1]) * P.ng[0] + g[0];
+      v = cvt<T>(f[(long long)r * P.N + gf]);
+    }
+  }
+  rpool[S.vec_off * kmax + (long long)r * S.nloc + c] = v;
+}
+
+template <typename T>
+void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
+                     long long max_nloc, int first_sweep, int nrhs, int kmax,
+                     const cpx<double>* f, cpx<T>* rpool, hipStream_t s) {
+  if (nmem <= 0 || nrhs <= 0) return;
+  dim3 grid(cdiv_u(max_nloc, 256), nrhs, nmem);
+  hipLaunchKernelGGL(k_init_rhs<T>, grid, dim3(256), 0, s, P, d_subs, d_members, first_sweep,
+                     nrhs, kmax, f, rpool);
+}
+
+template <typename T>
+__device__ inline bool in_box(const Edge& e, const int c[3]) {
+  return c[0] >= e.lo[0] && c[0] < e.hi[0] && c[1] >= e.lo[1] && c[1] < e.hi[1] &&
+         c[2] >= e.lo[2] && c[2] < e.hi[2];
+}
+
+template <typename T>
+__device__ cpx<T> psi(const Problem& P, const SubDesc& Sd, const Edge& e, const int c[3], int r,
+                      int kmax, const cpx<T>* vpool, long long pool_stride, const cpx<T>* diag,
+                      const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz) {
+  // sender-local cell
+  int cs[3] = {c[0] + e.off[0], c[1] + e.off[1], c[2] + e.off[2]};
+  const int* dm = Sd.dims;
+  auto w_at = [&](int x, int y, int z) -> cpx<T> {
+    if (x < 0 || y < 0 || z < 0 || x >= dm[0] || y >= dm[1] || z >= dm[2]) return mk((T)0, (T)0);
+    const int gg[3] = {Sd.ax[0].g0 + x, Sd.ax[1].g0 + y, Sd.ax[2].g0 + z};
+    double beta = 1.0;
+    for (int a = 0; a < P.dim; ++a) beta *= cutoff(Sd.pt[a], e.t[a], gg[a], P.d);
+    if (beta == 0.0) return mk((T)0, (T)0);
+    const long long cell = ((long long)z * dm[1] + y) * dm[0] + x;
+    cpx<T> v = mk((T)0, (T)0);
+    for (int l = 0; l < 8; ++l)
+      if (e.lmask & (1u << l))
+        v = v + vpool[l * pool_stride + Sd.vec_off * kmax + (long long)r * Sd.nloc + cell];
+    return (T)beta * v;
+  };
+  const long long cc = ((long long)cs[2] * dm[1] + cs[1]) * dm[0] + cs[0];
+  const long long co = Sd.coef_off + cc;
+  cpx<T> acc = diag[co] * w_at(cs[0], cs[1], cs[2]);
+  if (cs[0] + 1 < dm[0]) acc = acc + cx[co] * w_at(cs[0] + 1, cs[1], cs[2]);
+  if (cs[0] > 0) acc = acc + cx[co - 1] * w_at(cs[0] - 1, cs[1], cs[2]);
+  if (cs[1] + 1 < dm[1]) acc = acc + cy[co] * w_at(cs[0], cs[1] + 1, cs[2]);
+  if (cs[1] > 0) acc = acc + cy[co - dm[0]] * w_at(cs[0], cs[1] - 1, cs[2]);
+  if (P.dim == 3) {
+    const long long plane = (long long)dm[0] * dm[1];
+    if (cs[2] + 1 < dm[2]) acc = acc + cz[co] * w_at(cs[0], cs[1], cs[2] + 1);
+    if (cs[2] > 0) acc = acc + cz[co - plane] * w_at(cs[0], cs[1], cs[2] - 1);
+  }
+  return -acc;
+}
+
+template <typename T>
+__global__ void k_pull(Problem P, const SubDesc* subs, const int* members, const Edge* edges,
+                       const int2* erange, int nrhs, int kmax, const cpx<T>* vpool,
+                       long long pool_stride, const cpx<T>* diag, const cpx<T>* cx,
+                       const cpx<T>* cy, const cpx<T>* cz, cpx<T>* rpool) {
+  const int recv = members[blockIdx.z];
+  const int2 er = erange[blockIdx.z];
+  const int r = blockIdx.y;
+  if (r >= nrhs || er.y <= 0) return;
+  const Edge* E = edges + er.x;
+  const int ne = er.y;
+  long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // locate (edge, cell) from the flat index over the concatenated boxes
+  int eidx = -1;
+  for (int e = 0; e < ne; ++e) {
+    const long long vol = (long long)(E[e].hi[0] - E[e].lo[0]) * (E[e].hi[1] - E[e].lo[1]) *
+                          (E[e].hi[2] - E[e].lo[2]);
+    if (f < vol) { eidx = e; break; }
+    f -= vol;
+  }
+  if (eidx < 0) return;
+  const Edge& e0 = E[eidx];
+  const int bx = e0.hi[0] - e0.lo[0], by = e0.hi[1] - e0.lo[1];
+  int c[3];
+  c[0] = e0.lo[0] + (int)(f % bx);
+  const long long q = f / bx;
+  c[1] = e0.lo[1] + (int)(q % by);
+  c[2] = e0.lo[2] + (int)(q / by);
+  for (int e = 0; e < eidx; ++e)
+    if (in_box<T>(E[e], c)) return;          // an earlier box owns this cell
+  const SubDesc R = subs[recv];
+  cpx<T> sum = mk((T)0, (T)0);
+  for (int e = eidx; e < ne; ++e) {
+    if (!in_box<T>(E[e], c)) continue;
+    const SubDesc Sd = subs[E[e].sender];
+    sum = sum + psi<T>(P, Sd, E[e], c, r, kmax, vpool, pool_stride, diag, cx, cy, cz);
+  }
+  const long long cell = ((long long)c[2] * R.dims[1] + c[1]) * R.dims[0] + c[0];
+  const long long o = R.vec_off * kmax + (long long)r * R.nloc + cell;
+  rpool[o] = rpool[o] + sum;
+}
+
+template <typename T>
+void launch_pull(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
+                 const Edge* d_edges, const int2* d_edge_range, long long max_box_cells,
+                 int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
+                 const cpx<T>* diag, const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz,
+                 cpx<T>* rpool, hipStream_t s) {
+  if (nmem <= 0 || nrhs <= 0 || max_box_cells <= 0) return;
+  dim3 grid(cdiv_u(max_box_cells, 256), nrhs, nmem);
+  hipLaunchKernelGGL(k_pull<T>, grid, dim3(256), 0, s, P, d_subs, d_members, d_edges,
+                     d_edge_range, nrhs, kmax, vpool, pool_stride, diag, cx, cy, cz, rpool);
+}
+
+// ============================================================================
+// a5: u_DDM = sum_sub beta_{0;sub} sum_l v_sub^l, FP64, pulled per global cell
+// from the (at most two per axis) subdomains whose cutoff support covers it.
+// ============================================================================
+template <typename T>
+__global__ void k_assemble_u(Problem P, const SubDesc* subs, PartTables pt, int nsweeps, int nrhs,
+                             int kmax, const cpx<T>* vpool, long long pool_stride,
+                             cpx<double>* u) {
+  const long long gflat = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (gflat >= P.N || r >= nrhs) return;
+  int g[3];
+  g[0] = (int)(gflat % P.ng[0]);
+  const long long q = gflat / P.ng[0];
+  g[1] = (int)(q % P.ng[1]);
+  g[2] = (int)(q / P.ng[1]);
+  int cand[3][3], ncand[3];
+  double wgt[3][3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= P.dim) { cand[a][0] = 0; wgt[a][0] = 1.0; ncand[a] = 1; continue; }
+    const int p = pt.part_of[a][g[a]];
+    int nc = 0;
+    for (int dp = -1; dp <= 1; ++dp) {
+      const int pp = p + dp;
+      if (pp < 0 || pp >= pt.P[a]) continue;
+      const AxisPart ap = pt.parts[a][pp];
+      const double w = cutoff(ap, -1, g[a], P.d) * cutoff(ap, 1, g[a], P.d);
+      if (w != 0.0) { cand[a][nc] = pp; wgt[a][nc] = w; ++nc; }
+    }
+    ncand[a] = nc;
+  }
+  cpx<double> acc = mk(0.0, 0.0);
+  for (int iz = 0; iz < ncand[2]; ++iz)
+    for (int iy = 0; iy < ncand[1]; ++iy)
+      for (int ix = 0; ix < ncand[0]; ++ix) {
+        const int sub = (cand[2][iz] * pt.P[1] + cand[1][iy]) * pt.P[0] + cand[0][ix];
+        const SubDesc& S = subs[sub];
+        const int lx = g[0] - S.ax[0].g0, ly = g[1] - S.ax[1].g0, lz = g[2] - S.ax[2].g0;
+        const long long cell = ((long long)lz * S.dims[1] + ly) * S.dims[0] + lx;
+        const long long o = S.vec_off * kmax + (long long)r * S.nloc + cell;
+        cpx<double> v = mk(0.0, 0.0);
+        for (int l = 0; l < nsweeps; ++l) v = v + cvt<double>(vpool[l * pool_stride + o]);
+        const double w = wgt[0][ix] * wgt[1][iy] * wgt[2][iz];
+        acc = acc + w * v;
+      }
+  u[(long long)r * P.N + gflat] = acc;
+}
+
+template <typename T>
+void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int nsweeps,
+                       int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
+                       cpx<double>* u, hipStream_t s) {
+  dim3 grid(cdiv_u(P.N, 256), nrhs);
+  hipLaunchKernelGGL(k_assemble_u<T>, grid, dim3(256), 0, s, P, d_subs, pt, nsweeps, nrhs, kmax,
+                     vpool, pool_stride, u);
+}
+
+template <typename T>
+__global__ void k_pack_local(const cpx<double>* src, cpx<T>* dst, long long nloc, int nrhs) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nloc * nrhs) dst[i] = cvt<T>(src[i]);
+}
+template <typename T>
+__global__ void k_unpack_local(const cpx<T>* src, cpx<double>* dst, long long nloc, int nrhs) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nloc * nrhs) dst[i] = cvt<double>(src[i]);
+}
+template <typename T>
+void launch_pack_local(const cpx<double>* src, cpx<T>* dst, long long nloc, int nrhs, int kmax,
+                       hipStream_t s) {
+  (void)kmax;
+  hipLaunchKernelGGL(k_pack_local<T>, dim3(cdiv_u(nloc * nrhs, 256)), dim3(256), 0, s, src, dst,
+                     nloc, nrhs);
+}
+template <typename T>
+void launch_unpack_local(const cpx<T>* src, cpx<double>* dst, long long nloc, int nrhs, int kmax,
+                         hipStream_t s) {
+  (void)kmax;
+  hipLaunchKernelGGL(k_unpack_local<T>, dim3(cdiv_u(nloc * nrhs, 256)), dim3(256), 0, s, src,
+                     dst, nloc, nrhs);
+}
+
+// ============================================================================
+// a7: y = M x, FP64 global 5/7-point operator (coefficients per cell).
+// ============================================================================
+__global__ void k_apply_op(Problem P, const cpx<double>* diag, const cpx<double>* cx,
+                           const cpx<double>* cy, const cpx<double>* cz, const cpx<double>* x,
+                           cpx<double>* y, int nrhs) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.N) return;
+  const int ix = (int)(c % P.ng[0]);
+  const long long q = c / P.ng[0];
+  const int iy = (int)(q % P.ng[1]);
+  const int iz = (int)(q / P.ng[1]);
+  const long long sy = P.ng[0], sz = (long long)P.ng[0] * P.ng[1];
+  const cpx<double> d = diag[c];
+  const cpx<double> xp = ix + 1 < P.ng[0] ? cx[c] : mk(0.0, 0.0);
+  const cpx<double> xm = ix > 0 ? cx[c - 1] : mk(0.0, 0.0);
+  const cpx<double> yp = iy + 1 < P.ng[1] ? cy[c] : mk(0.0, 0.0);
+  const cpx<double> ym = iy > 0 ? cy[c - sy] : mk(0.0, 0.0);
+  cpx<double> zp = mk(0.0, 0.0), zm = mk(0.0, 0.0);
+  if (P.dim == 3) {
+    zp = iz + 1 < P.ng[2] ? cz[c] : mk(0.0, 0.0);
+    zm = iz > 0 ? cz[c - sz] : mk(0.0, 0.0);
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    const cpx<double>* xr = x + (long long)r * P.N;
+    cpx<double> acc = d * xr[c];
+    if (ix + 1 < P.ng[0]) acc = acc + xp * xr[c + 1];
+    if (ix > 0) acc = acc + xm * xr[c - 1];
+    if (iy + 1 < P.ng[1]) acc = acc + yp * xr[c + sy];
+    if (iy > 0) acc = acc + ym * xr[c - sy];
+    if (P.dim == 3) {
+      if (iz + 1 < P.ng[2]) acc = acc + zp * xr[c + sz];
+      if (iz > 0) acc = acc + zm * xr[c - sz];
+    }
+    y[(long long)r * P.N + c] = acc;
+  }
+}
+
+void launch_apply_op(const Problem& P, const cpx<double>* diag, const cpx<double>* cx,
+                     const cpx<double>* cy, const cpx<double>* cz, const cpx<double>* x,
+                     cpx<double>* y, int nrhs, hipStream_t s) {
+  if (nrhs <= 0) return;
+  hipLaunchKernelGGL(k_apply_op, dim3(cdiv_u(P.N, 256)), dim3(256), 0, s, P, diag, cx, cy, cz, x,
+                     y, nrhs);
+}
+
+// ============================================================================
+// a8: FP64 Krylov kernels (batched over RHS).  Reductions are two-stage with a
+// fixed summation order, so results are reproducible run to run.
+// ============================================================================
+__device__ inline cpx<double> block_sum(cpx<double> v, cpx<double>* sh) {
+  for (int o = 32; o > 0; o >>= 1) {
+    v.re += __shfl_down(v.re, o, 64);
+    v.im += __shfl_down(v.im, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  cpx<double> t = mk(0.0, 0.0);
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t = t + sh[w];
+  __syncthreads();
+  return t;
+}
+
+// part[(i * nrhs + r) * nblk + b]
+__global__ __launch_bounds__(256) void k_mdot(const cpx<double>* V, int nv, const cpx<double>* w,
+                                              int nrhs, long long N, cpx<double>* part,
+                                              int nblk) {
+  __shared__ cpx<double> sh[4];
+  const int r = blockIdx.y;
+  const int b = blockIdx.x;
+  const cpx<double>* wr = w + (long long)r * N;
+  for (int i0 = 0; i0 < nv; i0 += 4) {
+    cpx<double> acc[4];
+    for (int t = 0; t < 4; ++t) acc[t] = mk(0.0, 0.0);
+    for (long long c = (long long)b * blockDim.x + threadIdx.x; c < N;
+         c += (long long)nblk * blockDim.x) {
+      const cpx<double> wv = wr[c];
+      for (int t = 0; t < 4; ++t)
+        if (i0 + t < nv) fma_acc(acc[t], conj(V[((long long)(i0 + t) * nrhs + r) * N + c]), wv);
+    }
+    for (int t = 0; t < 4 && i0 + t < nv; ++t) {
+      cpx<double> s = block_sum(acc[t], sh);
+      if (threadIdx.x == 0) part[((long long)(i0 + t) * nrhs + r) * nblk + b] = s;
+    }
+  }
+}
+
+__global__ void k_mdot_final(const cpx<double>* part, int nv, int nrhs, int nblk,
+                             cpx<double>* out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nv * nrhs) return;
+  cpx<double> s = mk(0.0, 0.0);
+  for (int b = 0; b < nblk; ++b) s = s + part[(long long)idx * nblk + b];
+  out[idx] = s;
+}
+
+void launch_mdot(const cpx<double>* V, int nv, const cpx<double>* w, int nrhs, long long N,
+                 cpx<double>* part, int nblk, cpx<double>* out, hipStream_t s) {
+  if (nv <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_mdot, dim3(nblk, nrhs), dim3(256), 0, s, V, nv, w, nrhs, N, part, nblk);
+  hipLaunchKernelGGL(k_mdot_final, dim3(cdiv_u((long long)nv * nrhs, 256)), dim3(256), 0, s, part,
+                     nv, nrhs, nblk, out);
+}
+
+__global__ void k_maxpy(const cpx<double>* V, int nv, const cpx<double>* coef, double sign,
+                        cpx<double>* w, int nrhs, long long N) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= N) return;
+  cpx<double> acc = mk(0.0, 0.0);
+  for (int i = 0; i < nv; ++i) fma_acc(acc, coef[i * nrhs + r], V[((long long)i * nrhs + r) * N + c]);
+  const long long o = (long long)r * N + c;
+  w[o] = w[o] + sign * acc;
+}
+
+void launch_maxpy(const cpx<double>* V, int nv, const cpx<double>* coef, double sign,
+                  cpx<double>* w, int nrhs, long long N, hipStream_t s) {
+  if (nv <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_maxpy, dim3(cdiv_u(N, 256), nrhs), dim3(256), 0, s, V, nv, coef, sign, w,
+                     nrhs, N);
+}
+
+__global__ void k_scale(const cpx<double>* src, const double* scal, cpx<double>* dst, int nrhs,
+                        long long N) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= N) return;
+  const long long o = (long long)r * N + c;
+  dst[o] = scal[r] * src[o];
+}
+void launch_scale(const cpx<double>* src, const double* scal, cpx<double>* dst, int nrhs,
+                  long long N, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale, dim3(cdiv_u(N, 256), nrhs), dim3(256), 0, s, src, scal, dst, nrhs, N);
+}
+
+__global__ void k_sub(const cpx<double>* a, const cpx<double>* b, cpx<double>* y, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a[i] - b[i];
+}
+void launch_sub(const cpx<double>* a, const cpx<double>* b, cpx<double>* y, long long n,
+                hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_sub, dim3(cdiv_u(n, 256)), dim3(256), 0, s, a, b, y, n);
+}
+__global__ void k_conj(const cpx<double>* a, cpx<double>* y, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = conj(a[i]);
+}
+void launch_conj(const cpx<double>* a, cpx<double>* y, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_conj, dim3(cdiv_u(n, 256)), dim3(256), 0, s, a, y, n);
+}
+__global__ void k_gather_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst,
+                             long long N) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c < N) dst[(long long)r * N + c] = src[(long long)idx[r] * N + c];
+}
+__global__ void k_scatter_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst,
+                              long long N) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c < N) dst[(long long)idx[r] * N + c] = src[(long long)r * N + c];
+}
+void launch_gather_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst, int nsel,
+                       long long N, hipStream_t s) {
+  if (nsel > 0)
+    hipLaunchKernelGGL(k_gather_rhs, dim3(cdiv_u(N, 256), nsel), dim3(256), 0, s, src, idx, dst, N);
+}
+void launch_scatter_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst, int nsel,
+                        long long N, hipStream_t s) {
+  if (nsel > 0)
+    hipLaunchKernelGGL(k_scatter_rhs, dim3(cdiv_u(N, 256), nsel), dim3(256), 0, s, src, idx, dst,
+                       N);
+}
+
+// ============================================================================
+// a9: FWI.  res = P u - d at the receivers; adjoint source conj(P^T res)
+// (summed per cell in receiver order by one thread per source); misfit
+// partials per source; gradient -omega^2 Re(J sum_s y_s u_s) with
+// y_s = M^{-1} conj(P^T res_s) (so lam_s = conj(y_s)), transposed through
+// the clamp extension onto the physical cells.
+// ============================================================================
+__global__ void k_fwi_residual(const cpx<double>* u, int nsrc, long long N, const long long* rec,
+                               int nrec, const cpx<double>* dobs, cpx<double>* res,
+                               cpx<double>* adj, double* mpart) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsrc) return;
+  double acc = 0.0;
+  for (int k = 0; k < nrec; ++k) {
+    const cpx<double> rv = u[(long long)s * N + rec[k]] - dobs[(long long)s * nrec + k];
+    res[(long long)s * nrec + k] = rv;
+    acc += abs2(rv);
+  }
+  for (int k = 0; k < nrec; ++k) {
+    const long long o = (long long)s * N + rec[k];
+    adj[o] = adj[o] + conj(res[(long long)s * nrec + k]);
+  }
+  mpart[s] = 0.5 * acc;
+}
+void launch_fwi_residual(const cpx<double>* u, int nsrc, long long N, const long long* rec,
+                         int nrec, const cpx<double>* dobs, cpx<double>* res,
+                         cpx<double>* adj_rhs, double* misfit_part, hipStream_t s) {
+  hipLaunchKernelGGL(k_fwi_residual, dim3(cdiv_u(nsrc, 64)), dim3(64), 0, s, u, nsrc, N, rec, nrec,
+                     dobs, res, adj_rhs, misfit_part);
+}
+
+__global__ void k_fwi_gradient(Problem P, const cpx<double>* u, const cpx<double>* y, int nsrc,
+                               double* grad) {
+  const long long pflat = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long nphys = (long long)P.n[0] * P.n[1] * (P.dim == 3 ? P.n[2] : 1);
+  if (pflat >= nphys) return;
+  int p[3];
+  p[0] = (int)(pflat % P.n[0]);
+  const long long q = pflat / P.n[0];
+  p[1] = (int)(q % P.n[1]);
+  p[2] = (int)(q / P.n[1]);
+  int lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= P.dim) { lo[a] = 0; hi[a] = 0; continue; }
+    lo[a] = p[a] == 0 ? 0 : p[a] + P.pml;
+    hi[a] = p[a] == P.n[a] - 1 ? P.ng[a] - 1 : p[a] + P.pml;
+  }
+  double acc = 0.0;
+  for (int gz = lo[2]; gz <= hi[2]; ++gz)
+    for (int gy = lo[1]; gy <= hi[1]; ++gy)
+      for (int gx = lo[0]; gx <= hi[0]; ++gx) {
+        const long long c = ((long long)gz * P.ng[1] + gy) * P.ng[0] + gx;
+        const double h = P.h;
+        const double xs[3] = {(gx - P.pml + 0.5) * h, (gy - P.pml + 0.5) * h,
+                              (gz - P.pml + 0.5) * h};
+        cpx<double> J = mk(1.0, 0.0);
+        for (int a = 0; a < P.dim; ++a) J = J * stretch(xs[a], 0.0, P.n[a] * h, P);
+        cpx<double> sum = mk(0.0, 0.0);
+        for (int s = 0; s < nsrc; ++s)
+          fma_acc(sum, y[(long long)s * P.N + c], u[(long long)s * P.N + c]);
+        acc += (J * sum).re;
+      }
+  grad[pflat] = -P.omega * P.omega * acc;
+}
+void launch_fwi_gradient(const Problem& P, const cpx<double>* u, const cpx<double>* y, int nsrc,
+                         double* grad, hipStream_t s) {
+  const long long nphys = (long long)P.n[0] * P.n[1] * (P.dim == 3 ? P.n[2] : 1);
+  hipLaunchKernelGGL(k_fwi_gradient, dim3(cdiv_u(nphys, 256)), dim3(256), 0, s, P, u, y, nsrc,
+                     grad);
+}
+
+__global__ void k_sample(const cpx<double>* u, int nsrc, long long N, const long long* rec,
+                         int nrec, cpx<double>* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsrc * nrec) return;
+  const int s = i / nrec, k = i - s * nrec;
+  d[i] = u[(long long)s * N + rec[k]];
+}
+void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long* rec, int nrec,
+                   cpx<double>* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample, dim3(cdiv_u((long long)nsrc * nrec, 256)), dim3(256), 0, s, u, nsrc,
+                     N, rec, nrec, d);
+}
+
+// ---- explicit instantiations
+#define DSD_INST(T)                                                                              \
+  template void launch_convert<T>(const cpx<double>*, cpx<T>*, long long, hipStream_t);          \
+  template void launch_invert<T>(const SubDesc*, const FactorJob*, int, int, cpx<double>*,      \
+                                 cpx<T>*, int*, int*, hipStream_t);                              \
+  template void launch_chain<T>(int, int, const SubDesc*, const int2*, int, int, int, int,      \
+                                const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*,            \
+                                hipStream_t);                                                    \
+  template void launch_init_rhs<T>(const Problem&, const SubDesc*, const int*, int, long long,  \
+                                   int, int, int, const cpx<double>*, cpx<T>*, hipStream_t);     \
+  template void launch_pull<T>(const Problem&, const SubDesc*, const int*, int, const Edge*,    \
+                               const int2*, long long, int, int, const cpx<T>*, long long,       \
+                               const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*,       \
+                               cpx<T>*, hipStream_t);                                            \
+  template void launch_assemble_u<T>(const Problem&, const SubDesc*, const PartTables&, int,    \
+                                     int, int, const cpx<T>*, long long, cpx<double>*,           \
+                                     hipStream_t);                                               \
+  template void launch_pack_local<T>(const cpx<double>*, cpx<T>*, long long, int, int,          \
+                                     hipStream_t);                                               \
+  template void launch_unpack_local<T>(const cpx<T>*, cpx<double>*, long long, int, int,        \
+                                       hipStream_t);
+DSD_INST(float)
+DSD_INST(double)
+
+}  // namespace dsd

@@ -1,0 +1,110 @@
+// Launchers of the dsweep kernels (internal; called by the plan in plan.hip).
+#pragma once
+#include "common.hpp"
+
+namespace dsd {
+
+// Tables describing the partition for the pull-style FP64 assembly.
+struct PartTables {
+  const int* part_of[3];        // [ng_a] own part of every global array index
+  const AxisPart* parts[3];     // [P_a] parts of each axis
+  int P[3];                     // parts per axis
+};
+
+// ---- a1: coefficient assembly (FP64) for a list of grids
+void launch_assemble(const Problem& P, const AxisGrid* d_grids, const long long* d_offs, int ngrids,
+                     long long max_cells, const double* d_m, cpx<double>* diag, cpx<double>* cx,
+                     cpx<double>* cy, cpx<double>* cz, hipStream_t s);
+
+template <typename T>
+void launch_convert(const cpx<double>* src, cpx<T>* dst, long long n, hipStream_t s);
+
+// ---- a2: factorisation
+// A factorisation job forms S = A_k - C_p Binv_p C_p (- C_q Binv_q C_q) in FP64
+// scratch and inverts it in place (Gauss-Jordan, partial pivoting), then rounds
+// it into the factor slot.
+struct FactorJob {
+  int sub;
+  int k;            // block being factored
+  int cp_blk;       // block index whose coupling array couples to the previous block (-1: none)
+  int cq_blk;       // second neighbour (middle block only; -1: none)
+  long long prev;   // scratch offset (doubles-complex) of the FP64 inverse of the previous block
+  long long prev2;  // second neighbour's inverse (middle block)
+  long long cur;    // scratch offset of this block's working matrix
+};
+void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jobs, int njobs,
+                  int max_nb, const cpx<double>* diag, const cpx<double>* cx,
+                  const cpx<double>* cy, const cpx<double>* cz, cpx<double>* scratch,
+                  hipStream_t s);
+template <typename T>
+void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
+                   cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s);
+
+// ---- a3: subdomain solves (block-tridiagonal chains); phase 0 fwd, 1 mid, 2 bwd
+template <typename T>
+void launch_chain(int kg, int phase, const SubDesc* d_subs, const int2* d_jobs, int njobs,
+                  int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                  const cpx<T>* rpool, cpx<T>* xpool, hipStream_t s);
+
+// ---- a4: local right-hand sides and source transfer (pull)
+template <typename T>
+void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
+                     long long max_nloc, int first_sweep, int nrhs, int kmax,
+                     const cpx<double>* f, cpx<T>* rpool, hipStream_t s);
+template <typename T>
+void launch_pull(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
+                 const Edge* d_edges, const int2* d_edge_range, long long max_box_cells,
+                 int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
+                 const cpx<T>* diag, const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz,
+                 cpx<T>* rpool, hipStream_t s);
+
+// ---- a5: u_DDM = sum_sub beta_0 sum_l v_sub^l (FP64, pull over global cells)
+template <typename T>
+void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int nsweeps,
+                       int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
+                       cpx<double>* u, hipStream_t s);
+
+// local solve entry point helpers: complex128 <-> plan precision on one subdomain
+template <typename T>
+void launch_pack_local(const cpx<double>* src, cpx<T>* dst, long long nloc, int nrhs, int kmax,
+                       hipStream_t s);
+template <typename T>
+void launch_unpack_local(const cpx<T>* src, cpx<double>* dst, long long nloc, int nrhs, int kmax,
+                         hipStream_t s);
+
+// ---- a7: FP64 global operator
+void launch_apply_op(const Problem& P, const cpx<double>* diag, const cpx<double>* cx,
+                     const cpx<double>* cy, const cpx<double>* cz, const cpx<double>* x,
+                     cpx<double>* y, int nrhs, hipStream_t s);
+
+// ---- a8: FP64 Krylov vector kernels
+// out[i][r] = sum_c conj(V[i][r][c]) w[r][c] for i < nv; V rows are [nrhs][N] blocks of
+// a basis laid out [nv_total][nrhs][N]; partial sums go to `part` ([nv][nrhs][nblk]).
+void launch_mdot(const cpx<double>* V, int nv, const cpx<double>* w, int nrhs, long long N,
+                 cpx<double>* part, int nblk, cpx<double>* out, hipStream_t s);
+// w[r] += sign * sum_{i<nv} coef[i][r] V[i][r]
+void launch_maxpy(const cpx<double>* V, int nv, const cpx<double>* coef, double sign,
+                  cpx<double>* w, int nrhs, long long N, hipStream_t s);
+// dst[r] = src[r] * scal[r] (scal real, per RHS)
+void launch_scale(const cpx<double>* src, const double* scal, cpx<double>* dst, int nrhs,
+                  long long N, hipStream_t s);
+// y = a - b
+void launch_sub(const cpx<double>* a, const cpx<double>* b, cpx<double>* y, long long n,
+                hipStream_t s);
+void launch_conj(const cpx<double>* a, cpx<double>* y, long long n, hipStream_t s);
+// gather / scatter RHS subsets: dst[r] = src[idx[r]] (and the reverse)
+void launch_gather_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst, int nsel,
+                       long long N, hipStream_t s);
+void launch_scatter_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst, int nsel,
+                        long long N, hipStream_t s);
+
+// ---- a9: FWI
+void launch_fwi_residual(const cpx<double>* u, int nsrc, long long N, const long long* rec,
+                         int nrec, const cpx<double>* dobs, cpx<double>* res,
+                         cpx<double>* adj_rhs, double* misfit_part, hipStream_t s);
+void launch_fwi_gradient(const Problem& P, const cpx<double>* u, const cpx<double>* y, int nsrc,
+                         double* grad, hipStream_t s);
+void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long* rec, int nrec,
+                   cpx<double>* d, hipStream_t s);
+
+}  // namespace dsd

@@ -1,0 +1,1092 @@
+// Host side of the dsweep library: partition, routing rules, schedules,
+// factorisation driver, sweeps, flexible GMRES and FWI, behind the C ABI of
+// include/dsweep.h.
+#include <algorithm>
+#include <complex>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dsweep.h"
+#include "kernels.hpp"
+
+using namespace dsd;
+
+namespace {
+
+thread_local std::string g_detail;
+
+#define HIPCHK(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      g_detail = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+      return e_ == hipErrorOutOfMemory ? DSD_ENOMEM : DSD_EHIP;                   \
+    }                                                                             \
+  } while (0)
+
+#define CHK(expr)                  \
+  do {                             \
+    int rc_ = (expr);              \
+    if (rc_ < 0) return rc_;       \
+  } while (0)
+
+// ---------------------------------------------------------------- sweep rules
+// Sweep directions: Section 3 (2D order) and (Sorder3D) of Section 4.1.
+const int ORDER2[4][3] = {{1, 1, 0}, {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}};
+const int ORDER3[8][3] = {{1, 1, 1},  {-1, 1, 1},  {1, -1, 1},  {-1, -1, 1},
+                          {1, 1, -1}, {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
+
+const int* sweep_dir(int dim, int l) { return dim == 2 ? ORDER2[l] : ORDER3[l]; }
+
+// Rule 3.1 (t.D > 0) / Rule 4.1 (t.D > 0 and every t_k D_k >= 0)
+bool similar(int dim, const int* t, const int* D) {
+  int dot = 0;
+  bool comp = true;
+  for (int k = 0; k < dim; ++k) {
+    dot += t[k] * D[k];
+    if (t[k] * D[k] < 0) comp = false;
+  }
+  return dim == 2 ? dot > 0 : (dot > 0 && comp);
+}
+
+// Rule 3.2 / 4.2: barred if, in a coordinate plane, the projection of t has
+// exactly one zero component and the projections of the sweeps are opposite.
+bool barred(int dim, const int* t, const int* D1, const int* D2) {
+  const int planes3[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  const int np = dim == 2 ? 1 : 3;
+  for (int q = 0; q < np; ++q) {
+    const int a = planes3[q][0], b = planes3[q][1];
+    const int zeros = (t[a] == 0) + (t[b] == 0);
+    if (zeros != 1) continue;
+    if (D1[a] == -D2[a] && D1[b] == -D2[b]) return true;
+  }
+  return false;
+}
+
+// Sweep (>= l) that uses a transfer of direction t generated in sweep l; -1 if dropped.
+int route(int dim, int l, const int* t) {
+  const int L = 1 << dim;
+  for (int lp = l; lp < L; ++lp)
+    if (similar(dim, t, sweep_dir(dim, lp)) && !barred(dim, t, sweep_dir(dim, l), sweep_dir(dim, lp)))
+      return lp;
+  return -1;
+}
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~Buf() { if (p) (void)hipFree(p); }
+  int alloc(size_t b) {
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
+    if (b == 0) return 0;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      g_detail = "hipMalloc of " + std::to_string(b) + " bytes failed";
+      return DSD_ENOMEM;
+    }
+    bytes = b;
+    return 0;
+  }
+  template <typename U> U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+template <typename U>
+int upload(Buf& b, const std::vector<U>& v) {
+  CHK(b.alloc(std::max<size_t>(1, v.size()) * sizeof(U)));
+  if (!v.empty()) HIPCHK(hipMemcpy(b.p, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice));
+  return 0;
+}
+
+struct StepTab {
+  int mem_off, nmem;           // members (subdomain ids) in d_members
+  int job_off;                 // fwd/bwd jobs (2 per member) in d_jobs2; mid jobs at d_jobs1
+  int er_off;                  // edge ranges (1 per member) in d_erange
+  long long max_nloc, max_box;
+  double fac_bytes_fb;         // factor bytes touched by the fwd (= bwd) launch
+  double fac_bytes_mid;
+  long long blk_cells_fb;      // block-cells processed by the fwd launch (for vector bytes)
+  long long blk_cells_mid;
+};
+
+}  // namespace
+
+struct dsd_plan {
+  dsd_params prm{};
+  double omega = 0;
+  Problem P{};
+  int dim = 2, L = 4, nsteps = 0, S = 0, kmax = 1, kg = 2, max_nb = 0;
+  bool c64 = true;
+  std::vector<SubDesc> subs;
+  std::vector<AxisPart> parts[3];
+  std::vector<StepTab> steps;   // [l * nsteps + s]
+  long long sum_nloc = 0, sum_fac = 0;
+
+  Buf d_subs, d_m, d_gcoef[4], d_lcoef64[4], d_lcoefT[4], d_fac;
+  Buf d_rpool, d_vpool, d_members, d_jobs2, d_jobs1, d_edges, d_erange;
+  Buf d_part_of[3], d_axparts[3];
+  Buf d_single_job, d_single_mem;
+  // Krylov workspace
+  Buf d_V, d_Z, d_w, d_r, d_xa, d_ba, d_part, d_h1, d_h2, d_hn, d_scal, d_idx, d_coef;
+  int kr_restart = 0, kr_k = 0;
+  // FWI workspace
+  Buf d_res, d_adj, d_y, d_mpart, d_u;
+
+  hipStream_t stream = nullptr;
+  // timing
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_solve_ms = 0, t_other_ms = 0, solve_bytes = 0;
+  long long solve_launches = 0;
+
+  ~dsd_plan() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+};
+
+namespace {
+
+size_t tsize(const dsd_plan* p) { return p->c64 ? sizeof(cpx<float>) : sizeof(cpx<double>); }
+
+int build_partition(dsd_plan* pl) {
+  const dsd_params& q = pl->prm;
+  Problem& P = pl->P;
+  P.dim = q.dim;
+  P.pml = q.pml;
+  P.d = q.overlap;
+  P.h = q.h;
+  P.omega = pl->omega;
+  P.s0d = q.sigma0_delta > 0 ? q.sigma0_delta : 60.0;
+  P.N = 1;
+  for (int a = 0; a < 3; ++a) {
+    P.n[a] = a < q.dim ? q.n[a] : 1;
+    P.ng[a] = a < q.dim ? q.n[a] + 2 * q.pml : 1;
+    P.N *= P.ng[a];
+  }
+  // axis partitions: array_split of the physical cells, larger parts first
+  for (int a = 0; a < 3; ++a) {
+    pl->parts[a].clear();
+    if (a >= q.dim) {
+      pl->parts[a].push_back(AxisPart{0, 1, 1, 1});
+      continue;
+    }
+    const int n = q.n[a], Pp = q.parts[a];
+    int q0 = 0;
+    for (int p = 0; p < Pp; ++p) {
+      const int len = n / Pp + (p < n % Pp ? 1 : 0);
+      const int q1 = q0 + len;
+      if (Pp > 1 && len < q.overlap) {
+        g_detail = "axis " + std::to_string(a) + " part " + std::to_string(p) +
+                   " owns fewer cells than the overlap";
+        return DSD_EINVAL;
+      }
+      AxisPart ap;
+      ap.o0 = p == 0 ? 0 : q0 + q.pml;
+      ap.o1 = p == Pp - 1 ? n + 2 * q.pml : q1 + q.pml;
+      ap.first = p == 0;
+      ap.last = p == Pp - 1;
+      pl->parts[a].push_back(ap);
+      q0 = q1;
+    }
+  }
+  // subdomains (x part fastest)
+  const int Px = q.parts[0], Py = q.parts[1], Pz = q.dim == 3 ? q.parts[2] : 1;
+  pl->S = Px * Py * Pz;
+  pl->subs.assign(pl->S, SubDesc{});
+  long long coff = 0, foff = 0;
+  pl->max_nb = 0;
+  for (int iz = 0; iz < Pz; ++iz)
+    for (int iy = 0; iy < Py; ++iy)
+      for (int ix = 0; ix < Px; ++ix) {
+        const int sid = (iz * Py + iy) * Px + ix;
+        SubDesc& S = pl->subs[sid];
+        const int pidx[3] = {ix, iy, iz};
+        S.nloc = 1;
+        for (int a = 0; a < 3; ++a) {
+          S.part[a] = pidx[a];
+          S.pt[a] = pl->parts[a][pidx[a]];
+          if (a >= q.dim) {
+            S.ax[a] = AxisGrid{0, 1, -1e300, 1e300, q.pml, q.pml};
+            S.dims[a] = 1;
+            continue;
+          }
+          const int n = q.n[a], Pp = q.parts[a], d = q.overlap, pm = q.pml;
+          const AxisPart& ap = S.pt[a];
+          const int q0 = ap.first ? 0 : ap.o0 - pm;        // physical own range
+          const int q1 = ap.last ? n : ap.o1 - pm;
+          AxisGrid g;
+          g.g0 = ap.first ? 0 : q0 - d;
+          const int g1 = ap.last ? n + 2 * pm : q1 + d + 2 * pm;
+          g.n = g1 - g.g0;
+          g.lo = ap.first ? 0.0 : (q0 - d) * q.h;
+          g.hi = ap.last ? n * q.h : (q1 + d) * q.h;
+          g.clo = ap.first ? pm : q0 - d + pm;
+          g.chi = ap.last ? n + pm - 1 : q1 + d + pm - 1;
+          (void)Pp;
+          S.ax[a] = g;
+          S.dims[a] = g.n;
+          S.nloc *= g.n;
+        }
+        if (q.dim == 2) {
+          S.nb = S.dims[0];
+          S.nblk = S.dims[1];
+        } else {
+          S.nb = S.dims[0] * S.dims[1];
+          S.nblk = S.dims[2];
+        }
+        S.mid = S.nblk / 2;
+        S.coef_off = coff;
+        S.vec_off = coff;
+        S.fac_off = foff;
+        coff += S.nloc;
+        foff += (long long)S.nblk * S.nb * S.nb;
+        pl->max_nb = std::max(pl->max_nb, S.nb);
+      }
+  pl->sum_nloc = coff;
+  pl->sum_fac = foff;
+  return 0;
+}
+
+int sub_index(const dsd_plan* pl, const int* pidx) {
+  for (int a = 0; a < pl->dim; ++a)
+    if (pidx[a] < 0 || pidx[a] >= pl->prm.parts[a]) return -1;
+  const int Px = pl->prm.parts[0], Py = pl->prm.parts[1];
+  const int z = pl->dim == 3 ? pidx[2] : 0;
+  return (z * Py + pidx[1]) * Px + pidx[0];
+}
+
+int build_schedule(dsd_plan* pl) {
+  const int dim = pl->dim, L = pl->L;
+  const dsd_params& q = pl->prm;
+  int nsteps = 1;
+  for (int a = 0; a < dim; ++a) nsteps += q.parts[a] - 1;
+  pl->nsteps = nsteps;
+  std::vector<int> members, erange_flat;
+  std::vector<int2> jobs2, jobs1, erange;
+  std::vector<Edge> edges;
+  // edges per (l, receiver)
+  std::vector<int2> edge_of((size_t)L * pl->S);
+  std::vector<int> tdirs;
+  for (int tz = (dim == 3 ? -1 : 0); tz <= (dim == 3 ? 1 : 0); ++tz)
+    for (int ty = -1; ty <= 1; ++ty)
+      for (int tx = -1; tx <= 1; ++tx) {
+        if (tx == 0 && ty == 0 && tz == 0) continue;
+        tdirs.push_back(tx);
+        tdirs.push_back(ty);
+        tdirs.push_back(tz);
+      }
+  const int ndir = (int)tdirs.size() / 3;
+  for (int l = 0; l < L; ++l)
+    for (int rid = 0; rid < pl->S; ++rid) {
+      const SubDesc& R = pl->subs[rid];
+      const int start = (int)edges.size();
+      for (int di = 0; di < ndir; ++di) {
+        const int* t = &tdirs[3 * di];
+        int sp[3] = {R.part[0] - t[0], R.part[1] - t[1], R.part[2] - t[2]};
+        const int sid = sub_index(pl, sp);
+        if (sid < 0) continue;
+        unsigned mask = 0;
+        for (int lg = 0; lg <= l; ++lg)
+          if (route(dim, lg, t) == l) mask |= 1u << lg;
+        if (!mask) continue;
+        const SubDesc& Sd = pl->subs[sid];
+        Edge e{};
+        e.sender = sid;
+        e.lmask = mask;
+        for (int a = 0; a < 3; ++a) {
+          e.t[a] = t[a];
+          e.off[a] = R.ax[a].g0 - Sd.ax[a].g0;
+          if (a >= dim || t[a] == 0) {
+            e.lo[a] = 0;
+            e.hi[a] = R.dims[a];
+            if (a < dim && (R.ax[a].g0 != Sd.ax[a].g0 || R.dims[a] != Sd.dims[a])) {
+              g_detail = "tangential grids of neighbours differ";
+              return DSD_EINVAL;
+            }
+          } else if (t[a] > 0) {
+            const int e0 = Sd.pt[a].o1 - R.ax[a].g0;   // receiver's first own cell
+            e.lo[a] = e0;
+            e.hi[a] = e0 + q.overlap;
+          } else {
+            const int e1 = Sd.pt[a].o0 - R.ax[a].g0;   // one past the receiver's last own cell
+            e.lo[a] = e1 - q.overlap;
+            e.hi[a] = e1;
+          }
+          if (e.lo[a] < 0 || e.hi[a] > R.dims[a] || e.lo[a] + e.off[a] < 0 ||
+              e.hi[a] + e.off[a] > Sd.dims[a]) {
+            g_detail = "transfer box outside a local grid";
+            return DSD_EINVAL;
+          }
+        }
+        edges.push_back(e);
+      }
+      edge_of[(size_t)l * pl->S + rid] = make_int2(start, (int)edges.size() - start);
+    }
+  pl->steps.assign((size_t)L * nsteps, StepTab{});
+  for (int l = 0; l < L; ++l) {
+    const int* D = sweep_dir(dim, l);
+    std::vector<std::vector<int>> groups(nsteps);
+    for (int sid = 0; sid < pl->S; ++sid) {
+      const SubDesc& S = pl->subs[sid];
+      int st = 0;
+      for (int a = 0; a < dim; ++a) st += D[a] > 0 ? S.part[a] : q.parts[a] - 1 - S.part[a];
+      groups[st].push_back(sid);
+    }
+    for (int s = 0; s < nsteps; ++s) {
+      StepTab& T = pl->steps[(size_t)l * nsteps + s];
+      T.mem_off = (int)members.size();
+      T.nmem = (int)groups[s].size();
+      T.job_off = (int)jobs2.size();
+      T.er_off = (int)erange.size();
+      T.max_nloc = 0;
+      T.max_box = 0;
+      T.fac_bytes_fb = T.fac_bytes_mid = 0;
+      T.blk_cells_fb = T.blk_cells_mid = 0;
+      for (int sid : groups[s]) {
+        const SubDesc& S = pl->subs[sid];
+        members.push_back(sid);
+        jobs2.push_back(make_int2(sid, 0));
+        jobs2.push_back(make_int2(sid, 1));
+        jobs1.push_back(make_int2(sid, 0));
+        const int2 er = edge_of[(size_t)l * pl->S + sid];
+        erange.push_back(er);
+        long long box = 0;
+        for (int e = er.x; e < er.x + er.y; ++e)
+          box += (long long)(edges[e].hi[0] - edges[e].lo[0]) * (edges[e].hi[1] - edges[e].lo[1]) *
+                 (edges[e].hi[2] - edges[e].lo[2]);
+        T.max_box = std::max(T.max_box, box);
+        T.max_nloc = std::max(T.max_nloc, S.nloc);
+        const double blk = (double)S.nb * S.nb * tsize(pl);
+        T.fac_bytes_fb += (double)(S.nblk - 1) * blk;
+        T.fac_bytes_mid += blk;
+        T.blk_cells_fb += (long long)(S.nblk - 1) * S.nb;
+        T.blk_cells_mid += S.nb;
+      }
+    }
+  }
+  CHK(upload(pl->d_members, members));
+  CHK(upload(pl->d_jobs2, jobs2));
+  CHK(upload(pl->d_jobs1, jobs1));
+  CHK(upload(pl->d_edges, edges));
+  CHK(upload(pl->d_erange, erange));
+  // part tables for the assembly of u_DDM
+  for (int a = 0; a < 3; ++a) {
+    std::vector<int> po(pl->P.ng[a], 0);
+    for (int g = 0; g < pl->P.ng[a]; ++g)
+      for (int p = 0; p < (int)pl->parts[a].size(); ++p)
+        if (g >= pl->parts[a][p].o0 && g < pl->parts[a][p].o1) po[g] = p;
+    CHK(upload(pl->d_part_of[a], po));
+    CHK(upload(pl->d_axparts[a], pl->parts[a]));
+  }
+  return 0;
+}
+
+int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
+  hipStream_t st = pl->stream;
+  const Problem& P = pl->P;
+  long long nphys = (long long)P.n[0] * P.n[1] * P.n[2];
+  CHK(pl->d_m.alloc(nphys * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(pl->d_m.p, m_dev, nphys * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // grids: 0 = global, 1.. = subdomains
+  std::vector<AxisGrid> grids;
+  std::vector<long long> offs;
+  for (int a = 0; a < 3; ++a) {
+    if (a < pl->dim)
+      grids.push_back(AxisGrid{0, P.ng[a], 0.0, P.n[a] * P.h, P.pml, P.n[a] + P.pml - 1});
+    else
+      grids.push_back(AxisGrid{0, 1, -1e300, 1e300, P.pml, P.pml});
+  }
+  offs.push_back(0);
+  long long maxc = P.N;
+  for (const SubDesc& S : pl->subs) {
+    for (int a = 0; a < 3; ++a) grids.push_back(S.ax[a]);
+    offs.push_back(S.coef_off);
+    maxc = std::max(maxc, S.nloc);
+  }
+  Buf dg, doff;
+  CHK(upload(dg, grids));
+  CHK(upload(doff, offs));
+  for (int i = 0; i < 4; ++i) {
+    CHK(pl->d_gcoef[i].alloc(P.N * sizeof(cpx<double>)));
+    CHK(pl->d_lcoef64[i].alloc(pl->sum_nloc * sizeof(cpx<double>)));
+    CHK(pl->d_lcoefT[i].alloc(pl->sum_nloc * tsize(pl)));
+  }
+  // global grid
+  launch_assemble(P, dg.as<AxisGrid>(), doff.as<long long>(), 1, P.N, pl->d_m.as<double>(),
+                  pl->d_gcoef[0].as<cpx<double>>(), pl->d_gcoef[1].as<cpx<double>>(),
+                  pl->d_gcoef[2].as<cpx<double>>(), pl->d_gcoef[3].as<cpx<double>>(), st);
+  HIPCHK(hipGetLastError());
+  // subdomain grids
+  launch_assemble(P, dg.as<AxisGrid>() + 3, doff.as<long long>() + 1, pl->S, maxc,
+                  pl->d_m.as<double>(), pl->d_lcoef64[0].as<cpx<double>>(),
+                  pl->d_lcoef64[1].as<cpx<double>>(), pl->d_lcoef64[2].as<cpx<double>>(),
+                  pl->d_lcoef64[3].as<cpx<double>>(), st);
+  HIPCHK(hipGetLastError());
+  for (int i = 0; i < 4; ++i) {
+    if (pl->c64)
+      launch_convert<float>(pl->d_lcoef64[i].as<cpx<double>>(), pl->d_lcoefT[i].as<cpx<float>>(),
+                            pl->sum_nloc, st);
+    else
+      launch_convert<double>(pl->d_lcoef64[i].as<cpx<double>>(),
+                             pl->d_lcoefT[i].as<cpx<double>>(), pl->sum_nloc, st);
+  }
+  HIPCHK(hipGetLastError());
+
+  // ---- factorisation: chains of Schur complements towards the middle block
+  CHK(pl->d_fac.alloc((size_t)pl->sum_fac * tsize(pl)));
+  const long long blk = (long long)pl->max_nb * pl->max_nb;
+  Buf scratch, derr, dpiv, djobs;
+  CHK(scratch.alloc((size_t)pl->S * 4 * blk * sizeof(cpx<double>)));
+  auto slot = [&](int sid, int half, int parity) {
+    return ((long long)sid * 4 + half * 2 + parity) * blk;
+  };
+  int maxlen = 0;
+  for (const SubDesc& S : pl->subs) maxlen = std::max(maxlen, std::max(S.mid, S.nblk - 1 - S.mid));
+  std::vector<FactorJob> all;
+  std::vector<int> job_off(maxlen + 2, 0);
+  for (int t = 0; t < maxlen; ++t) {
+    job_off[t] = (int)all.size();
+    for (int sid = 0; sid < pl->S; ++sid) {
+      const SubDesc& S = pl->subs[sid];
+      if (t < S.mid) {
+        FactorJob J{};
+        J.sub = sid;
+        J.k = t;
+        J.cp_blk = t > 0 ? t - 1 : -1;
+        J.cq_blk = -1;
+        J.prev = slot(sid, 0, (t + 1) & 1);
+        J.prev2 = 0;
+        J.cur = slot(sid, 0, t & 1);
+        all.push_back(J);
+      }
+      if (t < S.nblk - 1 - S.mid) {
+        FactorJob J{};
+        J.sub = sid;
+        J.k = S.nblk - 1 - t;
+        J.cp_blk = t > 0 ? J.k : -1;
+        J.cq_blk = -1;
+        J.prev = slot(sid, 1, (t + 1) & 1);
+        J.prev2 = 0;
+        J.cur = slot(sid, 1, t & 1);
+        all.push_back(J);
+      }
+    }
+  }
+  job_off[maxlen] = (int)all.size();
+  for (int sid = 0; sid < pl->S; ++sid) {
+    const SubDesc& S = pl->subs[sid];
+    FactorJob J{};
+    J.sub = sid;
+    J.k = S.mid;
+    J.cp_blk = S.mid > 0 ? S.mid - 1 : -1;
+    J.prev = slot(sid, 0, (S.mid - 1) & 1);
+    const int nbot = S.nblk - 1 - S.mid;
+    J.cq_blk = nbot > 0 ? S.mid : -1;
+    J.prev2 = slot(sid, 1, (nbot - 1) & 1);
+    J.cur = slot(sid, 0, S.mid & 1);
+    all.push_back(J);
+  }
+  job_off[maxlen + 1] = (int)all.size();
+  CHK(upload(djobs, all));
+  CHK(derr.alloc(all.size() * sizeof(int)));
+  HIPCHK(hipMemsetAsync(derr.p, 0, all.size() * sizeof(int), st));
+  int maxjobs = 0;
+  for (int t = 0; t <= maxlen; ++t) maxjobs = std::max(maxjobs, job_off[t + 1] - job_off[t]);
+  CHK(dpiv.alloc((size_t)maxjobs * pl->max_nb * sizeof(int)));
+  for (int t = 0; t <= maxlen; ++t) {
+    const int j0 = job_off[t], nj = job_off[t + 1] - j0;
+    const FactorJob* jp = djobs.as<FactorJob>() + j0;
+    launch_schur(P, pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
+                 pl->d_lcoef64[0].as<cpx<double>>(), pl->d_lcoef64[1].as<cpx<double>>(),
+                 pl->d_lcoef64[2].as<cpx<double>>(), pl->d_lcoef64[3].as<cpx<double>>(),
+                 scratch.as<cpx<double>>(), st);
+    if (pl->c64)
+      launch_invert<float>(pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
+                           scratch.as<cpx<double>>(), pl->d_fac.as<cpx<float>>(),
+                           derr.as<int>() + j0, dpiv.as<int>(), st);
+    else
+      launch_invert<double>(pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
+                            scratch.as<cpx<double>>(), pl->d_fac.as<cpx<double>>(),
+                            derr.as<int>() + j0, dpiv.as<int>(), st);
+    HIPCHK(hipGetLastError());
+  }
+  std::vector<int> herr(all.size());
+  HIPCHK(hipMemcpyAsync(herr.data(), derr.p, all.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int v : herr)
+    if (v) {
+      g_detail = "singular Schur block in subdomain " + std::to_string(v - 1);
+      return DSD_EPIVOT;
+    }
+  return 0;
+}
+
+int ensure_pools(dsd_plan* pl) {
+  if (pl->d_rpool.p) return 0;
+  CHK(pl->d_rpool.alloc((size_t)pl->sum_nloc * pl->kmax * tsize(pl)));
+  CHK(pl->d_vpool.alloc((size_t)pl->L * pl->sum_nloc * pl->kmax * tsize(pl)));
+  return 0;
+}
+
+template <typename T>
+void chain_phase(dsd_plan* pl, int phase, const int2* jobs, int njobs, int nrhs, double fbytes,
+                 long long blk_cells, cpx<T>* xpool) {
+  hipStream_t st = pl->stream;
+  if (pl->timing) (void)hipEventRecord(pl->ev0, st);
+  launch_chain<T>(pl->kg, phase, pl->d_subs.as<SubDesc>(), jobs, njobs, nrhs, pl->kmax,
+                  pl->max_nb, pl->d_fac.as<cpx<T>>(), pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>(),
+                  pl->d_rpool.as<cpx<T>>(), xpool, st);
+  if (pl->timing) {
+    (void)hipEventRecord(pl->ev1, st);
+    (void)hipEventSynchronize(pl->ev1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+    pl->t_solve_ms += ms;
+    pl->solve_launches += 1;
+    // factor blocks once per launch plus the vectors read and written per RHS
+    pl->solve_bytes += fbytes + (double)blk_cells * nrhs * 2.0 * sizeof(cpx<T>);
+  }
+}
+
+template <typename T>
+int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) {
+  CHK(ensure_pools(pl));
+  hipStream_t st = pl->stream;
+  const Problem& P = pl->P;
+  const long long pool_stride = pl->sum_nloc * pl->kmax;
+  cpx<T>* rpool = pl->d_rpool.as<cpx<T>>();
+  cpx<T>* vpool = pl->d_vpool.as<cpx<T>>();
+  for (int l = 0; l < pl->L; ++l) {
+    for (int s = 0; s < pl->nsteps; ++s) {
+      const StepTab& st_ = pl->steps[(size_t)l * pl->nsteps + s];
+      if (st_.nmem == 0) continue;
+      const int* mem = pl->d_members.as<int>() + st_.mem_off;
+      launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, l == 0, nrhs,
+                         pl->kmax, f, rpool, st);
+      launch_pull<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, pl->d_edges.as<Edge>(),
+                     pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
+                     pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
+                     pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
+      cpx<T>* xpool = vpool + (long long)l * pool_stride;
+      const int2* j2 = pl->d_jobs2.as<int2>() + st_.job_off;
+      const int2* j1 = pl->d_jobs1.as<int2>() + st_.mem_off;
+      chain_phase<T>(pl, 0, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb, xpool);
+      chain_phase<T>(pl, 1, j1, st_.nmem, nrhs, st_.fac_bytes_mid, st_.blk_cells_mid, xpool);
+      chain_phase<T>(pl, 2, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb, xpool);
+    }
+  }
+  PartTables pt;
+  for (int a = 0; a < 3; ++a) {
+    pt.part_of[a] = pl->d_part_of[a].as<int>();
+    pt.parts[a] = pl->d_axparts[a].as<AxisPart>();
+    pt.P[a] = (int)pl->parts[a].size();
+  }
+  launch_assemble_u<T>(P, pl->d_subs.as<SubDesc>(), pt, pl->L, nrhs, pl->kmax, vpool, pool_stride,
+                       u, st);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int sweep_apply_any(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) {
+  return pl->c64 ? sweep_apply_t<float>(pl, f, u, nrhs) : sweep_apply_t<double>(pl, f, u, nrhs);
+}
+
+// ---------------------------------------------------------------- FGMRES (FP64)
+int ensure_krylov(dsd_plan* pl, int restart) {
+  if (pl->kr_restart >= restart && pl->d_V.p) return 0;
+  const size_t vec = (size_t)pl->kmax * pl->P.N * sizeof(cpx<double>);
+  CHK(pl->d_V.alloc((size_t)(restart + 1) * vec));
+  CHK(pl->d_Z.alloc((size_t)restart * vec));
+  CHK(pl->d_w.alloc(vec));
+  CHK(pl->d_r.alloc(vec));
+  CHK(pl->d_xa.alloc(vec));
+  CHK(pl->d_ba.alloc(vec));
+  const int nblk = 256;
+  CHK(pl->d_part.alloc((size_t)(restart + 1) * pl->kmax * nblk * sizeof(cpx<double>)));
+  CHK(pl->d_h1.alloc((size_t)(restart + 1) * pl->kmax * sizeof(cpx<double>)));
+  CHK(pl->d_h2.alloc((size_t)(restart + 1) * pl->kmax * sizeof(cpx<double>)));
+  CHK(pl->d_hn.alloc((size_t)pl->kmax * sizeof(cpx<double>)));
+  CHK(pl->d_scal.alloc((size_t)pl->kmax * sizeof(double)));
+  CHK(pl->d_idx.alloc((size_t)pl->kmax * sizeof(int)));
+  CHK(pl->d_coef.alloc((size_t)(restart + 1) * pl->kmax * sizeof(cpx<double>)));
+  pl->kr_restart = restart;
+  return 0;
+}
+
+typedef std::complex<double> zc;
+
+// Flexible GMRES, right-preconditioned by one sweep application per step,
+// batched over the RHS that are still active; classical Gram-Schmidt applied
+// twice; restarts from the current iterate with the true FP64 residual.
+int gmres_core(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, double tol,
+               int maxit, int restart, int* iters_host, double* relres_host) {
+  hipStream_t st = pl->stream;
+  const long long N = pl->P.N;
+  if (nrhs <= 0) return 0;
+  if (nrhs > pl->kmax || maxit <= 0 || !(tol > 0)) {
+    g_detail = "gmres: nrhs must be <= max_rhs, maxit > 0 and tol > 0";
+    return DSD_EINVAL;
+  }
+  if (restart <= 0) restart = 30;
+  restart = std::min(restart, maxit);
+  CHK(ensure_krylov(pl, restart));
+  const int nblk = 256;
+  cpx<double>* V = pl->d_V.as<cpx<double>>();
+  cpx<double>* Z = pl->d_Z.as<cpx<double>>();
+  cpx<double>* w = pl->d_w.as<cpx<double>>();
+  cpx<double>* r = pl->d_r.as<cpx<double>>();
+  cpx<double>* xa = pl->d_xa.as<cpx<double>>();
+  cpx<double>* ba = pl->d_ba.as<cpx<double>>();
+  cpx<double>* part = pl->d_part.as<cpx<double>>();
+  cpx<double>* h1 = pl->d_h1.as<cpx<double>>();
+  cpx<double>* h2 = pl->d_h2.as<cpx<double>>();
+  cpx<double>* hn = pl->d_hn.as<cpx<double>>();
+  double* scal = pl->d_scal.as<double>();
+  int* idx = pl->d_idx.as<int>();
+  cpx<double>* coef = pl->d_coef.as<cpx<double>>();
+
+  std::vector<cpx<double>> hb(nrhs);
+  launch_mdot(b, 1, b, nrhs, N, part, nblk, h1, st);
+  HIPCHK(hipMemcpyAsync(hb.data(), h1, nrhs * sizeof(cpx<double>), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)nrhs * N * sizeof(cpx<double>), st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<double> bn(nrhs), rel(nrhs, 1.0);
+  std::vector<int> it(nrhs, 0);
+  std::vector<char> done(nrhs, 0);
+  for (int i = 0; i < nrhs; ++i) {
+    bn[i] = std::sqrt(hb[i].re);
+    if (!std::isfinite(bn[i])) { g_detail = "non-finite right-hand side"; return DSD_ENOTFINITE; }
+    if (bn[i] == 0) { done[i] = 1; rel[i] = 0; }
+  }
+  bool first = true;
+  std::vector<int> act, pend;
+  std::vector<cpx<double>> hh1, hh2, hhn;
+  std::vector<double> hscal;
+  while (true) {
+    // true residual of every RHS not yet converged
+    pend.clear();
+    for (int i = 0; i < nrhs; ++i)
+      if (!done[i]) pend.push_back(i);
+    if (pend.empty()) break;
+    const int np = (int)pend.size();
+    HIPCHK(hipMemcpyAsync(idx, pend.data(), np * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_gather_rhs(b, idx, ba, np, N, st);
+    if (first) {
+      HIPCHK(hipMemcpyAsync(r, ba, (size_t)np * N * sizeof(cpx<double>), hipMemcpyDeviceToDevice, st));
+    } else {
+      launch_gather_rhs(x, idx, xa, np, N, st);
+      launch_apply_op(pl->P, pl->d_gcoef[0].as<cpx<double>>(), pl->d_gcoef[1].as<cpx<double>>(),
+                      pl->d_gcoef[2].as<cpx<double>>(), pl->d_gcoef[3].as<cpx<double>>(), xa, w,
+                      np, st);
+      launch_sub(ba, w, r, (long long)np * N, st);
+    }
+    launch_mdot(r, 1, r, np, N, part, nblk, hn, st);
+    hhn.resize(np);
+    HIPCHK(hipMemcpyAsync(hhn.data(), hn, np * sizeof(cpx<double>), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    act.clear();
+    for (int k = 0; k < np; ++k) {
+      const int i = pend[k];
+      const double beta = std::sqrt(hhn[k].re);
+      if (!std::isfinite(beta)) { g_detail = "non-finite residual"; return DSD_ENOTFINITE; }
+      rel[i] = beta / bn[i];
+      if (rel[i] <= tol || it[i] >= maxit) done[i] = 1;
+      else act.push_back(i);
+    }
+    first = false;
+    if (act.empty()) break;
+    if ((int)act.size() != np) continue;   // recompute with the reduced set
+    const int na = np;
+    // V_0 = r / beta
+    hscal.resize(na);
+    std::vector<double> beta0(na);
+    for (int k = 0; k < na; ++k) {
+      beta0[k] = std::sqrt(hhn[k].re);
+      hscal[k] = 1.0 / beta0[k];
+    }
+    HIPCHK(hipMemcpyAsync(scal, hscal.data(), na * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_scale(r, scal, V, na, N, st);
+    const long long vs = (long long)na * N;
+    std::vector<std::vector<zc>> H(na, std::vector<zc>((size_t)(restart + 1) * restart));
+    std::vector<std::vector<zc>> cs(na, std::vector<zc>(restart)), sn(na, std::vector<zc>(restart));
+    std::vector<std::vector<zc>> g(na, std::vector<zc>(restart + 1));
+    std::vector<int> js(na, -1);
+    for (int k = 0; k < na; ++k) g[k][0] = beta0[k];
+    int jmax = 0;
+    for (int j = 0; j < restart; ++j) {
+      bool any = false;
+      for (int k = 0; k < na; ++k) any = any || js[k] < 0;
+      if (!any) break;
+      CHK(sweep_apply_any(pl, V + j * vs, Z + j * vs, na));
+      launch_apply_op(pl->P, pl->d_gcoef[0].as<cpx<double>>(), pl->d_gcoef[1].as<cpx<double>>(),
+                      pl->d_gcoef[2].as<cpx<double>>(), pl->d_gcoef[3].as<cpx<double>>(),
+                      Z + j * vs, w, na, st);
+      launch_mdot(V, j + 1, w, na, N, part, nblk, h1, st);
+      launch_maxpy(V, j + 1, h1, -1.0, w, na, N, st);
+      launch_mdot(V, j + 1, w, na, N, part, nblk, h2, st);
+      launch_maxpy(V, j + 1, h2, -1.0, w, na, N, st);
+      launch_mdot(w, 1, w, na, N, part, nblk, hn, st);
+      hh1.resize((size_t)(j + 1) * na);
+      hh2.resize((size_t)(j + 1) * na);
+      hhn.resize(na);
+      HIPCHK(hipMemcpyAsync(hh1.data(), h1, hh1.size() * sizeof(cpx<double>), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hh2.data(), h2, hh2.size() * sizeof(cpx<double>), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hhn.data(), hn, na * sizeof(cpx<double>), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int k = 0; k < na; ++k) {
+        const double hnorm = std::sqrt(hhn[k].re);
+        if (!std::isfinite(hnorm)) { g_detail = "non-finite Arnoldi norm"; return DSD_ENOTFINITE; }
+        hscal[k] = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
+      }
+      HIPCHK(hipMemcpyAsync(scal, hscal.data(), na * sizeof(double), hipMemcpyHostToDevice, st));
+      launch_scale(w, scal, V + (j + 1) * vs, na, N, st);
+      HIPCHK(hipGetLastError());
+      jmax = j + 1;
+      for (int k = 0; k < na; ++k) {
+        if (js[k] >= 0) continue;
+        const int i = act[k];
+        zc* Hk = H[k].data();
+        auto Hij = [&](int a, int c) -> zc& { return Hk[(size_t)a * restart + c]; };
+        for (int a = 0; a <= j; ++a) {
+          const size_t o = (size_t)a * na + k;
+          Hij(a, j) = zc(hh1[o].re + hh2[o].re, hh1[o].im + hh2[o].im);
+        }
+        Hij(j + 1, j) = std::sqrt(hhn[k].re);
+        // complex Givens rotations G = [[conj(c), conj(s)], [-s, c]]
+        for (int a = 0; a < j; ++a) {
+          const zc t0 = std::conj(cs[k][a]) * Hij(a, j) + std::conj(sn[k][a]) * Hij(a + 1, j);
+          Hij(a + 1, j) = -sn[k][a] * Hij(a, j) + cs[k][a] * Hij(a + 1, j);
+          Hij(a, j) = t0;
+        }
+        const zc av = Hij(j, j), cv = Hij(j + 1, j);
+        const double rho = std::sqrt(std::norm(av) + std::norm(cv));
+        cs[k][j] = rho > 0 ? av / rho : zc(1.0);
+        sn[k][j] = rho > 0 ? cv / rho : zc(0.0);
+        Hij(j, j) = rho;
+        Hij(j + 1, j) = 0.0;
+        g[k][j + 1] = -sn[k][j] * g[k][j];
+        g[k][j] = std::conj(cs[k][j]) * g[k][j];
+        it[i] += 1;
+        const double est = std::abs(g[k][j + 1]) / bn[i];
+        if (est <= tol || it[i] >= maxit || j == restart - 1) js[k] = j + 1;
+      }
+    }
+    // y = H^{-1} g per RHS, x += Z y
+    std::vector<cpx<double>> hc((size_t)jmax * na, mk(0.0, 0.0));
+    for (int k = 0; k < na; ++k) {
+      const int m = js[k] < 0 ? jmax : js[k];
+      std::vector<zc> y(m);
+      const zc* Hk = H[k].data();
+      for (int a = m - 1; a >= 0; --a) {
+        zc s = g[k][a];
+        for (int c = a + 1; c < m; ++c) s -= Hk[(size_t)a * restart + c] * y[c];
+        y[a] = s / Hk[(size_t)a * restart + a];
+      }
+      for (int a = 0; a < m; ++a) hc[(size_t)a * na + k] = mk(y[a].real(), y[a].imag());
+    }
+    HIPCHK(hipMemcpyAsync(coef, hc.data(), hc.size() * sizeof(cpx<double>), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(idx, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    launch_gather_rhs(x, idx, xa, na, N, st);
+    launch_maxpy(Z, jmax, coef, 1.0, xa, na, N, st);
+    launch_scatter_rhs(xa, idx, x, na, N, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  bool ok = true;
+  for (int i = 0; i < nrhs; ++i) {
+    if (iters_host) iters_host[i] = it[i];
+    if (relres_host) relres_host[i] = rel[i];
+    ok = ok && rel[i] <= tol;
+  }
+  return ok ? DSD_OK : DSD_NOT_CONVERGED;
+}
+
+// Receiver indices are read by kernels: check them on the host first.
+int check_receivers(const dsd_plan* pl, const long long* rec_dev, int nrec) {
+  std::vector<long long> rec(nrec);
+  HIPCHK(hipMemcpy(rec.data(), rec_dev, nrec * sizeof(long long), hipMemcpyDeviceToHost));
+  for (long long r : rec)
+    if (r < 0 || r >= pl->P.N) {
+      g_detail = "receiver index outside the global grid";
+      return DSD_EINVAL;
+    }
+  return 0;
+}
+
+int choose_kg(const dsd_plan* pl, int want) {
+  int kg = 8;
+  while (kg > want && kg > 1) kg >>= 1;
+  while (kg > 1 && (size_t)2 * pl->max_nb * kg * tsize(pl) > 64 * 1024) kg >>= 1;
+  return kg;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev, void* stream,
+                    dsd_plan** out) {
+  g_detail.clear();
+  if (!params || !out || !m_dev) { g_detail = "null argument"; return DSD_EINVAL; }
+  *out = nullptr;
+  const dsd_params& q = *params;
+  if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
+      (q.precision != DSD_C64 && q.precision != DSD_C128)) {
+    g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128";
+    return DSD_EINVAL;
+  }
+  for (int a = 0; a < q.dim; ++a)
+    if (q.n[a] < 1 || q.parts[a] < 1 || q.parts[a] > q.n[a]) {
+      g_detail = "bad grid or partition size";
+      return DSD_EINVAL;
+    }
+  dsd_plan* pl = new dsd_plan();
+  pl->prm = q;
+  pl->omega = omega;
+  pl->dim = q.dim;
+  pl->L = 1 << q.dim;
+  pl->c64 = q.precision == DSD_C64;
+  pl->kmax = std::max(1, q.max_rhs);
+  pl->stream = (hipStream_t)stream;
+  int rc = build_partition(pl);
+  if (rc == 0) pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : 2);
+  if (rc == 0) rc = upload(pl->d_subs, pl->subs);
+  if (rc == 0) rc = assemble_and_factor(pl, m_dev);
+  if (rc == 0) rc = build_schedule(pl);
+  if (rc == 0 && (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess)) {
+    g_detail = "hipEventCreate failed";
+    rc = DSD_EHIP;
+  }
+  if (rc != 0) {
+    delete pl;
+    return rc;
+  }
+  *out = pl;
+  return DSD_OK;
+}
+
+void dsd_destroy(dsd_plan* plan) {
+  if (plan) {
+    (void)hipDeviceSynchronize();
+    delete plan;
+  }
+}
+
+int dsd_plan_info(const dsd_plan* pl, long long* n_global, int* n_subdomains,
+                  long long* factor_bytes, long long* workspace_bytes) {
+  if (!pl) return DSD_EINVAL;
+  if (n_global) *n_global = pl->P.N;
+  if (n_subdomains) *n_subdomains = pl->S;
+  if (factor_bytes) *factor_bytes = (long long)(pl->sum_fac * tsize(pl));
+  if (workspace_bytes) {
+    long long w = 0;
+    const Buf* bs[] = {&pl->d_rpool, &pl->d_vpool, &pl->d_V, &pl->d_Z, &pl->d_w, &pl->d_r,
+                       &pl->d_xa, &pl->d_ba, &pl->d_lcoef64[0], &pl->d_lcoef64[1],
+                       &pl->d_lcoef64[2], &pl->d_lcoef64[3], &pl->d_gcoef[0], &pl->d_gcoef[1],
+                       &pl->d_gcoef[2], &pl->d_gcoef[3]};
+    for (const Buf* b : bs) w += (long long)b->bytes;
+    *workspace_bytes = w;
+  }
+  return DSD_OK;
+}
+
+int dsd_subdomain_grid(const dsd_plan* pl, int sub, int* dims, int* g0) {
+  if (!pl || sub < 0 || sub >= pl->S) return DSD_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    if (dims) dims[a] = pl->subs[sub].dims[a];
+    if (g0) g0[a] = pl->subs[sub].ax[a].g0;
+  }
+  return DSD_OK;
+}
+
+int dsd_local_solve(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, int nrhs,
+                    void* stream) {
+  g_detail.clear();
+  if (!pl || sub < 0 || sub >= pl->S || nrhs <= 0 || nrhs > pl->kmax || !r_dev || !u_dev) {
+    g_detail = "local_solve: bad subdomain, nrhs or pointer";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  CHK(ensure_pools(pl));
+  const SubDesc& S = pl->subs[sub];
+  std::vector<int2> jobs = {make_int2(sub, 0), make_int2(sub, 1), make_int2(sub, 0)};
+  CHK(upload(pl->d_single_job, jobs));
+  const long long off = S.vec_off * pl->kmax;
+  hipStream_t st = pl->stream;
+  if (pl->c64) {
+    cpx<float>* rp = pl->d_rpool.as<cpx<float>>() + off;
+    cpx<float>* xp = pl->d_vpool.as<cpx<float>>();
+    launch_pack_local<float>((const cpx<double>*)r_dev, rp, S.nloc, nrhs, pl->kmax, st);
+    for (int ph = 0; ph < 3; ++ph)
+      chain_phase<float>(pl, ph, pl->d_single_job.as<int2>() + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2,
+                         nrhs, 0, 0, xp);
+    launch_unpack_local<float>(xp + off, (cpx<double>*)u_dev, S.nloc, nrhs, pl->kmax, st);
+  } else {
+    cpx<double>* rp = pl->d_rpool.as<cpx<double>>() + off;
+    cpx<double>* xp = pl->d_vpool.as<cpx<double>>();
+    launch_pack_local<double>((const cpx<double>*)r_dev, rp, S.nloc, nrhs, pl->kmax, st);
+    for (int ph = 0; ph < 3; ++ph)
+      chain_phase<double>(pl, ph, pl->d_single_job.as<int2>() + (ph == 1 ? 2 : 0),
+                          ph == 1 ? 1 : 2, nrhs, 0, 0, xp);
+    launch_unpack_local<double>(xp + off, (cpx<double>*)u_dev, S.nloc, nrhs, pl->kmax, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return DSD_OK;
+}
+
+int dsd_sweep_apply(dsd_plan* pl, const double* f_dev, double* u_dev, int nrhs, void* stream) {
+  g_detail.clear();
+  if (!pl || !f_dev || !u_dev || nrhs <= 0 || nrhs > pl->kmax) {
+    g_detail = "sweep_apply: bad pointer or nrhs (must be 1..max_rhs)";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  return sweep_apply_any(pl, (const cpx<double>*)f_dev, (cpx<double>*)u_dev, nrhs);
+}
+
+int dsd_apply_operator(dsd_plan* pl, const double* x_dev, double* y_dev, int nrhs, void* stream) {
+  g_detail.clear();
+  if (!pl || !x_dev || !y_dev || nrhs <= 0 || x_dev == y_dev) {
+    g_detail = "apply_operator: bad pointer or nrhs";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  launch_apply_op(pl->P, pl->d_gcoef[0].as<cpx<double>>(), pl->d_gcoef[1].as<cpx<double>>(),
+                  pl->d_gcoef[2].as<cpx<double>>(), pl->d_gcoef[3].as<cpx<double>>(),
+                  (const cpx<double>*)x_dev, (cpx<double>*)y_dev, nrhs, pl->stream);
+  HIPCHK(hipGetLastError());
+  return DSD_OK;
+}
+
+int dsd_gmres_solve(dsd_plan* pl, const double* b_dev, double* x_dev, int nrhs, double tol,
+                    int maxit, int restart, int* iters_host, double* relres_host, void* stream) {
+  g_detail.clear();
+  if (!pl || !b_dev || !x_dev || b_dev == x_dev) { g_detail = "gmres: bad pointer"; return DSD_EINVAL; }
+  pl->stream = (hipStream_t)stream;
+  return gmres_core(pl, (const cpx<double>*)b_dev, (cpx<double>*)x_dev, nrhs, tol, maxit, restart,
+                    iters_host, relres_host);
+}
+
+int dsd_adjoint_solve(dsd_plan* pl, const double* b_dev, double* x_dev, int nrhs, double tol,
+                      int maxit, int restart, int* iters_host, double* relres_host,
+                      void* stream) {
+  g_detail.clear();
+  if (!pl || !b_dev || !x_dev || b_dev == x_dev || nrhs <= 0 || nrhs > pl->kmax) {
+    g_detail = "adjoint: bad pointer or nrhs";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  const long long n = (long long)nrhs * pl->P.N;
+  CHK(pl->d_y.bytes >= (size_t)n * sizeof(cpx<double>) ? 0 : pl->d_y.alloc((size_t)pl->kmax * pl->P.N * sizeof(cpx<double>)));
+  cpx<double>* tmp = pl->d_y.as<cpx<double>>();
+  launch_conj((const cpx<double>*)b_dev, tmp, n, pl->stream);
+  int rc = gmres_core(pl, tmp, (cpx<double>*)x_dev, nrhs, tol, maxit, restart, iters_host,
+                      relres_host);
+  if (rc < 0) return rc;
+  launch_conj((const cpx<double>*)x_dev, (cpx<double>*)x_dev, n, pl->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return rc;
+}
+
+int dsd_fwi_forward(dsd_plan* pl, const double* f_dev, int nsrc, const long long* rec_dev,
+                    int nrec, double tol, int maxit, double* d_dev, void* stream) {
+  g_detail.clear();
+  if (!pl || !f_dev || !rec_dev || !d_dev || nsrc <= 0 || nsrc > pl->kmax || nrec <= 0) {
+    g_detail = "fwi_forward: bad pointer, nsrc (<= max_rhs) or nrec";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  CHK(check_receivers(pl, rec_dev, nrec));
+  const size_t vec = (size_t)pl->kmax * pl->P.N * sizeof(cpx<double>);
+  if (pl->d_u.bytes < vec) CHK(pl->d_u.alloc(vec));
+  int rc = gmres_core(pl, (const cpx<double>*)f_dev, pl->d_u.as<cpx<double>>(), nsrc, tol, maxit,
+                      0, nullptr, nullptr);
+  if (rc < 0) return rc;
+  launch_sample(pl->d_u.as<cpx<double>>(), nsrc, pl->P.N, rec_dev, nrec, (cpx<double>*)d_dev,
+                pl->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return rc;
+}
+
+int dsd_fwi_gradient(dsd_plan* pl, const double* f_dev, int nsrc, const long long* rec_dev,
+                     int nrec, const double* dobs_dev, double tol, int maxit, double* grad_dev,
+                     double* misfit_host, double* u_dev, void* stream) {
+  g_detail.clear();
+  if (!pl || !f_dev || !rec_dev || !dobs_dev || !grad_dev || nsrc <= 0 || nsrc > pl->kmax ||
+      nrec <= 0) {
+    g_detail = "fwi_gradient: bad pointer, nsrc (<= max_rhs) or nrec";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  CHK(check_receivers(pl, rec_dev, nrec));
+  hipStream_t st = pl->stream;
+  const long long N = pl->P.N;
+  const size_t vec = (size_t)pl->kmax * N * sizeof(cpx<double>);
+  if (pl->d_u.bytes < vec) CHK(pl->d_u.alloc(vec));
+  if (pl->d_adj.bytes < vec) CHK(pl->d_adj.alloc(vec));
+  if (pl->d_y.bytes < vec) CHK(pl->d_y.alloc(vec));
+  CHK(pl->d_res.alloc((size_t)nsrc * nrec * sizeof(cpx<double>)));
+  CHK(pl->d_mpart.alloc((size_t)nsrc * sizeof(double)));
+  cpx<double>* u = u_dev ? (cpx<double>*)u_dev : pl->d_u.as<cpx<double>>();
+  int rc1 = gmres_core(pl, (const cpx<double>*)f_dev, u, nsrc, tol, maxit, 0, nullptr, nullptr);
+  if (rc1 < 0) return rc1;
+  HIPCHK(hipMemsetAsync(pl->d_adj.p, 0, (size_t)nsrc * N * sizeof(cpx<double>), st));
+  launch_fwi_residual(u, nsrc, N, rec_dev, nrec, (const cpx<double>*)dobs_dev,
+                      pl->d_res.as<cpx<double>>(), pl->d_adj.as<cpx<double>>(),
+                      pl->d_mpart.as<double>(), st);
+  std::vector<double> mp(nsrc);
+  HIPCHK(hipMemcpyAsync(mp.data(), pl->d_mpart.p, nsrc * sizeof(double), hipMemcpyDeviceToHost, st));
+  int rc2 = gmres_core(pl, pl->d_adj.as<cpx<double>>(), pl->d_y.as<cpx<double>>(), nsrc, tol,
+                       maxit, 0, nullptr, nullptr);
+  if (rc2 < 0) return rc2;
+  launch_fwi_gradient(pl->P, u, pl->d_y.as<cpx<double>>(), nsrc, grad_dev, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  double J = 0;
+  for (double v : mp) J += v;
+  if (misfit_host) *misfit_host = J;
+  return (rc1 == DSD_NOT_CONVERGED || rc2 == DSD_NOT_CONVERGED) ? DSD_NOT_CONVERGED : DSD_OK;
+}
+
+const char* dsd_strerror(int code) {
+  switch (code) {
+    case DSD_OK: return "success";
+    case DSD_NOT_CONVERGED: return "tolerance not reached within maxit";
+    case DSD_EINVAL: return "invalid argument";
+    case DSD_ENOMEM: return "out of device memory";
+    case DSD_EHIP: return "HIP runtime error";
+    case DSD_EPIVOT: return "singular block in a subdomain factorisation";
+    case DSD_ENOTFINITE: return "non-finite value in a norm";
+    default: return "unknown error";
+  }
+}
+
+const char* dsd_last_error_detail(void) { return g_detail.c_str(); }
+
+int dsd_timing_enable(dsd_plan* pl, int on) {
+  if (!pl) return DSD_EINVAL;
+  pl->timing = on != 0;
+  pl->t_solve_ms = pl->t_other_ms = pl->solve_bytes = 0;
+  pl->solve_launches = 0;
+  return DSD_OK;
+}
+
+int dsd_timing_read(dsd_plan* pl, double* solve_ms, long long* solve_launches,
+                    double* solve_bytes, double* other_ms) {
+  if (!pl) return DSD_EINVAL;
+  if (solve_ms) *solve_ms = pl->t_solve_ms;
+  if (solve_launches) *solve_launches = pl->solve_launches;
+  if (solve_bytes) *solve_bytes = pl->solve_bytes;
+  if (other_ms) *other_ms = pl->t_other_ms;
+  return DSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+"""GPU parity: every entry point of libdsweep.so against the FP64 CPU oracle.
+
+Tolerances: complex128 path 1e-10 relative (1e-12 for a single local solve),
+complex64 path bounded by the single-precision rounding of the factors
+(a few 1e-6 per local solve), FP64 operator 1e-14.
+"""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from _cases import embed_physical, medium, rel, slowness2, sources, sub_tuple
+from oracle.pml import assemble, global_axes
+from oracle.sweep import DiagonalSweepDDM, global_solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0):
+    import paper_2002_05327_amd as dsw
+    m = torch.from_numpy(slowness2(c)).cuda()
+    return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
+                    max_rhs=k, rhs_per_group=kg)
+
+
+def _cuda(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+CASES = {
+    # name: n, h, omega, pml, overlap, parts, medium
+    "c1": ((128, 128), 1 / 128, 2 * np.pi * 8, 16, 8, (2, 2), "const"),
+    "lay33": ((72, 66), 1 / 72, 2 * np.pi * 5, 8, 4, (3, 3), "layered"),
+    "rag34": ((61, 70), 1 / 61, 2 * np.pi * 4, 6, 4, (3, 4), "random"),
+    "d3": ((14, 13, 12), 1 / 14, 2 * np.pi * 1.5, 3, 3, (2, 2, 2), "random"),
+}
+
+
+def _case(name):
+    n, h, om, pml, d, parts, med = CASES[name]
+    return n, h, om, pml, d, parts, medium(med, n, seed=3)
+
+
+@pytest.mark.parametrize("name", ["c1", "rag34", "d3"])
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_local_solve_matches_oracle(name, prec):
+    n, h, om, pml, d, parts, c = _case(name)
+    k = 3
+    plan = _plan(n, h, om, pml, d, parts, c, prec, k)
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    nsub = int(np.prod(parts))
+    for sid in sorted({0, nsub - 1, nsub // 2}):
+        st = sub_tuple(sid, parts)
+        sp = ddm.spaces[st]
+        dims, g0 = plan.subdomain_grid(sid)
+        assert dims == tuple(ax.n for ax in sp.axes) and g0 == tuple(ax.g0 for ax in sp.axes)
+        rng = np.random.default_rng(sid)
+        r = rng.standard_normal((k, sp.N)) + 1j * rng.standard_normal((k, sp.N))
+        u_ref = sp.solve(r.T).T
+        u = plan.local_solve(sid, _cuda(r.reshape((k,) + sp.shape))).cpu().numpy().reshape(k, -1)
+        tol = 1e-11 if prec == "c128" else 2e-4
+        print(f"{name} {prec} sub {sid}: rel err {rel(u, u_ref):.2e}", flush=True)
+        assert rel(u, u_ref) < tol
+
+
+@pytest.mark.parametrize("name", ["lay33", "d3"])
+def test_operator_matches_oracle(name):
+    n, h, om, pml, d, parts, c = _case(name)
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", 2)
+    M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((2,) + plan.gshape) + 1j * rng.standard_normal((2,) + plan.gshape)
+    y = plan.apply_operator(_cuda(x)).cpu().numpy()
+    y_ref = (M @ x.reshape(2, -1).T).T.reshape(y.shape)
+    assert rel(y, y_ref) < 1e-14
+
+
+@pytest.mark.parametrize("name", ["c1", "lay33", "rag34", "d3"])
+def test_sweep_apply_c128_matches_oracle_real_mode(name):
+    """One application of Algorithm 3.1 / 4.1 (real local PML solves)."""
+    n, h, om, pml, d, parts, c = _case(name)
+    k = 2
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k)
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    u_ref = ddm.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    e = rel(u, u_ref)
+    print(f"{name}: GPU c128 sweep vs oracle {e:.2e}; DDM vs global solve "
+          f"{rel(u_ref, global_solve(ddm.M, f.reshape(k, -1).T).T):.2e}", flush=True)
+    assert e < 1e-10
+
+
+@pytest.mark.parametrize("name", ["c1", "lay33"])
+def test_sweep_apply_c64_close_to_oracle(name):
+    n, h, om, pml, d, parts, c = _case(name)
+    k = 2
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c64", k)
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    u_ref = ddm.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    e = rel(u, u_ref)
+    print(f"{name}: GPU c64 sweep vs oracle {e:.2e}", flush=True)
+    assert e < 1e-3
+
+
+def test_sweep_apply_deterministic():
+    n, h, om, pml, d, parts, c = _case("rag34")
+    f = _cuda(sources(n, h, pml, 2))
+    plan = _plan(n, h, om, pml, d, parts, c, "c64", 2)
+    a = plan.sweep_apply(f).cpu().numpy()
+    b = plan.sweep_apply(f).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kg", [1, 2, 4, 8])
+def test_rhs_grouping_does_not_change_result(kg):
+    n, h, om, pml, d, parts, c = _case("lay33")
+    k = 5
+    f = _cuda(sources(n, h, pml, k))
+    ref = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=1).sweep_apply(f).cpu().numpy()
+    got = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=kg).sweep_apply(f).cpu().numpy()
+    assert rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol,bound", [("c128", 1e-12, 1e-10), ("c64", 1e-11, 1e-8)])
+def test_gmres_matches_global_solve(prec, tol, bound):
+    n, h, om, pml, d, parts, c = _case("lay33")
+    k = 3
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, prec, k)
+    x, its, res, ok = plan.gmres(_cuda(f), tol=tol, maxit=80)
+    M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml)
+    x_ref = global_solve(M, f.reshape(k, -1).T).T
+    xg = x.cpu().numpy().reshape(k, -1)
+    true_res = [np.linalg.norm(f[i].ravel() - M @ xg[i]) / np.linalg.norm(f[i]) for i in range(k)]
+    print(f"{prec}: iters {its} relres {res} true {true_res} err {rel(xg, x_ref):.2e}", flush=True)
+    assert ok and max(true_res) <= tol * 1.01
+    assert rel(xg, x_ref) < bound
+
+
+def test_gmres_c1_reaches_global_solution():
+    """Config 1 reading: GMRES-DDM driven to relres 1e-13 equals the global LU to 1e-10."""
+    n, h, om, pml, d, parts, c = _case("c1")
+    f = embed_physical(__import__("synth").gaussian_source(n, h, (0.5, 0.5), 2 * h), pml)[None]
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", 1)
+    x, its, res, ok = plan.gmres(_cuda(f.astype(complex)), tol=1e-13, maxit=40)
+    M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml)
+    x_ref = global_solve(M, f.reshape(-1))
+    print(f"c1 gmres iters {its} relres {res} err {rel(x.cpu().numpy().ravel(), x_ref):.2e}")
+    assert ok and rel(x.cpu().numpy().ravel(), x_ref) < 1e-10
+
+
+def test_adjoint_solve():
+    n, h, om, pml, d, parts, c = _case("lay33")
+    k = 2
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k)
+    y, _, _, ok = plan.adjoint_solve(_cuda(f), tol=1e-12, maxit=80)
+    M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml).tocsc()
+    y_ref = spla.splu(M.conj().T.tocsc()).solve(f.reshape(k, -1).T).T
+    assert ok and rel(y.cpu().numpy().reshape(k, -1), y_ref) < 1e-10
+
+
+def test_fwi_gradient_matches_oracle():
+    import synth
+    from oracle.fwi import FWIOracle
+    import paper_2002_05327_amd as dsw
+    N, pml, parts, d = 48, 8, (3, 3), 4
+    n, h, om = (N, N), 1 / N, 2 * np.pi * 3
+    c_true = synth.layered_medium(N, N, seed=0)
+    c0 = synth.smooth_medium(c_true, 4.0)
+    src = synth.surface_gaussian_sources(N, N, h, 4)
+    iy, ix = synth.surface_receivers(N, N, h, 12)
+    fw = FWIOracle(n, h, om, pml, src, (iy, ix))
+    d_obs = fw.observed(slowness2(c_true))
+    J_ref, g_ref = fw.gradient(slowness2(c0), d_obs)
+    gshape = (N + 2 * pml, N + 2 * pml)
+    f = np.stack([embed_physical(s, pml) for s in src]).astype(complex)
+    rec = torch.tensor((iy + pml) * gshape[1] + (ix + pml), dtype=torch.int64).cuda()
+    for prec, tol, bound in [("c128", 1e-12, 1e-8), ("c64", 1e-11, 1e-7)]:
+        plan = _plan(n, h, om, pml, d, parts, c0, prec, 4)
+        J, g = plan.fwi_gradient(_cuda(f), rec, _cuda(d_obs.T.copy()), tol=tol, maxit=80)
+        eg = rel(g.cpu().numpy(), g_ref)
+        print(f"fwi {prec}: misfit rel {abs(J - J_ref) / J_ref:.2e} grad rel {eg:.2e}")
+        assert abs(J - J_ref) / J_ref < bound and eg < bound * 10
