@@ -61,6 +61,10 @@ typedef struct {
   int max_rhs;           /* largest batch any later call will pass                     */
   int rhs_per_group;     /* RHS handled by one workgroup in the subdomain solves;
                             0 = let the library choose                                 */
+  int schedule;          /* 0: launch every solve as soon as the solves it depends on
+                               are done (dependency levels of Algorithms 3.1 / 4.1);
+                            1: the anti-diagonal steps of each sweep in order.  Both
+                               give identical results.                                  */
 } dsd_params;
 
 /*

@@ -5,6 +5,8 @@
 // SubDesc::vec_off (times the plan's max RHS); complex values are interleaved.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace dsd {
 
 static inline unsigned cdiv_u(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
@@ -251,152 +253,469 @@ void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, in
 //   middle         x_m = B_m (r_m - c_{m-1} w_{m-1} - c_m w_{m+1})
 //   backward top    x_k = w_k - B_k (c_k x_{k+1})                      (k < m)
 //   backward bottom x_k = w_k - B_k (c_{k-1} x_{k-1})                  (k > m)
-// One workgroup runs one chain (subdomain, half) for KG right-hand sides;
-// block steps are dense matrix x (nb x KG) products with B_k read once per
-// workgroup in coalesced columns.  Workgroups of the same chain (different
-// RHS groups) are placed on the same XCD so that B_k is shared through L2.
+// One workgroup (8 waves) runs one chain (subdomain, half, sweep) for KG
+// right-hand sides.  A block step is a dense (nb x nb) x (nb x KG) product:
+// the eight waves split the columns of B_k (each lane owns rows lane + 64 t
+// of a 256-row chunk, loads are coalesced 64-element column segments issued
+// eight columns deep), partial sums meet in LDS.  Workgroups of one chain
+// (different RHS groups) are placed on one XCD so that B_k is shared in L2.
 // ============================================================================
-template <typename T, int KG>
-__global__ __launch_bounds__(256) void k_chain(int phase, const SubDesc* subs, const int2* jobs,
-                                               int njobs, int G, int nrhs, int kmax,
-                                               const cpx<T>* fac, const cpx<T>* cpl,
-                                               const cpx<T>* rpool, cpx<T>* xpool) {
+constexpr int CH_WAVES = 8;
+constexpr int CH_THREADS = 64 * CH_WAVES;
+constexpr int CH_ROUND_BYTES = 96;   // bytes of B per lane and row tile in one round
+
+template <typename T> struct vec2;
+template <> struct vec2<float> { typedef float2 type; };
+template <> struct vec2<double> { typedef double2 type; };
+
+// Block index processed at step t of a chain phase.
+__device__ __forceinline__ int chain_block(int phase, int half, int t, int nblk, int mid) {
+  if (phase == 0) return half == 0 ? t : nblk - 1 - t;
+  if (phase == 1) return mid;
+  return half == 0 ? mid - 1 - t : mid + 1 + t;
+}
+
+// Workgroup barrier that orders LDS only: waits for this wave's LDS operations
+// and meets the other waves, leaving global loads (prefetches) and stores in
+// flight.  Used where the data exchanged between waves lives in LDS and no
+// global location is written and then read inside the kernel.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <typename T, int KG, int RT>
+__global__ __launch_bounds__(CH_THREADS) void k_chain(int phase, const SubDesc* __restrict__ subs,
+                                                      const int4* __restrict__ jobs, int njobs,
+                                                      int G, int nrhs, int kmax,
+                                                      const cpx<T>* __restrict__ fac,
+                                                      const cpx<T>* __restrict__ cpl,
+                                                      const cpx<T>* __restrict__ rpool,
+                                                      cpx<T>* __restrict__ vpool,
+                                                      long long pool_stride) {
+  typedef typename vec2<T>::type V2;
+  constexpr int U = CH_ROUND_BYTES / (int)sizeof(V2);   // columns per round
+  constexpr int ROWS = 64 * RT;                          // rows per chunk
   const int total = gridDim.x;
   const int per = total >> 3;
   const int b = blockIdx.x;
-  const int L = (b & 7) * per + (b >> 3);
-  const int job = L / G, g = L - (L / G) * G;
+  const int Lg = (b & 7) * per + (b >> 3);
+  const int job = Lg / G, g = Lg - (Lg / G) * G;
   if (job >= njobs) return;
-  const int2 jb = jobs[job];
+  const int4 jb = jobs[job];
   const SubDesc S = subs[jb.x];
   const int half = jb.y;
   const int nb = S.nb, nblk = S.nblk, mid = S.mid;
-  const long long nloc = S.nloc;
+  const long long nloc = S.nloc, nb2 = (long long)nb * nb;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* yin = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* prev = yin + (long long)nb * KG;
-  const cpx<T>* R = rpool + S.vec_off * kmax;
-  cpx<T>* X = xpool + S.vec_off * kmax;
-  const cpx<T>* C = cpl + S.coef_off;
-  const cpx<T>* F = fac + S.fac_off;
-  const int tid = threadIdx.x;
+  cpx<T>* red = prev + (long long)nb * KG;              // [CH_WAVES][KG][ROWS]
+  const cpx<T>* __restrict__ R = rpool + (long long)jb.z * pool_stride + S.vec_off * kmax;
+  cpx<T>* __restrict__ X = vpool + (long long)jb.z * pool_stride + S.vec_off * kmax;
+  const cpx<T>* __restrict__ C = cpl + S.coef_off;
+  const V2* __restrict__ Bv = reinterpret_cast<const V2*>(fac + S.fac_off);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const cpx<T> zero = mk((T)0, (T)0);
-  int rr[KG];
-#pragma unroll
-  for (int q = 0; q < KG; ++q) rr[q] = g * KG + q;
+  const int nsteps = phase == 1 ? 1 : (half == 0 ? mid : nblk - 1 - mid);
+  if (nsteps <= 0) return;
+  const int cw = (nb + CH_WAVES - 1) / CH_WAVES;
+  const int j0 = w * cw;
+  const int j1 = min(nb, j0 + cw);
+  const int nr = (cw + U - 1) / U;                       // rounds per chunk (same for all waves)
+  const int nchunk = (nb + ROWS - 1) / ROWS;
+  const int per_step = nchunk * nr;                      // rounds per block step
+  const int total_rounds = nsteps * per_step;
 
-  auto matvec_rows = [&](int k, int mode) {
-    // mode 0: out = B y ; mode 1: out = w_k - B y (w_k read from X)
-    const cpx<T>* B = F + (long long)k * nb * nb;
-    for (int i = tid; i < nb; i += 256) {
-      cpx<T> acc[KG];
+  // Issue the loads of round `gr` (a position in the whole chain's column stream).
+  auto issue = [&](V2 (&buf)[U][RT], int gr) {
+    const int t = gr / per_step, rem = gr - t * per_step;
+    const int ch = rem / nr, rd = rem - ch * nr;
+    const int k = chain_block(phase, half, t, nblk, mid);
+    const V2* __restrict__ Bk = Bv + k * nb2;
 #pragma unroll
-      for (int q = 0; q < KG; ++q) acc[q] = zero;
-      int j = 0;
-      for (; j + 4 <= nb; j += 4) {
-        cpx<T> b0 = B[(long long)(j + 0) * nb + i];
-        cpx<T> b1 = B[(long long)(j + 1) * nb + i];
-        cpx<T> b2 = B[(long long)(j + 2) * nb + i];
-        cpx<T> b3 = B[(long long)(j + 3) * nb + i];
+    for (int u = 0; u < U; ++u) {
+      int jc = j0 + rd * U + u;
+      jc = jc < j1 ? jc : (j1 > j0 ? j1 - 1 : 0);
 #pragma unroll
-        for (int q = 0; q < KG; ++q) {
-          fma_acc(acc[q], b0, yin[q * nb + j + 0]);
-          fma_acc(acc[q], b1, yin[q * nb + j + 1]);
-          fma_acc(acc[q], b2, yin[q * nb + j + 2]);
-          fma_acc(acc[q], b3, yin[q * nb + j + 3]);
-        }
-      }
-      for (; j < nb; ++j) {
-        cpx<T> b0 = B[(long long)j * nb + i];
-#pragma unroll
-        for (int q = 0; q < KG; ++q) fma_acc(acc[q], b0, yin[q * nb + j]);
-      }
-#pragma unroll
-      for (int q = 0; q < KG; ++q) {
-        cpx<T> out = acc[q];
-        const long long o = (long long)rr[q] * nloc + (long long)k * nb + i;
-        if (mode == 1) out = (rr[q] < nrhs ? X[o] : zero) - out;
-        prev[q * nb + i] = out;
-        if (rr[q] < nrhs) X[o] = out;
+      for (int tt = 0; tt < RT; ++tt) {
+        int row = ch * ROWS + tt * 64 + lane;
+        row = row < nb ? row : nb - 1;
+        buf[u][tt] = Bk[(long long)jc * nb + row];
       }
     }
   };
 
-  if (phase == 0) {
-    const int nsteps = half == 0 ? mid : (nblk - 1 - mid);
-    for (int t = 0; t < nsteps; ++t) {
-      const int k = half == 0 ? t : nblk - 1 - t;
-      for (int idx = tid; idx < nb * KG; idx += 256) {
-        const int q = idx / nb, i = idx - (idx / nb) * nb;
-        cpx<T> y = rr[q] < nrhs ? R[(long long)rr[q] * nloc + (long long)k * nb + i] : zero;
+  V2 cur[U][RT], nxt[U][RT];
+  issue(cur, 0);
+  int gr = 0;
+  for (int t = 0; t < nsteps; ++t) {
+    const int k = chain_block(phase, half, t, nblk, mid);
+    // ---- right-hand side of this block step into yin
+    for (int idx = tid; idx < nb * KG; idx += CH_THREADS) {
+      const int q = idx / nb, i = idx - q * nb;
+      const int rq = g * KG + q;
+      cpx<T> y = zero;
+      if (phase == 0) {
+        y = rq < nrhs ? R[(long long)rq * nloc + (long long)k * nb + i] : zero;
         if (t > 0) {
           const cpx<T> c = half == 0 ? C[(long long)(k - 1) * nb + i] : C[(long long)k * nb + i];
           y = y - c * prev[q * nb + i];
         }
-        yin[q * nb + i] = y;
-      }
-      __syncthreads();
-      matvec_rows(k, 0);
-      __syncthreads();
-    }
-  } else if (phase == 1) {
-    const int k = mid;
-    for (int idx = tid; idx < nb * KG; idx += 256) {
-      const int q = idx / nb, i = idx - (idx / nb) * nb;
-      cpx<T> y = zero;
-      if (rr[q] < nrhs) {
-        const long long ro = (long long)rr[q] * nloc;
-        y = R[ro + (long long)k * nb + i];
-        if (k > 0) y = y - C[(long long)(k - 1) * nb + i] * X[ro + (long long)(k - 1) * nb + i];
-        if (k < nblk - 1) y = y - C[(long long)k * nb + i] * X[ro + (long long)(k + 1) * nb + i];
+      } else if (phase == 1) {
+        if (rq < nrhs) {
+          const long long ro = (long long)rq * nloc;
+          y = R[ro + (long long)k * nb + i];
+          if (k > 0) y = y - C[(long long)(k - 1) * nb + i] * X[ro + (long long)(k - 1) * nb + i];
+          if (k < nblk - 1) y = y - C[(long long)k * nb + i] * X[ro + (long long)(k + 1) * nb + i];
+        }
+      } else {
+        const int kn = half == 0 ? k + 1 : k - 1;
+        const int cb = half == 0 ? k : k - 1;
+        cpx<T> xn;
+        if (t == 0) xn = rq < nrhs ? X[(long long)rq * nloc + (long long)kn * nb + i] : zero;
+        else xn = prev[q * nb + i];
+        y = C[(long long)cb * nb + i] * xn;
       }
       yin[q * nb + i] = y;
     }
-    __syncthreads();
-    matvec_rows(k, 0);
-  } else {
-    const int nsteps = half == 0 ? mid : (nblk - 1 - mid);
-    for (int t = 0; t < nsteps; ++t) {
-      const int k = half == 0 ? mid - 1 - t : mid + 1 + t;
-      const int kn = half == 0 ? k + 1 : k - 1;          // already-solved neighbour
-      const int cb = half == 0 ? k : k - 1;              // coupling block index
-      for (int idx = tid; idx < nb * KG; idx += 256) {
-        const int q = idx / nb, i = idx - (idx / nb) * nb;
-        cpx<T> xn;
-        if (t == 0) xn = rr[q] < nrhs ? X[(long long)rr[q] * nloc + (long long)kn * nb + i] : zero;
-        else xn = prev[q * nb + i];
-        yin[q * nb + i] = C[(long long)cb * nb + i] * xn;
+    lds_barrier();
+    for (int ch = 0; ch < nchunk; ++ch) {
+      T ar[RT][KG], ai[RT][KG];
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+        for (int q = 0; q < KG; ++q) { ar[tt][q] = (T)0; ai[tt][q] = (T)0; }
+      for (int rd = 0; rd < nr; ++rd, ++gr) {
+        if (gr + 1 < total_rounds) issue(nxt, gr + 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int j = j0 + rd * U + u;
+          const bool ok = j < j1;
+          const int jc = ok ? j : 0;
+#pragma unroll
+          for (int q = 0; q < KG; ++q) {
+            const cpx<T> y = yin[q * nb + jc];
+            const T yr = ok ? y.re : (T)0, yi = ok ? y.im : (T)0;
+#pragma unroll
+            for (int tt = 0; tt < RT; ++tt) {
+              ar[tt][q] = fma(cur[u][tt].x, yr, ar[tt][q]);
+              ar[tt][q] = fma(-cur[u][tt].y, yi, ar[tt][q]);
+              ai[tt][q] = fma(cur[u][tt].x, yi, ai[tt][q]);
+              ai[tt][q] = fma(cur[u][tt].y, yr, ai[tt][q]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int tt = 0; tt < RT; ++tt) cur[u][tt] = nxt[u][tt];
       }
-      __syncthreads();
-      matvec_rows(k, 1);
-      __syncthreads();
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+        for (int q = 0; q < KG; ++q)
+          red[(w * KG + q) * ROWS + tt * 64 + lane] = mk(ar[tt][q], ai[tt][q]);
+      lds_barrier();
+      for (int o = tid; o < KG * ROWS; o += CH_THREADS) {
+        const int q = o / ROWS, il = o - q * ROWS, i = ch * ROWS + il;
+        if (i >= nb) continue;
+        cpx<T> out = zero;
+#pragma unroll
+        for (int ww = 0; ww < CH_WAVES; ++ww) out = out + red[(ww * KG + q) * ROWS + il];
+        const int rq = g * KG + q;
+        const long long oo = (long long)rq * nloc + (long long)k * nb + i;
+        if (phase == 2) out = (rq < nrhs ? X[oo] : zero) - out;
+        prev[q * nb + i] = out;
+        if (rq < nrhs) X[oo] = out;
+      }
+      lds_barrier();
     }
   }
 }
 
-template <typename T, int KG>
-static void launch_chain_kg(int phase, const SubDesc* d_subs, const int2* d_jobs, int njobs,
-                            int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                            const cpx<T>* rpool, cpx<T>* xpool, hipStream_t s) {
-  const int G = (nrhs + KG - 1) / KG;
-  long long total = (long long)njobs * G;
-  total = (total + 7) / 8 * 8;
-  const size_t lds = (size_t)2 * max_nb * KG * sizeof(cpx<T>);
-  hipLaunchKernelGGL((k_chain<T, KG>), dim3((unsigned)total), dim3(256), lds, s, phase, d_subs,
-                     d_jobs, njobs, G, nrhs, kmax, fac, cpl, rpool, xpool);
+// Complex64 variant on the matrix cores.  v_mfma_f32_4x4x1f32 computes 16
+// independent 4x4 outer products: lane 4b+i supplies A[b][i], lane 4b+j
+// supplies B[b][j] and holds D[b][i][j] in accumulator register i.  Here the
+// 16 blocks are 16 groups of 4 rows of a 64-row tile (A = one factor element
+// per lane: Re in one product, Im in the other) and the 4 columns of a block
+// are (Re, Im) of two right-hand sides, so
+//   D += Re(B) (x) [yr0, yi0, yr1, yi1] + Im(B) (x) [-yi0, yr0, -yi1, yr1]
+// accumulates the complex product without waste.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+template <int KG, int RT>
+__global__ __launch_bounds__(CH_THREADS) void k_chain_mfma(int phase, const SubDesc* __restrict__ subs,
+                                                           const int4* __restrict__ jobs, int njobs,
+                                                           int G, int nrhs, int kmax,
+                                                           const cpx<float>* __restrict__ fac,
+                                                           const cpx<float>* __restrict__ cpl,
+                                                           const cpx<float>* __restrict__ rpool,
+                                                           cpx<float>* __restrict__ vpool,
+                                                           long long pool_stride) {
+  typedef float2 V2;
+  typedef cpx<float> C;
+  constexpr int U = CH_ROUND_BYTES / (int)sizeof(V2);   // columns per round (12)
+  constexpr int NG = KG / 2;                             // RHS pairs
+  constexpr int ROWS = 64 * RT;
+  constexpr int PF = (KG * 256 + CH_THREADS - 1) / CH_THREADS;   // vector elements per thread
+  const int total = gridDim.x;
+  const int per = total >> 3;
+  const int b = blockIdx.x;
+  const int Lg = (b & 7) * per + (b >> 3);
+  const int job = Lg / G, g = Lg - (Lg / G) * G;
+  if (job >= njobs) return;
+  const int4 jb = jobs[job];
+  const SubDesc S = subs[jb.x];
+  const int half = jb.y;
+  const int nb = S.nb, nblk = S.nblk, mid = S.mid;
+  const long long nloc = S.nloc, nb2 = (long long)nb * nb;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cw = (nb + CH_WAVES - 1) / CH_WAVES;
+  int nr = (cw + U - 1) / U;
+  nr += nr & 1;                                          // even: chunks start in buffer A
+  const int ncol = CH_WAVES * nr * U;                    // padded column count of the operands
+  extern __shared__ unsigned char smem_raw[];
+  V2* yop = reinterpret_cast<V2*>(smem_raw);            // [NG][ncol][4] MFMA B-operand pairs
+  C* prev = reinterpret_cast<C*>(yop + (long long)NG * ncol * 4);   // [KG][nb]
+  float* redf = reinterpret_cast<float*>(prev + (long long)KG * nb); // [W][RT][NG][4][64]
+  const C* __restrict__ R = rpool + (long long)jb.z * pool_stride + S.vec_off * kmax;
+  C* __restrict__ X = vpool + (long long)jb.z * pool_stride + S.vec_off * kmax;
+  const C* __restrict__ Cp = cpl + S.coef_off;
+  const V2* __restrict__ Bv = reinterpret_cast<const V2*>(fac + S.fac_off);
+  const C zero = mk(0.f, 0.f);
+  const int nsteps = phase == 1 ? 1 : (half == 0 ? mid : nblk - 1 - mid);
+  if (nsteps <= 0) return;
+  const int j0 = w * cw;
+  const int j1 = min(nb, j0 + cw);
+  const int nchunk = (nb + ROWS - 1) / ROWS;
+
+  // Operand slots: wave w owns slots [w * nr * U, (w + 1) * nr * U); slot
+  // w * nr * U + l holds column j0 + l for l < cw (and j0 + l < nb).  The
+  // other slots stay zero, so padded rounds add nothing.
+  const int nru = nr * U;
+  for (int idx = tid; idx < NG * ncol * 4; idx += CH_THREADS) yop[idx] = make_float2(0.f, 0.f);
+  __syncthreads();
+
+  // column stream position of the next issue: (step, chunk, round)
+  int is_t = 0, is_ch = 0, is_rd = 0;
+  auto issue = [&](V2 (&buf)[U][RT]) {
+    if (is_t < nsteps) {
+      const int k = chain_block(phase, half, is_t, nblk, mid);
+      const V2* __restrict__ Bk = Bv + k * nb2;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int jc = j0 + is_rd * U + u;
+        jc = jc < j1 ? jc : (j1 > j0 ? j1 - 1 : 0);
+        const V2* __restrict__ col = Bk + (long long)jc * nb;
+#pragma unroll
+        for (int tt = 0; tt < RT; ++tt) {
+          int row = is_ch * ROWS + tt * 64 + lane;
+          row = row < nb ? row : nb - 1;
+          buf[u][tt] = col[row];
+        }
+      }
+    }
+    if (++is_rd == nr) { is_rd = 0; if (++is_ch == nchunk) { is_ch = 0; ++is_t; } }
+  };
+  auto compute = [&](const V2 (&buf)[U][RT], int rd, mf4 (&acc)[RT][NG]) {
+    const int sb0 = w * nru + rd * U;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int ng = 0; ng < NG; ++ng) {
+        const V2 y = yop[((long long)ng * ncol + sb0 + u) * 4 + (lane & 3)];
+#pragma unroll
+        for (int tt = 0; tt < RT; ++tt) {
+          acc[tt][ng] = __builtin_amdgcn_mfma_f32_4x4x1f32(buf[u][tt].x, y.x, acc[tt][ng], 0, 0, 0);
+          acc[tt][ng] = __builtin_amdgcn_mfma_f32_4x4x1f32(buf[u][tt].y, y.y, acc[tt][ng], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // Store the block step's input y(q, i) as MFMA operands: slot 2(q&1) holds
+  // (Re y, -Im y), slot 2(q&1)+1 holds (Im y, Re y).
+  auto put_y = [&](int q, int i, C y) {
+    const int slot = (i / cw) * nru + (i - (i / cw) * cw);
+    V2* o = yop + ((long long)(q >> 1) * ncol + slot) * 4 + 2 * (q & 1);
+    o[0] = make_float2(y.re, -y.im);
+    o[1] = make_float2(y.im, y.re);
+  };
+
+  // prefetched inputs of the next step's right-hand side (phases 0 and 2)
+  C pre_r[PF], pre_c[PF];
+  auto prefetch_rhs = [&](int t) {
+    const int k = chain_block(phase, half, t, nblk, mid);
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int idx = tid + p * CH_THREADS;
+      pre_r[p] = zero;
+      pre_c[p] = zero;
+      if (idx < nb * KG && t < nsteps) {
+        const int q = idx / nb, i = idx - q * nb;
+        const int rq = g * KG + q;
+        if (phase == 0) {
+          if (rq < nrhs) pre_r[p] = R[(long long)rq * nloc + (long long)k * nb + i];
+          if (t > 0) pre_c[p] = half == 0 ? Cp[(long long)(k - 1) * nb + i] : Cp[(long long)k * nb + i];
+        } else if (phase == 2) {
+          pre_c[p] = Cp[(long long)(half == 0 ? k : k - 1) * nb + i];
+          if (t == 0) {
+            const int kn = half == 0 ? k + 1 : k - 1;
+            pre_r[p] = rq < nrhs ? X[(long long)rq * nloc + (long long)kn * nb + i] : zero;
+          }
+        }
+      }
+    }
+  };
+
+  V2 bufA[U][RT], bufB[U][RT];
+  issue(bufA);
+  if (phase != 1) prefetch_rhs(0);
+  for (int t = 0; t < nsteps; ++t) {
+    const int k = chain_block(phase, half, t, nblk, mid);
+    // ---- right-hand side of this block step as MFMA operands
+    if (phase == 1) {
+      for (int idx = tid; idx < nb * KG; idx += CH_THREADS) {
+        const int q = idx / nb, i = idx - q * nb;
+        const int rq = g * KG + q;
+        C y = zero;
+        if (rq < nrhs) {
+          const long long ro = (long long)rq * nloc;
+          y = R[ro + (long long)k * nb + i];
+          if (k > 0) y = y - Cp[(long long)(k - 1) * nb + i] * X[ro + (long long)(k - 1) * nb + i];
+          if (k < nblk - 1) y = y - Cp[(long long)k * nb + i] * X[ro + (long long)(k + 1) * nb + i];
+        }
+        put_y(q, i, y);
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int idx = tid + p * CH_THREADS;
+        if (idx < nb * KG) {
+          const int q = idx / nb, i = idx - q * nb;
+          C y;
+          if (phase == 0) y = t > 0 ? pre_r[p] - pre_c[p] * prev[q * nb + i] : pre_r[p];
+          else y = pre_c[p] * (t == 0 ? pre_r[p] : prev[q * nb + i]);
+          put_y(q, i, y);
+        }
+      }
+    }
+    lds_barrier();
+    if (phase != 1 && t + 1 < nsteps) prefetch_rhs(t + 1);
+    for (int ch = 0; ch < nchunk; ++ch) {
+      // w_k of the outputs this thread will write (backward phase)
+      C pre_x[PF];
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        pre_x[p] = zero;
+        const int o = tid + p * CH_THREADS;
+        if (phase == 2 && o < KG * ROWS) {
+          const int q = o / ROWS, i = ch * ROWS + (o - q * ROWS);
+          const int rq = g * KG + q;
+          if (i < nb && rq < nrhs) pre_x[p] = X[(long long)rq * nloc + (long long)k * nb + i];
+        }
+      }
+      mf4 acc[RT][NG];
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng) acc[tt][ng] = mf4{0.f, 0.f, 0.f, 0.f};
+      for (int rd = 0; rd < nr; rd += 2) {
+        issue(bufB);
+        compute(bufA, rd, acc);
+        issue(bufA);
+        compute(bufB, rd + 1, acc);
+      }
+      // D[b][i][jj] of lane 4b+jj, register i  ->  redf[w][tt][ng][i][lane]
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            redf[((((long long)w * RT + tt) * NG + ng) * 4 + i) * 64 + lane] = acc[tt][ng][i];
+      lds_barrier();
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        const int o = tid + p * CH_THREADS;
+        if (o >= KG * ROWS) continue;
+        const int q = o / ROWS, il = o - q * ROWS, i = ch * ROWS + il;
+        if (i >= nb) continue;
+        const int tt = il >> 6, r64 = il & 63;
+        const int src = 4 * (r64 >> 2) + 2 * (q & 1);   // lane holding (row, q, Re); Im is next
+        const int ii = r64 & 3, ng = q >> 1;
+        C out = zero;
+#pragma unroll
+        for (int ww = 0; ww < CH_WAVES; ++ww) {
+          const float* rb = redf + ((((long long)ww * RT + tt) * NG + ng) * 4 + ii) * 64 + src;
+          out.re += rb[0];
+          out.im += rb[1];
+        }
+        const int rq = g * KG + q;
+        if (phase == 2) out = pre_x[p] - out;
+        prev[q * nb + i] = out;
+        if (rq < nrhs) X[(long long)rq * nloc + (long long)k * nb + i] = out;
+      }
+      lds_barrier();
+    }
+  }
 }
 
 template <typename T>
-void launch_chain(int kg, int phase, const SubDesc* d_subs, const int2* d_jobs, int njobs,
-                  int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                  const cpx<T>* rpool, cpx<T>* xpool, hipStream_t s) {
-  if (njobs <= 0 || nrhs <= 0) return;
-  switch (kg) {
-    case 1: launch_chain_kg<T, 1>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
-    case 2: launch_chain_kg<T, 2>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
-    case 4: launch_chain_kg<T, 4>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
-    default: launch_chain_kg<T, 8>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, xpool, s); break;
+size_t chain_lds_bytes(int max_nb, int kg) {
+  const int rows = max_nb <= 192 ? 192 : 256;
+  if (std::is_same<T, float>::value && kg >= 2) {
+    const int U = CH_ROUND_BYTES / 8;
+    const int cw = (max_nb + CH_WAVES - 1) / CH_WAVES;
+    int nr = (cw + U - 1) / U;
+    nr += nr & 1;
+    const size_t ncol = (size_t)CH_WAVES * nr * U;
+    return (size_t)(kg / 2) * ncol * 4 * sizeof(float2) + (size_t)kg * max_nb * sizeof(cpx<float>) +
+           (size_t)CH_WAVES * rows * (kg / 2) * 4 * sizeof(float);
   }
+  return (size_t)(2 * max_nb + CH_WAVES * rows) * kg * sizeof(cpx<T>);
+}
+
+template <typename T, int KG, int RT>
+static void launch_chain_kg(int phase, const SubDesc* d_subs, const int4* d_jobs, int njobs,
+                            int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                            const cpx<T>* rpool, cpx<T>* vpool, long long pool_stride,
+                            hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  long long total = (long long)njobs * G;
+  total = (total + 7) / 8 * 8;
+  if constexpr (std::is_same<T, float>::value && KG >= 2) {
+    hipLaunchKernelGGL((k_chain_mfma<KG, RT>), dim3((unsigned)total), dim3(CH_THREADS),
+                       chain_lds_bytes<T>(max_nb, KG), s, phase, d_subs, d_jobs, njobs, G, nrhs,
+                       kmax, fac, cpl, rpool, vpool, pool_stride);
+  } else {
+    hipLaunchKernelGGL((k_chain<T, KG, RT>), dim3((unsigned)total), dim3(CH_THREADS),
+                       chain_lds_bytes<T>(max_nb, KG), s, phase, d_subs, d_jobs, njobs, G, nrhs,
+                       kmax, fac, cpl, rpool, vpool, pool_stride);
+  }
+}
+
+template <typename T, int RT>
+static void launch_chain_rt(int kg, int phase, const SubDesc* d_subs, const int4* d_jobs,
+                            int njobs, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
+                            const cpx<T>* cpl, const cpx<T>* rpool, cpx<T>* vpool,
+                            long long pool_stride, hipStream_t s) {
+  switch (kg) {
+    case 1: launch_chain_kg<T, 1, RT>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 2: launch_chain_kg<T, 2, RT>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    default: launch_chain_kg<T, 4, RT>(phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+  }
+}
+
+template <typename T>
+void launch_chain(int kg, int phase, const SubDesc* d_subs, const int4* d_jobs, int njobs,
+                  int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                  const cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0) return;
+  if (max_nb <= 192)
+    launch_chain_rt<T, 3>(kg, phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+  else
+    launch_chain_rt<T, 4>(kg, phase, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
 }
 
 // ============================================================================
@@ -406,9 +725,11 @@ void launch_chain(int kg, int phase, const SubDesc* d_subs, const int2* d_jobs, 
 // holds it; each cell is written by exactly one thread (no atomics).
 // ============================================================================
 template <typename T>
-__global__ void k_init_rhs(Problem P, const SubDesc* subs, const int* members, int first_sweep,
-                           int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool) {
-  const SubDesc S = subs[members[blockIdx.z]];
+__global__ void k_init_rhs(Problem P, const SubDesc* subs, const int2* members, int nrhs, int kmax,
+                           const cpx<double>* f, cpx<T>* rpool, long long pool_stride) {
+  const int2 mb = members[blockIdx.z];
+  const SubDesc S = subs[mb.x];
+  const int first_sweep = mb.y == 0;
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (c >= S.nloc || r >= nrhs) return;
@@ -426,17 +747,17 @@ __global__ void k_init_rhs(Problem P, const SubDesc* subs, const int* members, i
       v = cvt<T>(f[(long long)r * P.N + gf]);
     }
   }
-  rpool[S.vec_off * kmax + (long long)r * S.nloc + c] = v;
+  rpool[(long long)mb.y * pool_stride + S.vec_off * kmax + (long long)r * S.nloc + c] = v;
 }
 
 template <typename T>
-void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
-                     long long max_nloc, int first_sweep, int nrhs, int kmax,
-                     const cpx<double>* f, cpx<T>* rpool, hipStream_t s) {
+void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
+                     long long max_nloc, int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool,
+                     long long pool_stride, hipStream_t s) {
   if (nmem <= 0 || nrhs <= 0) return;
   dim3 grid(cdiv_u(max_nloc, 256), nrhs, nmem);
-  hipLaunchKernelGGL(k_init_rhs<T>, grid, dim3(256), 0, s, P, d_subs, d_members, first_sweep,
-                     nrhs, kmax, f, rpool);
+  hipLaunchKernelGGL(k_init_rhs<T>, grid, dim3(256), 0, s, P, d_subs, d_members, nrhs, kmax, f,
+                     rpool, pool_stride);
 }
 
 template <typename T>
@@ -481,11 +802,12 @@ __device__ cpx<T> psi(const Problem& P, const SubDesc& Sd, const Edge& e, const 
 }
 
 template <typename T>
-__global__ void k_pull(Problem P, const SubDesc* subs, const int* members, const Edge* edges,
+__global__ void k_pull(Problem P, const SubDesc* subs, const int2* members, const Edge* edges,
                        const int2* erange, int nrhs, int kmax, const cpx<T>* vpool,
                        long long pool_stride, const cpx<T>* diag, const cpx<T>* cx,
                        const cpx<T>* cy, const cpx<T>* cz, cpx<T>* rpool) {
-  const int recv = members[blockIdx.z];
+  const int2 mb = members[blockIdx.z];
+  const int recv = mb.x;
   const int2 er = erange[blockIdx.z];
   const int r = blockIdx.y;
   if (r >= nrhs || er.y <= 0) return;
@@ -518,12 +840,12 @@ __global__ void k_pull(Problem P, const SubDesc* subs, const int* members, const
     sum = sum + psi<T>(P, Sd, E[e], c, r, kmax, vpool, pool_stride, diag, cx, cy, cz);
   }
   const long long cell = ((long long)c[2] * R.dims[1] + c[1]) * R.dims[0] + c[0];
-  const long long o = R.vec_off * kmax + (long long)r * R.nloc + cell;
+  const long long o = (long long)mb.y * pool_stride + R.vec_off * kmax + (long long)r * R.nloc + cell;
   rpool[o] = rpool[o] + sum;
 }
 
 template <typename T>
-void launch_pull(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
+void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
                  const Edge* d_edges, const int2* d_edge_range, long long max_box_cells,
                  int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
                  const cpx<T>* diag, const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz,
@@ -881,12 +1203,14 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
   template void launch_convert<T>(const cpx<double>*, cpx<T>*, long long, hipStream_t);          \
   template void launch_invert<T>(const SubDesc*, const FactorJob*, int, int, cpx<double>*,      \
                                  cpx<T>*, int*, int*, hipStream_t);                              \
-  template void launch_chain<T>(int, int, const SubDesc*, const int2*, int, int, int, int,      \
-                                const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*,            \
+  template void launch_chain<T>(int, int, const SubDesc*, const int4*, int, int, int, int,      \
+                                const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*, long long, \
                                 hipStream_t);                                                    \
-  template void launch_init_rhs<T>(const Problem&, const SubDesc*, const int*, int, long long,  \
-                                   int, int, int, const cpx<double>*, cpx<T>*, hipStream_t);     \
-  template void launch_pull<T>(const Problem&, const SubDesc*, const int*, int, const Edge*,    \
+  template size_t chain_lds_bytes<T>(int, int);                                                 \
+  template void launch_init_rhs<T>(const Problem&, const SubDesc*, const int2*, int, long long, \
+                                   int, int, const cpx<double>*, cpx<T>*, long long,             \
+                                   hipStream_t);                                                 \
+  template void launch_pull<T>(const Problem&, const SubDesc*, const int2*, int, const Edge*,   \
                                const int2*, long long, int, int, const cpx<T>*, long long,       \
                                const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*,       \
                                cpx<T>*, hipStream_t);                                            \

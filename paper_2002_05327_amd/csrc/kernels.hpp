@@ -40,19 +40,24 @@ template <typename T>
 void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
                    cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s);
 
-// ---- a3: subdomain solves (block-tridiagonal chains); phase 0 fwd, 1 mid, 2 bwd
+// ---- a3: subdomain solves (block-tridiagonal chains); phase 0 fwd, 1 mid, 2 bwd.
+// A job is {subdomain, half (0 top / 1 bottom), sweep, unused}; the right-hand
+// side and the solution of sweep l live at pool offset l * pool_stride.
 template <typename T>
-void launch_chain(int kg, int phase, const SubDesc* d_subs, const int2* d_jobs, int njobs,
+void launch_chain(int kg, int phase, const SubDesc* d_subs, const int4* d_jobs, int njobs,
                   int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                  const cpx<T>* rpool, cpx<T>* xpool, hipStream_t s);
+                  const cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s);
+template <typename T>
+size_t chain_lds_bytes(int max_nb, int kg);
 
 // ---- a4: local right-hand sides and source transfer (pull)
+// members are {subdomain, sweep}; the first sweep's right-hand side is f on own cells
 template <typename T>
-void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
-                     long long max_nloc, int first_sweep, int nrhs, int kmax,
-                     const cpx<double>* f, cpx<T>* rpool, hipStream_t s);
+void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
+                     long long max_nloc, int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool,
+                     long long pool_stride, hipStream_t s);
 template <typename T>
-void launch_pull(const Problem& P, const SubDesc* d_subs, const int* d_members, int nmem,
+void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
                  const Edge* d_edges, const int2* d_edge_range, long long max_box_cells,
                  int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
                  const cpx<T>* diag, const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz,

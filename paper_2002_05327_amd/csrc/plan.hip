@@ -120,9 +120,10 @@ struct dsd_plan {
   Problem P{};
   int dim = 2, L = 4, nsteps = 0, S = 0, kmax = 1, kg = 2, max_nb = 0;
   bool c64 = true;
+  bool sequential = false;      // anti-diagonal steps in order instead of DAG launch groups
   std::vector<SubDesc> subs;
   std::vector<AxisPart> parts[3];
-  std::vector<StepTab> steps;   // [l * nsteps + s]
+  std::vector<StepTab> steps;   // launch groups, in order
   long long sum_nloc = 0, sum_fac = 0;
 
   Buf d_subs, d_m, d_gcoef[4], d_lcoef64[4], d_lcoefT[4], d_fac;
@@ -265,10 +266,8 @@ int build_schedule(dsd_plan* pl) {
   int nsteps = 1;
   for (int a = 0; a < dim; ++a) nsteps += q.parts[a] - 1;
   pl->nsteps = nsteps;
-  std::vector<int> members, erange_flat;
-  std::vector<int2> jobs2, jobs1, erange;
   std::vector<Edge> edges;
-  // edges per (l, receiver)
+  // incoming transfers of every (sweep, receiver), in a fixed direction order
   std::vector<int2> edge_of((size_t)L * pl->S);
   std::vector<int> tdirs;
   for (int tz = (dim == 3 ? -1 : 0); tz <= (dim == 3 ? 1 : 0); ++tz)
@@ -326,47 +325,70 @@ int build_schedule(dsd_plan* pl) {
       }
       edge_of[(size_t)l * pl->S + rid] = make_int2(start, (int)edges.size() - start);
     }
-  pl->steps.assign((size_t)L * nsteps, StepTab{});
+  // Launch groups.  Sequential: the anti-diagonal steps of every sweep in
+  // order (Algorithms 3.1 / 4.1).  DAG: every (sweep, subdomain) solve is
+  // launched at 1 + the latest launch group of the solves its transfers come
+  // from; the sources and their summation order are unchanged, so both
+  // schedules give identical results.
+  std::vector<int> level((size_t)L * pl->S, 0);
+  std::vector<std::vector<int2>> groups;
   for (int l = 0; l < L; ++l) {
     const int* D = sweep_dir(dim, l);
-    std::vector<std::vector<int>> groups(nsteps);
+    std::vector<std::vector<int>> steps(nsteps);
     for (int sid = 0; sid < pl->S; ++sid) {
       const SubDesc& S = pl->subs[sid];
       int st = 0;
       for (int a = 0; a < dim; ++a) st += D[a] > 0 ? S.part[a] : q.parts[a] - 1 - S.part[a];
-      groups[st].push_back(sid);
+      steps[st].push_back(sid);
     }
-    for (int s = 0; s < nsteps; ++s) {
-      StepTab& T = pl->steps[(size_t)l * nsteps + s];
-      T.mem_off = (int)members.size();
-      T.nmem = (int)groups[s].size();
-      T.job_off = (int)jobs2.size();
-      T.er_off = (int)erange.size();
-      T.max_nloc = 0;
-      T.max_box = 0;
-      T.fac_bytes_fb = T.fac_bytes_mid = 0;
-      T.blk_cells_fb = T.blk_cells_mid = 0;
-      for (int sid : groups[s]) {
-        const SubDesc& S = pl->subs[sid];
-        members.push_back(sid);
-        jobs2.push_back(make_int2(sid, 0));
-        jobs2.push_back(make_int2(sid, 1));
-        jobs1.push_back(make_int2(sid, 0));
-        const int2 er = edge_of[(size_t)l * pl->S + sid];
-        erange.push_back(er);
-        long long box = 0;
-        for (int e = er.x; e < er.x + er.y; ++e)
-          box += (long long)(edges[e].hi[0] - edges[e].lo[0]) * (edges[e].hi[1] - edges[e].lo[1]) *
-                 (edges[e].hi[2] - edges[e].lo[2]);
-        T.max_box = std::max(T.max_box, box);
-        T.max_nloc = std::max(T.max_nloc, S.nloc);
-        const double blk = (double)S.nb * S.nb * tsize(pl);
-        T.fac_bytes_fb += (double)(S.nblk - 1) * blk;
-        T.fac_bytes_mid += blk;
-        T.blk_cells_fb += (long long)(S.nblk - 1) * S.nb;
-        T.blk_cells_mid += S.nb;
+    for (int s = 0; s < nsteps; ++s)
+      for (int sid : steps[s]) {
+        int lev;
+        if (pl->sequential) {
+          lev = l * nsteps + s;
+        } else {
+          lev = 0;
+          const int2 er = edge_of[(size_t)l * pl->S + sid];
+          for (int e = er.x; e < er.x + er.y; ++e)
+            for (int lg = 0; lg < L; ++lg)
+              if (edges[e].lmask & (1u << lg))
+                lev = std::max(lev, level[(size_t)lg * pl->S + edges[e].sender] + 1);
+        }
+        level[(size_t)l * pl->S + sid] = lev;
+        if ((int)groups.size() <= lev) groups.resize(lev + 1);
+        groups[lev].push_back(make_int2(sid, l));
       }
+  }
+  std::vector<int2> members, erange;
+  std::vector<int4> jobs2, jobs1;
+  pl->steps.clear();
+  for (auto& grp : groups) {
+    StepTab T{};
+    T.mem_off = (int)members.size();
+    T.nmem = (int)grp.size();
+    T.job_off = (int)jobs2.size();
+    T.er_off = (int)erange.size();
+    for (const int2& mb : grp) {
+      const SubDesc& S = pl->subs[mb.x];
+      members.push_back(mb);
+      jobs2.push_back(make_int4(mb.x, 0, mb.y, 0));
+      jobs2.push_back(make_int4(mb.x, 1, mb.y, 0));
+      jobs1.push_back(make_int4(mb.x, 0, mb.y, 0));
+      const int2 er = edge_of[(size_t)mb.y * pl->S + mb.x];
+      erange.push_back(er);
+      long long box = 0;
+      for (int e = er.x; e < er.x + er.y; ++e)
+        box += (long long)(edges[e].hi[0] - edges[e].lo[0]) * (edges[e].hi[1] - edges[e].lo[1]) *
+               (edges[e].hi[2] - edges[e].lo[2]);
+      T.max_box = std::max(T.max_box, box);
+      T.max_nloc = std::max(T.max_nloc, S.nloc);
+      const double blk = (double)S.nb * S.nb * tsize(pl);
+      T.fac_bytes_fb += (double)(S.nblk - 1) * blk;
+      T.fac_bytes_mid += blk;
+      T.blk_cells_fb += (long long)(S.nblk - 1) * S.nb;
+      T.blk_cells_mid += S.nb;
     }
+    pl->steps.push_back(T);
   }
   CHK(upload(pl->d_members, members));
   CHK(upload(pl->d_jobs2, jobs2));
@@ -527,19 +549,19 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
 
 int ensure_pools(dsd_plan* pl) {
   if (pl->d_rpool.p) return 0;
-  CHK(pl->d_rpool.alloc((size_t)pl->sum_nloc * pl->kmax * tsize(pl)));
+  CHK(pl->d_rpool.alloc((size_t)pl->L * pl->sum_nloc * pl->kmax * tsize(pl)));
   CHK(pl->d_vpool.alloc((size_t)pl->L * pl->sum_nloc * pl->kmax * tsize(pl)));
   return 0;
 }
 
 template <typename T>
-void chain_phase(dsd_plan* pl, int phase, const int2* jobs, int njobs, int nrhs, double fbytes,
-                 long long blk_cells, cpx<T>* xpool) {
+void chain_phase(dsd_plan* pl, int phase, const int4* jobs, int njobs, int nrhs, double fbytes,
+                 long long blk_cells) {
   hipStream_t st = pl->stream;
   if (pl->timing) (void)hipEventRecord(pl->ev0, st);
   launch_chain<T>(pl->kg, phase, pl->d_subs.as<SubDesc>(), jobs, njobs, nrhs, pl->kmax,
                   pl->max_nb, pl->d_fac.as<cpx<T>>(), pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>(),
-                  pl->d_rpool.as<cpx<T>>(), xpool, st);
+                  pl->d_rpool.as<cpx<T>>(), pl->d_vpool.as<cpx<T>>(), pl->sum_nloc * pl->kmax, st);
   if (pl->timing) {
     (void)hipEventRecord(pl->ev1, st);
     (void)hipEventSynchronize(pl->ev1);
@@ -560,24 +582,20 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
   const long long pool_stride = pl->sum_nloc * pl->kmax;
   cpx<T>* rpool = pl->d_rpool.as<cpx<T>>();
   cpx<T>* vpool = pl->d_vpool.as<cpx<T>>();
-  for (int l = 0; l < pl->L; ++l) {
-    for (int s = 0; s < pl->nsteps; ++s) {
-      const StepTab& st_ = pl->steps[(size_t)l * pl->nsteps + s];
-      if (st_.nmem == 0) continue;
-      const int* mem = pl->d_members.as<int>() + st_.mem_off;
-      launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, l == 0, nrhs,
-                         pl->kmax, f, rpool, st);
-      launch_pull<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, pl->d_edges.as<Edge>(),
-                     pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
-                     pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
-                     pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
-      cpx<T>* xpool = vpool + (long long)l * pool_stride;
-      const int2* j2 = pl->d_jobs2.as<int2>() + st_.job_off;
-      const int2* j1 = pl->d_jobs1.as<int2>() + st_.mem_off;
-      chain_phase<T>(pl, 0, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb, xpool);
-      chain_phase<T>(pl, 1, j1, st_.nmem, nrhs, st_.fac_bytes_mid, st_.blk_cells_mid, xpool);
-      chain_phase<T>(pl, 2, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb, xpool);
-    }
+  for (const StepTab& st_ : pl->steps) {
+    if (st_.nmem == 0) continue;
+    const int2* mem = pl->d_members.as<int2>() + st_.mem_off;
+    launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, nrhs, pl->kmax,
+                       f, rpool, pool_stride, st);
+    launch_pull<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, pl->d_edges.as<Edge>(),
+                   pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
+                   pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
+                   pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
+    const int4* j2 = pl->d_jobs2.as<int4>() + st_.job_off;
+    const int4* j1 = pl->d_jobs1.as<int4>() + st_.mem_off;
+    chain_phase<T>(pl, 0, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
+    chain_phase<T>(pl, 1, j1, st_.nmem, nrhs, st_.fac_bytes_mid, st_.blk_cells_mid);
+    chain_phase<T>(pl, 2, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
   }
   PartTables pt;
   for (int a = 0; a < 3; ++a) {
@@ -818,9 +836,20 @@ int check_receivers(const dsd_plan* pl, const long long* rec_dev, int nrec) {
 }
 
 int choose_kg(const dsd_plan* pl, int want) {
-  int kg = 8;
+  int dev = 0, lds = 65536;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      lds = v;
+  }
+  int kg = 4;
+  if (!pl->c64 && pl->max_nb > 192) kg = 2;   // register budget of the 4-tile c128 kernel
   while (kg > want && kg > 1) kg >>= 1;
-  while (kg > 1 && (size_t)2 * pl->max_nb * kg * tsize(pl) > 64 * 1024) kg >>= 1;
+  auto need = [&](int k) {
+    return pl->c64 ? chain_lds_bytes<float>(pl->max_nb, k) : chain_lds_bytes<double>(pl->max_nb, k);
+  };
+  while (kg > 1 && need(kg) > (size_t)lds) kg >>= 1;
+  if (need(kg) > (size_t)lds) return 0;
   return kg;
 }
 
@@ -854,7 +883,14 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   pl->kmax = std::max(1, q.max_rhs);
   pl->stream = (hipStream_t)stream;
   int rc = build_partition(pl);
-  if (rc == 0) pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : 2);
+  pl->sequential = q.schedule == 1;
+  if (rc == 0) {
+    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : 2);
+    if (pl->kg == 0) {
+      g_detail = "subdomain blocks too large for the solve kernel's LDS";
+      rc = DSD_EINVAL;
+    }
+  }
   if (rc == 0) rc = upload(pl->d_subs, pl->subs);
   if (rc == 0) rc = assemble_and_factor(pl, m_dev);
   if (rc == 0) rc = build_schedule(pl);
@@ -914,26 +950,26 @@ int dsd_local_solve(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, i
   pl->stream = (hipStream_t)stream;
   CHK(ensure_pools(pl));
   const SubDesc& S = pl->subs[sub];
-  std::vector<int2> jobs = {make_int2(sub, 0), make_int2(sub, 1), make_int2(sub, 0)};
+  std::vector<int4> jobs = {make_int4(sub, 0, 0, 0), make_int4(sub, 1, 0, 0),
+                            make_int4(sub, 0, 0, 0)};
   CHK(upload(pl->d_single_job, jobs));
   const long long off = S.vec_off * pl->kmax;
   hipStream_t st = pl->stream;
+  const int4* jb = pl->d_single_job.as<int4>();
   if (pl->c64) {
-    cpx<float>* rp = pl->d_rpool.as<cpx<float>>() + off;
-    cpx<float>* xp = pl->d_vpool.as<cpx<float>>();
-    launch_pack_local<float>((const cpx<double>*)r_dev, rp, S.nloc, nrhs, pl->kmax, st);
+    launch_pack_local<float>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<float>>() + off, S.nloc,
+                             nrhs, pl->kmax, st);
     for (int ph = 0; ph < 3; ++ph)
-      chain_phase<float>(pl, ph, pl->d_single_job.as<int2>() + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2,
-                         nrhs, 0, 0, xp);
-    launch_unpack_local<float>(xp + off, (cpx<double>*)u_dev, S.nloc, nrhs, pl->kmax, st);
+      chain_phase<float>(pl, ph, jb + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2, nrhs, 0, 0);
+    launch_unpack_local<float>(pl->d_vpool.as<cpx<float>>() + off, (cpx<double>*)u_dev, S.nloc,
+                               nrhs, pl->kmax, st);
   } else {
-    cpx<double>* rp = pl->d_rpool.as<cpx<double>>() + off;
-    cpx<double>* xp = pl->d_vpool.as<cpx<double>>();
-    launch_pack_local<double>((const cpx<double>*)r_dev, rp, S.nloc, nrhs, pl->kmax, st);
+    launch_pack_local<double>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<double>>() + off,
+                              S.nloc, nrhs, pl->kmax, st);
     for (int ph = 0; ph < 3; ++ph)
-      chain_phase<double>(pl, ph, pl->d_single_job.as<int2>() + (ph == 1 ? 2 : 0),
-                          ph == 1 ? 1 : 2, nrhs, 0, 0, xp);
-    launch_unpack_local<double>(xp + off, (cpx<double>*)u_dev, S.nloc, nrhs, pl->kmax, st);
+      chain_phase<double>(pl, ph, jb + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2, nrhs, 0, 0);
+    launch_unpack_local<double>(pl->d_vpool.as<cpx<double>>() + off, (cpx<double>*)u_dev, S.nloc,
+                                nrhs, pl->kmax, st);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));

@@ -17,11 +17,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0):
+def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag"):
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(slowness2(c)).cuda()
     return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
-                    max_rhs=k, rhs_per_group=kg)
+                    max_rhs=k, rhs_per_group=kg, schedule=schedule)
 
 
 def _cuda(x):
@@ -115,7 +115,17 @@ def test_sweep_apply_deterministic():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("kg", [1, 2, 4, 8])
+@pytest.mark.parametrize("name", ["rag34", "d3"])
+def test_dependency_schedule_equals_sequential_steps(name):
+    """Launching each solve at its dependency level reorders nothing that is summed."""
+    n, h, om, pml, d, parts, c = _case(name)
+    f = _cuda(sources(n, h, pml, 3))
+    a = _plan(n, h, om, pml, d, parts, c, "c64", 3, schedule="dag").sweep_apply(f).cpu().numpy()
+    b = _plan(n, h, om, pml, d, parts, c, "c64", 3, schedule="sequential").sweep_apply(f).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("kg", [1, 2, 4])
 def test_rhs_grouping_does_not_change_result(kg):
     n, h, om, pml, d, parts, c = _case("lay33")
     k = 5
