@@ -65,6 +65,13 @@ typedef struct {
                                are done (dependency levels of Algorithms 3.1 / 4.1);
                             1: the anti-diagonal steps of each sweep in order.  Both
                                give identical results.                                  */
+  int local_solver;      /* factorisation and solve of the block-tridiagonal subdomain
+                            operators: 1: twisted block LDL^T (two Schur-complement
+                               chains meeting in the middle block; least memory,
+                               sequential in the blocks);
+                            2: block cyclic reduction (about three times the factor
+                               memory; every reduction level is one batched launch);
+                            0: 2 unless its factor would exceed 45% of device memory. */
 } dsd_params;
 
 /*

@@ -719,6 +719,579 @@ void launch_chain(int kg, int phase, const SubDesc* d_subs, const int4* d_jobs, 
 }
 
 // ============================================================================
+// a2/a3, block cyclic reduction.  The local operator is block tridiagonal
+// (blocks A_k, couplings C_k = diag(c_k) between blocks k and k+1).  Level
+// by level the even-position blocks of the remaining system are eliminated:
+//   P_i = D_i^{-1};  D'_j = D_j - E_{j-1}^T P_{j-1} E_{j-1} - E_j P_{j+1} E_j^T;
+//   E'_j = -E_j P_{j+1} E_{j+1}   (coupling of the kept neighbours j, j+2).
+// Forward solve: z_i = P_i r_i, r'_j = r_j - E_{j-1}^T z_{j-1} - E_j z_{j+1};
+// backward: x_i = z_i - P_i (E_{i-1}^T x_{i-1} + E_i x_{i+1}).  Every level is
+// a batch of independent dense block products.
+// ============================================================================
+__global__ void k_bcr_assemble(Problem P, const SubDesc* subs, const BcrBlkJob* jobs,
+                               const cpx<double>* diag, const cpx<double>* cx,
+                               const cpx<double>* cy, cpx<double>* work) {
+  const BcrBlkJob J = jobs[blockIdx.y];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nb * nb) return;
+  const int j = (int)(e / nb), i = (int)(e - (long long)j * nb);
+  work[J.dst + e] = block_entry(S, P.dim, J.k, i, j, diag, cx, cy);
+}
+
+void launch_bcr_assemble(const Problem& P, const SubDesc* d_subs, const BcrBlkJob* d_jobs, int njobs,
+                         int max_nb, const cpx<double>* diag, const cpx<double>* cx,
+                         const cpx<double>* cy, cpx<double>* work, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_bcr_assemble, dim3(cdiv_u((long long)max_nb * max_nb, 256), njobs),
+                     dim3(256), 0, s, P, d_subs, d_jobs, diag, cx, cy, work);
+}
+
+// Gauss-Jordan inversion with partial pivoting, in place, one workgroup per job.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_bcr_invert(const BcrInvJob* jobs, cpx<double>* work,
+                                                     cpx<T>* fac, int* err, int* pivbuf,
+                                                     int max_nb) {
+  const BcrInvJob J = jobs[blockIdx.x];
+  const int nb = J.nb;
+  cpx<double>* a = work + J.src;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* rowj = tcol + nb;
+  int* piv = pivbuf + (long long)blockIdx.x * max_nb;
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ int s_p;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
+  int bad = 0;
+  for (int j = 0; j < nb; ++j) {
+    double bv = -1.0;
+    int bi = nb;
+    for (int i = j + tid; i < nb; i += bs) {
+      const double v = abs2(a[(long long)j * nb + i]);
+      if (v > bv) { bv = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_down(bv, o, 64);
+      const int oi = __shfl_down(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double v = red_v[0];
+      int p = red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
+      if (!(v > 0.0)) { bad = 1; p = j; }
+      s_p = p;
+      piv[j] = p;
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j) {
+      for (int c = tid; c < nb; c += bs) {
+        const cpx<double> t0 = a[(long long)c * nb + j];
+        a[(long long)c * nb + j] = a[(long long)c * nb + p];
+        a[(long long)c * nb + p] = t0;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nb; i += bs) tcol[i] = a[(long long)j * nb + i];
+    __syncthreads();
+    const cpx<double> pv = tcol[j];
+    const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+    for (int c = tid; c < nb; c += bs) rowj[c] = (c == j) ? pinv : a[(long long)c * nb + j] * pinv;
+    __syncthreads();
+    const long long ne = (long long)nb * nb;
+    for (long long e = tid; e < ne; e += bs) {
+      const int c = (int)(e / nb), i = (int)(e - (long long)c * nb);
+      if (i == j) a[e] = rowj[c];
+      else if (c == j) a[e] = -(tcol[i] * pinv);
+      else a[e] = a[e] - tcol[i] * rowj[c];
+    }
+    __syncthreads();
+  }
+  for (int j = nb - 1; j >= 0; --j) {
+    const int p = piv[j];
+    if (p != j) {
+      for (int i = tid; i < nb; i += bs) {
+        const cpx<double> t0 = a[(long long)j * nb + i];
+        a[(long long)j * nb + i] = a[(long long)p * nb + i];
+        a[(long long)p * nb + i] = t0;
+      }
+    }
+    __syncthreads();
+  }
+  if (J.dst >= 0) {
+    const long long ne = (long long)nb * nb;
+    for (long long e = tid; e < ne; e += bs) fac[J.dst + e] = cvt<T>(a[e]);
+  }
+  if (tid == 0 && bad) err[blockIdx.x] = 1;
+}
+
+template <typename T>
+void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
+                       cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s) {
+  if (njobs <= 0) return;
+  const size_t lds = (size_t)max_nb * 2 * sizeof(cpx<double>);
+  hipLaunchKernelGGL(k_bcr_invert<T>, dim3(njobs), dim3(1024), lds, s, d_jobs, work, fac, d_err,
+                     d_piv, max_nb);
+}
+
+__global__ void k_bcr_diag_update(Problem P, const SubDesc* subs, const BcrDiagUpd* jobs,
+                                  const cpx<double>* cy, const cpx<double>* cz,
+                                  cpx<double>* work) {
+  const BcrDiagUpd J = jobs[blockIdx.y];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nb * nb) return;
+  const int col = (int)(e / nb), i = (int)(e - (long long)col * nb);
+  const cpx<double>* c = (P.dim == 2 ? cy : cz) + S.coef_off;
+  const long long j = J.j;
+  if (J.d >= 0) {
+    cpx<double> v = work[J.d + e];
+    if (J.pl >= 0) {
+      const cpx<double> cl_i = c[(j - 1) * nb + i], cl_c = c[(j - 1) * nb + col];
+      v = v - (cl_i * work[J.pl + e]) * cl_c;
+    }
+    if (J.pr >= 0) {
+      const cpx<double> cr_i = c[j * nb + i], cr_c = c[j * nb + col];
+      v = v - (cr_i * work[J.pr + e]) * cr_c;
+    }
+    work[J.d + e] = v;
+  }
+  if (J.eout >= 0)
+    work[J.eout + e] = -((c[j * nb + i] * work[J.pr + e]) * c[(j + 1) * nb + col]);
+}
+
+void launch_bcr_diag_update(const Problem& P, const SubDesc* d_subs, const BcrDiagUpd* d_jobs,
+                            int njobs, int max_nb, const cpx<double>* cy, const cpx<double>* cz,
+                            cpx<double>* work, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_bcr_diag_update, dim3(cdiv_u((long long)max_nb * max_nb, 256), njobs),
+                     dim3(256), 0, s, P, d_subs, d_jobs, cy, cz, work);
+}
+
+template <typename T>
+__global__ void k_bcr_copy(const BcrCopyJob* jobs, const cpx<double>* work, cpx<T>* fac) {
+  const BcrCopyJob J = jobs[blockIdx.y];
+  const int nb = J.nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nb * nb) return;
+  const int col = (int)(e / nb), i = (int)(e - (long long)col * nb);
+  const long long se = J.trans ? (long long)i * nb + col : e;
+  fac[J.dst + e] = cvt<T>(work[J.src + se]);
+}
+
+template <typename T>
+void launch_bcr_copy(const BcrCopyJob* d_jobs, int njobs, int max_nb, const cpx<double>* work,
+                     cpx<T>* fac, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_bcr_copy<T>, dim3(cdiv_u((long long)max_nb * max_nb, 256), njobs),
+                     dim3(256), 0, s, d_jobs, work, fac);
+}
+
+// Batched FP64 complex GEMM for the reduction levels: 32x32 output tile per
+// 256-thread workgroup, the K dimension staged through LDS in panels of 16.
+__global__ __launch_bounds__(256) void k_zgemm(const ZGemmJob* jobs, cpx<double>* W) {
+  const ZGemmJob J = jobs[blockIdx.x];
+  const int nb = J.nb;
+  const int tm = blockIdx.y * 32, tn = blockIdx.z * 32;
+  if (tm >= nb || tn >= nb) return;
+  __shared__ cpx<double> As[16][33];   // [k][m]
+  __shared__ cpx<double> Bs[16][33];   // [k][n]
+  const cpx<double>* __restrict__ A = W + J.a;
+  const cpx<double>* __restrict__ B = W + J.b;
+  cpx<double>* C = W + J.c;
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  cpx<double> acc[2][2];
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) acc[r][c] = mk(0.0, 0.0);
+  for (int k0 = 0; k0 < nb; k0 += 16) {
+    for (int e = tid; e < 512; e += 256) {
+      int mm, kk;
+      if (J.ta) { kk = e & 15; mm = e >> 4; } else { mm = e & 31; kk = e >> 5; }
+      const int m = tm + mm, k = k0 + kk;
+      cpx<double> v = mk(0.0, 0.0);
+      if (m < nb && k < nb) v = J.ta ? A[(long long)m * nb + k] : A[(long long)k * nb + m];
+      As[kk][mm] = v;
+      int nn;
+      if (J.tb) { nn = e & 31; kk = e >> 5; } else { kk = e & 15; nn = e >> 4; }
+      const int n = tn + nn, k2 = k0 + kk;
+      cpx<double> u = mk(0.0, 0.0);
+      if (n < nb && k2 < nb) u = J.tb ? B[(long long)k2 * nb + n] : B[(long long)n * nb + k2];
+      Bs[kk][nn] = u;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      const cpx<double> a0 = As[kk][2 * tx], a1 = As[kk][2 * tx + 1];
+      const cpx<double> b0 = Bs[kk][2 * ty], b1 = Bs[kk][2 * ty + 1];
+      acc[0][0] = acc[0][0] + a0 * b0;
+      acc[1][0] = acc[1][0] + a1 * b0;
+      acc[0][1] = acc[0][1] + a0 * b1;
+      acc[1][1] = acc[1][1] + a1 * b1;
+    }
+    __syncthreads();
+  }
+  for (int r = 0; r < 2; ++r)
+    for (int c = 0; c < 2; ++c) {
+      const int m = tm + 2 * tx + r, n = tn + 2 * ty + c;
+      if (m < nb && n < nb) {
+        const long long o = (long long)n * nb + m;
+        const cpx<double> v = mk(J.alpha * acc[r][c].re, J.alpha * acc[r][c].im);
+        C[o] = J.beta ? C[o] + v : v;
+      }
+    }
+}
+
+void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* work, hipStream_t s) {
+  if (njobs <= 0) return;
+  const unsigned t = (unsigned)((max_nb + 31) / 32);
+  hipLaunchKernelGGL(k_zgemm, dim3(njobs, t, t), dim3(256), 0, s, d_jobs, work);
+}
+
+// ---- solve jobs ------------------------------------------------------------
+// One workgroup (8 waves) runs one job for KG right-hand sides:
+//   out = sum_m M_m v_m  (up to three dense blocks, operands prepared in LDS)
+// The matrices stream column by column: the waves split the columns, lanes
+// own rows (64-row tiles, RT tiles per chunk), each lane keeps CH_ROUND_BYTES
+// per tile in flight one round ahead, and the partial sums of the waves meet
+// in LDS.  complex64 with KG >= 2 runs on v_mfma_f32_4x4x1f32 (operand layout
+// as in k_chain_mfma); otherwise vector FMAs.
+template <typename T, int KG, int RT>
+__global__ __launch_bounds__(CH_THREADS) void k_bcr(const SubDesc* __restrict__ subs,
+                                                    const BcrJob* __restrict__ jobs, int njobs,
+                                                    int G, int nrhs, int kmax,
+                                                    const cpx<T>* __restrict__ fac,
+                                                    const cpx<T>* __restrict__ cpl,
+                                                    cpx<T>* __restrict__ rpool,
+                                                    cpx<T>* __restrict__ vpool,
+                                                    long long pool_stride) {
+  typedef typename vec2<T>::type V2;
+  typedef cpx<T> C;
+  constexpr bool MF = std::is_same<T, float>::value && KG >= 2;
+  constexpr int U = CH_ROUND_BYTES / (int)sizeof(V2);
+  constexpr int NG = MF ? KG / 2 : 1;
+  constexpr int ROWS = 64 * RT;
+  typedef float mf4v __attribute__((ext_vector_type(4)));
+  const int total = gridDim.x;
+  const int per = total >> 3;
+  const int bid = blockIdx.x;
+  const int Lg = (bid & 7) * per + (bid >> 3);   // XCD-aware: a job's RHS groups share an L2
+  const int job = Lg / G, g = Lg - (Lg / G) * G;
+  if (job >= njobs) return;
+  const BcrJob J = jobs[job];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  const long long nloc = S.nloc;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int cw = (nb + CH_WAVES - 1) / CH_WAVES;
+  const int nr = (cw + U - 1) / U;
+  const int nru = nr * U;
+  const int ncol = CH_WAVES * nru;
+  const int nchunk = (nb + ROWS - 1) / ROWS;
+  const int j0 = w * cw;
+  const int j1 = min(nb, j0 + cw);
+  const C zero = mk((T)0, (T)0);
+  extern __shared__ unsigned char smem_raw[];
+  const long long opsz = MF ? (long long)NG * ncol * 4 : (long long)KG * nb;
+  V2* opv = reinterpret_cast<V2*>(smem_raw);
+  C* opc = reinterpret_cast<C*>(smem_raw);
+  unsigned char* after_ops = smem_raw + 3 * opsz * (MF ? sizeof(V2) : sizeof(C));
+  float* redf = reinterpret_cast<float*>(after_ops);
+  C* redc = reinterpret_cast<C*>(after_ops);
+  C* __restrict__ X = vpool + (long long)J.l * pool_stride + S.vec_off * kmax;
+  C* __restrict__ R = rpool + (long long)J.l * pool_stride + S.vec_off * kmax;
+  const C* __restrict__ Cp = cpl + S.coef_off;
+  const V2* __restrict__ Fv = reinterpret_cast<const V2*>(fac);
+  const int mode = J.mode, blk = J.blk;
+  const bool hl = J.nl >= 0, hr = J.nr >= 0;
+
+  // matrices in use, compacted; operand set m belongs to matrix m
+  int nm;
+  long long mo0, mo1 = 0, mo2 = 0;
+  if (mode == BCR_KEPT) {
+    nm = (int)hl + (int)hr;
+    mo0 = hl ? J.m0 : J.m1;
+    mo1 = J.m1;
+  } else if (mode == BCR_BWD) {
+    nm = 1 + (int)hl + (int)hr;
+    mo0 = J.m0;
+    mo1 = hl ? J.m1 : J.m2;
+    mo2 = J.m2;
+  } else {
+    nm = 1;
+    mo0 = J.m0;
+  }
+
+  if (MF) {
+    for (long long idx = tid; idx < 3 * opsz; idx += CH_THREADS) opv[idx] = V2{(T)0, (T)0};
+    __syncthreads();
+  }
+  auto put_op = [&](int set, int q, int i, C y) {
+    if constexpr (MF) {
+      const int slot = (i / cw) * nru + (i - (i / cw) * cw);
+      V2* o = opv + set * opsz + ((long long)(q >> 1) * ncol + slot) * 4 + 2 * (q & 1);
+      o[0] = V2{y.re, -y.im};
+      o[1] = V2{y.im, y.re};
+    } else {
+      opc[set * opsz + (long long)q * nb + i] = y;
+    }
+  };
+  for (int idx = tid; idx < nb * KG; idx += CH_THREADS) {
+    const int q = idx / nb, i = idx - q * nb;
+    const int rq = g * KG + q;
+    const bool live = rq < nrhs;
+    const long long ro = (long long)rq * nloc;
+    if (mode == BCR_KEPT) {
+      const C vl = (live && hl) ? R[ro + (long long)J.nl * nb + i] : zero;
+      const C vr = (live && hr) ? R[ro + (long long)J.nr * nb + i] : zero;
+      if (hl) put_op(0, q, i, -vl);
+      if (hr) put_op(hl ? 1 : 0, q, i, -vr);
+    } else if (mode == BCR_BWD) {
+      put_op(0, q, i, live ? R[ro + (long long)blk * nb + i] : zero);
+      const C vl = (live && hl) ? X[ro + (long long)J.nl * nb + i] : zero;
+      const C vr = (live && hr) ? X[ro + (long long)J.nr * nb + i] : zero;
+      if (hl) put_op(1, q, i, -vl);
+      if (hr) put_op(hl ? 2 : 1, q, i, -vr);
+    } else if (mode == BCR_BWD0) {
+      C y = zero;
+      if (live) {
+        y = R[ro + (long long)blk * nb + i];
+        if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * X[ro + (long long)J.nl * nb + i];
+        if (hr) y = y - Cp[(long long)blk * nb + i] * X[ro + (long long)J.nr * nb + i];
+      }
+      put_op(0, q, i, y);
+    } else {
+      put_op(0, q, i, live ? R[ro + (long long)blk * nb + i] : zero);
+    }
+  }
+  lds_barrier();
+
+  const int per_ch = nm * nr;
+  const int total_rounds = nchunk * per_ch;
+  const long long d01 = mo1 - mo0, d12 = mo2 - mo1;
+  auto issue = [&](V2 (&buf)[U][RT], int gr) {
+    const int ch = gr / per_ch, rem = gr - ch * per_ch;
+    const int m = rem / nr, rd = rem - m * nr;
+    const V2* __restrict__ Mv = Fv + mo0 + (m >= 1 ? d01 : 0) + (m >= 2 ? d12 : 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      int jc = j0 + rd * U + u;
+      jc = jc < j1 ? jc : (j1 > j0 ? j1 - 1 : 0);
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt) {
+        int row = ch * ROWS + tt * 64 + lane;
+        row = row < nb ? row : nb - 1;
+        buf[u][tt] = Mv[(long long)jc * nb + row];
+      }
+    }
+  };
+  V2 cur[U][RT], nxt[U][RT];
+  if (total_rounds > 0) issue(cur, 0);
+  int gr = 0;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    T ar[RT][KG], ai[RT][KG];
+    mf4v acc[RT][NG];
+#pragma unroll
+    for (int tt = 0; tt < RT; ++tt) {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) { ar[tt][q] = (T)0; ai[tt][q] = (T)0; }
+#pragma unroll
+      for (int ng = 0; ng < NG; ++ng) acc[tt][ng] = mf4v{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int m = 0; m < nm; ++m) {
+      const long long ob = (long long)m * opsz;
+      for (int rd = 0; rd < nr; ++rd, ++gr) {
+        if (gr + 1 < total_rounds) issue(nxt, gr + 1);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if constexpr (MF) {
+            const int sl = w * nru + rd * U + u;
+#pragma unroll
+            for (int ng = 0; ng < NG; ++ng) {
+              const V2 y = opv[ob + ((long long)ng * ncol + sl) * 4 + (lane & 3)];
+#pragma unroll
+              for (int tt = 0; tt < RT; ++tt) {
+                acc[tt][ng] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)cur[u][tt].x, (float)y.x, acc[tt][ng], 0, 0, 0);
+                acc[tt][ng] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)cur[u][tt].y, (float)y.y, acc[tt][ng], 0, 0, 0);
+              }
+            }
+          } else {
+            const int j = j0 + rd * U + u;
+            const bool ok = j < j1;
+            const int jc = ok ? j : 0;
+#pragma unroll
+            for (int q = 0; q < KG; ++q) {
+              const C y = opc[ob + (long long)q * nb + jc];
+              const T yr = ok ? y.re : (T)0, yi = ok ? y.im : (T)0;
+#pragma unroll
+              for (int tt = 0; tt < RT; ++tt) {
+                ar[tt][q] = fma(cur[u][tt].x, yr, ar[tt][q]);
+                ar[tt][q] = fma(-cur[u][tt].y, yi, ar[tt][q]);
+                ai[tt][q] = fma(cur[u][tt].x, yi, ai[tt][q]);
+                ai[tt][q] = fma(cur[u][tt].y, yr, ai[tt][q]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int tt = 0; tt < RT; ++tt) cur[u][tt] = nxt[u][tt];
+      }
+    }
+    if constexpr (MF) {
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+        for (int ng = 0; ng < NG; ++ng)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            redf[((((long long)w * RT + tt) * NG + ng) * 4 + i) * 64 + lane] = acc[tt][ng][i];
+    } else {
+#pragma unroll
+      for (int tt = 0; tt < RT; ++tt)
+#pragma unroll
+        for (int q = 0; q < KG; ++q)
+          redc[((long long)w * KG + q) * ROWS + tt * 64 + lane] = mk(ar[tt][q], ai[tt][q]);
+    }
+    lds_barrier();
+    for (int o = tid; o < KG * ROWS; o += CH_THREADS) {
+      const int q = o / ROWS, il = o - q * ROWS, i = ch * ROWS + il;
+      const int rq = g * KG + q;
+      if (i >= nb || rq >= nrhs) continue;
+      C out = zero;
+      if constexpr (MF) {
+        const int tt = il >> 6, r64 = il & 63;
+        const int src = 4 * (r64 >> 2) + 2 * (q & 1);
+        const int ii = r64 & 3, ng = q >> 1;
+#pragma unroll
+        for (int ww = 0; ww < CH_WAVES; ++ww) {
+          const float* rb = redf + ((((long long)ww * RT + tt) * NG + ng) * 4 + ii) * 64 + src;
+          out.re += rb[0];
+          out.im += rb[1];
+        }
+      } else {
+#pragma unroll
+        for (int ww = 0; ww < CH_WAVES; ++ww) out = out + redc[((long long)ww * KG + q) * ROWS + il];
+      }
+      const long long oo = (long long)rq * nloc + (long long)blk * nb + i;
+      if (mode == BCR_KEPT) R[oo] = R[oo] + out;
+      else X[oo] = out;
+    }
+    lds_barrier();
+  }
+}
+
+template <typename T>
+__global__ void k_bcr_dfwd(const SubDesc* __restrict__ subs, const BcrJob* __restrict__ jobs,
+                           int nrhs, int kmax, const cpx<T>* __restrict__ cpl,
+                           cpx<T>* __restrict__ rpool, const cpx<T>* __restrict__ vpool,
+                           long long pool_stride) {
+  const BcrJob J = jobs[blockIdx.y];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nb * nrhs) return;
+  const int q = (int)(e / nb), i = (int)(e - (long long)q * nb);
+  const cpx<T>* X = vpool + (long long)J.l * pool_stride + S.vec_off * kmax + (long long)q * S.nloc;
+  cpx<T>* R = rpool + (long long)J.l * pool_stride + S.vec_off * kmax + (long long)q * S.nloc;
+  const cpx<T>* Cp = cpl + S.coef_off;
+  cpx<T> y = R[(long long)J.blk * nb + i];
+  if (J.nl >= 0) y = y - Cp[(long long)(J.blk - 1) * nb + i] * X[(long long)J.nl * nb + i];
+  if (J.nr >= 0) y = y - Cp[(long long)J.blk * nb + i] * X[(long long)J.nr * nb + i];
+  R[(long long)J.blk * nb + i] = y;
+}
+
+template <typename T>
+void launch_bcr_dfwd(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs, int kmax,
+                     int max_nb, const cpx<T>* cpl, cpx<T>* rpool, const cpx<T>* vpool,
+                     long long pool_stride, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_bcr_dfwd<T>, dim3(cdiv_u((long long)max_nb * nrhs, 256), njobs), dim3(256),
+                     0, s, d_subs, d_jobs, nrhs, kmax, cpl, rpool, vpool, pool_stride);
+}
+
+template <typename T>
+int bcr_kg(int max_nb, int kg) {
+  const bool rt3 = max_nb <= 192;
+  int cap;
+  if (std::is_same<T, float>::value) cap = rt3 ? 8 : 4;
+  else cap = rt3 ? 2 : 1;
+  int k = 1;
+  while (k * 2 <= kg && k * 2 <= cap) k *= 2;
+  return k;
+}
+
+template <typename T>
+size_t bcr_lds_bytes(int max_nb, int kg) {
+  const int U = CH_ROUND_BYTES / (int)(2 * sizeof(T));
+  const int cw = (max_nb + CH_WAVES - 1) / CH_WAVES;
+  const int nr = (cw + U - 1) / U;
+  const size_t ncol = (size_t)CH_WAVES * nr * U;
+  const bool mf = std::is_same<T, float>::value && kg >= 2;
+  const int rt = max_nb <= 192 ? 3 : 4;
+  const size_t ops = mf ? 3 * (size_t)(kg / 2) * ncol * 4 * 2 * sizeof(T)
+                        : 3 * (size_t)kg * max_nb * sizeof(cpx<T>);
+  const size_t red = mf ? (size_t)CH_WAVES * rt * (kg / 2) * 4 * 64 * sizeof(float)
+                        : (size_t)CH_WAVES * kg * 64 * rt * sizeof(cpx<T>);
+  return ops + red;
+}
+
+template <typename T, int KG, int RT>
+static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
+                         int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                         cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  long long total = (long long)njobs * G;
+  total = (total + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_bcr<T, KG, RT>), dim3((unsigned)total), dim3(CH_THREADS),
+                     bcr_lds_bytes<T>(max_nb, KG), s, d_subs, d_jobs, njobs, G, nrhs, kmax, fac,
+                     cpl, rpool, vpool, pool_stride);
+}
+
+template <typename T, int RT>
+static void launch_bcr_rt(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
+                          int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                          cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    switch (kg) {
+      case 1: launch_bcr_k<T, 1, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+      case 2: launch_bcr_k<T, 2, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+      case 4: launch_bcr_k<T, 4, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+      default:
+        if constexpr (RT == 3) launch_bcr_k<T, 8, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+        break;
+    }
+  } else {
+    if (kg >= 2) {
+      if constexpr (RT == 3) launch_bcr_k<T, 2, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+    } else {
+      launch_bcr_k<T, 1, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+    }
+  }
+}
+
+template <typename T>
+void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
+                      int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl, cpx<T>* rpool,
+                      cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0) return;
+  kg = bcr_kg<T>(max_nb, kg);
+  if (max_nb <= 192)
+    launch_bcr_rt<T, 3>(kg, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+  else
+    launch_bcr_rt<T, 4>(kg, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+}
+
+// ============================================================================
 // a4: local right-hand sides.  init: r^1 = f on own cells (first sweep), 0
 // otherwise.  pull: every receiver cell sums, in a fixed edge order, the
 // transferred sources Psi_t(v) = -M_sender(beta_t v) of the edges whose box
@@ -1217,6 +1790,18 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
   template void launch_assemble_u<T>(const Problem&, const SubDesc*, const PartTables&, int,    \
                                      int, int, const cpx<T>*, long long, cpx<double>*,           \
                                      hipStream_t);                                               \
+  template void launch_bcr_invert<T>(const BcrInvJob*, int, int, cpx<double>*, cpx<T>*, int*,  \
+                                     int*, hipStream_t);                                         \
+  template void launch_bcr_copy<T>(const BcrCopyJob*, int, int, const cpx<double>*, cpx<T>*,    \
+                                   hipStream_t);                                                 \
+  template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int,     \
+                                    const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, long long,   \
+                                    hipStream_t);                                                \
+  template void launch_bcr_dfwd<T>(const SubDesc*, const BcrJob*, int, int, int, int,           \
+                                   const cpx<T>*, cpx<T>*, const cpx<T>*, long long,            \
+                                   hipStream_t);                                                 \
+  template int bcr_kg<T>(int, int);                                                             \
+  template size_t bcr_lds_bytes<T>(int, int);                                                   \
   template void launch_pack_local<T>(const cpx<double>*, cpx<T>*, long long, int, int,          \
                                      hipStream_t);                                               \
   template void launch_unpack_local<T>(const cpx<T>*, cpx<double>*, long long, int, int,        \

@@ -50,6 +50,77 @@ void launch_chain(int kg, int phase, const SubDesc* d_subs, const int4* d_jobs, 
 template <typename T>
 size_t chain_lds_bytes(int max_nb, int kg);
 
+// ---- a2/a3 (block cyclic reduction form).  Every level eliminates the
+// even-position blocks of the remaining block-tridiagonal system.
+// Factorisation jobs operate on FP64 working blocks (column-major nb x nb,
+// offsets in complex entries into one working array).
+struct BcrBlkJob {        // D := A_k (assembly of a diagonal block)
+  int sub, k;
+  long long dst;
+};
+struct BcrInvJob {        // invert src in place (FP64); round the inverse into fac[dst] (dst >= 0)
+  int nb;
+  int pad;
+  long long src, dst;
+};
+struct BcrDiagUpd {       // level 0: D_j -= c_{j-1} P_{j-1} c_{j-1} + c_j P_{j+1} c_j;
+  int sub, j;             //          E_out = -c_j P_{j+1} c_{j+1}
+  long long d, pl, pr, eout;   // working offsets (-1: absent)
+};
+struct BcrCopyJob {       // fac[dst] = (T) work[src] or its transpose
+  int nb, trans;
+  long long src, dst;
+};
+void launch_bcr_assemble(const Problem& P, const SubDesc* d_subs, const BcrBlkJob* d_jobs, int njobs,
+                         int max_nb, const cpx<double>* diag, const cpx<double>* cx,
+                         const cpx<double>* cy, cpx<double>* work, hipStream_t s);
+template <typename T>
+void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
+                       cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s);
+void launch_bcr_diag_update(const Problem& P, const SubDesc* d_subs, const BcrDiagUpd* d_jobs,
+                            int njobs, int max_nb, const cpx<double>* cy, const cpx<double>* cz,
+                            cpx<double>* work, hipStream_t s);
+template <typename T>
+void launch_bcr_copy(const BcrCopyJob* d_jobs, int njobs, int max_nb, const cpx<double>* work,
+                     cpx<T>* fac, hipStream_t s);
+
+// Solve jobs of the block cyclic reduction: one block of one subdomain in
+// pool slot l.  R = reduced right-hand sides, X = solution (both in the pools).
+enum {
+  BCR_PR = 0,     // X_blk = M0 R_blk                                   (level-0 z; top level)
+  BCR_KEPT = 1,   // R_blk = R_blk - M0 R_nl - M1 R_nr                  (forward, level >= 1)
+  BCR_BWD0 = 2,   // X_blk = M0 (R_blk - c_{blk-1} X_nl - c_blk X_nr)   (backward, level 0)
+  BCR_BWD = 3,    // X_blk = M0 R_blk - M1 X_nl - M2 X_nr               (backward, level >= 1)
+  BCR_DFWD = 4    // R_blk = R_blk - c_{blk-1} X_nl - c_blk X_nr        (forward, level 0)
+};
+struct BcrJob {
+  int sub, l, blk, mode;
+  int nl, nr, pad0, pad1;     // neighbour blocks (-1: none)
+  long long m0, m1, m2;       // factor element offsets of the matrices
+};
+template <typename T>
+void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
+                      int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl, cpx<T>* rpool,
+                      cpx<T>* vpool, long long pool_stride, hipStream_t s);
+template <typename T>
+void launch_bcr_dfwd(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs, int kmax,
+                     int max_nb, const cpx<T>* cpl, cpx<T>* rpool, const cpx<T>* vpool,
+                     long long pool_stride, hipStream_t s);
+// RHS per workgroup the solve kernel uses for a requested kg (register budget).
+template <typename T>
+int bcr_kg(int max_nb, int kg);
+template <typename T>
+size_t bcr_lds_bytes(int max_nb, int kg);
+
+// Batched FP64 complex GEMM on working blocks: C = beta C + alpha op(A) op(B),
+// nb x nb column-major; op transposes when ta / tb is set; beta is 0 or 1.
+struct ZGemmJob {
+  int nb, ta, tb, beta;
+  double alpha;
+  long long a, b, c;
+};
+void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* work, hipStream_t s);
+
 // ---- a4: local right-hand sides and source transfer (pull)
 // members are {subdomain, sweep}; the first sweep's right-hand side is f on own cells
 template <typename T>

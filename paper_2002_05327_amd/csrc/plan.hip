@@ -112,6 +112,23 @@ struct StepTab {
   long long blk_cells_mid;
 };
 
+// Block cyclic reduction of one subdomain: the blocks still present at every
+// level (original indices; the even positions are eliminated there) and the
+// factor offsets of W_L = P_k A[k][left], W_R = P_k A[k][right] and of their
+// transposes (the products A[j][k] P_k the kept neighbours use), per block.
+struct BcrSub {
+  int top = 0;                               // level where a single block remains
+  std::vector<std::vector<int>> lev;
+  std::vector<long long> wl, wr, wlt, wrt;   // -1: absent
+};
+
+struct BcrLaunch {
+  int off, n;        // job range
+  int dfwd;          // 1: level-0 coupling update (vector kernel)
+  double fbytes;     // factor bytes streamed (once per launch)
+  double vcells;     // vector entries read and written per right-hand side
+};
+
 }  // namespace
 
 struct dsd_plan {
@@ -124,6 +141,11 @@ struct dsd_plan {
   std::vector<SubDesc> subs;
   std::vector<AxisPart> parts[3];
   std::vector<StepTab> steps;   // launch groups, in order
+  int solver = 2;               // 1: twisted block LDL^T chains, 2: block cyclic reduction
+  std::vector<BcrSub> bcr;
+  std::vector<std::vector<BcrLaunch>> bcr_launch;   // per launch group
+  std::vector<BcrLaunch> bcr_single;                // dsd_local_solve (jobs in d_single_job)
+  Buf d_bcr_jobs;
   long long sum_nloc = 0, sum_fac = 0;
 
   Buf d_subs, d_m, d_gcoef[4], d_lcoef64[4], d_lcoefT[4], d_fac;
@@ -260,6 +282,10 @@ int sub_index(const dsd_plan* pl, const int* pidx) {
   return (z * Py + pidx[1]) * Px + pidx[0];
 }
 
+void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
+                    std::vector<BcrLaunch>& out);
+int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs);
+
 int build_schedule(dsd_plan* pl) {
   const int dim = pl->dim, L = pl->L;
   const dsd_params& q = pl->prm;
@@ -390,6 +416,16 @@ int build_schedule(dsd_plan* pl) {
     }
     pl->steps.push_back(T);
   }
+  pl->bcr_launch.clear();
+  if (pl->solver == 2) {
+    std::vector<BcrJob> bj;
+    for (auto& grp : groups) {
+      pl->bcr_launch.emplace_back();
+      bcr_group_jobs(pl, grp, bj, pl->bcr_launch.back());
+    }
+    CHK(bcr_check_jobs(pl, bj));
+    CHK(upload(pl->d_bcr_jobs, bj));
+  }
   CHK(upload(pl->d_members, members));
   CHK(upload(pl->d_jobs2, jobs2));
   CHK(upload(pl->d_jobs1, jobs1));
@@ -403,6 +439,357 @@ int build_schedule(dsd_plan* pl) {
         if (g >= pl->parts[a][p].o0 && g < pl->parts[a][p].o1) po[g] = p;
     CHK(upload(pl->d_part_of[a], po));
     CHK(upload(pl->d_axparts[a], pl->parts[a]));
+  }
+  return 0;
+}
+
+// ------------------------------------------------------ block cyclic reduction
+// Level structure and factor layout: P_k = D_k^{-1} of every block at
+// fac_off + k nb^2, then the W blocks of the blocks eliminated at levels >= 1.
+void bcr_layout(dsd_plan* pl) {
+  pl->bcr.assign(pl->S, BcrSub{});
+  long long foff = 0;
+  for (int sid = 0; sid < pl->S; ++sid) {
+    SubDesc& S = pl->subs[sid];
+    BcrSub& B = pl->bcr[sid];
+    const long long nb2 = (long long)S.nb * S.nb;
+    std::vector<int> all(S.nblk);
+    for (int k = 0; k < S.nblk; ++k) all[k] = k;
+    B.lev.push_back(all);
+    while (B.lev.back().size() > 1) {
+      const std::vector<int>& c = B.lev.back();
+      std::vector<int> nxt;
+      for (size_t q = 1; q < c.size(); q += 2) nxt.push_back(c[q]);
+      B.lev.push_back(nxt);
+    }
+    B.top = (int)B.lev.size() - 1;
+    B.wl.assign(S.nblk, -1);
+    B.wr.assign(S.nblk, -1);
+    B.wlt.assign(S.nblk, -1);
+    B.wrt.assign(S.nblk, -1);
+    S.fac_off = foff;
+    long long slot = S.nblk;
+    for (int l = 1; l < B.top; ++l) {
+      const std::vector<int>& c = B.lev[l];
+      for (size_t p = 0; p < c.size(); p += 2) {
+        const int k = c[p];
+        if (p > 0) {
+          B.wl[k] = foff + slot++ * nb2;
+          B.wlt[k] = foff + slot++ * nb2;
+        }
+        if (p + 1 < c.size()) {
+          B.wr[k] = foff + slot++ * nb2;
+          B.wrt[k] = foff + slot++ * nb2;
+        }
+      }
+    }
+    foff += slot * nb2;
+  }
+  pl->sum_fac = foff;
+}
+
+// Runs `fn(first, count)` over [0, n) in pieces the grid's y dimension holds.
+template <typename F>
+void in_chunks(int n, F fn) {
+  const int cap = 65535;
+  for (int i = 0; i < n; i += cap) fn(i, std::min(cap, n - i));
+}
+
+// FP64 factorisation by block cyclic reduction, subdomains in batches sized to
+// the free device memory.  Level 0 has the diagonal couplings of the stencil
+// (elementwise updates); the deeper levels use batched GEMMs.
+int bcr_factor(dsd_plan* pl) {
+  hipStream_t st = pl->stream;
+  const Problem& P = pl->P;
+  CHK(pl->d_fac.alloc((size_t)pl->sum_fac * tsize(pl)));
+  const long long blk = (long long)pl->max_nb * pl->max_nb;
+  int maxblk = 1;
+  for (const SubDesc& S : pl->subs) maxblk = std::max(maxblk, S.nblk);
+  const long long half = maxblk / 2 + 1;
+  const long long slots = maxblk + 4 * half;             // D, E (two levels), W_L, W_R
+  const long long per_sub = slots * blk;                 // complex entries per subdomain
+  size_t freeb = 0, totb = 0;
+  HIPCHK(hipMemGetInfo(&freeb, &totb));
+  const long long budget = std::min<long long>((long long)(freeb / 2), 48LL << 30);
+  int batch = (int)std::max<long long>(1, budget / (per_sub * (long long)sizeof(cpx<double>)));
+  batch = std::min(batch, pl->S);
+  Buf work, derr, dpiv, dj;
+  CHK(work.alloc((size_t)batch * per_sub * sizeof(cpx<double>)));
+  long long ninv = 0;
+  for (const SubDesc& S : pl->subs) ninv += S.nblk;
+  CHK(derr.alloc((size_t)ninv * sizeof(int)));
+  HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)ninv * sizeof(int), st));
+  const int maxinv = batch * (int)half;
+  CHK(dpiv.alloc((size_t)maxinv * pl->max_nb * sizeof(int)));
+  cpx<double>* W = work.as<cpx<double>>();
+  const cpx<double>* c64d[4] = {pl->d_lcoef64[0].as<cpx<double>>(), pl->d_lcoef64[1].as<cpx<double>>(),
+                                pl->d_lcoef64[2].as<cpx<double>>(), pl->d_lcoef64[3].as<cpx<double>>()};
+  long long err_off = 0;
+  std::vector<unsigned char> hbuf;
+  // uploads a job vector into dj (the previous launches on the stream are done with it)
+  auto put = [&](const void* data, size_t bytes) -> int {
+    HIPCHK(hipStreamSynchronize(st));
+    if (dj.bytes < bytes) CHK(dj.alloc(std::max<size_t>(bytes, 1 << 20)));
+    HIPCHK(hipMemcpy(dj.p, data, bytes, hipMemcpyHostToDevice));
+    return 0;
+  };
+  for (int s0 = 0; s0 < pl->S; s0 += batch) {
+    const int s1 = std::min(pl->S, s0 + batch);
+    auto slot = [&](int sid, long long k) { return ((long long)(sid - s0) * slots + k) * blk; };
+    auto D = [&](int sid, int k) { return slot(sid, k); };
+    auto E = [&](int sid, int which, long long e) { return slot(sid, maxblk + which * half + e); };
+    auto WL = [&](int sid, long long e) { return slot(sid, maxblk + 2 * half + e); };
+    auto WR = [&](int sid, long long e) { return slot(sid, maxblk + 3 * half + e); };
+    const long long wend = (long long)(s1 - s0) * per_sub;   // working entries in use
+    // every block a job touches must lie inside its buffer (checked before any launch)
+    auto inw = [&](long long off, int nb) { return off >= 0 && off + (long long)nb * nb <= wend; };
+    auto inf = [&](long long off, int nb) { return off >= 0 && off + (long long)nb * nb <= pl->sum_fac; };
+    bool bad_off = false;
+    {
+      std::vector<BcrBlkJob> aj;
+      for (int sid = s0; sid < s1; ++sid)
+        for (int k = 0; k < pl->subs[sid].nblk; ++k) {
+          aj.push_back(BcrBlkJob{sid, k, D(sid, k)});
+          bad_off |= !inw(D(sid, k), pl->subs[sid].nb);
+        }
+      if (bad_off) {
+        g_detail = "internal error: cyclic-reduction assembly job outside its buffer";
+        return DSD_EINVAL;
+      }
+      CHK(put(aj.data(), aj.size() * sizeof(BcrBlkJob)));
+      in_chunks((int)aj.size(), [&](int i0, int n) {
+        launch_bcr_assemble(P, pl->d_subs.as<SubDesc>(), dj.as<BcrBlkJob>() + i0, n, pl->max_nb,
+                            c64d[0], c64d[1], c64d[2], W, st);
+      });
+      HIPCHK(hipGetLastError());
+    }
+    int maxtop = 0;
+    for (int sid = s0; sid < s1; ++sid) maxtop = std::max(maxtop, pl->bcr[sid].top);
+    for (int l = 0; l <= maxtop; ++l) {
+      std::vector<BcrInvJob> inv;
+      std::vector<BcrDiagUpd> du;
+      std::vector<ZGemmJob> gw, gd1, gd2, ge;
+      std::vector<BcrCopyJob> cp;
+      const int rd = l & 1, wr_ = (l + 1) & 1;
+      for (int sid = s0; sid < s1; ++sid) {
+        const BcrSub& B = pl->bcr[sid];
+        if (l > B.top) continue;
+        const SubDesc& S = pl->subs[sid];
+        const int nb = S.nb;
+        const long long nb2 = (long long)nb * nb;
+        const std::vector<int>& c = B.lev[l];
+        const int len = (int)c.size();
+        for (int p = 0; p < len; p += 2)
+          inv.push_back(BcrInvJob{nb, 0, D(sid, c[p]), S.fac_off + (long long)c[p] * nb2});
+        if (l == B.top) continue;
+        if (l == 0) {
+          for (int q = 1; q < len; q += 2) {
+            const int j = c[q];
+            du.push_back(BcrDiagUpd{sid, j, D(sid, j), D(sid, j - 1),
+                                    j + 1 < S.nblk ? D(sid, j + 1) : -1,
+                                    j + 2 < S.nblk ? E(sid, wr_, (q - 1) / 2) : -1});
+          }
+          continue;
+        }
+        for (int p = 0; p < len; p += 2) {
+          const int k = c[p];
+          if (p > 0) {
+            gw.push_back(ZGemmJob{nb, 0, 1, 0, 1.0, D(sid, k), E(sid, rd, p - 1), WL(sid, p / 2)});
+            cp.push_back(BcrCopyJob{nb, 0, WL(sid, p / 2), B.wl[k]});
+            cp.push_back(BcrCopyJob{nb, 1, WL(sid, p / 2), B.wlt[k]});
+          }
+          if (p + 1 < len) {
+            gw.push_back(ZGemmJob{nb, 0, 0, 0, 1.0, D(sid, k), E(sid, rd, p), WR(sid, p / 2)});
+            cp.push_back(BcrCopyJob{nb, 0, WR(sid, p / 2), B.wr[k]});
+            cp.push_back(BcrCopyJob{nb, 1, WR(sid, p / 2), B.wrt[k]});
+          }
+        }
+        for (int q = 1; q < len; q += 2) {
+          const int j = c[q];
+          gd1.push_back(ZGemmJob{nb, 1, 0, 1, -1.0, E(sid, rd, q - 1), WR(sid, (q - 1) / 2), D(sid, j)});
+          if (q + 1 < len)
+            gd2.push_back(ZGemmJob{nb, 0, 0, 1, -1.0, E(sid, rd, q), WL(sid, (q + 1) / 2), D(sid, j)});
+          if (q + 2 < len)
+            ge.push_back(ZGemmJob{nb, 0, 0, 0, -1.0, E(sid, rd, q), WR(sid, (q + 1) / 2),
+                                  E(sid, wr_, (q - 1) / 2)});
+        }
+      }
+      for (const BcrInvJob& j : inv) bad_off |= !inw(j.src, j.nb) || !inf(j.dst, j.nb);
+      for (const BcrDiagUpd& j : du) {
+        const int nb = pl->subs[j.sub].nb;
+        bad_off |= !inw(j.d, nb) || !inw(j.pl, nb) || (j.pr >= 0 && !inw(j.pr, nb)) ||
+                   (j.eout >= 0 && (j.pr < 0 || !inw(j.eout, nb)));
+      }
+      for (const std::vector<ZGemmJob>* v : {&gw, &gd1, &gd2, &ge})
+        for (const ZGemmJob& j : *v) bad_off |= !inw(j.a, j.nb) || !inw(j.b, j.nb) || !inw(j.c, j.nb);
+      for (const BcrCopyJob& j : cp) bad_off |= !inw(j.src, j.nb) || !inf(j.dst, j.nb);
+      if (bad_off) {
+        g_detail = "internal error: cyclic-reduction factor job outside its buffer";
+        return DSD_EINVAL;
+      }
+      // inversions of the eliminated blocks (FP64 in place; rounded copy into the factor)
+      CHK(put(inv.data(), inv.size() * sizeof(BcrInvJob)));
+      for (int i0 = 0; i0 < (int)inv.size(); i0 += maxinv) {
+        const int n = std::min(maxinv, (int)inv.size() - i0);
+        if (pl->c64)
+          launch_bcr_invert<float>(dj.as<BcrInvJob>() + i0, n, pl->max_nb, W, pl->d_fac.as<cpx<float>>(),
+                                   derr.as<int>() + err_off, dpiv.as<int>(), st);
+        else
+          launch_bcr_invert<double>(dj.as<BcrInvJob>() + i0, n, pl->max_nb, W,
+                                    pl->d_fac.as<cpx<double>>(), derr.as<int>() + err_off,
+                                    dpiv.as<int>(), st);
+        err_off += n;
+      }
+      HIPCHK(hipGetLastError());
+      if (!du.empty()) {
+        CHK(put(du.data(), du.size() * sizeof(BcrDiagUpd)));
+        in_chunks((int)du.size(), [&](int i0, int n) {
+          launch_bcr_diag_update(P, pl->d_subs.as<SubDesc>(), dj.as<BcrDiagUpd>() + i0, n,
+                                 pl->max_nb, c64d[2], c64d[3], W, st);
+        });
+        HIPCHK(hipGetLastError());
+      }
+      auto gemm = [&](const std::vector<ZGemmJob>& v) -> int {
+        if (v.empty()) return 0;
+        CHK(put(v.data(), v.size() * sizeof(ZGemmJob)));
+        launch_zgemm(dj.as<ZGemmJob>(), (int)v.size(), pl->max_nb, W, st);
+        HIPCHK(hipGetLastError());
+        return 0;
+      };
+      CHK(gemm(gw));
+      if (!cp.empty()) {
+        CHK(put(cp.data(), cp.size() * sizeof(BcrCopyJob)));
+        in_chunks((int)cp.size(), [&](int i0, int n) {
+          if (pl->c64)
+            launch_bcr_copy<float>(dj.as<BcrCopyJob>() + i0, n, pl->max_nb, W, pl->d_fac.as<cpx<float>>(), st);
+          else
+            launch_bcr_copy<double>(dj.as<BcrCopyJob>() + i0, n, pl->max_nb, W, pl->d_fac.as<cpx<double>>(), st);
+        });
+        HIPCHK(hipGetLastError());
+      }
+      CHK(gemm(gd1));
+      CHK(gemm(gd2));
+      CHK(gemm(ge));
+    }
+  }
+  std::vector<int> herr(ninv);
+  HIPCHK(hipMemcpyAsync(herr.data(), derr.p, ninv * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (long long i = 0; i < ninv; ++i)
+    if (herr[i]) {
+      g_detail = "singular block in the cyclic reduction (inversion " + std::to_string(i) + ")";
+      return DSD_EPIVOT;
+    }
+  return 0;
+}
+
+// Solve launches of one launch group (members {subdomain, sweep}): the forward
+// reduction levels, then the backward substitution from the top level down.
+void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
+                    std::vector<BcrLaunch>& out) {
+  int maxtop = 0;
+  for (const int2& m : mem) maxtop = std::max(maxtop, pl->bcr[m.x].top);
+  const double ts = (double)tsize(pl);
+  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 0.0, 0.0}; };
+  auto finish = [&](BcrLaunch& L) {
+    L.n = (int)jobs.size() - L.off;
+    if (L.n > 0) out.push_back(L);
+  };
+  auto add = [&](BcrLaunch& L, const int2& m, int blk, int mode, int nl, int nr, long long m0,
+                 long long m1, long long m2, int nmat, int nvec) {
+    jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, 0, 0, m0, m1, m2});
+    const SubDesc& S = pl->subs[m.x];
+    L.fbytes += (double)nmat * S.nb * S.nb * ts;
+    L.vcells += (double)nvec * S.nb;
+  };
+  auto Pk = [&](const SubDesc& S, int k) { return S.fac_off + (long long)k * S.nb * S.nb; };
+  for (int f = 0; f < maxtop; ++f) {
+    if (f == 0) {
+      BcrLaunch L = begin(0);
+      for (const int2& m : mem) {
+        const SubDesc& S = pl->subs[m.x];
+        if (pl->bcr[m.x].top == 0) continue;
+        for (int k = 0; k < S.nblk; k += 2) add(L, m, k, BCR_PR, -1, -1, Pk(S, k), 0, 0, 1, 2);
+      }
+      finish(L);
+      BcrLaunch Ld = begin(1);
+      for (const int2& m : mem) {
+        const SubDesc& S = pl->subs[m.x];
+        if (pl->bcr[m.x].top == 0) continue;
+        for (int k = 1; k < S.nblk; k += 2)
+          add(Ld, m, k, BCR_DFWD, k - 1, k + 1 < S.nblk ? k + 1 : -1, 0, 0, 0, 0, 4);
+      }
+      finish(Ld);
+      continue;
+    }
+    BcrLaunch L = begin(0);
+    for (const int2& m : mem) {
+      const BcrSub& B = pl->bcr[m.x];
+      if (f >= B.top) continue;
+      const std::vector<int>& c = B.lev[f];
+      const int len = (int)c.size();
+      for (int q = 1; q < len; q += 2) {
+        const bool hr = q + 1 < len;
+        add(L, m, c[q], BCR_KEPT, c[q - 1], hr ? c[q + 1] : -1, B.wrt[c[q - 1]],
+            hr ? B.wlt[c[q + 1]] : 0, 0, 1 + (int)hr, 3 + (int)hr);
+      }
+    }
+    finish(L);
+  }
+  for (int b = maxtop; b >= 0; --b) {
+    BcrLaunch L = begin(0);
+    for (const int2& m : mem) {
+      const BcrSub& B = pl->bcr[m.x];
+      const SubDesc& S = pl->subs[m.x];
+      if (b > B.top) continue;
+      const std::vector<int>& c = B.lev[b];
+      const int len = (int)c.size();
+      if (b == B.top) {
+        add(L, m, c[0], BCR_PR, -1, -1, Pk(S, c[0]), 0, 0, 1, 2);
+        continue;
+      }
+      for (int p = 0; p < len; p += 2) {
+        const int k = c[p];
+        const bool hl = p > 0, hr = p + 1 < len;
+        const int nl = hl ? c[p - 1] : -1, nr = hr ? c[p + 1] : -1;
+        if (b == 0)
+          add(L, m, k, BCR_BWD0, nl, nr, Pk(S, k), 0, 0, 1, 2 + (int)hl + (int)hr);
+        else
+          add(L, m, k, BCR_BWD, nl, nr, Pk(S, k), hl ? B.wl[k] : 0, hr ? B.wr[k] : 0,
+              1 + (int)hl + (int)hr, 2 + (int)hl + (int)hr);
+      }
+    }
+    finish(L);
+  }
+}
+
+// Host check of a solve-job table against the factor and the subdomain grids.
+int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
+  for (const BcrJob& J : jobs) {
+    bool ok = J.sub >= 0 && J.sub < pl->S && J.l >= 0 && J.l < pl->L;
+    if (ok) {
+      const SubDesc& S = pl->subs[J.sub];
+      const long long nb2 = (long long)S.nb * S.nb;
+      auto blk_ok = [&](int b) { return b >= 0 && b < S.nblk; };
+      auto mat_ok = [&](long long o) { return o >= 0 && o + nb2 <= pl->sum_fac; };
+      ok = blk_ok(J.blk) && (J.nl == -1 || blk_ok(J.nl)) && (J.nr == -1 || blk_ok(J.nr));
+      const bool hl = J.nl >= 0, hr = J.nr >= 0;
+      switch (J.mode) {
+        case BCR_PR: ok = ok && mat_ok(J.m0); break;
+        case BCR_KEPT: ok = ok && hl && mat_ok(J.m0) && (!hr || mat_ok(J.m1)); break;
+        case BCR_BWD0:
+        case BCR_DFWD:
+          ok = ok && (!hl || J.blk >= 1) && (!hr || J.blk + 1 < S.nblk) &&
+               (J.mode == BCR_DFWD || mat_ok(J.m0));
+          break;
+        case BCR_BWD: ok = ok && mat_ok(J.m0) && (!hl || mat_ok(J.m1)) && (!hr || mat_ok(J.m2)); break;
+        default: ok = false;
+      }
+    }
+    if (!ok) {
+      g_detail = "internal error: cyclic-reduction solve job out of range";
+      return DSD_EINVAL;
+    }
   }
   return 0;
 }
@@ -458,6 +845,7 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
   }
   HIPCHK(hipGetLastError());
 
+  if (pl->solver == 2) return bcr_factor(pl);
   // ---- factorisation: chains of Schur complements towards the middle block
   CHK(pl->d_fac.alloc((size_t)pl->sum_fac * tsize(pl)));
   const long long blk = (long long)pl->max_nb * pl->max_nb;
@@ -575,6 +963,32 @@ void chain_phase(dsd_plan* pl, int phase, const int4* jobs, int njobs, int nrhs,
 }
 
 template <typename T>
+void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
+  hipStream_t st = pl->stream;
+  const long long ps = pl->sum_nloc * pl->kmax;
+  const cpx<T>* cpl = pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>();
+  cpx<T>* rpool = pl->d_rpool.as<cpx<T>>();
+  cpx<T>* vpool = pl->d_vpool.as<cpx<T>>();
+  if (L.dfwd) {
+    launch_bcr_dfwd<T>(pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, nrhs, pl->kmax, pl->max_nb, cpl,
+                       rpool, vpool, ps, st);
+    return;
+  }
+  if (pl->timing) (void)hipEventRecord(pl->ev0, st);
+  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, nrhs, pl->kmax,
+                      pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
+  if (pl->timing) {
+    (void)hipEventRecord(pl->ev1, st);
+    (void)hipEventSynchronize(pl->ev1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
+    pl->t_solve_ms += ms;
+    pl->solve_launches += 1;
+    pl->solve_bytes += L.fbytes + L.vcells * nrhs * (double)sizeof(cpx<T>);
+  }
+}
+
+template <typename T>
 int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) {
   CHK(ensure_pools(pl));
   hipStream_t st = pl->stream;
@@ -591,6 +1005,11 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
                    pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
                    pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
                    pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
+    if (pl->solver == 2) {
+      for (const BcrLaunch& L : pl->bcr_launch[&st_ - pl->steps.data()])
+        bcr_phase<T>(pl, pl->d_bcr_jobs.as<BcrJob>(), L, nrhs);
+      continue;
+    }
     const int4* j2 = pl->d_jobs2.as<int4>() + st_.job_off;
     const int4* j1 = pl->d_jobs1.as<int4>() + st_.mem_off;
     chain_phase<T>(pl, 0, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
@@ -842,6 +1261,14 @@ int choose_kg(const dsd_plan* pl, int want) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
       lds = v;
   }
+  if (pl->solver == 2) {
+    int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
+    auto need = [&](int k) {
+      return pl->c64 ? bcr_lds_bytes<float>(pl->max_nb, k) : bcr_lds_bytes<double>(pl->max_nb, k);
+    };
+    while (kg > 1 && need(kg) > (size_t)lds) kg >>= 1;
+    return need(kg) > (size_t)lds ? 0 : kg;
+  }
   int kg = 4;
   if (!pl->c64 && pl->max_nb > 192) kg = 2;   // register budget of the 4-tile c128 kernel
   while (kg > want && kg > 1) kg >>= 1;
@@ -865,8 +1292,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   *out = nullptr;
   const dsd_params& q = *params;
   if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
-      (q.precision != DSD_C64 && q.precision != DSD_C128)) {
-    g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128";
+      (q.precision != DSD_C64 && q.precision != DSD_C128) || q.local_solver < 0 ||
+      q.local_solver > 2 || q.schedule < 0 || q.schedule > 1) {
+    g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
+               "local_solver 0..2, schedule 0..1";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)
@@ -885,7 +1314,25 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   int rc = build_partition(pl);
   pl->sequential = q.schedule == 1;
   if (rc == 0) {
-    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : 2);
+    // local solver: block cyclic reduction unless its factor (about three
+    // times the chain factor) would take more than 45% of the device memory
+    std::vector<long long> toff(pl->S);
+    for (int i = 0; i < pl->S; ++i) toff[i] = pl->subs[i].fac_off;
+    const long long tsum = pl->sum_fac;
+    pl->solver = q.local_solver == 1 ? 1 : 2;
+    if (pl->solver == 2) {
+      bcr_layout(pl);
+      size_t fr = 0, tot = 0;
+      if (q.local_solver == 0 && hipMemGetInfo(&fr, &tot) == hipSuccess &&
+          (double)pl->sum_fac * tsize(pl) > 0.45 * (double)tot) {
+        pl->solver = 1;
+        for (int i = 0; i < pl->S; ++i) pl->subs[i].fac_off = toff[i];
+        pl->sum_fac = tsum;
+      }
+    }
+  }
+  if (rc == 0) {
+    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : (pl->solver == 2 ? 4 : 2));
     if (pl->kg == 0) {
       g_detail = "subdomain blocks too large for the solve kernel's LDS";
       rc = DSD_EINVAL;
@@ -950,11 +1397,35 @@ int dsd_local_solve(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, i
   pl->stream = (hipStream_t)stream;
   CHK(ensure_pools(pl));
   const SubDesc& S = pl->subs[sub];
+  const long long off = S.vec_off * pl->kmax;
+  hipStream_t st = pl->stream;
+  if (pl->solver == 2) {
+    std::vector<BcrJob> bj;
+    pl->bcr_single.clear();
+    bcr_group_jobs(pl, std::vector<int2>{make_int2(sub, 0)}, bj, pl->bcr_single);
+    CHK(bcr_check_jobs(pl, bj));
+    CHK(upload(pl->d_single_job, bj));
+    const BcrJob* jb = pl->d_single_job.as<BcrJob>();
+    if (pl->c64) {
+      launch_pack_local<float>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<float>>() + off,
+                               S.nloc, nrhs, pl->kmax, st);
+      for (const BcrLaunch& L : pl->bcr_single) bcr_phase<float>(pl, jb, L, nrhs);
+      launch_unpack_local<float>(pl->d_vpool.as<cpx<float>>() + off, (cpx<double>*)u_dev, S.nloc,
+                                 nrhs, pl->kmax, st);
+    } else {
+      launch_pack_local<double>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<double>>() + off,
+                                S.nloc, nrhs, pl->kmax, st);
+      for (const BcrLaunch& L : pl->bcr_single) bcr_phase<double>(pl, jb, L, nrhs);
+      launch_unpack_local<double>(pl->d_vpool.as<cpx<double>>() + off, (cpx<double>*)u_dev,
+                                  S.nloc, nrhs, pl->kmax, st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return DSD_OK;
+  }
   std::vector<int4> jobs = {make_int4(sub, 0, 0, 0), make_int4(sub, 1, 0, 0),
                             make_int4(sub, 0, 0, 0)};
   CHK(upload(pl->d_single_job, jobs));
-  const long long off = S.vec_off * pl->kmax;
-  hipStream_t st = pl->stream;
   const int4* jb = pl->d_single_job.as<int4>();
   if (pl->c64) {
     launch_pack_local<float>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<float>>() + off, S.nloc,

@@ -17,11 +17,14 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag"):
+def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="auto"):
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(slowness2(c)).cuda()
     return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
-                    max_rhs=k, rhs_per_group=kg, schedule=schedule)
+                    max_rhs=k, rhs_per_group=kg, schedule=schedule, local_solver=solver)
+
+
+SOLVERS = ["bcr", "chain"]
 
 
 def _cuda(x):
@@ -42,12 +45,13 @@ def _case(name):
     return n, h, om, pml, d, parts, medium(med, n, seed=3)
 
 
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["c1", "rag34", "d3"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_local_solve_matches_oracle(name, prec):
+def test_local_solve_matches_oracle(name, prec, solver):
     n, h, om, pml, d, parts, c = _case(name)
     k = 3
-    plan = _plan(n, h, om, pml, d, parts, c, prec, k)
+    plan = _plan(n, h, om, pml, d, parts, c, prec, k, solver=solver)
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     nsub = int(np.prod(parts))
     for sid in sorted({0, nsub - 1, nsub // 2}):
@@ -60,7 +64,7 @@ def test_local_solve_matches_oracle(name, prec):
         u_ref = sp.solve(r.T).T
         u = plan.local_solve(sid, _cuda(r.reshape((k,) + sp.shape))).cpu().numpy().reshape(k, -1)
         tol = 1e-11 if prec == "c128" else 2e-4
-        print(f"{name} {prec} sub {sid}: rel err {rel(u, u_ref):.2e}", flush=True)
+        print(f"{name} {prec} {solver} sub {sid}: rel err {rel(u, u_ref):.2e}", flush=True)
         assert rel(u, u_ref) < tol
 
 
@@ -76,33 +80,35 @@ def test_operator_matches_oracle(name):
     assert rel(y, y_ref) < 1e-14
 
 
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["c1", "lay33", "rag34", "d3"])
-def test_sweep_apply_c128_matches_oracle_real_mode(name):
+def test_sweep_apply_c128_matches_oracle_real_mode(name, solver):
     """One application of Algorithm 3.1 / 4.1 (real local PML solves)."""
     n, h, om, pml, d, parts, c = _case(name)
     k = 2
     f = sources(n, h, pml, k)
-    plan = _plan(n, h, om, pml, d, parts, c, "c128", k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k, solver=solver)
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
     e = rel(u, u_ref)
-    print(f"{name}: GPU c128 sweep vs oracle {e:.2e}; DDM vs global solve "
+    print(f"{name} {solver}: GPU c128 sweep vs oracle {e:.2e}; DDM vs global solve "
           f"{rel(u_ref, global_solve(ddm.M, f.reshape(k, -1).T).T):.2e}", flush=True)
     assert e < 1e-10
 
 
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["c1", "lay33"])
-def test_sweep_apply_c64_close_to_oracle(name):
+def test_sweep_apply_c64_close_to_oracle(name, solver):
     n, h, om, pml, d, parts, c = _case(name)
     k = 2
     f = sources(n, h, pml, k)
-    plan = _plan(n, h, om, pml, d, parts, c, "c64", k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c64", k, solver=solver)
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
     e = rel(u, u_ref)
-    print(f"{name}: GPU c64 sweep vs oracle {e:.2e}", flush=True)
+    print(f"{name} {solver}: GPU c64 sweep vs oracle {e:.2e}", flush=True)
     assert e < 1e-3
 
 
@@ -115,24 +121,49 @@ def test_sweep_apply_deterministic():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["rag34", "d3"])
-def test_dependency_schedule_equals_sequential_steps(name):
+def test_dependency_schedule_equals_sequential_steps(name, solver):
     """Launching each solve at its dependency level reorders nothing that is summed."""
     n, h, om, pml, d, parts, c = _case(name)
     f = _cuda(sources(n, h, pml, 3))
-    a = _plan(n, h, om, pml, d, parts, c, "c64", 3, schedule="dag").sweep_apply(f).cpu().numpy()
-    b = _plan(n, h, om, pml, d, parts, c, "c64", 3, schedule="sequential").sweep_apply(f).cpu().numpy()
+    a = _plan(n, h, om, pml, d, parts, c, "c64", 3, schedule="dag",
+              solver=solver).sweep_apply(f).cpu().numpy()
+    b = _plan(n, h, om, pml, d, parts, c, "c64", 3, schedule="sequential",
+              solver=solver).sweep_apply(f).cpu().numpy()
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("kg", [1, 2, 4])
-def test_rhs_grouping_does_not_change_result(kg):
+def test_rhs_grouping_does_not_change_result(kg, solver):
     n, h, om, pml, d, parts, c = _case("lay33")
     k = 5
     f = _cuda(sources(n, h, pml, k))
-    ref = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=1).sweep_apply(f).cpu().numpy()
-    got = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=kg).sweep_apply(f).cpu().numpy()
-    assert rel(got, ref) < 1e-13
+    ref = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=1, solver=solver).sweep_apply(f)
+    got = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=kg, solver=solver).sweep_apply(f)
+    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("kg", [2, 4, 8])
+def test_rhs_grouping_c64_matrix_core_path(kg):
+    """complex64 groups of 2, 4 and 8 RHS all run on the matrix cores."""
+    n, h, om, pml, d, parts, c = _case("lay33")
+    k = 9
+    f = _cuda(sources(n, h, pml, k))
+    ref = _plan(n, h, om, pml, d, parts, c, "c64", k, kg=2, solver="bcr").sweep_apply(f)
+    got = _plan(n, h, om, pml, d, parts, c, "c64", k, kg=kg, solver="bcr").sweep_apply(f)
+    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["lay33", "rag34", "d3"])
+def test_cyclic_reduction_equals_chains(name):
+    """Both local solvers invert the same subdomain operators (complex128)."""
+    n, h, om, pml, d, parts, c = _case(name)
+    f = _cuda(sources(n, h, pml, 2))
+    a = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="bcr").sweep_apply(f).cpu().numpy()
+    b = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain").sweep_apply(f).cpu().numpy()
+    assert rel(a, b) < 1e-12
 
 
 @pytest.mark.parametrize("prec,tol,bound", [("c128", 1e-12, 1e-10), ("c64", 1e-11, 1e-8)])
