@@ -956,64 +956,82 @@ void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* wo
 }
 
 // ---- solve jobs ------------------------------------------------------------
-// One workgroup (8 waves) runs one job for KG right-hand sides:
-//   out = sum_m M_m v_m  (up to three dense blocks, operands prepared in LDS)
-// The matrices stream column by column: the waves split the columns, lanes
-// own rows (64-row tiles, RT tiles per chunk), each lane keeps CH_ROUND_BYTES
-// per tile in flight one round ahead, and the partial sums of the waves meet
-// in LDS.  complex64 with KG >= 2 runs on v_mfma_f32_4x4x1f32 (operand layout
-// as in k_chain_mfma); otherwise vector FMAs.
-template <typename T, int KG, int RT>
-__global__ __launch_bounds__(CH_THREADS) void k_bcr(const SubDesc* __restrict__ subs,
-                                                    const BcrJob* __restrict__ jobs, int njobs,
-                                                    int G, int nrhs, int kmax,
-                                                    const cpx<T>* __restrict__ fac,
-                                                    const cpx<T>* __restrict__ cpl,
-                                                    cpx<T>* __restrict__ rpool,
-                                                    cpx<T>* __restrict__ vpool,
-                                                    long long pool_stride) {
+// A task is (job, RHS group of KG, row group).  Its workgroup has RT x CG
+// waves: wave (rt, cg) owns the 64-row tile rt and the columns
+// [cg cw, (cg+1) cw) of each of the (up to three) matrices of the job,
+//   out = sum_m M_m v_m   (+ R_blk for BCR_KEPT),
+// and the CG partial sums of a tile meet in LDS (CG = 1 when the launch has
+// enough tasks to fill the chip; more column groups shorten the per-task
+// latency chain of the small, deep reduction levels).  The operand vectors
+// v_m are staged in LDS as [column][KG] complex values; the first round of
+// matrix loads is issued before the staging, and every round keeps the next
+// one in flight.
+//
+// complex64 with KG = 8 or 16 runs on v_mfma_f32_16x16x4f32 (A: lane l holds
+// row l%16, column l/16 of a 16x4 tile; B: lane l holds k = l/16, output
+// column l%16; D: lane l, register r holds row 4(l/16)+r, column l%16).  A
+// is Re(M) or Im(M) of a 16-row x 4-column tile; the 16 output columns are
+// (Re, Im) of 8 right-hand sides, with B = [Re y, Im y] against Re(M) and
+// [-Im y, Re y] against Im(M).  The four 16-row blocks of a wave keep four
+// independent accumulator chains.  Otherwise vector FMAs, one row per lane.
+constexpr int BCR_ROUND_BYTES = 192;        // matrix bytes per lane in one round
+constexpr int BCR_STAGE = 4;                // operand loads a thread keeps in flight
+constexpr int BCR_MAXW = 12;                // waves per workgroup
+constexpr int BCR_MAXRT = 4;                // 64-row tiles per workgroup
+
+template <typename T, int KG>
+struct BcrTraits {
+  static constexpr bool MF = std::is_same<T, float>::value && KG >= 8;
+  static constexpr int JB = MF ? KG / 8 : 1;            // 16-column output blocks
+  static constexpr int PW = MF ? 4 * 4 * JB : 2 * KG;   // partial-sum words per lane
+};
+
+template <typename T, int KG>
+__global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict__ subs,
+                                                       const BcrJob* __restrict__ jobs, int njobs,
+                                                       int G, int nrg, int RT, int CG, int nrhs,
+                                                       int kmax, const cpx<T>* __restrict__ fac,
+                                                       const cpx<T>* __restrict__ cpl,
+                                                       cpx<T>* __restrict__ rpool,
+                                                       cpx<T>* __restrict__ vpool,
+                                                       long long pool_stride, int lds_ops) {
   typedef typename vec2<T>::type V2;
   typedef cpx<T> C;
-  constexpr bool MF = std::is_same<T, float>::value && KG >= 2;
-  constexpr int U = CH_ROUND_BYTES / (int)sizeof(V2);
-  constexpr int NG = MF ? KG / 2 : 1;
-  constexpr int ROWS = 64 * RT;
+  typedef BcrTraits<T, KG> TR;
+  constexpr bool MF = TR::MF;
+  constexpr int JB = TR::JB;
+  constexpr int U = BCR_ROUND_BYTES / (int)sizeof(V2);   // loads per lane per round
+  constexpr int UG = U / 4;                              // MF: 4-column groups per round
   typedef float mf4v __attribute__((ext_vector_type(4)));
   const int total = gridDim.x;
   const int per = total >> 3;
   const int bid = blockIdx.x;
-  const int Lg = (bid & 7) * per + (bid >> 3);   // XCD-aware: a job's RHS groups share an L2
-  const int job = Lg / G, g = Lg - (Lg / G) * G;
+  const int Lg = (bid & 7) * per + (bid >> 3);   // XCD-aware: a job's tasks share an L2
+  const int tpj = G * nrg;
+  const int job = Lg / tpj;
   if (job >= njobs) return;
+  const int rem = Lg - job * tpj;
+  const int g = rem / nrg, rg = rem - (rem / nrg) * nrg;
   const BcrJob J = jobs[job];
-  const SubDesc S = subs[J.sub];
+  const SubDesc& S = subs[J.sub];
   const int nb = S.nb;
   const long long nloc = S.nloc;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int cw = (nb + CH_WAVES - 1) / CH_WAVES;
-  const int nr = (cw + U - 1) / U;
-  const int nru = nr * U;
-  const int ncol = CH_WAVES * nru;
-  const int nchunk = (nb + ROWS - 1) / ROWS;
-  const int j0 = w * cw;
-  const int j1 = min(nb, j0 + cw);
+  const int rt = w % RT, cg = w / RT;
+  const int row0 = (rg * RT + rt) * 64;
+  int cw = (nb + CG - 1) / CG;
+  cw = (cw + 3) & ~3;
+  const int c0 = cg * cw;
+  const int c1 = min(nb, c0 + cw);
+  const bool wave_live = row0 < nb && c0 < c1;
   const C zero = mk((T)0, (T)0);
-  extern __shared__ unsigned char smem_raw[];
-  const long long opsz = MF ? (long long)NG * ncol * 4 : (long long)KG * nb;
-  V2* opv = reinterpret_cast<V2*>(smem_raw);
-  C* opc = reinterpret_cast<C*>(smem_raw);
-  unsigned char* after_ops = smem_raw + 3 * opsz * (MF ? sizeof(V2) : sizeof(C));
-  float* redf = reinterpret_cast<float*>(after_ops);
-  C* redc = reinterpret_cast<C*>(after_ops);
   C* __restrict__ X = vpool + (long long)J.l * pool_stride + S.vec_off * kmax;
   C* __restrict__ R = rpool + (long long)J.l * pool_stride + S.vec_off * kmax;
   const C* __restrict__ Cp = cpl + S.coef_off;
   const V2* __restrict__ Fv = reinterpret_cast<const V2*>(fac);
   const int mode = J.mode, blk = J.blk;
   const bool hl = J.nl >= 0, hr = J.nr >= 0;
-
-  // matrices in use, compacted; operand set m belongs to matrix m
   int nm;
   long long mo0, mo1 = 0, mo2 = 0;
   if (mode == BCR_KEPT) {
@@ -1029,164 +1047,229 @@ __global__ __launch_bounds__(CH_THREADS) void k_bcr(const SubDesc* __restrict__ 
     nm = 1;
     mo0 = J.m0;
   }
-
-  if (MF) {
-    for (long long idx = tid; idx < 3 * opsz; idx += CH_THREADS) opv[idx] = V2{(T)0, (T)0};
-    __syncthreads();
-  }
-  auto put_op = [&](int set, int q, int i, C y) {
-    if constexpr (MF) {
-      const int slot = (i / cw) * nru + (i - (i / cw) * cw);
-      V2* o = opv + set * opsz + ((long long)(q >> 1) * ncol + slot) * 4 + 2 * (q & 1);
-      o[0] = V2{y.re, -y.im};
-      o[1] = V2{y.im, y.re};
-    } else {
-      opc[set * opsz + (long long)q * nb + i] = y;
-    }
-  };
-  for (int idx = tid; idx < nb * KG; idx += CH_THREADS) {
-    const int q = idx / nb, i = idx - q * nb;
-    const int rq = g * KG + q;
-    const bool live = rq < nrhs;
-    const long long ro = (long long)rq * nloc;
-    if (mode == BCR_KEPT) {
-      const C vl = (live && hl) ? R[ro + (long long)J.nl * nb + i] : zero;
-      const C vr = (live && hr) ? R[ro + (long long)J.nr * nb + i] : zero;
-      if (hl) put_op(0, q, i, -vl);
-      if (hr) put_op(hl ? 1 : 0, q, i, -vr);
-    } else if (mode == BCR_BWD) {
-      put_op(0, q, i, live ? R[ro + (long long)blk * nb + i] : zero);
-      const C vl = (live && hl) ? X[ro + (long long)J.nl * nb + i] : zero;
-      const C vr = (live && hr) ? X[ro + (long long)J.nr * nb + i] : zero;
-      if (hl) put_op(1, q, i, -vl);
-      if (hr) put_op(hl ? 2 : 1, q, i, -vr);
-    } else if (mode == BCR_BWD0) {
-      C y = zero;
-      if (live) {
-        y = R[ro + (long long)blk * nb + i];
-        if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * X[ro + (long long)J.nl * nb + i];
-        if (hr) y = y - Cp[(long long)blk * nb + i] * X[ro + (long long)J.nr * nb + i];
-      }
-      put_op(0, q, i, y);
-    } else {
-      put_op(0, q, i, live ? R[ro + (long long)blk * nb + i] : zero);
-    }
-  }
-  lds_barrier();
-
-  const int per_ch = nm * nr;
-  const int total_rounds = nchunk * per_ch;
   const long long d01 = mo1 - mo0, d12 = mo2 - mo1;
-  auto issue = [&](V2 (&buf)[U][RT], int gr) {
-    const int ch = gr / per_ch, rem = gr - ch * per_ch;
-    const int m = rem / nr, rd = rem - m * nr;
+  // rounds per matrix: MF covers 4 columns x 16 rows per load, else 1 column x 64 rows
+  const int cpr = MF ? 4 * UG : U;                       // columns per round
+  const int nr = (c1 - c0 + cpr - 1) / cpr;
+  const int total_rounds = nm * nr;
+  // per-lane load base: MF lane l reads row 16 rb + l%16 of column 4 g + l/16
+  int lrow, lcol;
+  if (MF) { lrow = row0 + (lane & 15); lcol = lane >> 4; }
+  else { lrow = row0 + lane; lcol = 0; }
+  auto issue = [&](V2 (&buf)[U], int gr) {
+    const int m = gr / nr, rd = gr - (gr / nr) * nr;
     const V2* __restrict__ Mv = Fv + mo0 + (m >= 1 ? d01 : 0) + (m >= 2 ? d12 : 0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      int jc = j0 + rd * U + u;
-      jc = jc < j1 ? jc : (j1 > j0 ? j1 - 1 : 0);
-#pragma unroll
-      for (int tt = 0; tt < RT; ++tt) {
-        int row = ch * ROWS + tt * 64 + lane;
-        row = row < nb ? row : nb - 1;
-        buf[u][tt] = Mv[(long long)jc * nb + row];
+      int col, rw;
+      if (MF) {
+        col = c0 + rd * cpr + 4 * (u / 4) + lcol;
+        rw = lrow + 16 * (u & 3);
+      } else {
+        col = c0 + rd * cpr + u;
+        rw = lrow;
       }
+      col = col < c1 ? col : c1 - 1;
+      rw = rw < nb ? rw : nb - 1;
+      buf[u] = Mv[(long long)col * nb + rw];
     }
   };
-  V2 cur[U][RT], nxt[U][RT];
-  if (total_rounds > 0) issue(cur, 0);
-  int gr = 0;
-  for (int ch = 0; ch < nchunk; ++ch) {
-    T ar[RT][KG], ai[RT][KG];
-    mf4v acc[RT][NG];
+  V2 cur[U], nxt[U];
+  if (wave_live) issue(cur, 0);
+
+  // ---- operands: set m at ops + m * nb * KG, [column][KG]; loads batched
+  extern __shared__ unsigned char smem_raw[];
+  C* ops = reinterpret_cast<C*>(smem_raw);
+  const long long ss = (long long)nb * KG;
+  const int nel = nb * KG;
+  for (int base = 0; base < nel; base += BCR_STAGE * (int)blockDim.x) {
+    C va[BCR_STAGE], vb[BCR_STAGE], vc[BCR_STAGE];
 #pragma unroll
-    for (int tt = 0; tt < RT; ++tt) {
-#pragma unroll
-      for (int q = 0; q < KG; ++q) { ar[tt][q] = (T)0; ai[tt][q] = (T)0; }
-#pragma unroll
-      for (int ng = 0; ng < NG; ++ng) acc[tt][ng] = mf4v{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int m = 0; m < nm; ++m) {
-      const long long ob = (long long)m * opsz;
-      for (int rd = 0; rd < nr; ++rd, ++gr) {
-        if (gr + 1 < total_rounds) issue(nxt, gr + 1);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if constexpr (MF) {
-            const int sl = w * nru + rd * U + u;
-#pragma unroll
-            for (int ng = 0; ng < NG; ++ng) {
-              const V2 y = opv[ob + ((long long)ng * ncol + sl) * 4 + (lane & 3)];
-#pragma unroll
-              for (int tt = 0; tt < RT; ++tt) {
-                acc[tt][ng] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)cur[u][tt].x, (float)y.x, acc[tt][ng], 0, 0, 0);
-                acc[tt][ng] = __builtin_amdgcn_mfma_f32_4x4x1f32((float)cur[u][tt].y, (float)y.y, acc[tt][ng], 0, 0, 0);
-              }
-            }
-          } else {
-            const int j = j0 + rd * U + u;
-            const bool ok = j < j1;
-            const int jc = ok ? j : 0;
-#pragma unroll
-            for (int q = 0; q < KG; ++q) {
-              const C y = opc[ob + (long long)q * nb + jc];
-              const T yr = ok ? y.re : (T)0, yi = ok ? y.im : (T)0;
-#pragma unroll
-              for (int tt = 0; tt < RT; ++tt) {
-                ar[tt][q] = fma(cur[u][tt].x, yr, ar[tt][q]);
-                ar[tt][q] = fma(-cur[u][tt].y, yi, ar[tt][q]);
-                ai[tt][q] = fma(cur[u][tt].x, yi, ai[tt][q]);
-                ai[tt][q] = fma(cur[u][tt].y, yr, ai[tt][q]);
-              }
-            }
+    for (int k = 0; k < BCR_STAGE; ++k) {
+      const int idx = base + k * (int)blockDim.x + tid;
+      const int q = idx / nb, i = idx - q * nb;
+      const int rq = g * KG + q;
+      const bool live = idx < nel && rq < nrhs;
+      const long long ro = (long long)rq * nloc;
+      va[k] = vb[k] = vc[k] = zero;
+      if (live) {
+        if (mode == BCR_KEPT) {
+          if (hl) va[k] = R[ro + (long long)J.nl * nb + i];
+          if (hr) vb[k] = R[ro + (long long)J.nr * nb + i];
+        } else {
+          va[k] = R[ro + (long long)blk * nb + i];
+          if (mode == BCR_BWD || mode == BCR_BWD0) {
+            if (hl) vb[k] = X[ro + (long long)J.nl * nb + i];
+            if (hr) vc[k] = X[ro + (long long)J.nr * nb + i];
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int tt = 0; tt < RT; ++tt) cur[u][tt] = nxt[u][tt];
       }
     }
-    if constexpr (MF) {
 #pragma unroll
-      for (int tt = 0; tt < RT; ++tt)
-#pragma unroll
-        for (int ng = 0; ng < NG; ++ng)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            redf[((((long long)w * RT + tt) * NG + ng) * 4 + i) * 64 + lane] = acc[tt][ng][i];
-    } else {
-#pragma unroll
-      for (int tt = 0; tt < RT; ++tt)
-#pragma unroll
-        for (int q = 0; q < KG; ++q)
-          redc[((long long)w * KG + q) * ROWS + tt * 64 + lane] = mk(ar[tt][q], ai[tt][q]);
+    for (int k = 0; k < BCR_STAGE; ++k) {
+      const int idx = base + k * (int)blockDim.x + tid;
+      if (idx >= nel) break;
+      const int q = idx / nb, i = idx - q * nb;
+      C* o = ops + (long long)i * KG + q;
+      if (mode == BCR_KEPT) {
+        if (hl) o[0] = -va[k];
+        if (hr) o[hl ? ss : 0] = -vb[k];
+      } else if (mode == BCR_BWD) {
+        o[0] = va[k];
+        if (hl) o[ss] = -vb[k];
+        if (hr) o[hl ? 2 * ss : ss] = -vc[k];
+      } else if (mode == BCR_BWD0) {
+        C y = va[k];
+        if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * vb[k];
+        if (hr) y = y - Cp[(long long)blk * nb + i] * vc[k];
+        o[0] = y;
+      } else {
+        o[0] = va[k];
+      }
     }
-    lds_barrier();
-    for (int o = tid; o < KG * ROWS; o += CH_THREADS) {
-      const int q = o / ROWS, il = o - q * ROWS, i = ch * ROWS + il;
-      const int rq = g * KG + q;
-      if (i >= nb || rq >= nrhs) continue;
-      C out = zero;
-      if constexpr (MF) {
-        const int tt = il >> 6, r64 = il & 63;
-        const int src = 4 * (r64 >> 2) + 2 * (q & 1);
-        const int ii = r64 & 3, ng = q >> 1;
+  }
+  __syncthreads();
+
+  mf4v acc[4][JB];
+  T ar[KG], ai[KG];
 #pragma unroll
-        for (int ww = 0; ww < CH_WAVES; ++ww) {
-          const float* rb = redf + ((((long long)ww * RT + tt) * NG + ng) * 4 + ii) * 64 + src;
-          out.re += rb[0];
-          out.im += rb[1];
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb) acc[rb][jb] = mf4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < KG; ++q) { ar[q] = (T)0; ai[q] = (T)0; }
+  if (wave_live) {
+    for (int gr = 0; gr < total_rounds; ++gr) {
+      if (gr + 1 < total_rounds) issue(nxt, gr + 1);
+      const int m = gr / nr, rd = gr - (gr / nr) * nr;
+      const C* __restrict__ op = ops + m * ss;
+      if constexpr (MF) {
+#pragma unroll
+        for (int ug = 0; ug < UG; ++ug) {
+          const int col = c0 + rd * cpr + 4 * ug + lcol;   // this lane's k
+          const bool ok = col < c1;
+          const int cc = ok ? col : 0;
+          float bre[JB], bim[JB];
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb) {
+            const int j = jb * 16 + (lane & 15);
+            const C y = op[(long long)cc * KG + (j >> 1)];
+            const bool im = j & 1;
+            bre[jb] = ok ? (im ? y.im : y.re) : 0.f;
+            bim[jb] = ok ? (im ? y.re : -y.im) : 0.f;
+          }
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+              acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)cur[4 * ug + rb].x, bre[jb], acc[rb][jb], 0, 0, 0);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+              acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)cur[4 * ug + rb].y, bim[jb], acc[rb][jb], 0, 0, 0);
+          }
         }
       } else {
 #pragma unroll
-        for (int ww = 0; ww < CH_WAVES; ++ww) out = out + redc[((long long)ww * KG + q) * ROWS + il];
+        for (int u = 0; u < U; ++u) {
+          const int col = c0 + rd * cpr + u;
+          const bool ok = col < c1;
+          const int cc = ok ? col : 0;
+#pragma unroll
+          for (int q = 0; q < KG; ++q) {
+            const C y = op[(long long)cc * KG + q];
+            const T yr = ok ? y.re : (T)0, yi = ok ? y.im : (T)0;
+            ar[q] = fma(cur[u].x, yr, ar[q]);
+            ar[q] = fma(-cur[u].y, yi, ar[q]);
+            ai[q] = fma(cur[u].x, yi, ai[q]);
+            ai[q] = fma(cur[u].y, yr, ai[q]);
+          }
+        }
       }
-      const long long oo = (long long)rq * nloc + (long long)blk * nb + i;
-      if (mode == BCR_KEPT) R[oo] = R[oo] + out;
-      else X[oo] = out;
+#pragma unroll
+      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
-    lds_barrier();
+  }
+  // ---- column-group partial sums meet in LDS (after the operand area)
+  if (CG > 1) {
+    float* part = reinterpret_cast<float*>(smem_raw + lds_ops);
+    constexpr int PW = TR::PW;
+    if (cg > 0) {
+      if constexpr (MF) {
+        float* pw = part + (long long)((cg - 1) * RT + rt) * PW * 64;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) pw[((rb * JB + jb) * 4 + r) * 64 + lane] = acc[rb][jb][r];
+      } else {
+        T* pt = reinterpret_cast<T*>(part) + (long long)((cg - 1) * RT + rt) * PW * 64;
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          pt[(2 * q) * 64 + lane] = ar[q];
+          pt[(2 * q + 1) * 64 + lane] = ai[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (cg == 0) {
+      for (int o = 1; o < CG; ++o) {
+        if constexpr (MF) {
+          const float* pw = part + (long long)((o - 1) * RT + rt) * PW * 64;
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) acc[rb][jb][r] += pw[((rb * JB + jb) * 4 + r) * 64 + lane];
+        } else {
+          const T* pt = reinterpret_cast<const T*>(part) + (long long)((o - 1) * RT + rt) * PW * 64;
+#pragma unroll
+          for (int q = 0; q < KG; ++q) {
+            ar[q] += pt[(2 * q) * 64 + lane];
+            ai[q] += pt[(2 * q + 1) * 64 + lane];
+          }
+        }
+      }
+    }
+  }
+  const int orow = row0 + lane;
+  if constexpr (MF) {
+    // regroup rows through LDS (the operand area, free once every wave is done)
+    __syncthreads();
+    float* st = reinterpret_cast<float*>(smem_raw) + (long long)rt * 64 * KG * 2;
+    if (cg == 0) {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int rl = 16 * rb + 4 * (lane >> 4) + r;
+            const int j = jb * 16 + (lane & 15);
+            st[((long long)(j >> 1) * 64 + rl) * 2 + (j & 1)] = acc[rb][jb][r];
+          }
+    }
+    __syncthreads();
+    if (cg == 0) {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        ar[q] = st[((long long)q * 64 + lane) * 2];
+        ai[q] = st[((long long)q * 64 + lane) * 2 + 1];
+      }
+    }
+  }
+  if (cg == 0 && orow < nb) {
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      const int rq = g * KG + q;
+      if (rq < nrhs) {
+        const long long oo = (long long)rq * nloc + (long long)blk * nb + orow;
+        const C out = mk(ar[q], ai[q]);
+        if (mode == BCR_KEPT) R[oo] = R[oo] + out;
+        else X[oo] = out;
+      }
+    }
   }
 }
 
@@ -1221,74 +1304,84 @@ void launch_bcr_dfwd(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int
 
 template <typename T>
 int bcr_kg(int max_nb, int kg) {
-  const bool rt3 = max_nb <= 192;
-  int cap;
-  if (std::is_same<T, float>::value) cap = rt3 ? 8 : 4;
-  else cap = rt3 ? 2 : 1;
+  (void)max_nb;
+  const int cap = std::is_same<T, float>::value ? 16 : 8;
   int k = 1;
   while (k * 2 <= kg && k * 2 <= cap) k *= 2;
   return k;
 }
 
-template <typename T>
-size_t bcr_lds_bytes(int max_nb, int kg) {
-  const int U = CH_ROUND_BYTES / (int)(2 * sizeof(T));
-  const int cw = (max_nb + CH_WAVES - 1) / CH_WAVES;
-  const int nr = (cw + U - 1) / U;
-  const size_t ncol = (size_t)CH_WAVES * nr * U;
-  const bool mf = std::is_same<T, float>::value && kg >= 2;
-  const int rt = max_nb <= 192 ? 3 : 4;
-  const size_t ops = mf ? 3 * (size_t)(kg / 2) * ncol * 4 * 2 * sizeof(T)
-                        : 3 * (size_t)kg * max_nb * sizeof(cpx<T>);
-  const size_t red = mf ? (size_t)CH_WAVES * rt * (kg / 2) * 4 * 64 * sizeof(float)
-                        : (size_t)CH_WAVES * kg * 64 * rt * sizeof(cpx<T>);
-  return ops + red;
+// Waves of a solve workgroup: RT 64-row tiles (a block's rows in row groups
+// of at most BCR_MAXRT tiles) times CG column groups.
+static inline void bcr_shape(int max_nb, long long tasks_per_rg, int& RT, int& CG, int& nrg) {
+  const int tiles = (max_nb + 63) / 64;
+  RT = tiles < BCR_MAXRT ? tiles : BCR_MAXRT;
+  nrg = (tiles + RT - 1) / RT;
+  const long long tasks = tasks_per_rg * nrg;
+  int cg = 1;
+  if (tasks < 512) cg = 4;
+  else if (tasks < 1024) cg = 2;
+  while (cg > 1 && RT * cg > BCR_MAXW) cg >>= 1;
+  CG = cg;
 }
 
-template <typename T, int KG, int RT>
-static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
+template <typename T>
+static size_t bcr_ops_bytes(int max_nb, int kg, int nset, int RT) {
+  const size_t ops = (size_t)nset * max_nb * kg * sizeof(cpx<T>);
+  const size_t stage = (size_t)RT * 64 * kg * sizeof(cpx<T>);
+  const size_t b = ops > stage ? ops : stage;
+  return (b + 255) / 256 * 256;
+}
+
+template <typename T>
+static size_t bcr_part_bytes(int kg, int RT, int CG) {
+  if (CG <= 1) return 0;
+  const bool mf = std::is_same<T, float>::value && kg >= 8;
+  const size_t per_lane = mf ? (size_t)16 * (kg / 8) * sizeof(float) : 2 * (size_t)kg * sizeof(T);
+  return (size_t)(CG - 1) * RT * 64 * per_lane;
+}
+
+// Largest LDS any launch of this shape family can ask for (CG up to 4).
+template <typename T>
+size_t bcr_lds_bytes(int max_nb, int kg, int nset) {
+  const int tiles = (max_nb + 63) / 64;
+  const int RT = tiles < BCR_MAXRT ? tiles : BCR_MAXRT;
+  int cg = 4;
+  while (cg > 1 && RT * cg > BCR_MAXW) cg >>= 1;
+  return bcr_ops_bytes<T>(max_nb, kg, nset, RT) + bcr_part_bytes<T>(kg, RT, cg);
+}
+
+template <typename T, int KG>
+static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset, int nrhs,
                          int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
                          cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  long long total = (long long)njobs * G;
+  int RT, CG, nrg;
+  bcr_shape(max_nb, (long long)njobs * G, RT, CG, nrg);
+  long long total = (long long)njobs * G * nrg;
   total = (total + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_bcr<T, KG, RT>), dim3((unsigned)total), dim3(CH_THREADS),
-                     bcr_lds_bytes<T>(max_nb, KG), s, d_subs, d_jobs, njobs, G, nrhs, kmax, fac,
-                     cpl, rpool, vpool, pool_stride);
-}
-
-template <typename T, int RT>
-static void launch_bcr_rt(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
-                          int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                          cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
-  if constexpr (std::is_same<T, float>::value) {
-    switch (kg) {
-      case 1: launch_bcr_k<T, 1, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-      case 2: launch_bcr_k<T, 2, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-      case 4: launch_bcr_k<T, 4, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-      default:
-        if constexpr (RT == 3) launch_bcr_k<T, 8, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
-        break;
-    }
-  } else {
-    if (kg >= 2) {
-      if constexpr (RT == 3) launch_bcr_k<T, 2, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
-    } else {
-      launch_bcr_k<T, 1, RT>(d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
-    }
-  }
+  const size_t ob = bcr_ops_bytes<T>(max_nb, KG, nset, RT);
+  const size_t lds = ob + bcr_part_bytes<T>(KG, RT, CG);
+  hipLaunchKernelGGL((k_bcr<T, KG>), dim3((unsigned)total), dim3(64 * RT * CG), lds, s, d_subs,
+                     d_jobs, njobs, G, nrg, RT, CG, nrhs, kmax, fac, cpl, rpool, vpool,
+                     pool_stride, (int)ob);
 }
 
 template <typename T>
-void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
-                      int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl, cpx<T>* rpool,
-                      cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset,
+                      int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                      cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0) return;
-  kg = bcr_kg<T>(max_nb, kg);
-  if (max_nb <= 192)
-    launch_bcr_rt<T, 3>(kg, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
-  else
-    launch_bcr_rt<T, 4>(kg, d_subs, d_jobs, njobs, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+  switch (bcr_kg<T>(max_nb, kg)) {
+    case 1: launch_bcr_k<T, 1>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 2: launch_bcr_k<T, 2>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 4: launch_bcr_k<T, 4>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 8: launch_bcr_k<T, 8>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    default:
+      if constexpr (std::is_same<T, float>::value)
+        launch_bcr_k<T, 16>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+      break;
+  }
 }
 
 // ============================================================================
@@ -1298,29 +1391,26 @@ void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int n
 // holds it; each cell is written by exactly one thread (no atomics).
 // ============================================================================
 template <typename T>
-__global__ void k_init_rhs(Problem P, const SubDesc* subs, const int2* members, int nrhs, int kmax,
+__global__ __launch_bounds__(256) void k_init_rhs(Problem P, const SubDesc* subs, const int2* members, int nrhs, int kmax,
                            const cpx<double>* f, cpx<T>* rpool, long long pool_stride) {
-  const int2 mb = members[blockIdx.z];
-  const SubDesc S = subs[mb.x];
-  const int first_sweep = mb.y == 0;
-  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (c >= S.nloc || r >= nrhs) return;
-  cpx<T> v = mk((T)0, (T)0);
-  if (first_sweep) {
-    const int ix = (int)(c % S.dims[0]);
-    const long long q = c / S.dims[0];
-    const int iy = (int)(q % S.dims[1]);
-    const int iz = (int)(q / S.dims[1]);
-    const int g[3] = {S.ax[0].g0 + ix, S.ax[1].g0 + iy, S.ax[2].g0 + iz};
-    bool own = true;
-    for (int a = 0; a < P.dim; ++a) own = own && g[a] >= S.pt[a].o0 && g[a] < S.pt[a].o1;
-    if (own) {
-      const long long gf = ((long long)g[2] * P.ng[1] + g[1]) * P.ng[0] + g[0];
-      v = cvt<T>(f[(long long)r * P.N + gf]);
-    }
+  const int2 mb = members[blockIdx.y];
+  const SubDesc& S = subs[mb.x];
+  const int nloc = (int)S.nloc;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nloc) return;
+  cpx<T>* R = rpool + (long long)mb.y * pool_stride + S.vec_off * kmax + c;
+  long long gf = -1;
+  if (mb.y == 0) {   // first sweep: f on the subdomain's own cells
+    const int nx = S.dims[0], ny = S.dims[1];
+    const int ix = c % nx, q = c / nx;
+    const int iy = q % ny, iz = q / ny;
+    const int g0 = S.ax[0].g0 + ix, g1 = S.ax[1].g0 + iy, g2 = S.ax[2].g0 + iz;
+    bool own = g0 >= S.pt[0].o0 && g0 < S.pt[0].o1 && g1 >= S.pt[1].o0 && g1 < S.pt[1].o1;
+    if (P.dim == 3) own = own && g2 >= S.pt[2].o0 && g2 < S.pt[2].o1;
+    if (own) gf = ((long long)g2 * P.ng[1] + g1) * P.ng[0] + g0;
   }
-  rpool[(long long)mb.y * pool_stride + S.vec_off * kmax + (long long)r * S.nloc + c] = v;
+  for (int r = 0; r < nrhs; ++r)
+    R[(long long)r * nloc] = gf >= 0 ? cvt<T>(f[(long long)r * P.N + gf]) : mk((T)0, (T)0);
 }
 
 template <typename T>
@@ -1328,7 +1418,7 @@ void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int2* d_memb
                      long long max_nloc, int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool,
                      long long pool_stride, hipStream_t s) {
   if (nmem <= 0 || nrhs <= 0) return;
-  dim3 grid(cdiv_u(max_nloc, 256), nrhs, nmem);
+  dim3 grid(cdiv_u(max_nloc, 256), nmem);
   hipLaunchKernelGGL(k_init_rhs<T>, grid, dim3(256), 0, s, P, d_subs, d_members, nrhs, kmax, f,
                      rpool, pool_stride);
 }
@@ -1339,59 +1429,28 @@ __device__ inline bool in_box(const Edge& e, const int c[3]) {
          c[2] >= e.lo[2] && c[2] < e.hi[2];
 }
 
-template <typename T>
-__device__ cpx<T> psi(const Problem& P, const SubDesc& Sd, const Edge& e, const int c[3], int r,
-                      int kmax, const cpx<T>* vpool, long long pool_stride, const cpx<T>* diag,
-                      const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz) {
-  // sender-local cell
-  int cs[3] = {c[0] + e.off[0], c[1] + e.off[1], c[2] + e.off[2]};
-  const int* dm = Sd.dims;
-  auto w_at = [&](int x, int y, int z) -> cpx<T> {
-    if (x < 0 || y < 0 || z < 0 || x >= dm[0] || y >= dm[1] || z >= dm[2]) return mk((T)0, (T)0);
-    const int gg[3] = {Sd.ax[0].g0 + x, Sd.ax[1].g0 + y, Sd.ax[2].g0 + z};
-    double beta = 1.0;
-    for (int a = 0; a < P.dim; ++a) beta *= cutoff(Sd.pt[a], e.t[a], gg[a], P.d);
-    if (beta == 0.0) return mk((T)0, (T)0);
-    const long long cell = ((long long)z * dm[1] + y) * dm[0] + x;
-    cpx<T> v = mk((T)0, (T)0);
-    for (int l = 0; l < 8; ++l)
-      if (e.lmask & (1u << l))
-        v = v + vpool[l * pool_stride + Sd.vec_off * kmax + (long long)r * Sd.nloc + cell];
-    return (T)beta * v;
-  };
-  const long long cc = ((long long)cs[2] * dm[1] + cs[1]) * dm[0] + cs[0];
-  const long long co = Sd.coef_off + cc;
-  cpx<T> acc = diag[co] * w_at(cs[0], cs[1], cs[2]);
-  if (cs[0] + 1 < dm[0]) acc = acc + cx[co] * w_at(cs[0] + 1, cs[1], cs[2]);
-  if (cs[0] > 0) acc = acc + cx[co - 1] * w_at(cs[0] - 1, cs[1], cs[2]);
-  if (cs[1] + 1 < dm[1]) acc = acc + cy[co] * w_at(cs[0], cs[1] + 1, cs[2]);
-  if (cs[1] > 0) acc = acc + cy[co - dm[0]] * w_at(cs[0], cs[1] - 1, cs[2]);
-  if (P.dim == 3) {
-    const long long plane = (long long)dm[0] * dm[1];
-    if (cs[2] + 1 < dm[2]) acc = acc + cz[co] * w_at(cs[0], cs[1], cs[2] + 1);
-    if (cs[2] > 0) acc = acc + cz[co - plane] * w_at(cs[0], cs[1], cs[2] - 1);
-  }
-  return -acc;
-}
+// Source transfer into receiver cell c (receiver-local coordinates) for a
+// group of up to PR right-hand sides starting at r0: for every incoming edge
+// whose box holds c, g = -M (beta_t v) evaluated with the sender's stencil and
+// the sender solutions of the sweeps in the edge's mask (Section 2.2).  The
+// stencil weights (coefficient times cutoff) are formed once per group.
+constexpr int PULL_R = 2;
 
 template <typename T>
-__global__ void k_pull(Problem P, const SubDesc* subs, const int2* members, const Edge* edges,
+__global__ __launch_bounds__(256) void k_pull(Problem P, const SubDesc* subs, const int2* members, const Edge* edges,
                        const int2* erange, int nrhs, int kmax, const cpx<T>* vpool,
                        long long pool_stride, const cpx<T>* diag, const cpx<T>* cx,
                        const cpx<T>* cy, const cpx<T>* cz, cpx<T>* rpool) {
   const int2 mb = members[blockIdx.z];
-  const int recv = mb.x;
   const int2 er = erange[blockIdx.z];
-  const int r = blockIdx.y;
-  if (r >= nrhs || er.y <= 0) return;
+  const int r0 = blockIdx.y * PULL_R;
+  if (r0 >= nrhs || er.y <= 0) return;
   const Edge* E = edges + er.x;
   const int ne = er.y;
-  long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  // locate (edge, cell) from the flat index over the concatenated boxes
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
   int eidx = -1;
   for (int e = 0; e < ne; ++e) {
-    const long long vol = (long long)(E[e].hi[0] - E[e].lo[0]) * (E[e].hi[1] - E[e].lo[1]) *
-                          (E[e].hi[2] - E[e].lo[2]);
+    const int vol = (E[e].hi[0] - E[e].lo[0]) * (E[e].hi[1] - E[e].lo[1]) * (E[e].hi[2] - E[e].lo[2]);
     if (f < vol) { eidx = e; break; }
     f -= vol;
   }
@@ -1399,22 +1458,62 @@ __global__ void k_pull(Problem P, const SubDesc* subs, const int2* members, cons
   const Edge& e0 = E[eidx];
   const int bx = e0.hi[0] - e0.lo[0], by = e0.hi[1] - e0.lo[1];
   int c[3];
-  c[0] = e0.lo[0] + (int)(f % bx);
-  const long long q = f / bx;
-  c[1] = e0.lo[1] + (int)(q % by);
-  c[2] = e0.lo[2] + (int)(q / by);
+  c[0] = e0.lo[0] + f % bx;
+  const int q = f / bx;
+  c[1] = e0.lo[1] + q % by;
+  c[2] = e0.lo[2] + q / by;
   for (int e = 0; e < eidx; ++e)
     if (in_box<T>(E[e], c)) return;          // an earlier box owns this cell
-  const SubDesc R = subs[recv];
-  cpx<T> sum = mk((T)0, (T)0);
+  cpx<T> acc[PULL_R];
+#pragma unroll
+  for (int k = 0; k < PULL_R; ++k) acc[k] = mk((T)0, (T)0);
+  const int nst = P.dim == 3 ? 7 : 5;
   for (int e = eidx; e < ne; ++e) {
-    if (!in_box<T>(E[e], c)) continue;
-    const SubDesc Sd = subs[E[e].sender];
-    sum = sum + psi<T>(P, Sd, E[e], c, r, kmax, vpool, pool_stride, diag, cx, cy, cz);
+    const Edge& ed = E[e];
+    if (!in_box<T>(ed, c)) continue;
+    const SubDesc& Sd = subs[ed.sender];
+    const int dm0 = Sd.dims[0], dm1 = Sd.dims[1], dm2 = Sd.dims[2];
+    const int cs0 = c[0] + ed.off[0], cs1 = c[1] + ed.off[1], cs2 = c[2] + ed.off[2];
+    const long long co = Sd.coef_off + ((long long)cs2 * dm1 + cs1) * dm0 + cs0;
+    const long long plane = (long long)dm0 * dm1;
+    const cpx<T>* V = vpool + Sd.vec_off * kmax;
+    for (int st = 0; st < nst; ++st) {
+      // stencil point: 0 centre, 1/2 +-x, 3/4 +-y, 5/6 +-z
+      int p0 = cs0, p1 = cs1, p2 = cs2;
+      cpx<T> a;
+      if (st == 0) { a = diag[co]; }
+      else if (st == 1) { if (cs0 + 1 >= dm0) continue; p0 += 1; a = cx[co]; }
+      else if (st == 2) { if (cs0 <= 0) continue; p0 -= 1; a = cx[co - 1]; }
+      else if (st == 3) { if (cs1 + 1 >= dm1) continue; p1 += 1; a = cy[co]; }
+      else if (st == 4) { if (cs1 <= 0) continue; p1 -= 1; a = cy[co - dm0]; }
+      else if (st == 5) { if (cs2 + 1 >= dm2) continue; p2 += 1; a = cz[co]; }
+      else { if (cs2 <= 0) continue; p2 -= 1; a = cz[co - plane]; }
+      double beta = cutoff(Sd.pt[0], ed.t[0], Sd.ax[0].g0 + p0, P.d) *
+                    cutoff(Sd.pt[1], ed.t[1], Sd.ax[1].g0 + p1, P.d);
+      if (P.dim == 3) beta *= cutoff(Sd.pt[2], ed.t[2], Sd.ax[2].g0 + p2, P.d);
+      if (beta == 0.0) continue;
+      const cpx<T> wgt = (T)beta * a;
+      const long long cell = ((long long)p2 * dm1 + p1) * dm0 + p0;
+#pragma unroll
+      for (int k = 0; k < PULL_R; ++k) {
+        const int r = r0 + k;
+        if (r < nrhs) {
+          cpx<T> v = mk((T)0, (T)0);
+          for (int l = 0; l < 8; ++l)
+            if (ed.lmask & (1u << l)) v = v + V[l * pool_stride + (long long)r * Sd.nloc + cell];
+          acc[k] = acc[k] + wgt * v;
+        }
+      }
+    }
   }
+  const SubDesc& R = subs[mb.x];
   const long long cell = ((long long)c[2] * R.dims[1] + c[1]) * R.dims[0] + c[0];
-  const long long o = (long long)mb.y * pool_stride + R.vec_off * kmax + (long long)r * R.nloc + cell;
-  rpool[o] = rpool[o] + sum;
+  cpx<T>* out = rpool + (long long)mb.y * pool_stride + R.vec_off * kmax + cell;
+#pragma unroll
+  for (int k = 0; k < PULL_R; ++k) {
+    const int r = r0 + k;
+    if (r < nrhs) out[(long long)r * R.nloc] = out[(long long)r * R.nloc] - acc[k];
+  }
 }
 
 template <typename T>
@@ -1424,7 +1523,7 @@ void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members,
                  const cpx<T>* diag, const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz,
                  cpx<T>* rpool, hipStream_t s) {
   if (nmem <= 0 || nrhs <= 0 || max_box_cells <= 0) return;
-  dim3 grid(cdiv_u(max_box_cells, 256), nrhs, nmem);
+  dim3 grid(cdiv_u(max_box_cells, 256), (nrhs + PULL_R - 1) / PULL_R, nmem);
   hipLaunchKernelGGL(k_pull<T>, grid, dim3(256), 0, s, P, d_subs, d_members, d_edges,
                      d_edge_range, nrhs, kmax, vpool, pool_stride, diag, cx, cy, cz, rpool);
 }
@@ -1794,14 +1893,14 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
                                      int*, hipStream_t);                                         \
   template void launch_bcr_copy<T>(const BcrCopyJob*, int, int, const cpx<double>*, cpx<T>*,    \
                                    hipStream_t);                                                 \
-  template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int,     \
+  template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int, int,\
                                     const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, long long,   \
                                     hipStream_t);                                                \
   template void launch_bcr_dfwd<T>(const SubDesc*, const BcrJob*, int, int, int, int,           \
                                    const cpx<T>*, cpx<T>*, const cpx<T>*, long long,            \
                                    hipStream_t);                                                 \
   template int bcr_kg<T>(int, int);                                                             \
-  template size_t bcr_lds_bytes<T>(int, int);                                                   \
+  template size_t bcr_lds_bytes<T>(int, int, int);                                              \
   template void launch_pack_local<T>(const cpx<double>*, cpx<T>*, long long, int, int,          \
                                      hipStream_t);                                               \
   template void launch_unpack_local<T>(const cpx<T>*, cpx<double>*, long long, int, int,        \

@@ -98,10 +98,11 @@ struct BcrJob {
   int nl, nr, pad0, pad1;     // neighbour blocks (-1: none)
   long long m0, m1, m2;       // factor element offsets of the matrices
 };
+// nset: most operand vectors a job of the launch uses (LDS is sized for it)
 template <typename T>
-void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs,
-                      int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl, cpx<T>* rpool,
-                      cpx<T>* vpool, long long pool_stride, hipStream_t s);
+void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset,
+                      int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+                      cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s);
 template <typename T>
 void launch_bcr_dfwd(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs, int kmax,
                      int max_nb, const cpx<T>* cpl, cpx<T>* rpool, const cpx<T>* vpool,
@@ -110,7 +111,7 @@ void launch_bcr_dfwd(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int
 template <typename T>
 int bcr_kg(int max_nb, int kg);
 template <typename T>
-size_t bcr_lds_bytes(int max_nb, int kg);
+size_t bcr_lds_bytes(int max_nb, int kg, int nset);
 
 // Batched FP64 complex GEMM on working blocks: C = beta C + alpha op(A) op(B),
 // nb x nb column-major; op transposes when ta / tb is set; beta is 0 or 1.

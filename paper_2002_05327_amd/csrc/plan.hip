@@ -125,6 +125,7 @@ struct BcrSub {
 struct BcrLaunch {
   int off, n;        // job range
   int dfwd;          // 1: level-0 coupling update (vector kernel)
+  int nset;          // most matrices (operand vectors) of one job
   double fbytes;     // factor bytes streamed (once per launch)
   double vcells;     // vector entries read and written per right-hand side
 };
@@ -690,7 +691,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   int maxtop = 0;
   for (const int2& m : mem) maxtop = std::max(maxtop, pl->bcr[m.x].top);
   const double ts = (double)tsize(pl);
-  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 0.0, 0.0}; };
+  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, 0.0, 0.0}; };
   auto finish = [&](BcrLaunch& L) {
     L.n = (int)jobs.size() - L.off;
     if (L.n > 0) out.push_back(L);
@@ -698,6 +699,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   auto add = [&](BcrLaunch& L, const int2& m, int blk, int mode, int nl, int nr, long long m0,
                  long long m1, long long m2, int nmat, int nvec) {
     jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, 0, 0, m0, m1, m2});
+    L.nset = std::max(L.nset, nmat);
     const SubDesc& S = pl->subs[m.x];
     L.fbytes += (double)nmat * S.nb * S.nb * ts;
     L.vcells += (double)nvec * S.nb;
@@ -975,7 +977,7 @@ void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
     return;
   }
   if (pl->timing) (void)hipEventRecord(pl->ev0, st);
-  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, nrhs, pl->kmax,
+  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, nrhs, pl->kmax,
                       pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
   if (pl->timing) {
     (void)hipEventRecord(pl->ev1, st);
@@ -1264,7 +1266,7 @@ int choose_kg(const dsd_plan* pl, int want) {
   if (pl->solver == 2) {
     int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
     auto need = [&](int k) {
-      return pl->c64 ? bcr_lds_bytes<float>(pl->max_nb, k) : bcr_lds_bytes<double>(pl->max_nb, k);
+      return pl->c64 ? bcr_lds_bytes<float>(pl->max_nb, k, 3) : bcr_lds_bytes<double>(pl->max_nb, k, 3);
     };
     while (kg > 1 && need(kg) > (size_t)lds) kg >>= 1;
     return need(kg) > (size_t)lds ? 0 : kg;
@@ -1332,7 +1334,7 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
     }
   }
   if (rc == 0) {
-    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : (pl->solver == 2 ? 4 : 2));
+    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : (pl->solver == 2 ? 8 : 2));
     if (pl->kg == 0) {
       g_detail = "subdomain blocks too large for the solve kernel's LDS";
       rc = DSD_EINVAL;
