@@ -77,7 +77,9 @@ def _roofline(plan, b):
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_chain (block solves)", "launches": t["solve_launches"],
+            "kernel": {"bcr": "k_bcr (block cyclic reduction solves)",
+                       "chain": "k_chain (block LDL^T chain solves)"}[plan.local_solver],
+            "launches": t["solve_launches"],
             "avg_launch_ms": round(avg_ms, 4), "avg_launch_bytes": avg_bytes}
 
 

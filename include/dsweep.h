@@ -94,6 +94,10 @@ void dsd_destroy(dsd_plan* plan);
 int dsd_plan_info(const dsd_plan* plan, long long* n_global, int* n_subdomains,
                   long long* factor_bytes, long long* workspace_bytes);
 
+/* Local solver in use: 1 = twisted block LDL^T chains, 2 = block cyclic reduction
+ * (dsd_params.local_solver after the automatic choice); negative on a NULL plan. */
+int dsd_plan_local_solver(const dsd_plan* plan);
+
 /* Local grid of subdomain `sub` (lexicographic index, x part fastest):
  * dims[3] = local cells per axis, g0[3] = global array index of its first cell
  * per axis (local PML cells included). */
@@ -110,8 +114,9 @@ int dsd_local_solve(dsd_plan* plan, int sub, const double* r_dev, double* u_dev,
 
 /*
  * One application of the diagonal-sweeping DDM (Algorithm 3.1 in 2D, 4.1 in
- * 3D): 2^dim sweeps; in every step all subdomains of the anti-diagonal are
- * solved in one batched launch, the source-transfer operator Psi passes the
+ * 3D): 2^dim sweeps; every subdomain solve is launched, batched with all other
+ * solves of its dependency level (schedule 0) or of its anti-diagonal step
+ * (schedule 1), as soon as its sources exist; the source-transfer operator Psi passes the
  * cutoff-weighted sources to the neighbours (Section 2.2) routed by Rules
  * 3.1/3.2 (4.1/4.2), and u_DDM = sum beta_{0;ij} u_ij (eq. (eq:sumdiag2D),
  * (eq:sumdiag3D)) is accumulated in FP64.

@@ -176,6 +176,10 @@ class Plan:
         return J.value, g
 
     # -------------------------------------------------------------- timing
+    @property
+    def local_solver(self) -> str:
+        return {1: "chain", 2: "bcr"}[self._lib.dsd_plan_local_solver(self._h)]
+
     def timing(self, on: bool):
         check(self._lib.dsd_timing_enable(self._h, int(bool(on))), "dsd_timing_enable")
 

@@ -1380,6 +1380,8 @@ int dsd_plan_info(const dsd_plan* pl, long long* n_global, int* n_subdomains,
   return DSD_OK;
 }
 
+int dsd_plan_local_solver(const dsd_plan* pl) { return pl ? pl->solver : DSD_EINVAL; }
+
 int dsd_subdomain_grid(const dsd_plan* pl, int sub, int* dims, int* g0) {
   if (!pl || sub < 0 || sub >= pl->S) return DSD_EINVAL;
   for (int a = 0; a < 3; ++a) {
