@@ -63,7 +63,37 @@ def _solve_steps(plan, b, tol, maxit, restart, warmup, steps):
     return dt, its, rel, ok
 
 
-def _roofline(plan, b):
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bcr_c2_traffic.md")
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2002_05327_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def _measured_traffic(workload):
+    """HBM bytes per solve-kernel dispatch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the counter
+    reads for a 1 GiB device copy); None when the summary was taken on another
+    workload or before the kernels last changed."""
+    try:
+        vals = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    vals[k.strip()] = v.strip().strip("`")
+        if vals.get("workload") != workload or vals.get("kernels.hip sha256") != _kernel_source_hash():
+            return None
+        return float(vals["HBM bytes per dispatch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def _roofline(plan, b, workload):
     """Average duration and algorithmic bytes of the subdomain-solve launches
     over one preconditioner application, timed with HIP events on the plan's stream."""
     import torch
@@ -76,11 +106,13 @@ def _roofline(plan, b):
     avg_bytes = t["solve_bytes"] / max(1, t["solve_launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": _measured_traffic(workload),
             "kernel": {"bcr": "k_bcr (block cyclic reduction solves)",
                        "chain": "k_chain (block LDL^T chain solves)"}[plan.local_solver],
             "launches": t["solve_launches"],
-            "avg_launch_ms": round(avg_ms, 4), "avg_launch_bytes": avg_bytes}
+            "avg_launch_ms": round(avg_ms, 4), "avg_launch_bytes": round(avg_bytes),
+            "traffic_unit": "HBM bytes per dispatch"}
 
 
 def _cpu_baseline(w, c, F):
@@ -145,7 +177,7 @@ def main():
                                             args.warmup, args.steps)
     print(f"# c64 solve {dt64 / args.steps * 1e3:.1f} ms/step iters {its64}", file=sys.stderr,
           flush=True)
-    roof = _roofline(plan64, b)
+    roof = _roofline(plan64, b, w.name)
     info64 = plan64.info()
     plan64.close()
     del plan64

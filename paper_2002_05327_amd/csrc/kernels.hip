@@ -960,12 +960,12 @@ void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* wo
 // waves: wave (rt, cg) owns the 64-row tile rt and the columns
 // [cg cw, (cg+1) cw) of each of the (up to three) matrices of the job,
 //   out = sum_m M_m v_m   (+ R_blk for BCR_KEPT),
-// and the CG partial sums of a tile meet in LDS (CG = 1 when the launch has
-// enough tasks to fill the chip; more column groups shorten the per-task
-// latency chain of the small, deep reduction levels).  The operand vectors
+// and the CG partial sums of a tile meet in LDS (CG = 1 on the wide levels;
+// more column groups shorten the per-task latency chain of the small, deep
+// reduction levels).  The operand vectors
 // v_m are staged in LDS as [column][KG] complex values; the first round of
 // matrix loads is issued before the staging, and every round keeps the next
-// one in flight.
+// one in flight.  CG is set per reduction level by the caller.
 //
 // complex64 with KG = 8 or 16 runs on v_mfma_f32_16x16x4f32 (A: lane l holds
 // row l%16, column l/16 of a 16x4 tile; B: lane l holds k = l/16, output
@@ -1020,9 +1020,12 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rt = w % RT, cg = w / RT;
   const int row0 = (rg * RT + rt) * 64;
+  // CG wave groups split the columns (CG depends on the job's reduction level
+  // only, so a job's summation order is the same in every schedule)
   int cw = (nb + CG - 1) / CG;
   cw = (cw + 3) & ~3;
-  const int c0 = cg * cw;
+  const int wc0 = 0, wc1 = nb;
+  const int c0 = min(nb, cg * cw);
   const int c1 = min(nb, c0 + cw);
   const bool wave_live = row0 < nb && c0 < c1;
   const C zero = mk((T)0, (T)0);
@@ -1081,13 +1084,14 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   extern __shared__ unsigned char smem_raw[];
   C* ops = reinterpret_cast<C*>(smem_raw);
   const long long ss = (long long)nb * KG;
-  const int nel = nb * KG;
+  const int wcn = wc1 - wc0;                        // only this workgroup's columns are staged
+  const int nel = wcn * KG;
   for (int base = 0; base < nel; base += BCR_STAGE * (int)blockDim.x) {
     C va[BCR_STAGE], vb[BCR_STAGE], vc[BCR_STAGE];
 #pragma unroll
     for (int k = 0; k < BCR_STAGE; ++k) {
       const int idx = base + k * (int)blockDim.x + tid;
-      const int q = idx / nb, i = idx - q * nb;
+      const int q = idx / (wcn > 0 ? wcn : 1), i = wc0 + idx - q * wcn;
       const int rq = g * KG + q;
       const bool live = idx < nel && rq < nrhs;
       const long long ro = (long long)rq * nloc;
@@ -1109,7 +1113,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
     for (int k = 0; k < BCR_STAGE; ++k) {
       const int idx = base + k * (int)blockDim.x + tid;
       if (idx >= nel) break;
-      const int q = idx / nb, i = idx - q * nb;
+      const int q = idx / wcn, i = wc0 + idx - q * wcn;
       C* o = ops + (long long)i * KG + q;
       if (mode == BCR_KEPT) {
         if (hl) o[0] = -va[k];
@@ -1313,16 +1317,12 @@ int bcr_kg(int max_nb, int kg) {
 
 // Waves of a solve workgroup: RT 64-row tiles (a block's rows in row groups
 // of at most BCR_MAXRT tiles) times CG column groups.
-static inline void bcr_shape(int max_nb, long long tasks_per_rg, int& RT, int& CG, int& nrg) {
+static inline void bcr_shape(int max_nb, int cg, int& RT, int& CG, int& nrg) {
   const int tiles = (max_nb + 63) / 64;
   RT = tiles < BCR_MAXRT ? tiles : BCR_MAXRT;
   nrg = (tiles + RT - 1) / RT;
-  const long long tasks = tasks_per_rg * nrg;
-  int cg = 1;
-  if (tasks < 512) cg = 4;
-  else if (tasks < 1024) cg = 2;
-  while (cg > 1 && RT * cg > BCR_MAXW) cg >>= 1;
-  CG = cg;
+  CG = cg < 1 ? 1 : cg;
+  while (CG > 1 && RT * CG > BCR_MAXW) CG >>= 1;
 }
 
 template <typename T>
@@ -1352,12 +1352,12 @@ size_t bcr_lds_bytes(int max_nb, int kg, int nset) {
 }
 
 template <typename T, int KG>
-static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset, int nrhs,
-                         int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
+static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset, int cg,
+                         int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
                          cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
   int RT, CG, nrg;
-  bcr_shape(max_nb, (long long)njobs * G, RT, CG, nrg);
+  bcr_shape(max_nb, cg, RT, CG, nrg);
   long long total = (long long)njobs * G * nrg;
   total = (total + 7) / 8 * 8;
   const size_t ob = bcr_ops_bytes<T>(max_nb, KG, nset, RT);
@@ -1369,17 +1369,18 @@ static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs,
 
 template <typename T>
 void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset,
-                      int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                      cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+                      int cg, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
+                      const cpx<T>* cpl, cpx<T>* rpool, cpx<T>* vpool, long long pool_stride,
+                      hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0) return;
   switch (bcr_kg<T>(max_nb, kg)) {
-    case 1: launch_bcr_k<T, 1>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-    case 2: launch_bcr_k<T, 2>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-    case 4: launch_bcr_k<T, 4>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-    case 8: launch_bcr_k<T, 8>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 1: launch_bcr_k<T, 1>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 2: launch_bcr_k<T, 2>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 4: launch_bcr_k<T, 4>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 8: launch_bcr_k<T, 8>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
     default:
       if constexpr (std::is_same<T, float>::value)
-        launch_bcr_k<T, 16>(d_subs, d_jobs, njobs, nset, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+        launch_bcr_k<T, 16>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
       break;
   }
 }
@@ -1894,8 +1895,8 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
   template void launch_bcr_copy<T>(const BcrCopyJob*, int, int, const cpx<double>*, cpx<T>*,    \
                                    hipStream_t);                                                 \
   template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int, int,\
-                                    const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*, long long,   \
-                                    hipStream_t);                                                \
+                                    int, const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*,         \
+                                    long long, hipStream_t);                                     \
   template void launch_bcr_dfwd<T>(const SubDesc*, const BcrJob*, int, int, int, int,           \
                                    const cpx<T>*, cpx<T>*, const cpx<T>*, long long,            \
                                    hipStream_t);                                                 \

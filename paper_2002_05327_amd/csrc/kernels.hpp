@@ -98,11 +98,13 @@ struct BcrJob {
   int nl, nr, pad0, pad1;     // neighbour blocks (-1: none)
   long long m0, m1, m2;       // factor element offsets of the matrices
 };
-// nset: most operand vectors a job of the launch uses (LDS is sized for it)
+// nset: most operand vectors a job of the launch uses (LDS is sized for it);
+// cg: wave groups splitting the columns of every job (1, 2 or 4).
 template <typename T>
 void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset,
-                      int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                      cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s);
+                      int cg, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
+                      const cpx<T>* cpl, cpx<T>* rpool, cpx<T>* vpool, long long pool_stride,
+                      hipStream_t s);
 template <typename T>
 void launch_bcr_dfwd(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nrhs, int kmax,
                      int max_nb, const cpx<T>* cpl, cpx<T>* rpool, const cpx<T>* vpool,

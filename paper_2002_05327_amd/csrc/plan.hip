@@ -126,6 +126,7 @@ struct BcrLaunch {
   int off, n;        // job range
   int dfwd;          // 1: level-0 coupling update (vector kernel)
   int nset;          // most matrices (operand vectors) of one job
+  int cg;            // wave groups splitting the columns (from the level only)
   double fbytes;     // factor bytes streamed (once per launch)
   double vcells;     // vector entries read and written per right-hand side
 };
@@ -691,7 +692,18 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   int maxtop = 0;
   for (const int2& m : mem) maxtop = std::max(maxtop, pl->bcr[m.x].top);
   const double ts = (double)tsize(pl);
-  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, 0.0, 0.0}; };
+  int maxblk = 1;
+  for (const SubDesc& S : pl->subs) maxblk = std::max(maxblk, S.nblk);
+  // Column groups of a level: wide levels (many blocks per subdomain) keep one
+  // wave per row tile; the deep levels split the columns to shorten each job.
+  // It depends on the level and the plan only, never on the launch, so every
+  // schedule sums every job in the same order.
+  auto level_cg = [&](int lev) {
+    const int per_sub = maxblk >> (lev + 1);
+    return per_sub >= 32 ? 1 : (per_sub >= 8 ? 2 : 4);
+  };
+  int cur_cg = 1;
+  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, cur_cg, 0.0, 0.0}; };
   auto finish = [&](BcrLaunch& L) {
     L.n = (int)jobs.size() - L.off;
     if (L.n > 0) out.push_back(L);
@@ -706,6 +718,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   };
   auto Pk = [&](const SubDesc& S, int k) { return S.fac_off + (long long)k * S.nb * S.nb; };
   for (int f = 0; f < maxtop; ++f) {
+    cur_cg = level_cg(f);
     if (f == 0) {
       BcrLaunch L = begin(0);
       for (const int2& m : mem) {
@@ -739,6 +752,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
     finish(L);
   }
   for (int b = maxtop; b >= 0; --b) {
+    cur_cg = level_cg(b);
     BcrLaunch L = begin(0);
     for (const int2& m : mem) {
       const BcrSub& B = pl->bcr[m.x];
@@ -977,8 +991,8 @@ void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
     return;
   }
   if (pl->timing) (void)hipEventRecord(pl->ev0, st);
-  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, nrhs, pl->kmax,
-                      pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
+  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, nrhs,
+                      pl->kmax, pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
   if (pl->timing) {
     (void)hipEventRecord(pl->ev1, st);
     (void)hipEventSynchronize(pl->ev1);
