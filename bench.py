@@ -209,10 +209,11 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(dt64 / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.n[0]}x{w.n[1]} layered medium, omega=2pi*"
-                               f"{w.omega / (2 * math.pi):g}, {w.parts[0]}x{w.parts[1]} "
-                               f"subdomains, PML {w.pml}, overlap {w.overlap}, {w.nrhs} RHS, "
-                               f"FGMRES to {args.tol:g}",
+        "config": {"workload": f"{w.name}: {'x'.join(map(str, w.n))} {w.medium} medium, "
+                               f"omega=2pi*{w.omega / (2 * math.pi):g}, "
+                               f"{'x'.join(map(str, w.parts))} subdomains, PML {w.pml}, overlap "
+                               f"{w.overlap}, {w.nrhs} RHS, FGMRES(restart {args.restart}) to "
+                               f"{args.tol:g}",
                    "global_batch": w.nrhs, "precision": "c64 factors + FP64 refinement"},
         "iters": its64, "max_relres": max(rel64), "converged": ok64,
         "factor_s": round(tf64, 3), "factor_bytes": info64["factor_bytes"],

@@ -1013,9 +1013,8 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   const int rem = Lg - job * tpj;
   const int g = rem / nrg, rg = rem - (rem / nrg) * nrg;
   const BcrJob J = jobs[job];
-  const SubDesc& S = subs[J.sub];
-  const int nb = S.nb;
-  const long long nloc = S.nloc;
+  const int nb = J.nb;
+  const long long nloc = J.nloc;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int rt = w % RT, cg = w / RT;
@@ -1029,9 +1028,9 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   const int c1 = min(nb, c0 + cw);
   const bool wave_live = row0 < nb && c0 < c1;
   const C zero = mk((T)0, (T)0);
-  C* __restrict__ X = vpool + (long long)J.l * pool_stride + S.vec_off * kmax;
-  C* __restrict__ R = rpool + (long long)J.l * pool_stride + S.vec_off * kmax;
-  const C* __restrict__ Cp = cpl + S.coef_off;
+  C* __restrict__ X = vpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  const C* __restrict__ Cp = cpl + J.cbase;
   const V2* __restrict__ Fv = reinterpret_cast<const V2*>(fac);
   const int mode = J.mode, blk = J.blk;
   const bool hl = J.nl >= 0, hr = J.nr >= 0;
@@ -1074,17 +1073,18 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
       }
       col = col < c1 ? col : c1 - 1;
       rw = rw < nb ? rw : nb - 1;
-      buf[u] = Mv[(long long)col * nb + rw];
+      buf[u] = Mv[(unsigned)(col * nb + rw)];
     }
   };
-  V2 cur[U], nxt[U];
-  if (wave_live) issue(cur, 0);
+  V2 bufA[U], bufB[U];
+  if (wave_live) issue(bufA, 0);
 
   // ---- operands: set m at ops + m * nb * KG, [column][KG]; loads batched
   extern __shared__ unsigned char smem_raw[];
   C* ops = reinterpret_cast<C*>(smem_raw);
-  const long long ss = (long long)nb * KG;
-  const int wcn = wc1 - wc0;                        // only this workgroup's columns are staged
+  const int nb4 = (nb + 3) & ~3;                    // operand columns, zero beyond nb
+  const long long ss = (long long)nb4 * KG;
+  const int wcn = (wc1 == nb ? nb4 : wc1) - wc0;
   const int nel = wcn * KG;
   for (int base = 0; base < nel; base += BCR_STAGE * (int)blockDim.x) {
     C va[BCR_STAGE], vb[BCR_STAGE], vc[BCR_STAGE];
@@ -1093,7 +1093,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
       const int idx = base + k * (int)blockDim.x + tid;
       const int q = idx / (wcn > 0 ? wcn : 1), i = wc0 + idx - q * wcn;
       const int rq = g * KG + q;
-      const bool live = idx < nel && rq < nrhs;
+      const bool live = idx < nel && rq < nrhs && i < nb;
       const long long ro = (long long)rq * nloc;
       va[k] = vb[k] = vc[k] = zero;
       if (live) {
@@ -1124,8 +1124,10 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
         if (hr) o[hl ? 2 * ss : ss] = -vc[k];
       } else if (mode == BCR_BWD0) {
         C y = va[k];
-        if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * vb[k];
-        if (hr) y = y - Cp[(long long)blk * nb + i] * vc[k];
+        if (i < nb) {
+          if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * vb[k];
+          if (hr) y = y - Cp[(long long)blk * nb + i] * vc[k];
+        }
         o[0] = y;
       } else {
         o[0] = va[k];
@@ -1142,55 +1144,61 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
     for (int jb = 0; jb < JB; ++jb) acc[rb][jb] = mf4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int q = 0; q < KG; ++q) { ar[q] = (T)0; ai[q] = (T)0; }
-  if (wave_live) {
-    for (int gr = 0; gr < total_rounds; ++gr) {
-      if (gr + 1 < total_rounds) issue(nxt, gr + 1);
-      const int m = gr / nr, rd = gr - (gr / nr) * nr;
-      const C* __restrict__ op = ops + m * ss;
-      if constexpr (MF) {
+  const int jsel = lane & 15;                 // MF: output column of this lane
+  auto compute = [&](const V2 (&buf)[U], int gr) {
+    const int m = gr / nr, rd = gr - (gr / nr) * nr;
+    const C* __restrict__ op = ops + m * ss;
+    const int cbase = c0 + rd * cpr;
+    if constexpr (MF) {
 #pragma unroll
-        for (int ug = 0; ug < UG; ++ug) {
-          const int col = c0 + rd * cpr + 4 * ug + lcol;   // this lane's k
-          const bool ok = col < c1;
-          const int cc = ok ? col : 0;
-          float bre[JB], bim[JB];
+      for (int ug = 0; ug < UG; ++ug) {
+        if (cbase + 4 * ug >= c1) break;        // wave-uniform; operands are zero past nb
+        const int col = cbase + 4 * ug + lcol;  // this lane's k
+        float bre[JB], bim[JB];
 #pragma unroll
-          for (int jb = 0; jb < JB; ++jb) {
-            const int j = jb * 16 + (lane & 15);
-            const C y = op[(long long)cc * KG + (j >> 1)];
-            const bool im = j & 1;
-            bre[jb] = ok ? (im ? y.im : y.re) : 0.f;
-            bim[jb] = ok ? (im ? y.re : -y.im) : 0.f;
-          }
-#pragma unroll
-          for (int jb = 0; jb < JB; ++jb) {
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-              acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)cur[4 * ug + rb].x, bre[jb], acc[rb][jb], 0, 0, 0);
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-              acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)cur[4 * ug + rb].y, bim[jb], acc[rb][jb], 0, 0, 0);
-          }
+        for (int jb = 0; jb < JB; ++jb) {
+          const int j = jb * 16 + jsel;
+          const C y = op[col * KG + (j >> 1)];
+          const bool im = j & 1;
+          bre[jb] = im ? y.im : y.re;
+          bim[jb] = im ? y.re : -y.im;
         }
-      } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int col = c0 + rd * cpr + u;
-          const bool ok = col < c1;
-          const int cc = ok ? col : 0;
+        for (int jb = 0; jb < JB; ++jb) {
 #pragma unroll
-          for (int q = 0; q < KG; ++q) {
-            const C y = op[(long long)cc * KG + q];
-            const T yr = ok ? y.re : (T)0, yi = ok ? y.im : (T)0;
-            ar[q] = fma(cur[u].x, yr, ar[q]);
-            ar[q] = fma(-cur[u].y, yi, ar[q]);
-            ai[q] = fma(cur[u].x, yi, ai[q]);
-            ai[q] = fma(cur[u].y, yr, ai[q]);
-          }
+          for (int rb = 0; rb < 4; ++rb)
+            acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)buf[4 * ug + rb].x, bre[jb], acc[rb][jb], 0, 0, 0);
+#pragma unroll
+          for (int rb = 0; rb < 4; ++rb)
+            acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)buf[4 * ug + rb].y, bim[jb], acc[rb][jb], 0, 0, 0);
         }
       }
+    } else {
 #pragma unroll
-      for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+      for (int u = 0; u < U; ++u) {
+        const int col = cbase + u;
+        if (col >= c1) break;                    // wave-uniform
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          const C y = op[col * KG + q];
+          ar[q] = fma(buf[u].x, y.re, ar[q]);
+          ar[q] = fma(-buf[u].y, y.im, ar[q]);
+          ai[q] = fma(buf[u].x, y.im, ai[q]);
+          ai[q] = fma(buf[u].y, y.re, ai[q]);
+        }
+      }
+    }
+  };
+  if (wave_live) {
+    // ping-pong: one buffer is computed while the other one's loads are in flight
+    for (int gr = 0; gr < total_rounds; gr += 2) {
+      const bool two = gr + 1 < total_rounds;
+      if (two) issue(bufB, gr + 1);
+      compute(bufA, gr);
+      if (two) {
+        if (gr + 2 < total_rounds) issue(bufA, gr + 2);
+        compute(bufB, gr + 1);
+      }
     }
   }
   // ---- column-group partial sums meet in LDS (after the operand area)
@@ -1327,7 +1335,7 @@ static inline void bcr_shape(int max_nb, int cg, int& RT, int& CG, int& nrg) {
 
 template <typename T>
 static size_t bcr_ops_bytes(int max_nb, int kg, int nset, int RT) {
-  const size_t ops = (size_t)nset * max_nb * kg * sizeof(cpx<T>);
+  const size_t ops = (size_t)nset * ((max_nb + 3) & ~3) * kg * sizeof(cpx<T>);
   const size_t stage = (size_t)RT * 64 * kg * sizeof(cpx<T>);
   const size_t b = ops > stage ? ops : stage;
   return (b + 255) / 256 * 256;
@@ -1534,56 +1542,85 @@ void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members,
 // from the (at most two per axis) subdomains whose cutoff support covers it.
 // ============================================================================
 template <typename T>
-__global__ void k_assemble_u(Problem P, const SubDesc* subs, PartTables pt, int nsweeps, int nrhs,
-                             int kmax, const cpx<T>* vpool, long long pool_stride,
-                             cpx<double>* u) {
-  const long long gflat = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (gflat >= P.N || r >= nrhs) return;
+__global__ __launch_bounds__(256) void k_assemble_u(Problem P, const SubDesc* subs, PartTables pt,
+                                                    int nsweeps, int nrhs, int kmax,
+                                                    const cpx<T>* __restrict__ vpool,
+                                                    long long pool_stride,
+                                                    cpx<double>* __restrict__ u) {
+  const int gflat = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gflat >= (int)P.N) return;
   int g[3];
-  g[0] = (int)(gflat % P.ng[0]);
-  const long long q = gflat / P.ng[0];
-  g[1] = (int)(q % P.ng[1]);
-  g[2] = (int)(q / P.ng[1]);
-  int cand[3][3], ncand[3];
-  double wgt[3][3];
+  g[0] = gflat % P.ng[0];
+  const int q = gflat / P.ng[0];
+  g[1] = q % P.ng[1];
+  g[2] = q / P.ng[1];
+  // a cell lies in the cutoff support of at most two parts per axis (parts own
+  // at least d cells), so at most 2^dim subdomains contribute
+  int cand[3][2], ncand[3];
+  double wgt[3][2];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    if (a >= P.dim) { cand[a][0] = 0; wgt[a][0] = 1.0; ncand[a] = 1; continue; }
+    cand[a][0] = cand[a][1] = 0;
+    wgt[a][0] = wgt[a][1] = 0.0;
+    ncand[a] = 0;
+    if (a >= P.dim) { wgt[a][0] = 1.0; ncand[a] = 1; continue; }
     const int p = pt.part_of[a][g[a]];
-    int nc = 0;
+#pragma unroll
     for (int dp = -1; dp <= 1; ++dp) {
       const int pp = p + dp;
       if (pp < 0 || pp >= pt.P[a]) continue;
       const AxisPart ap = pt.parts[a][pp];
       const double w = cutoff(ap, -1, g[a], P.d) * cutoff(ap, 1, g[a], P.d);
-      if (w != 0.0) { cand[a][nc] = pp; wgt[a][nc] = w; ++nc; }
-    }
-    ncand[a] = nc;
-  }
-  cpx<double> acc = mk(0.0, 0.0);
-  for (int iz = 0; iz < ncand[2]; ++iz)
-    for (int iy = 0; iy < ncand[1]; ++iy)
-      for (int ix = 0; ix < ncand[0]; ++ix) {
-        const int sub = (cand[2][iz] * pt.P[1] + cand[1][iy]) * pt.P[0] + cand[0][ix];
-        const SubDesc& S = subs[sub];
-        const int lx = g[0] - S.ax[0].g0, ly = g[1] - S.ax[1].g0, lz = g[2] - S.ax[2].g0;
-        const long long cell = ((long long)lz * S.dims[1] + ly) * S.dims[0] + lx;
-        const long long o = S.vec_off * kmax + (long long)r * S.nloc + cell;
-        cpx<double> v = mk(0.0, 0.0);
-        for (int l = 0; l < nsweeps; ++l) v = v + cvt<double>(vpool[l * pool_stride + o]);
-        const double w = wgt[0][ix] * wgt[1][iy] * wgt[2][iz];
-        acc = acc + w * v;
+      if (w != 0.0 && ncand[a] < 2) {
+        if (ncand[a] == 0) { cand[a][0] = pp; wgt[a][0] = w; }
+        else { cand[a][1] = pp; wgt[a][1] = w; }
+        ++ncand[a];
       }
-  u[(long long)r * P.N + gflat] = acc;
+    }
+  }
+  long long base[8];
+  long long nl[8];
+  double wc[8];
+  int nc = 0;
+#pragma unroll
+  for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+    for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+      for (int ix = 0; ix < 2; ++ix) {
+        const int k = (iz * 2 + iy) * 2 + ix;
+        base[k] = 0; nl[k] = 0; wc[k] = 0.0;
+        if (ix < ncand[0] && iy < ncand[1] && iz < ncand[2]) {
+          const int sub = (cand[2][iz] * pt.P[1] + cand[1][iy]) * pt.P[0] + cand[0][ix];
+          const SubDesc& S = subs[sub];
+          const int lx = g[0] - S.ax[0].g0, ly = g[1] - S.ax[1].g0, lz = g[2] - S.ax[2].g0;
+          base[k] = S.vec_off * kmax + ((long long)lz * S.dims[1] + ly) * S.dims[0] + lx;
+          nl[k] = S.nloc;
+          wc[k] = wgt[0][ix] * wgt[1][iy] * wgt[2][iz];
+          ++nc;
+        }
+      }
+  for (int r = 0; r < nrhs; ++r) {
+    cpx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (wc[k] == 0.0) continue;
+      const long long o = base[k] + (long long)r * nl[k];
+      cpx<double> v = mk(0.0, 0.0);
+      for (int l = 0; l < nsweeps; ++l) v = v + cvt<double>(vpool[l * pool_stride + o]);
+      acc = acc + wc[k] * v;
+    }
+    u[(long long)r * P.N + gflat] = acc;
+  }
+  (void)nc;
 }
 
 template <typename T>
 void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int nsweeps,
                        int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
                        cpx<double>* u, hipStream_t s) {
-  dim3 grid(cdiv_u(P.N, 256), nrhs);
-  hipLaunchKernelGGL(k_assemble_u<T>, grid, dim3(256), 0, s, P, d_subs, pt, nsweeps, nrhs, kmax,
-                     vpool, pool_stride, u);
+  hipLaunchKernelGGL(k_assemble_u<T>, dim3(cdiv_u(P.N, 256)), dim3(256), 0, s, P, d_subs, pt,
+                     nsweeps, nrhs, kmax, vpool, pool_stride, u);
 }
 
 template <typename T>

@@ -95,8 +95,9 @@ enum {
 };
 struct BcrJob {
   int sub, l, blk, mode;
-  int nl, nr, pad0, pad1;     // neighbour blocks (-1: none)
+  int nl, nr, nb, pad;        // neighbour blocks (-1: none); block size of the subdomain
   long long m0, m1, m2;       // factor element offsets of the matrices
+  long long nloc, vbase, cbase;   // subdomain cells, vector-pool and coefficient offsets
 };
 // nset: most operand vectors a job of the launch uses (LDS is sized for it);
 // cg: wave groups splitting the columns of every job (1, 2 or 4).

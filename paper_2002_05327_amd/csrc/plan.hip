@@ -209,6 +209,13 @@ int build_partition(dsd_plan* pl) {
                    " owns fewer cells than the overlap";
         return DSD_EINVAL;
       }
+      // an interior part must own >= 2d-2 cells, so that no cell lies in the
+      // cutoff support of three parts of an axis (the assembly of u_DDM relies on it)
+      if (p > 0 && p < Pp - 1 && len < 2 * q.overlap - 2) {
+        g_detail = "axis " + std::to_string(a) + " part " + std::to_string(p) +
+                   " owns fewer than 2*overlap-2 cells";
+        return DSD_EINVAL;
+      }
       AxisPart ap;
       ap.o0 = p == 0 ? 0 : q0 + q.pml;
       ap.o1 = p == Pp - 1 ? n + 2 * q.pml : q1 + q.pml;
@@ -710,9 +717,10 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   };
   auto add = [&](BcrLaunch& L, const int2& m, int blk, int mode, int nl, int nr, long long m0,
                  long long m1, long long m2, int nmat, int nvec) {
-    jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, 0, 0, m0, m1, m2});
-    L.nset = std::max(L.nset, nmat);
     const SubDesc& S = pl->subs[m.x];
+    jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, S.nb, 0, m0, m1, m2, S.nloc,
+                          S.vec_off * pl->kmax, S.coef_off});
+    L.nset = std::max(L.nset, nmat);
     L.fbytes += (double)nmat * S.nb * S.nb * ts;
     L.vcells += (double)nvec * S.nb;
   };
@@ -786,6 +794,9 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
     if (ok) {
       const SubDesc& S = pl->subs[J.sub];
       const long long nb2 = (long long)S.nb * S.nb;
+      if (J.nb != S.nb || J.nloc != S.nloc || J.vbase != S.vec_off * pl->kmax ||
+          J.cbase != S.coef_off)
+        ok = false;
       auto blk_ok = [&](int b) { return b >= 0 && b < S.nblk; };
       auto mat_ok = [&](long long o) { return o >= 0 && o + nb2 <= pl->sum_fac; };
       ok = blk_ok(J.blk) && (J.nl == -1 || blk_ok(J.nl)) && (J.nr == -1 || blk_ok(J.nr));
@@ -1049,9 +1060,10 @@ int sweep_apply_any(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs
 }
 
 // ---------------------------------------------------------------- FGMRES (FP64)
-int ensure_krylov(dsd_plan* pl, int restart) {
-  if (pl->kr_restart >= restart && pl->d_V.p) return 0;
-  const size_t vec = (size_t)pl->kmax * pl->P.N * sizeof(cpx<double>);
+// Krylov workspace for batches of up to kb right-hand sides.
+int ensure_krylov(dsd_plan* pl, int restart, int kb) {
+  if (pl->kr_restart >= restart && pl->kr_k >= kb && pl->d_V.p) return 0;
+  const size_t vec = (size_t)kb * pl->P.N * sizeof(cpx<double>);
   CHK(pl->d_V.alloc((size_t)(restart + 1) * vec));
   CHK(pl->d_Z.alloc((size_t)restart * vec));
   CHK(pl->d_w.alloc(vec));
@@ -1059,15 +1071,31 @@ int ensure_krylov(dsd_plan* pl, int restart) {
   CHK(pl->d_xa.alloc(vec));
   CHK(pl->d_ba.alloc(vec));
   const int nblk = 256;
-  CHK(pl->d_part.alloc((size_t)(restart + 1) * pl->kmax * nblk * sizeof(cpx<double>)));
-  CHK(pl->d_h1.alloc((size_t)(restart + 1) * pl->kmax * sizeof(cpx<double>)));
-  CHK(pl->d_h2.alloc((size_t)(restart + 1) * pl->kmax * sizeof(cpx<double>)));
-  CHK(pl->d_hn.alloc((size_t)pl->kmax * sizeof(cpx<double>)));
-  CHK(pl->d_scal.alloc((size_t)pl->kmax * sizeof(double)));
-  CHK(pl->d_idx.alloc((size_t)pl->kmax * sizeof(int)));
-  CHK(pl->d_coef.alloc((size_t)(restart + 1) * pl->kmax * sizeof(cpx<double>)));
+  CHK(pl->d_part.alloc((size_t)(restart + 1) * kb * nblk * sizeof(cpx<double>)));
+  CHK(pl->d_h1.alloc((size_t)(restart + 1) * kb * sizeof(cpx<double>)));
+  CHK(pl->d_h2.alloc((size_t)(restart + 1) * kb * sizeof(cpx<double>)));
+  CHK(pl->d_hn.alloc((size_t)kb * sizeof(cpx<double>)));
+  CHK(pl->d_scal.alloc((size_t)kb * sizeof(double)));
+  CHK(pl->d_idx.alloc((size_t)kb * sizeof(int)));
+  CHK(pl->d_coef.alloc((size_t)(restart + 1) * kb * sizeof(cpx<double>)));
   pl->kr_restart = restart;
+  pl->kr_k = kb;
   return 0;
+}
+
+// Right-hand sides one FGMRES batch can hold: the FP64 Krylov vectors
+// (restart + 1 basis, restart preconditioned, 4 work) of every RHS must fit in
+// the free device memory (plus what the current workspace would release).
+int krylov_batch(dsd_plan* pl, int restart, int nrhs) {
+  if (pl->d_V.p && pl->kr_restart >= restart && pl->kr_k >= nrhs) return nrhs;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return nrhs;
+  const Buf* held[] = {&pl->d_V, &pl->d_Z, &pl->d_w, &pl->d_r, &pl->d_xa, &pl->d_ba};
+  double have = (double)fr;
+  for (const Buf* b : held) have += (double)b->bytes;
+  const double per = (double)(2 * restart + 5) * pl->P.N * sizeof(cpx<double>);
+  const long long kb = (long long)(0.85 * have / per);
+  return (int)std::max(0LL, std::min<long long>(kb, nrhs));
 }
 
 typedef std::complex<double> zc;
@@ -1075,18 +1103,11 @@ typedef std::complex<double> zc;
 // Flexible GMRES, right-preconditioned by one sweep application per step,
 // batched over the RHS that are still active; classical Gram-Schmidt applied
 // twice; restarts from the current iterate with the true FP64 residual.
-int gmres_core(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, double tol,
-               int maxit, int restart, int* iters_host, double* relres_host) {
+int gmres_batch(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, double tol,
+                int maxit, int restart, int* iters_host, double* relres_host) {
   hipStream_t st = pl->stream;
   const long long N = pl->P.N;
   if (nrhs <= 0) return 0;
-  if (nrhs > pl->kmax || maxit <= 0 || !(tol > 0)) {
-    g_detail = "gmres: nrhs must be <= max_rhs, maxit > 0 and tol > 0";
-    return DSD_EINVAL;
-  }
-  if (restart <= 0) restart = 30;
-  restart = std::min(restart, maxit);
-  CHK(ensure_krylov(pl, restart));
   const int nblk = 256;
   cpx<double>* V = pl->d_V.as<cpx<double>>();
   cpx<double>* Z = pl->d_Z.as<cpx<double>>();
@@ -1258,6 +1279,46 @@ int gmres_core(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, dou
   return ok ? DSD_OK : DSD_NOT_CONVERGED;
 }
 
+// Flexible GMRES over any number of right-hand sides (<= max_rhs), in batches
+// whose Krylov vectors fit the device memory.
+int gmres_core(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, double tol,
+               int maxit, int restart, int* iters_host, double* relres_host) {
+  if (nrhs <= 0) return 0;
+  if (nrhs > pl->kmax || maxit <= 0 || !(tol > 0)) {
+    g_detail = "gmres: nrhs must be <= max_rhs, maxit > 0 and tol > 0";
+    return DSD_EINVAL;
+  }
+  if (restart <= 0) restart = 30;
+  restart = std::min(restart, maxit);
+  CHK(ensure_pools(pl));                 // the sweeps' pools first, then the Krylov batch
+  int kb = krylov_batch(pl, restart, nrhs);
+  while (true) {
+    if (kb < 1) {
+      g_detail = "gmres: the Krylov vectors of one right-hand side do not fit in device memory";
+      return DSD_ENOMEM;
+    }
+    const int rc = ensure_krylov(pl, restart, kb);
+    if (rc == 0) break;
+    if (rc != DSD_ENOMEM) return rc;
+    // the free-memory estimate was optimistic: release and try half as many
+    Buf* kr[] = {&pl->d_V, &pl->d_Z, &pl->d_w, &pl->d_r, &pl->d_xa, &pl->d_ba};
+    for (Buf* b : kr) (void)b->alloc(0);
+    pl->kr_restart = pl->kr_k = 0;
+    kb /= 2;
+  }
+  const long long N = pl->P.N;
+  int worst = 0;
+  for (int r0 = 0; r0 < nrhs; r0 += kb) {
+    const int n = std::min(kb, nrhs - r0);
+    const int rc = gmres_batch(pl, b + (long long)r0 * N, x + (long long)r0 * N, n, tol, maxit,
+                               restart, iters_host ? iters_host + r0 : nullptr,
+                               relres_host ? relres_host + r0 : nullptr);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
+}
+
 // Receiver indices are read by kernels: check them on the host first.
 int check_receivers(const dsd_plan* pl, const long long* rec_dev, int nrec) {
   std::vector<long long> rec(nrec);
@@ -1348,7 +1409,8 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
     }
   }
   if (rc == 0) {
-    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : (pl->solver == 2 ? 8 : 2));
+    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group
+                                               : (pl->solver == 2 ? (pl->c64 ? 8 : 4) : 2));
     if (pl->kg == 0) {
       g_detail = "subdomain blocks too large for the solve kernel's LDS";
       rc = DSD_EINVAL;
