@@ -599,6 +599,32 @@ __global__ __launch_bounds__(CH_THREADS) void k_chain_mfma(int phase, const SubD
           put_y(q, i, y);
         }
       }
+      // blocks wider than the prefetch covers (nb > 256): the rest directly
+      for (int idx = PF * CH_THREADS + tid; idx < nb * KG; idx += CH_THREADS) {
+        const int q = idx / nb, i = idx - q * nb;
+        const int rq = g * KG + q;
+        C y = zero;
+        if (phase == 0) {
+          const C r = rq < nrhs ? R[(long long)rq * nloc + (long long)k * nb + i] : zero;
+          if (t > 0) {
+            const C c = half == 0 ? Cp[(long long)(k - 1) * nb + i] : Cp[(long long)k * nb + i];
+            y = r - c * prev[q * nb + i];
+          } else {
+            y = r;
+          }
+        } else {
+          const C c = Cp[(long long)(half == 0 ? k : k - 1) * nb + i];
+          C xin;
+          if (t == 0) {
+            const int kn = half == 0 ? k + 1 : k - 1;
+            xin = rq < nrhs ? X[(long long)rq * nloc + (long long)kn * nb + i] : zero;
+          } else {
+            xin = prev[q * nb + i];
+          }
+          y = c * xin;
+        }
+        put_y(q, i, y);
+      }
     }
     lds_barrier();
     if (phase != 1 && t + 1 < nsteps) prefetch_rhs(t + 1);

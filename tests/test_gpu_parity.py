@@ -37,6 +37,9 @@ CASES = {
     "lay33": ((72, 66), 1 / 72, 2 * np.pi * 5, 8, 4, (3, 3), "layered"),
     "rag34": ((61, 70), 1 / 61, 2 * np.pi * 4, 6, 4, (3, 4), "random"),
     "d3": ((14, 13, 12), 1 / 14, 2 * np.pi * 1.5, 3, 3, (2, 2, 2), "random"),
+    # blocks wider than 192 and 256 cells: four-tile chain kernels, several row groups
+    "wide2": ((400, 60), 1 / 400, 2 * np.pi * 4, 8, 4, (2, 2), "random"),
+    "wide3": ((24, 22, 10), 1 / 24, 2 * np.pi * 1.5, 3, 3, (2, 2, 2), "random"),
 }
 
 
@@ -46,7 +49,7 @@ def _case(name):
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
-@pytest.mark.parametrize("name", ["c1", "rag34", "d3"])
+@pytest.mark.parametrize("name", ["c1", "rag34", "d3", "wide2", "wide3"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_local_solve_matches_oracle(name, prec, solver):
     n, h, om, pml, d, parts, c = _case(name)
@@ -81,7 +84,7 @@ def test_operator_matches_oracle(name):
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
-@pytest.mark.parametrize("name", ["c1", "lay33", "rag34", "d3"])
+@pytest.mark.parametrize("name", ["c1", "lay33", "rag34", "d3", "wide2", "wide3"])
 def test_sweep_apply_c128_matches_oracle_real_mode(name, solver):
     """One application of Algorithm 3.1 / 4.1 (real local PML solves)."""
     n, h, om, pml, d, parts, c = _case(name)
@@ -98,7 +101,7 @@ def test_sweep_apply_c128_matches_oracle_real_mode(name, solver):
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
-@pytest.mark.parametrize("name", ["c1", "lay33"])
+@pytest.mark.parametrize("name", ["c1", "lay33", "wide3"])
 def test_sweep_apply_c64_close_to_oracle(name, solver):
     n, h, om, pml, d, parts, c = _case(name)
     k = 2
