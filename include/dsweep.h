@@ -38,7 +38,8 @@ extern "C" {
 enum {
   DSD_OK = 0,
   DSD_NOT_CONVERGED = 1,
-  DSD_EINVAL = -1,     /* bad shape, overlap < 3, a part smaller than the overlap ... */
+  DSD_EINVAL = -1,     /* bad shape, overlap < 3, a part smaller than the overlap, an
+                          interior part smaller than 2*overlap-2 ...                   */
   DSD_ENOMEM = -2,     /* device allocation failed                                    */
   DSD_EHIP = -3,       /* HIP runtime error                                           */
   DSD_EPIVOT = -4,     /* zero pivot in a subdomain factorisation                     */
@@ -97,6 +98,15 @@ int dsd_plan_info(const dsd_plan* plan, long long* n_global, int* n_subdomains,
 /* Local solver in use: 1 = twisted block LDL^T chains, 2 = block cyclic reduction
  * (dsd_params.local_solver after the automatic choice); negative on a NULL plan. */
 int dsd_plan_local_solver(const dsd_plan* plan);
+
+/* Graph mode: when on, dsd_sweep_apply (and the preconditioner applications
+ * inside dsd_gmres_solve and the FWI calls) run as a HIP graph captured on the
+ * first call for each (input pointer, output pointer, nrhs) and replayed on
+ * the caller's stream afterwards (the several hundred kernel launches of an
+ * application become one graph launch).  The plan keeps the graphs until dsd_destroy; the
+ * buffers a graph was captured with must stay valid while it can be replayed.
+ * Off by default; results are identical either way. */
+int dsd_set_graph(dsd_plan* plan, int on);
 
 /* Local grid of subdomain `sub` (lexicographic index, x part fastest):
  * dims[3] = local cells per axis, g0[3] = global array index of its first cell

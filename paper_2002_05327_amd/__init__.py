@@ -176,6 +176,10 @@ class Plan:
         return J.value, g
 
     # -------------------------------------------------------------- timing
+    def use_graph(self, on: bool = True):
+        """Run preconditioner applications as captured HIP graphs."""
+        check(self._lib.dsd_set_graph(self._h, int(bool(on))), "dsd_set_graph")
+
     @property
     def local_solver(self) -> str:
         return {1: "chain", 2: "bcr"}[self._lib.dsd_plan_local_solver(self._h)]

@@ -25,6 +25,7 @@ EXPORTS = {
     "dsd_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_int),
                                 C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     "dsd_plan_local_solver": (C.c_int, [C.c_void_p]),
+    "dsd_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "dsd_subdomain_grid": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]),
     "dsd_local_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,

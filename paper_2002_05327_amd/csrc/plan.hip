@@ -7,6 +7,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "dsweep.h"
@@ -167,7 +169,14 @@ struct dsd_plan {
   double t_solve_ms = 0, t_other_ms = 0, solve_bytes = 0;
   long long solve_launches = 0;
 
+  // captured preconditioner applications, keyed by (f, u, nrhs)
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::tuple<const void*, void*, int>, hipGraphExec_t> graphs;
+
   ~dsd_plan() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
   }
@@ -1055,8 +1064,42 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
   return 0;
 }
 
-int sweep_apply_any(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) {
+int sweep_apply_eager(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) {
   return pl->c64 ? sweep_apply_t<float>(pl, f, u, nrhs) : sweep_apply_t<double>(pl, f, u, nrhs);
+}
+
+// One application as a HIP graph: captured once per (f, u, nrhs) on a private
+// stream of default priority, replayed on the plan's stream.  The capture holds
+// kernels only (no memset nodes).  Timing mode runs eagerly.
+int sweep_apply_any(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) {
+  if (!pl->use_graph || pl->timing) return sweep_apply_eager(pl, f, u, nrhs);
+  CHK(ensure_pools(pl));
+  const auto key = std::make_tuple((const void*)f, (void*)u, nrhs);
+  auto it = pl->graphs.find(key);
+  if (it == pl->graphs.end()) {
+    if (!pl->cap_stream) HIPCHK(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    const hipStream_t caller = pl->stream;
+    pl->stream = pl->cap_stream;
+    hipError_t e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? sweep_apply_eager(pl, f, u, nrhs) : DSD_EHIP;
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(pl->cap_stream, &g) : e;
+    pl->stream = caller;
+    if (rc == 0 && e2 != hipSuccess) {
+      g_detail = std::string("graph capture: ") + hipGetErrorString(e2);
+      rc = DSD_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (rc == 0 && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+      g_detail = "graph instantiation failed";
+      rc = DSD_EHIP;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != 0) return rc;
+    it = pl->graphs.emplace(key, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, pl->stream));
+  return 0;
 }
 
 // ---------------------------------------------------------------- FGMRES (FP64)
@@ -1457,6 +1500,12 @@ int dsd_plan_info(const dsd_plan* pl, long long* n_global, int* n_subdomains,
 }
 
 int dsd_plan_local_solver(const dsd_plan* pl) { return pl ? pl->solver : DSD_EINVAL; }
+
+int dsd_set_graph(dsd_plan* pl, int on) {
+  if (!pl) return DSD_EINVAL;
+  pl->use_graph = on != 0;
+  return DSD_OK;
+}
 
 int dsd_subdomain_grid(const dsd_plan* pl, int sub, int* dims, int* g0) {
   if (!pl || sub < 0 || sub >= pl->S) return DSD_EINVAL;
