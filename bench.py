@@ -36,7 +36,7 @@ def _inputs(name):
     return w, c, F
 
 
-def _plan(w, c, prec, kg, graph=False):
+def _plan(w, c, prec, kg, graph=False, tune=False):
     import torch
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(1.0 / c ** 2).cuda()
@@ -46,6 +46,11 @@ def _plan(w, c, prec, kg, graph=False):
                     m=m, precision=prec, max_rhs=w.nrhs, rhs_per_group=kg)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if tune:
+        t1 = time.perf_counter()
+        res = plan.autotune()
+        print(f"# {prec} autotune {time.perf_counter() - t1:.2f} s -> {res}", file=sys.stderr,
+              flush=True)
     if graph:
         plan.use_graph(True)
     return plan, dt
@@ -159,6 +164,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=60)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--kg", type=int, default=0, help="RHS per workgroup in the block solves")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time the solve-launch shapes first (reported separately)")
     ap.add_argument("--graph", action="store_true",
                     help="run preconditioner applications as captured HIP graphs")
     ap.add_argument("--no-c128", action="store_true")
@@ -176,7 +183,7 @@ def main():
     b = torch.from_numpy(F).cuda()
     print(f"# workload {w.name}: n={w.n} parts={w.parts} nrhs={w.nrhs}", file=sys.stderr, flush=True)
 
-    plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph)
+    plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph, args.autotune)
     print(f"# c64 factorisation {tf64:.2f} s", file=sys.stderr, flush=True)
     dt64, its64, rel64, ok64 = _solve_steps(plan64, b, args.tol, args.maxit, args.restart,
                                             args.warmup, args.steps)
@@ -189,7 +196,7 @@ def main():
 
     c128 = None
     if not args.no_c128:
-        plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph)
+        plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph, args.autotune)
         dt128, its128, rel128, ok128 = _solve_steps(plan128, b, args.tol, args.maxit,
                                                     args.restart, min(args.warmup, 1),
                                                     max(1, min(args.steps, 2)))

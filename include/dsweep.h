@@ -108,6 +108,18 @@ int dsd_plan_local_solver(const dsd_plan* plan);
  * Off by default; results are identical either way. */
 int dsd_set_graph(dsd_plan* plan, int on);
 
+/* Autotuner: times `reps` preconditioner applications of `nrhs` right-hand
+ * sides for every candidate shape of the subdomain-solve launches -- RHS per
+ * workgroup (2, 4, 8, 16 as the LDS and register budgets allow) and, for the
+ * cyclic reduction, the thresholds that decide how many wave groups split the
+ * columns of the jobs of each reduction level -- and keeps the fastest in the
+ * plan.  Results of later calls may change at rounding level (a different
+ * summation order), never more.  Outputs (host, may be NULL): the chosen RHS
+ * per workgroup, the two thresholds, and the time of one application (ms).
+ * Captured graphs are dropped.  Synchronises the stream. */
+int dsd_autotune(dsd_plan* plan, int nrhs, int reps, int* kg_host, int* cg_wide_host,
+                 int* cg_mid_host, double* ms_host, void* stream);
+
 /* Local grid of subdomain `sub` (lexicographic index, x part fastest):
  * dims[3] = local cells per axis, g0[3] = global array index of its first cell
  * per axis (local PML cells included). */

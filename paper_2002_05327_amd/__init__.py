@@ -176,6 +176,15 @@ class Plan:
         return J.value, g
 
     # -------------------------------------------------------------- timing
+    def autotune(self, nrhs: Optional[int] = None, reps: int = 2) -> dict:
+        """Time the candidate launch shapes of the subdomain solves and keep the fastest."""
+        k = self.max_rhs if nrhs is None else int(nrhs)
+        kg, cw, cm, ms = C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        check(self._lib.dsd_autotune(self._h, k, int(reps), C.byref(kg), C.byref(cw), C.byref(cm),
+                                     C.byref(ms), _stream_ptr()), "dsd_autotune")
+        return {"rhs_per_group": kg.value, "cg_wide": cw.value, "cg_mid": cm.value,
+                "ms_per_application": ms.value}
+
     def use_graph(self, on: bool = True):
         """Run preconditioner applications as captured HIP graphs."""
         check(self._lib.dsd_set_graph(self._h, int(bool(on))), "dsd_set_graph")

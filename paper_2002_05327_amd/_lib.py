@@ -26,6 +26,9 @@ EXPORTS = {
                                 C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     "dsd_plan_local_solver": (C.c_int, [C.c_void_p]),
     "dsd_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
+    "dsd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
+                               C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                               C.c_void_p]),
     "dsd_subdomain_grid": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]),
     "dsd_local_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,

@@ -149,6 +149,9 @@ struct dsd_plan {
   std::vector<BcrSub> bcr;
   std::vector<std::vector<BcrLaunch>> bcr_launch;   // per launch group
   std::vector<BcrLaunch> bcr_single;                // dsd_local_solve (jobs in d_single_job)
+  std::vector<std::vector<int2>> groups;            // launch groups: {subdomain, sweep}
+  int cg_wide = 32, cg_mid = 8;   // column groups: 1 while >= cg_wide blocks per subdomain
+                                  // remain at a level, 2 while >= cg_mid, else 4
   Buf d_bcr_jobs;
   long long sum_nloc = 0, sum_fac = 0;
 
@@ -304,6 +307,20 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
                     std::vector<BcrLaunch>& out);
 int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs);
 
+// Solve-job tables of the cyclic reduction for every launch group.
+int build_bcr_jobs(dsd_plan* pl) {
+  pl->bcr_launch.clear();
+  if (pl->solver != 2) return 0;
+  std::vector<BcrJob> bj;
+  for (auto& grp : pl->groups) {
+    pl->bcr_launch.emplace_back();
+    bcr_group_jobs(pl, grp, bj, pl->bcr_launch.back());
+  }
+  CHK(bcr_check_jobs(pl, bj));
+  CHK(upload(pl->d_bcr_jobs, bj));
+  return 0;
+}
+
 int build_schedule(dsd_plan* pl) {
   const int dim = pl->dim, L = pl->L;
   const dsd_params& q = pl->prm;
@@ -434,16 +451,8 @@ int build_schedule(dsd_plan* pl) {
     }
     pl->steps.push_back(T);
   }
-  pl->bcr_launch.clear();
-  if (pl->solver == 2) {
-    std::vector<BcrJob> bj;
-    for (auto& grp : groups) {
-      pl->bcr_launch.emplace_back();
-      bcr_group_jobs(pl, grp, bj, pl->bcr_launch.back());
-    }
-    CHK(bcr_check_jobs(pl, bj));
-    CHK(upload(pl->d_bcr_jobs, bj));
-  }
+  pl->groups = groups;
+  CHK(build_bcr_jobs(pl));
   CHK(upload(pl->d_members, members));
   CHK(upload(pl->d_jobs2, jobs2));
   CHK(upload(pl->d_jobs1, jobs1));
@@ -712,11 +721,11 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   for (const SubDesc& S : pl->subs) maxblk = std::max(maxblk, S.nblk);
   // Column groups of a level: wide levels (many blocks per subdomain) keep one
   // wave per row tile; the deep levels split the columns to shorten each job.
-  // It depends on the level and the plan only, never on the launch, so every
-  // schedule sums every job in the same order.
+  // It depends on the level and the plan's thresholds only, never on the
+  // launch, so every schedule sums every job in the same order.
   auto level_cg = [&](int lev) {
     const int per_sub = maxblk >> (lev + 1);
-    return per_sub >= 32 ? 1 : (per_sub >= 8 ? 2 : 4);
+    return per_sub >= pl->cg_wide ? 1 : (per_sub >= pl->cg_mid ? 2 : 4);
   };
   int cur_cg = 1;
   auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, cur_cg, 0.0, 0.0}; };
@@ -1504,6 +1513,76 @@ int dsd_plan_local_solver(const dsd_plan* pl) { return pl ? pl->solver : DSD_EIN
 int dsd_set_graph(dsd_plan* pl, int on) {
   if (!pl) return DSD_EINVAL;
   pl->use_graph = on != 0;
+  return DSD_OK;
+}
+
+int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_host,
+                 int* cg_mid_host, double* ms_host, void* stream) {
+  g_detail.clear();
+  if (!pl || nrhs <= 0 || nrhs > pl->kmax || reps <= 0) {
+    g_detail = "autotune: bad plan, nrhs (1..max_rhs) or reps";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  hipStream_t st = pl->stream;
+  const bool was_timing = pl->timing;
+  pl->timing = false;
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);   // tables change
+  pl->graphs.clear();
+  CHK(ensure_pools(pl));
+  Buf f, u;
+  const size_t vb = (size_t)nrhs * pl->P.N * sizeof(cpx<double>);
+  CHK(f.alloc(vb));
+  CHK(u.alloc(vb));
+  HIPCHK(hipMemsetAsync(f.p, 0, vb, st));
+  // candidates: RHS per workgroup, and the column-group thresholds (2D and 3D
+  // block counts differ by an order of magnitude, so the thresholds scale)
+  std::vector<int> kgs;
+  for (int k : {2, 4, 8, 16}) {
+    const int kk = choose_kg(pl, k);
+    if (kk > 0 && std::find(kgs.begin(), kgs.end(), kk) == kgs.end()) kgs.push_back(kk);
+  }
+  const int pols[][2] = {{32, 8}, {64, 16}, {16, 4}, {1 << 30, 1 << 30}, {32, 1 << 30}};
+  const int best0_kg = pl->kg, best0_w = pl->cg_wide, best0_m = pl->cg_mid;
+  double best = 1e300;
+  int bkg = best0_kg, bw = best0_w, bm = best0_m;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  int rc = 0;
+  for (int kg : kgs) {
+    for (const auto& pol : pols) {
+      pl->kg = kg;
+      pl->cg_wide = pol[0];
+      pl->cg_mid = pol[1];
+      if ((rc = build_bcr_jobs(pl)) != 0) break;
+      if ((rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs)) != 0) break;
+      (void)hipEventRecord(a, st);
+      for (int r = 0; r < reps && rc == 0; ++r)
+        rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs);
+      (void)hipEventRecord(b, st);
+      if (rc != 0 || hipEventSynchronize(b) != hipSuccess) { rc = rc ? rc : DSD_EHIP; break; }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (ms / reps < best) { best = ms / reps; bkg = kg; bw = pol[0]; bm = pol[1]; }
+      if (pl->solver != 2) break;             // the thresholds only shape the reduction
+    }
+    if (rc != 0) break;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  pl->kg = rc == 0 ? bkg : best0_kg;
+  pl->cg_wide = rc == 0 ? bw : best0_w;
+  pl->cg_mid = rc == 0 ? bm : best0_m;
+  const int rc2 = build_bcr_jobs(pl);
+  pl->timing = was_timing;
+  if (rc != 0) return rc;
+  if (rc2 != 0) return rc2;
+  if (kg_host) *kg_host = pl->kg;
+  if (cg_wide_host) *cg_wide_host = pl->cg_wide;
+  if (cg_mid_host) *cg_mid_host = pl->cg_mid;
+  if (ms_host) *ms_host = best;
+  HIPCHK(hipStreamSynchronize(st));
   return DSD_OK;
 }
 

@@ -124,6 +124,22 @@ def test_sweep_apply_deterministic():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-3)])
+def test_autotuned_plan_matches_oracle(prec, tol):
+    """The autotuner only picks launch shapes: the tuned plan still matches the oracle."""
+    n, h, om, pml, d, parts, c = _case("lay33")
+    k = 3
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, prec, k, solver="bcr")
+    res = plan.autotune(reps=1)
+    assert res["rhs_per_group"] >= 1 and res["ms_per_application"] > 0
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    u_ref = ddm.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    print(f"autotune {prec}: {res}; vs oracle {rel(u, u_ref):.2e}", flush=True)
+    assert rel(u, u_ref) < tol
+
+
 @pytest.mark.parametrize("solver", SOLVERS)
 def test_graph_replays_equal_eager_application(solver):
     """A captured application replays bitwise like the eager one, also with eager
