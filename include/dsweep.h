@@ -73,6 +73,13 @@ typedef struct {
                             2: block cyclic reduction (about three times the factor
                                memory; every reduction level is one batched launch);
                             0: 2 unless its factor would exceed 45% of device memory. */
+  int dense_top;         /* block cyclic reduction only: the reduction stops at the first
+                            level that has at most this many blocks (at least 2) and
+                            applies the precomputed inverse of that reduced system as one
+                            dense product (fewer, wider launches for the deep levels);
+                            0: the library's bound (8, lowered to fit the solve kernel's
+                            LDS and an order of at most 2048); -1: reduce to one block.
+                            Valid range -1..64.                                          */
 } dsd_params;
 
 /*

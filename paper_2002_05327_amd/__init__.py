@@ -42,7 +42,7 @@ class Plan:
     def __init__(self, n: Sequence[int], h: float, omega: float, pml: int, overlap: int,
                  parts: Sequence[int], m: torch.Tensor, precision: str = "c64",
                  max_rhs: int = 1, rhs_per_group: int = 0, sigma0_delta: float = 60.0,
-                 schedule: str = "dag", local_solver: str = "auto"):
+                 schedule: str = "dag", local_solver: str = "auto", dense_top: int = 0):
         self._lib = _lib.load()
         dim = len(n)
         if dim not in (2, 3) or len(parts) != dim:
@@ -58,6 +58,7 @@ class Plan:
         p.max_rhs, p.rhs_per_group = int(max_rhs), int(rhs_per_group)
         p.schedule = {"dag": 0, "sequential": 1}[schedule]
         p.local_solver = {"auto": 0, "chain": 1, "bcr": 2}[local_solver]
+        p.dense_top = int(dense_top)
         self.params = p
         self.n, self.dim, self.pml, self.omega = tuple(int(k) for k in n), dim, int(pml), omega
         self.precision, self.max_rhs = precision, int(max_rhs)

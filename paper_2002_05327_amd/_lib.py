@@ -14,7 +14,7 @@ class Params(C.Structure):
         ("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double), ("pml", C.c_int),
         ("overlap", C.c_int), ("parts", C.c_int * 3), ("sigma0_delta", C.c_double),
         ("precision", C.c_int), ("max_rhs", C.c_int), ("rhs_per_group", C.c_int),
-        ("schedule", C.c_int), ("local_solver", C.c_int),
+        ("schedule", C.c_int), ("local_solver", C.c_int), ("dense_top", C.c_int),
     ]
 
 

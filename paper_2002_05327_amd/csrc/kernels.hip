@@ -988,7 +988,9 @@ void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* wo
 //   out = sum_m M_m v_m   (+ R_blk for BCR_KEPT),
 // and the CG partial sums of a tile meet in LDS (CG = 1 on the wide levels;
 // more column groups shorten the per-task latency chain of the small, deep
-// reduction levels).  The operand vectors
+// reduction levels).  A dense job has one nb x (m nb) matrix: a row block of
+// the inverse of the small reduced system left at the top of the reduction,
+// applied to the m right-hand-side blocks of that system.  The operand vectors
 // v_m are staged in LDS as [column][KG] complex values; the first round of
 // matrix loads is issued before the staging, and every round keeps the next
 // one in flight.  CG is set per reduction level by the caller.
@@ -1020,7 +1022,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
                                                        const cpx<T>* __restrict__ cpl,
                                                        cpx<T>* __restrict__ rpool,
                                                        cpx<T>* __restrict__ vpool,
-                                                       long long pool_stride, int lds_ops) {
+                                                       long long pool_stride) {
   typedef typename vec2<T>::type V2;
   typedef cpx<T> C;
   typedef BcrTraits<T, KG> TR;
@@ -1040,6 +1042,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   const int g = rem / nrg, rg = rem - (rem / nrg) * nrg;
   const BcrJob J = jobs[job];
   const int nb = J.nb;
+  const int ncol = J.mode == BCR_DENSE ? J.pad * nb : nb;   // columns of every matrix
   const long long nloc = J.nloc;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1047,11 +1050,10 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   const int row0 = (rg * RT + rt) * 64;
   // CG wave groups split the columns (CG depends on the job's reduction level
   // only, so a job's summation order is the same in every schedule)
-  int cw = (nb + CG - 1) / CG;
+  int cw = (ncol + CG - 1) / CG;
   cw = (cw + 3) & ~3;
-  const int wc0 = 0, wc1 = nb;
-  const int c0 = min(nb, cg * cw);
-  const int c1 = min(nb, c0 + cw);
+  const int c0 = min(ncol, cg * cw);
+  const int c1 = min(ncol, c0 + cw);
   const bool wave_live = row0 < nb && c0 < c1;
   const C zero = mk((T)0, (T)0);
   C* __restrict__ X = vpool + (long long)J.l * pool_stride + J.vbase;
@@ -1105,25 +1107,29 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   V2 bufA[U], bufB[U];
   if (wave_live) issue(bufA, 0);
 
-  // ---- operands: set m at ops + m * nb * KG, [column][KG]; loads batched
+  // ---- operands: set m at ops + m * nb4 * KG, [column][KG]; loads batched
+  // (a dense job has one set of ncol columns)
   extern __shared__ unsigned char smem_raw[];
   C* ops = reinterpret_cast<C*>(smem_raw);
   const int nb4 = (nb + 3) & ~3;                    // operand columns, zero beyond nb
   const long long ss = (long long)nb4 * KG;
-  const int wcn = (wc1 == nb ? nb4 : wc1) - wc0;
+  const int wcn = (ncol + 3) & ~3;
   const int nel = wcn * KG;
   for (int base = 0; base < nel; base += BCR_STAGE * (int)blockDim.x) {
     C va[BCR_STAGE], vb[BCR_STAGE], vc[BCR_STAGE];
 #pragma unroll
     for (int k = 0; k < BCR_STAGE; ++k) {
       const int idx = base + k * (int)blockDim.x + tid;
-      const int q = idx / (wcn > 0 ? wcn : 1), i = wc0 + idx - q * wcn;
+      const int q = idx / wcn, i = idx - q * wcn;
       const int rq = g * KG + q;
-      const bool live = idx < nel && rq < nrhs && i < nb;
+      const bool live = idx < nel && rq < nrhs && i < ncol;
       const long long ro = (long long)rq * nloc;
       va[k] = vb[k] = vc[k] = zero;
       if (live) {
-        if (mode == BCR_KEPT) {
+        if (mode == BCR_DENSE) {
+          const int bq = i / nb;
+          va[k] = R[ro + (long long)(J.nl + bq * J.nr) * nb + (i - bq * nb)];
+        } else if (mode == BCR_KEPT) {
           if (hl) va[k] = R[ro + (long long)J.nl * nb + i];
           if (hr) vb[k] = R[ro + (long long)J.nr * nb + i];
         } else {
@@ -1139,7 +1145,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
     for (int k = 0; k < BCR_STAGE; ++k) {
       const int idx = base + k * (int)blockDim.x + tid;
       if (idx >= nel) break;
-      const int q = idx / wcn, i = wc0 + idx - q * wcn;
+      const int q = idx / wcn, i = idx - q * wcn;
       C* o = ops + (long long)i * KG + q;
       if (mode == BCR_KEPT) {
         if (hl) o[0] = -va[k];
@@ -1227,9 +1233,11 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
       }
     }
   }
-  // ---- column-group partial sums meet in LDS (after the operand area)
+  // ---- column-group partial sums meet in LDS (in the operand area, once
+  // every wave is done with the operands)
   if (CG > 1) {
-    float* part = reinterpret_cast<float*>(smem_raw + lds_ops);
+    __syncthreads();
+    float* part = reinterpret_cast<float*>(smem_raw);
     constexpr int PW = TR::PW;
     if (cg > 0) {
       if constexpr (MF) {
@@ -1350,73 +1358,127 @@ int bcr_kg(int max_nb, int kg) {
 }
 
 // Waves of a solve workgroup: RT 64-row tiles (a block's rows in row groups
-// of at most BCR_MAXRT tiles) times CG column groups.
-static inline void bcr_shape(int max_nb, int cg, int& RT, int& CG, int& nrg) {
+// of at most rt tiles) times CG column groups.
+static inline void bcr_shape(int max_nb, int cg, int rt, int& RT, int& CG, int& nrg) {
   const int tiles = (max_nb + 63) / 64;
-  RT = tiles < BCR_MAXRT ? tiles : BCR_MAXRT;
+  const int rmax = rt >= 1 && rt < BCR_MAXRT ? rt : BCR_MAXRT;
+  RT = tiles < rmax ? tiles : rmax;
   nrg = (tiles + RT - 1) / RT;
   CG = cg < 1 ? 1 : cg;
-  while (CG > 1 && RT * CG > BCR_MAXW) CG >>= 1;
+  while (CG > 1 && RT * CG > BCR_MAXW) --CG;
 }
 
+// LDS of a launch: the operand sets, reused for the MF row regrouping and the
+// column-group partial sums once every wave is done with the operands.
 template <typename T>
-static size_t bcr_ops_bytes(int max_nb, int kg, int nset, int RT) {
+size_t bcr_launch_lds_bytes(int max_nb, int kg, int nset, int cg, int rt) {
+  int RT, CG, nrg;
+  bcr_shape(max_nb, cg, rt, RT, CG, nrg);
   const size_t ops = (size_t)nset * ((max_nb + 3) & ~3) * kg * sizeof(cpx<T>);
   const size_t stage = (size_t)RT * 64 * kg * sizeof(cpx<T>);
-  const size_t b = ops > stage ? ops : stage;
+  const bool mf = std::is_same<T, float>::value && kg >= 8;
+  const size_t per_lane = mf ? (size_t)16 * (kg / 8) * sizeof(float) : 2 * (size_t)kg * sizeof(T);
+  const size_t part = CG > 1 ? (size_t)(CG - 1) * RT * 64 * per_lane : 0;
+  size_t b = ops > stage ? ops : stage;
+  b = b > part ? b : part;
   return (b + 255) / 256 * 256;
 }
 
-template <typename T>
-static size_t bcr_part_bytes(int kg, int RT, int CG) {
-  if (CG <= 1) return 0;
-  const bool mf = std::is_same<T, float>::value && kg >= 8;
-  const size_t per_lane = mf ? (size_t)16 * (kg / 8) * sizeof(float) : 2 * (size_t)kg * sizeof(T);
-  return (size_t)(CG - 1) * RT * 64 * per_lane;
-}
-
-// Largest LDS any launch of this shape family can ask for (CG up to 4).
+// Largest LDS a launch of the level-by-level shapes (CG up to 4) can ask for.
 template <typename T>
 size_t bcr_lds_bytes(int max_nb, int kg, int nset) {
-  const int tiles = (max_nb + 63) / 64;
-  const int RT = tiles < BCR_MAXRT ? tiles : BCR_MAXRT;
-  int cg = 4;
-  while (cg > 1 && RT * cg > BCR_MAXW) cg >>= 1;
-  return bcr_ops_bytes<T>(max_nb, kg, nset, RT) + bcr_part_bytes<T>(kg, RT, cg);
+  size_t b = 0;
+  for (int cg = 1; cg <= 4; cg *= 2) {
+    const size_t v = bcr_launch_lds_bytes<T>(max_nb, kg, nset, cg, 0);
+    b = v > b ? v : b;
+  }
+  return b;
 }
 
 template <typename T, int KG>
 static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset, int cg,
-                         int nrhs, int kmax, int max_nb, const cpx<T>* fac, const cpx<T>* cpl,
-                         cpx<T>* rpool, cpx<T>* vpool, long long pool_stride, hipStream_t s) {
+                         int rt, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
+                         const cpx<T>* cpl, cpx<T>* rpool, cpx<T>* vpool, long long pool_stride,
+                         hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
   int RT, CG, nrg;
-  bcr_shape(max_nb, cg, RT, CG, nrg);
+  bcr_shape(max_nb, cg, rt, RT, CG, nrg);
   long long total = (long long)njobs * G * nrg;
   total = (total + 7) / 8 * 8;
-  const size_t ob = bcr_ops_bytes<T>(max_nb, KG, nset, RT);
-  const size_t lds = ob + bcr_part_bytes<T>(KG, RT, CG);
+  const size_t lds = bcr_launch_lds_bytes<T>(max_nb, KG, nset, cg, rt);
   hipLaunchKernelGGL((k_bcr<T, KG>), dim3((unsigned)total), dim3(64 * RT * CG), lds, s, d_subs,
                      d_jobs, njobs, G, nrg, RT, CG, nrhs, kmax, fac, cpl, rpool, vpool,
-                     pool_stride, (int)ob);
+                     pool_stride);
 }
 
 template <typename T>
 void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset,
-                      int cg, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
+                      int cg, int rt, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
                       const cpx<T>* cpl, cpx<T>* rpool, cpx<T>* vpool, long long pool_stride,
                       hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0) return;
+#define DSD_BCR_K(K) \
+  launch_bcr_k<T, K>(d_subs, d_jobs, njobs, nset, cg, rt, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s)
   switch (bcr_kg<T>(max_nb, kg)) {
-    case 1: launch_bcr_k<T, 1>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-    case 2: launch_bcr_k<T, 2>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-    case 4: launch_bcr_k<T, 4>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
-    case 8: launch_bcr_k<T, 8>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s); break;
+    case 1: DSD_BCR_K(1); break;
+    case 2: DSD_BCR_K(2); break;
+    case 4: DSD_BCR_K(4); break;
+    case 8: DSD_BCR_K(8); break;
     default:
-      if constexpr (std::is_same<T, float>::value)
-        launch_bcr_k<T, 16>(d_subs, d_jobs, njobs, nset, cg, nrhs, kmax, max_nb, fac, cpl, rpool, vpool, pool_stride, s);
+      if constexpr (std::is_same<T, float>::value) DSD_BCR_K(16);
       break;
   }
+#undef DSD_BCR_K
+}
+
+// Dense top level: assemble the reduced block-tridiagonal system of one
+// subdomain as a column-major n x n matrix (n = m nb).
+__global__ void k_bcr_dense_build(const BcrDenseJob* jobs, const cpx<double>* work,
+                                  cpx<double>* dense) {
+  const BcrDenseJob J = jobs[blockIdx.y];
+  const int nb = J.nb;
+  const long long n = (long long)J.m * nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const long long C = e / n, R = e - C * n;
+  const int qc = (int)(C / nb), qr = (int)(R / nb);
+  const int c = (int)(C - (long long)qc * nb), r = (int)(R - (long long)qr * nb);
+  cpx<double> v = mk(0.0, 0.0);
+  if (qr == qc)
+    v = work[J.dbase + (long long)(J.first + qr * J.stride) * J.slot + (long long)c * nb + r];
+  else if (qc == qr + 1)
+    v = work[J.ebase + (long long)qr * J.slot + (long long)c * nb + r];
+  else if (qr == qc + 1)
+    v = work[J.ebase + (long long)qc * J.slot + (long long)r * nb + c];
+  dense[J.out + e] = v;
+}
+
+void launch_bcr_dense_build(const BcrDenseJob* d_jobs, int njobs, int max_n,
+                            const cpx<double>* work, cpx<double>* dense, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_bcr_dense_build, dim3(cdiv_u((long long)max_n * max_n, 256), njobs),
+                     dim3(256), 0, s, d_jobs, work, dense);
+}
+
+// Rounds the inverse into the factor as m row blocks, each nb x n column-major.
+template <typename T>
+__global__ void k_bcr_dense_store(const BcrDenseJob* jobs, const cpx<double>* dense, cpx<T>* fac) {
+  const BcrDenseJob J = jobs[blockIdx.y];
+  const int nb = J.nb;
+  const long long n = (long long)J.m * nb;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const long long C = e / n, R = e - C * n;
+  const long long i = R / nb, r = R - i * nb;
+  fac[J.fac + i * nb * n + C * nb + r] = cvt<T>(dense[J.out + e]);
+}
+
+template <typename T>
+void launch_bcr_dense_store(const BcrDenseJob* d_jobs, int njobs, int max_n,
+                            const cpx<double>* dense, cpx<T>* fac, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_bcr_dense_store<T>, dim3(cdiv_u((long long)max_n * max_n, 256), njobs),
+                     dim3(256), 0, s, d_jobs, dense, fac);
 }
 
 // ============================================================================
@@ -1958,8 +2020,11 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
   template void launch_bcr_copy<T>(const BcrCopyJob*, int, int, const cpx<double>*, cpx<T>*,    \
                                    hipStream_t);                                                 \
   template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int, int,\
-                                    int, const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*,         \
+                                    int, int, const cpx<T>*, const cpx<T>*, cpx<T>*, cpx<T>*,    \
                                     long long, hipStream_t);                                     \
+  template size_t bcr_launch_lds_bytes<T>(int, int, int, int, int);                             \
+  template void launch_bcr_dense_store<T>(const BcrDenseJob*, int, int, const cpx<double>*,     \
+                                          cpx<T>*, hipStream_t);                                 \
   template void launch_bcr_dfwd<T>(const SubDesc*, const BcrJob*, int, int, int, int,           \
                                    const cpx<T>*, cpx<T>*, const cpx<T>*, long long,            \
                                    hipStream_t);                                                 \

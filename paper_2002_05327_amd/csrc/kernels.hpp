@@ -91,7 +91,9 @@ enum {
   BCR_KEPT = 1,   // R_blk = R_blk - M0 R_nl - M1 R_nr                  (forward, level >= 1)
   BCR_BWD0 = 2,   // X_blk = M0 (R_blk - c_{blk-1} X_nl - c_blk X_nr)   (backward, level 0)
   BCR_BWD = 3,    // X_blk = M0 R_blk - M1 X_nl - M2 X_nr               (backward, level >= 1)
-  BCR_DFWD = 4    // R_blk = R_blk - c_{blk-1} X_nl - c_blk X_nr        (forward, level 0)
+  BCR_DFWD = 4,   // R_blk = R_blk - c_{blk-1} X_nl - c_blk X_nr        (forward, level 0)
+  BCR_DENSE = 5   // X_blk = M0 [R_b0; R_b1; ...; R_b(m-1)] with b_q = nl + q nr, m = pad:
+                  // one nb x (m nb) row block of the inverse of a small reduced system
 };
 struct BcrJob {
   int sub, l, blk, mode;
@@ -100,10 +102,11 @@ struct BcrJob {
   long long nloc, vbase, cbase;   // subdomain cells, vector-pool and coefficient offsets
 };
 // nset: most operand vectors a job of the launch uses (LDS is sized for it);
-// cg: wave groups splitting the columns of every job (1, 2 or 4).
+// cg: wave groups splitting the columns of every job (1 to 12); rt: most
+// 64-row tiles per workgroup (0: up to 4).
 template <typename T>
 void launch_bcr_solve(int kg, const SubDesc* d_subs, const BcrJob* d_jobs, int njobs, int nset,
-                      int cg, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
+                      int cg, int rt, int nrhs, int kmax, int max_nb, const cpx<T>* fac,
                       const cpx<T>* cpl, cpx<T>* rpool, cpx<T>* vpool, long long pool_stride,
                       hipStream_t s);
 template <typename T>
@@ -115,6 +118,27 @@ template <typename T>
 int bcr_kg(int max_nb, int kg);
 template <typename T>
 size_t bcr_lds_bytes(int max_nb, int kg, int nset);
+// LDS of one launch of the given shape (the check the plan makes before it
+// accepts a dense top level).
+template <typename T>
+size_t bcr_launch_lds_bytes(int max_nb, int kg, int nset, int cg, int rt);
+
+// Dense top level of the reduction: the m-block reduced system of one
+// subdomain, assembled column-major (n = m nb) from its diagonal blocks
+// D_q = work[dbase + (first + q stride) slot] and couplings
+// E_q = work[ebase + q slot] (block (q, q+1) = E_q, block (q+1, q) = E_q^T).
+struct BcrDenseJob {
+  int nb, m, first, stride;
+  long long slot, dbase, ebase;   // working offsets (complex entries)
+  long long out;                  // dense matrix offset in the dense work array
+  long long fac;                  // factor offset of the m row blocks (nb x n each)
+};
+void launch_bcr_dense_build(const BcrDenseJob* d_jobs, int njobs, int max_n,
+                            const cpx<double>* work, cpx<double>* dense, hipStream_t s);
+// fac[J.fac + i nb n + c nb + r] = (T) dense[J.out + c n + i nb + r]
+template <typename T>
+void launch_bcr_dense_store(const BcrDenseJob* d_jobs, int njobs, int max_n,
+                            const cpx<double>* dense, cpx<T>* fac, hipStream_t s);
 
 // Batched FP64 complex GEMM on working blocks: C = beta C + alpha op(A) op(B),
 // nb x nb column-major; op transposes when ta / tb is set; beta is 0 or 1.

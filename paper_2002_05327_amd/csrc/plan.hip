@@ -120,6 +120,9 @@ struct StepTab {
 // transposes (the products A[j][k] P_k the kept neighbours use), per block.
 struct BcrSub {
   int top = 0;                               // level where a single block remains
+  int dtop = -1;                             // level solved densely (-1: none)
+  int dm = 0;                                // blocks of that level
+  long long dense = -1;                      // factor offset of its inverse (dm row blocks)
   std::vector<std::vector<int>> lev;
   std::vector<long long> wl, wr, wlt, wrt;   // -1: absent
 };
@@ -129,6 +132,7 @@ struct BcrLaunch {
   int dfwd;          // 1: level-0 coupling update (vector kernel)
   int nset;          // most matrices (operand vectors) of one job
   int cg;            // wave groups splitting the columns (from the level only)
+  int rt;            // most 64-row tiles per workgroup (0: default)
   double fbytes;     // factor bytes streamed (once per launch)
   double vcells;     // vector entries read and written per right-hand side
 };
@@ -152,6 +156,7 @@ struct dsd_plan {
   std::vector<std::vector<int2>> groups;            // launch groups: {subdomain, sweep}
   int cg_wide = 32, cg_mid = 8;   // column groups: 1 while >= cg_wide blocks per subdomain
                                   // remain at a level, 2 while >= cg_mid, else 4
+  int dense_max = 0;              // largest reduced system solved densely (0: none)
   Buf d_bcr_jobs;
   long long sum_nloc = 0, sum_fac = 0;
 
@@ -471,8 +476,21 @@ int build_schedule(dsd_plan* pl) {
 }
 
 // ------------------------------------------------------ block cyclic reduction
+// Level of the reduction solved densely: the first level >= 1 with at most
+// dense_max blocks, unless that is the single top block.
+int dense_level(const BcrSub& B, int dense_max) {
+  if (dense_max < 2) return -1;
+  for (int l = 1; l < B.top; ++l)
+    if ((int)B.lev[l].size() <= dense_max) return l;
+  return -1;
+}
+// last level of the reduction a subdomain's solve runs level by level
+inline int etop(const BcrSub& B) { return B.dtop >= 0 ? B.dtop : B.top; }
+
 // Level structure and factor layout: P_k = D_k^{-1} of every block at
-// fac_off + k nb^2, then the W blocks of the blocks eliminated at levels >= 1.
+// fac_off + k nb^2, then the W blocks of the blocks eliminated at levels >= 1
+// below the dense level, then the dm row blocks (nb x dm nb) of the inverse of
+// the reduced system at the dense level.
 void bcr_layout(dsd_plan* pl) {
   pl->bcr.assign(pl->S, BcrSub{});
   long long foff = 0;
@@ -490,13 +508,15 @@ void bcr_layout(dsd_plan* pl) {
       B.lev.push_back(nxt);
     }
     B.top = (int)B.lev.size() - 1;
+    B.dtop = dense_level(B, pl->dense_max);
+    B.dm = B.dtop >= 0 ? (int)B.lev[B.dtop].size() : 0;
     B.wl.assign(S.nblk, -1);
     B.wr.assign(S.nblk, -1);
     B.wlt.assign(S.nblk, -1);
     B.wrt.assign(S.nblk, -1);
     S.fac_off = foff;
     long long slot = S.nblk;
-    for (int l = 1; l < B.top; ++l) {
+    for (int l = 1; l < etop(B); ++l) {
       const std::vector<int>& c = B.lev[l];
       for (size_t p = 0; p < c.size(); p += 2) {
         const int k = c[p];
@@ -509,6 +529,10 @@ void bcr_layout(dsd_plan* pl) {
           B.wrt[k] = foff + slot++ * nb2;
         }
       }
+    }
+    if (B.dtop >= 0) {
+      B.dense = foff + slot * nb2;
+      slot += (long long)B.dm * B.dm;
     }
     foff += slot * nb2;
   }
@@ -535,15 +559,23 @@ int bcr_factor(dsd_plan* pl) {
   const long long half = maxblk / 2 + 1;
   const long long slots = maxblk + 4 * half;             // D, E (two levels), W_L, W_R
   const long long per_sub = slots * blk;                 // complex entries per subdomain
+  long long dn_max = 0;                                  // order of the largest dense system
+  for (int sid = 0; sid < pl->S; ++sid)
+    if (pl->bcr[sid].dtop >= 0) dn_max = std::max(dn_max, (long long)pl->bcr[sid].dm * pl->subs[sid].nb);
+  const long long dn2 = dn_max * dn_max;
   size_t freeb = 0, totb = 0;
   HIPCHK(hipMemGetInfo(&freeb, &totb));
   const long long budget = std::min<long long>((long long)(freeb / 2), 48LL << 30);
-  int batch = (int)std::max<long long>(1, budget / (per_sub * (long long)sizeof(cpx<double>)));
+  int batch = (int)std::max<long long>(1, budget / ((per_sub + dn2) * (long long)sizeof(cpx<double>)));
   batch = std::min(batch, pl->S);
-  Buf work, derr, dpiv, dj;
+  Buf work, derr, dpiv, dj, dwork, dpivd;
   CHK(work.alloc((size_t)batch * per_sub * sizeof(cpx<double>)));
+  if (dn_max > 0) {
+    CHK(dwork.alloc((size_t)batch * dn2 * sizeof(cpx<double>)));
+    CHK(dpivd.alloc((size_t)batch * dn_max * sizeof(int)));
+  }
   long long ninv = 0;
-  for (const SubDesc& S : pl->subs) ninv += S.nblk;
+  for (const SubDesc& S : pl->subs) ninv += S.nblk + 1;
   CHK(derr.alloc((size_t)ninv * sizeof(int)));
   HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)ninv * sizeof(int), st));
   const int maxinv = batch * (int)half;
@@ -591,21 +623,36 @@ int bcr_factor(dsd_plan* pl) {
       HIPCHK(hipGetLastError());
     }
     int maxtop = 0;
-    for (int sid = s0; sid < s1; ++sid) maxtop = std::max(maxtop, pl->bcr[sid].top);
+    for (int sid = s0; sid < s1; ++sid) maxtop = std::max(maxtop, etop(pl->bcr[sid]));
     for (int l = 0; l <= maxtop; ++l) {
       std::vector<BcrInvJob> inv;
       std::vector<BcrDiagUpd> du;
       std::vector<ZGemmJob> gw, gd1, gd2, ge;
       std::vector<BcrCopyJob> cp;
+      std::vector<BcrDenseJob> dns;
       const int rd = l & 1, wr_ = (l + 1) & 1;
       for (int sid = s0; sid < s1; ++sid) {
         const BcrSub& B = pl->bcr[sid];
-        if (l > B.top) continue;
+        if (l > etop(B)) continue;
         const SubDesc& S = pl->subs[sid];
         const int nb = S.nb;
         const long long nb2 = (long long)nb * nb;
         const std::vector<int>& c = B.lev[l];
         const int len = (int)c.size();
+        if (l == B.dtop) {
+          // the reduced system left at this level, inverted as one dense matrix
+          const int first = c[0], stride = c[1] - c[0];
+          for (int q = 0; q < len; ++q) bad_off |= c[q] != first + q * stride;
+          const long long n = (long long)len * nb;
+          const BcrDenseJob dj_{nb, len, first, stride, blk, D(sid, 0), E(sid, rd, 0),
+                                (long long)(sid - s0) * dn2, B.dense};
+          for (int q = 0; q < len; ++q) bad_off |= !inw(D(sid, c[q]), nb);
+          for (int q = 0; q + 1 < len; ++q) bad_off |= !inw(E(sid, rd, q), nb);
+          bad_off |= n > dn_max || dj_.out + n * n > (long long)batch * dn2 ||
+                     B.dense < 0 || B.dense + n * n > pl->sum_fac;
+          dns.push_back(dj_);
+          continue;
+        }
         for (int p = 0; p < len; p += 2)
           inv.push_back(BcrInvJob{nb, 0, D(sid, c[p]), S.fac_off + (long long)c[p] * nb2});
         if (l == B.top) continue;
@@ -653,6 +700,32 @@ int bcr_factor(dsd_plan* pl) {
       if (bad_off) {
         g_detail = "internal error: cyclic-reduction factor job outside its buffer";
         return DSD_EINVAL;
+      }
+      if (!dns.empty()) {
+        // dense top level: assemble, invert in FP64 (Gauss-Jordan), round into row blocks
+        std::vector<BcrInvJob> dinv;
+        for (const BcrDenseJob& j : dns) dinv.push_back(BcrInvJob{j.nb * j.m, 0, j.out, -1});
+        std::vector<unsigned char> pack(dns.size() * sizeof(BcrDenseJob) + dinv.size() * sizeof(BcrInvJob));
+        memcpy(pack.data(), dns.data(), dns.size() * sizeof(BcrDenseJob));
+        memcpy(pack.data() + dns.size() * sizeof(BcrDenseJob), dinv.data(), dinv.size() * sizeof(BcrInvJob));
+        CHK(put(pack.data(), pack.size()));
+        const BcrDenseJob* ddj = dj.as<BcrDenseJob>();
+        const BcrInvJob* dij = reinterpret_cast<const BcrInvJob*>(dj.as<unsigned char>() +
+                                                                   dns.size() * sizeof(BcrDenseJob));
+        cpx<double>* DW = dwork.as<cpx<double>>();
+        launch_bcr_dense_build(ddj, (int)dns.size(), (int)dn_max, W, DW, st);
+        if (pl->c64) {
+          launch_bcr_invert<float>(dij, (int)dinv.size(), (int)dn_max, DW, pl->d_fac.as<cpx<float>>(),
+                                   derr.as<int>() + err_off, dpivd.as<int>(), st);
+          launch_bcr_dense_store<float>(ddj, (int)dns.size(), (int)dn_max, DW, pl->d_fac.as<cpx<float>>(), st);
+        } else {
+          launch_bcr_invert<double>(dij, (int)dinv.size(), (int)dn_max, DW, pl->d_fac.as<cpx<double>>(),
+                                    derr.as<int>() + err_off, dpivd.as<int>(), st);
+          launch_bcr_dense_store<double>(ddj, (int)dns.size(), (int)dn_max, DW,
+                                         pl->d_fac.as<cpx<double>>(), st);
+        }
+        err_off += (long long)dinv.size();
+        HIPCHK(hipGetLastError());
       }
       // inversions of the eliminated blocks (FP64 in place; rounded copy into the factor)
       CHK(put(inv.data(), inv.size() * sizeof(BcrInvJob)));
@@ -715,7 +788,7 @@ int bcr_factor(dsd_plan* pl) {
 void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
                     std::vector<BcrLaunch>& out) {
   int maxtop = 0;
-  for (const int2& m : mem) maxtop = std::max(maxtop, pl->bcr[m.x].top);
+  for (const int2& m : mem) maxtop = std::max(maxtop, etop(pl->bcr[m.x]));
   const double ts = (double)tsize(pl);
   int maxblk = 1;
   for (const SubDesc& S : pl->subs) maxblk = std::max(maxblk, S.nblk);
@@ -728,15 +801,15 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
     return per_sub >= pl->cg_wide ? 1 : (per_sub >= pl->cg_mid ? 2 : 4);
   };
   int cur_cg = 1;
-  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, cur_cg, 0.0, 0.0}; };
+  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, cur_cg, 0, 0.0, 0.0}; };
   auto finish = [&](BcrLaunch& L) {
     L.n = (int)jobs.size() - L.off;
     if (L.n > 0) out.push_back(L);
   };
   auto add = [&](BcrLaunch& L, const int2& m, int blk, int mode, int nl, int nr, long long m0,
-                 long long m1, long long m2, int nmat, int nvec) {
+                 long long m1, long long m2, int nmat, int nvec, int pad = 0) {
     const SubDesc& S = pl->subs[m.x];
-    jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, S.nb, 0, m0, m1, m2, S.nloc,
+    jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, S.nb, pad, m0, m1, m2, S.nloc,
                           S.vec_off * pl->kmax, S.coef_off});
     L.nset = std::max(L.nset, nmat);
     L.fbytes += (double)nmat * S.nb * S.nb * ts;
@@ -766,7 +839,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
     BcrLaunch L = begin(0);
     for (const int2& m : mem) {
       const BcrSub& B = pl->bcr[m.x];
-      if (f >= B.top) continue;
+      if (f >= etop(B)) continue;
       const std::vector<int>& c = B.lev[f];
       const int len = (int)c.size();
       for (int q = 1; q < len; q += 2) {
@@ -778,12 +851,28 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
     finish(L);
   }
   for (int b = maxtop; b >= 0; --b) {
+    // dense top levels: one job per block row of the inverse, in a launch of
+    // their own (fixed shape: one row tile, eight column groups)
+    cur_cg = 8;
+    BcrLaunch Ld = begin(0);
+    Ld.rt = 1;
+    for (const int2& m : mem) {
+      const BcrSub& B = pl->bcr[m.x];
+      const SubDesc& S = pl->subs[m.x];
+      if (b != B.dtop) continue;
+      const std::vector<int>& c = B.lev[b];
+      const int len = (int)c.size();
+      const long long rows = (long long)S.nb * len * S.nb;   // one row block: nb x (len nb)
+      for (int q = 0; q < len; ++q)
+        add(Ld, m, c[q], BCR_DENSE, c[0], c[1] - c[0], B.dense + q * rows, 0, 0, len, len + 1, len);
+    }
+    finish(Ld);
     cur_cg = level_cg(b);
     BcrLaunch L = begin(0);
     for (const int2& m : mem) {
       const BcrSub& B = pl->bcr[m.x];
       const SubDesc& S = pl->subs[m.x];
-      if (b > B.top) continue;
+      if (b > etop(B) || b == B.dtop) continue;
       const std::vector<int>& c = B.lev[b];
       const int len = (int)c.size();
       if (b == B.top) {
@@ -817,7 +906,7 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
         ok = false;
       auto blk_ok = [&](int b) { return b >= 0 && b < S.nblk; };
       auto mat_ok = [&](long long o) { return o >= 0 && o + nb2 <= pl->sum_fac; };
-      ok = blk_ok(J.blk) && (J.nl == -1 || blk_ok(J.nl)) && (J.nr == -1 || blk_ok(J.nr));
+      ok = ok && blk_ok(J.blk) && (J.nl == -1 || blk_ok(J.nl)) && (J.nr == -1 || blk_ok(J.nr));
       const bool hl = J.nl >= 0, hr = J.nr >= 0;
       switch (J.mode) {
         case BCR_PR: ok = ok && mat_ok(J.m0); break;
@@ -828,6 +917,14 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
                (J.mode == BCR_DFWD || mat_ok(J.m0));
           break;
         case BCR_BWD: ok = ok && mat_ok(J.m0) && (!hl || mat_ok(J.m1)) && (!hr || mat_ok(J.m2)); break;
+        case BCR_DENSE: {
+          // blocks nl + q nr, q < pad, of one reduction level; matrix nb x (pad nb)
+          const int m = J.pad;
+          ok = ok && m >= 2 && hl && J.nr >= 1 && (long long)J.nl + (long long)(m - 1) * J.nr < S.nblk &&
+               (J.blk - J.nl) % J.nr == 0 && J.blk >= J.nl && (J.blk - J.nl) / J.nr < m &&
+               J.m0 >= 0 && J.m0 + (long long)m * nb2 <= pl->sum_fac;
+          break;
+        }
         default: ok = false;
       }
     }
@@ -1020,7 +1117,7 @@ void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
     return;
   }
   if (pl->timing) (void)hipEventRecord(pl->ev0, st);
-  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, nrhs,
+  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, L.rt, nrhs,
                       pl->kmax, pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
   if (pl->timing) {
     (void)hipEventRecord(pl->ev1, st);
@@ -1383,13 +1480,34 @@ int check_receivers(const dsd_plan* pl, const long long* rec_dev, int nrec) {
   return 0;
 }
 
-int choose_kg(const dsd_plan* pl, int want) {
+int device_lds() {
   int dev = 0, lds = 65536;
   if (hipGetDevice(&dev) == hipSuccess) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
       lds = v;
   }
+  return lds;
+}
+
+// Largest reduced system (in blocks) the cyclic reduction solves densely: the
+// requested bound (default 8), lowered until the dense solve launch fits the
+// LDS at the widest RHS group the plan may use, and its order m nb <= 2048.
+int dense_blocks(const dsd_plan* pl, int req) {
+  if (req < 0) return 0;
+  int m = req > 0 ? req : 8;
+  const int lds = device_lds();
+  const int kgcap = pl->c64 ? bcr_kg<float>(pl->max_nb, 16) : bcr_kg<double>(pl->max_nb, 16);
+  auto need = [&](int mm) {
+    return pl->c64 ? bcr_launch_lds_bytes<float>(pl->max_nb, kgcap, mm, 8, 1)
+                   : bcr_launch_lds_bytes<double>(pl->max_nb, kgcap, mm, 8, 1);
+  };
+  while (m >= 2 && (need(m) > (size_t)lds || (long long)m * pl->max_nb > 2048)) --m;
+  return m >= 2 ? m : 0;
+}
+
+int choose_kg(const dsd_plan* pl, int want) {
+  const int lds = device_lds();
   if (pl->solver == 2) {
     int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
     auto need = [&](int k) {
@@ -1422,9 +1540,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   const dsd_params& q = *params;
   if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
       (q.precision != DSD_C64 && q.precision != DSD_C128) || q.local_solver < 0 ||
-      q.local_solver > 2 || q.schedule < 0 || q.schedule > 1) {
+      q.local_solver > 2 || q.schedule < 0 || q.schedule > 1 || q.dense_top < -1 ||
+      q.dense_top > 64) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
-               "local_solver 0..2, schedule 0..1";
+               "local_solver 0..2, schedule 0..1, dense_top -1..64";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)
@@ -1450,6 +1569,7 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
     const long long tsum = pl->sum_fac;
     pl->solver = q.local_solver == 1 ? 1 : 2;
     if (pl->solver == 2) {
+      pl->dense_max = dense_blocks(pl, q.dense_top);
       bcr_layout(pl);
       size_t fr = 0, tot = 0;
       if (q.local_solver == 0 && hipMemGetInfo(&fr, &tot) == hipSuccess &&

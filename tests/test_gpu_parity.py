@@ -17,11 +17,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="auto"):
+def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="auto", dense_top=0):
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(slowness2(c)).cuda()
     return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
-                    max_rhs=k, rhs_per_group=kg, schedule=schedule, local_solver=solver)
+                    max_rhs=k, rhs_per_group=kg, schedule=schedule, local_solver=solver,
+                    dense_top=dense_top)
 
 
 SOLVERS = ["bcr", "chain"]
@@ -206,6 +207,31 @@ def test_cyclic_reduction_equals_chains(name):
     a = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="bcr").sweep_apply(f).cpu().numpy()
     b = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain").sweep_apply(f).cpu().numpy()
     assert rel(a, b) < 1e-12
+
+
+@pytest.mark.parametrize("dense_top", [-1, 2, 3, 8])
+@pytest.mark.parametrize("name", ["c1", "rag34", "wide2", "d3"])
+def test_dense_top_level_matches_oracle(name, dense_top):
+    """Stopping the reduction at a small level and applying that reduced system's
+    dense inverse solves the same local problems (c128 to rounding) as reducing
+    to a single block (dense_top = -1)."""
+    n, h, om, pml, d, parts, c = _case(name)
+    k = 3
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k, solver="bcr", dense_top=dense_top)
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    nsub = int(np.prod(parts))
+    for sid in sorted({0, nsub - 1}):
+        sp = ddm.spaces[sub_tuple(sid, parts)]
+        rng = np.random.default_rng(sid + 7)
+        r = rng.standard_normal((k, sp.N)) + 1j * rng.standard_normal((k, sp.N))
+        u_ref = sp.solve(r.T).T
+        u = plan.local_solve(sid, _cuda(r.reshape((k,) + sp.shape))).cpu().numpy().reshape(k, -1)
+        print(f"{name} dense_top={dense_top} sub {sid}: rel err {rel(u, u_ref):.2e}", flush=True)
+        assert rel(u, u_ref) < 1e-11
+    f = sources(n, h, pml, k)
+    u_ref = ddm.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    assert rel(u, u_ref) < 1e-10
 
 
 @pytest.mark.parametrize("prec,tol,bound", [("c128", 1e-12, 1e-10), ("c64", 1e-11, 1e-8)])
