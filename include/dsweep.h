@@ -118,14 +118,29 @@ int dsd_set_graph(dsd_plan* plan, int on);
 /* Autotuner: times `reps` preconditioner applications of `nrhs` right-hand
  * sides for every candidate shape of the subdomain-solve launches -- RHS per
  * workgroup (2, 4, 8, 16 as the LDS and register budgets allow) and, for the
- * cyclic reduction, the thresholds that decide how many wave groups split the
- * columns of the jobs of each reduction level -- and keeps the fastest in the
+ * cyclic reduction, a set of level-shape policies: two thresholds on the blocks
+ * per subdomain left at a level split the levels into wide, middle and deep
+ * ones, and each class has its own count of wave groups splitting the columns
+ * of a job and of 64-row tiles per workgroup -- and keeps the fastest in the
  * plan.  Results of later calls may change at rounding level (a different
  * summation order), never more.  Outputs (host, may be NULL): the chosen RHS
- * per workgroup, the two thresholds, and the time of one application (ms).
- * Captured graphs are dropped.  Synchronises the stream. */
+ * per workgroup, the two thresholds of the chosen policy, and the time of one
+ * application (ms).  Captured graphs are dropped.  Synchronises the stream. */
 int dsd_autotune(dsd_plan* plan, int nrhs, int reps, int* kg_host, int* cg_wide_host,
                  int* cg_mid_host, double* ms_host, void* stream);
+
+/* Launch shape of the subdomain solves as 11 ints: RHS per workgroup, then
+ * the cyclic-reduction level policy: cg_wide, cg_mid (thresholds on the blocks
+ * per subdomain left at a level that make it a wide, middle or deep level),
+ * (wide_cg, wide_rt), (mid_cg, mid_rt), (deep_cg, deep_rt) (wave groups
+ * splitting the columns of a job, 64-row tiles per workgroup: rt 0 = up to 4),
+ * dense_cg, and wide_kg (RHS per workgroup on the wide levels; 0 = the first
+ * entry).  get writes the plan's current shape (for instance after
+ * dsd_autotune); set applies a saved one without timing anything (rt 0 with
+ * cg 1..4 or rt 1 with cg 1..12; RHS-per-workgroup entries must be ones the
+ * plan supports, else DSD_EINVAL).  set drops captured graphs. */
+int dsd_get_solve_shape(const dsd_plan* plan, int* shape11_host);
+int dsd_set_solve_shape(dsd_plan* plan, const int* shape11_host);
 
 /* Local grid of subdomain `sub` (lexicographic index, x part fastest):
  * dims[3] = local cells per axis, g0[3] = global array index of its first cell

@@ -184,7 +184,20 @@ class Plan:
         check(self._lib.dsd_autotune(self._h, k, int(reps), C.byref(kg), C.byref(cw), C.byref(cm),
                                      C.byref(ms), _stream_ptr()), "dsd_autotune")
         return {"rhs_per_group": kg.value, "cg_wide": cw.value, "cg_mid": cm.value,
-                "ms_per_application": ms.value}
+                "ms_per_application": ms.value, "shape": self.solve_shape}
+
+    @property
+    def solve_shape(self) -> tuple:
+        """Launch shape of the subdomain solves (11 ints: RHS per workgroup, then the
+        cyclic-reduction level policy); set it to reuse an autotuned shape."""
+        v = (C.c_int * 11)()
+        check(self._lib.dsd_get_solve_shape(self._h, v), "dsd_get_solve_shape")
+        return tuple(v)
+
+    @solve_shape.setter
+    def solve_shape(self, shape):
+        v = (C.c_int * 11)(*[int(x) for x in shape])
+        check(self._lib.dsd_set_solve_shape(self._h, v), "dsd_set_solve_shape")
 
     def use_graph(self, on: bool = True):
         """Run preconditioner applications as captured HIP graphs."""

@@ -29,6 +29,8 @@ EXPORTS = {
     "dsd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),
                                C.c_void_p]),
+    "dsd_get_solve_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "dsd_set_solve_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
     "dsd_subdomain_grid": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int),
                                      C.POINTER(C.c_int)]),
     "dsd_local_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,

@@ -1384,14 +1384,17 @@ size_t bcr_launch_lds_bytes(int max_nb, int kg, int nset, int cg, int rt) {
   return (b + 255) / 256 * 256;
 }
 
-// Largest LDS a launch of the level-by-level shapes (CG up to 4) can ask for.
+// Largest LDS a launch of the level-by-level shapes can ask for (CG up to 4
+// at the default row tiles, up to 12 at one row tile).
 template <typename T>
 size_t bcr_lds_bytes(int max_nb, int kg, int nset) {
   size_t b = 0;
-  for (int cg = 1; cg <= 4; cg *= 2) {
-    const size_t v = bcr_launch_lds_bytes<T>(max_nb, kg, nset, cg, 0);
-    b = v > b ? v : b;
-  }
+  for (int cg = 1; cg <= 12; ++cg)
+    for (int rt : {0, 1}) {
+      if (rt == 0 && cg > 4) continue;
+      const size_t v = bcr_launch_lds_bytes<T>(max_nb, kg, nset, cg, rt);
+      b = v > b ? v : b;
+    }
   return b;
 }
 

@@ -133,6 +133,7 @@ struct BcrLaunch {
   int nset;          // most matrices (operand vectors) of one job
   int cg;            // wave groups splitting the columns (from the level only)
   int rt;            // most 64-row tiles per workgroup (0: default)
+  int kg;            // RHS per workgroup (0: the plan's)
   double fbytes;     // factor bytes streamed (once per launch)
   double vcells;     // vector entries read and written per right-hand side
 };
@@ -154,8 +155,14 @@ struct dsd_plan {
   std::vector<std::vector<BcrLaunch>> bcr_launch;   // per launch group
   std::vector<BcrLaunch> bcr_single;                // dsd_local_solve (jobs in d_single_job)
   std::vector<std::vector<int2>> groups;            // launch groups: {subdomain, sweep}
-  int cg_wide = 32, cg_mid = 8;   // column groups: 1 while >= cg_wide blocks per subdomain
-                                  // remain at a level, 2 while >= cg_mid, else 4
+  // launch shape of a reduction level: (wide_cg, wide_rt) column groups and
+  // row tiles per workgroup while >= cg_wide blocks per subdomain remain at the
+  // level, (mid_cg, mid_rt) while >= cg_mid remain, else (deep_cg, deep_rt);
+  // dense jobs use (dense_cg, one row tile).  Only the column groups change
+  // the summation order.
+  int cg_wide = 64, cg_mid = 16;
+  int wide_cg = 1, wide_rt = 0, mid_cg = 4, mid_rt = 1, deep_cg = 8, deep_rt = 1, dense_cg = 8;
+  int wide_kg = 0;                // RHS per workgroup on the wide levels (0: kg)
   int dense_max = 0;              // largest reduced system solved densely (0: none)
   Buf d_bcr_jobs;
   long long sum_nloc = 0, sum_fac = 0;
@@ -796,12 +803,17 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   // wave per row tile; the deep levels split the columns to shorten each job.
   // It depends on the level and the plan's thresholds only, never on the
   // launch, so every schedule sums every job in the same order.
-  auto level_cg = [&](int lev) {
+  int cur_cg = 1, cur_rt = 0, cur_kg = 0;
+  auto level_shape = [&](int lev) {
     const int per_sub = maxblk >> (lev + 1);
-    return per_sub >= pl->cg_wide ? 1 : (per_sub >= pl->cg_mid ? 2 : 4);
+    cur_kg = 0;
+    if (per_sub >= pl->cg_wide) { cur_cg = pl->wide_cg; cur_rt = pl->wide_rt; cur_kg = pl->wide_kg; }
+    else if (per_sub >= pl->cg_mid) { cur_cg = pl->mid_cg; cur_rt = pl->mid_rt; }
+    else { cur_cg = pl->deep_cg; cur_rt = pl->deep_rt; }
   };
-  int cur_cg = 1;
-  auto begin = [&](int dfwd) { return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, cur_cg, 0, 0.0, 0.0}; };
+  auto begin = [&](int dfwd) {
+    return BcrLaunch{(int)jobs.size(), 0, dfwd, 1, cur_cg, cur_rt, cur_kg, 0.0, 0.0};
+  };
   auto finish = [&](BcrLaunch& L) {
     L.n = (int)jobs.size() - L.off;
     if (L.n > 0) out.push_back(L);
@@ -817,7 +829,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   };
   auto Pk = [&](const SubDesc& S, int k) { return S.fac_off + (long long)k * S.nb * S.nb; };
   for (int f = 0; f < maxtop; ++f) {
-    cur_cg = level_cg(f);
+    level_shape(f);
     if (f == 0) {
       BcrLaunch L = begin(0);
       for (const int2& m : mem) {
@@ -852,10 +864,11 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   }
   for (int b = maxtop; b >= 0; --b) {
     // dense top levels: one job per block row of the inverse, in a launch of
-    // their own (fixed shape: one row tile, eight column groups)
-    cur_cg = 8;
+    // their own (one row tile per workgroup)
+    cur_cg = pl->dense_cg;
+    cur_rt = 1;
+    cur_kg = 0;
     BcrLaunch Ld = begin(0);
-    Ld.rt = 1;
     for (const int2& m : mem) {
       const BcrSub& B = pl->bcr[m.x];
       const SubDesc& S = pl->subs[m.x];
@@ -867,7 +880,7 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
         add(Ld, m, c[q], BCR_DENSE, c[0], c[1] - c[0], B.dense + q * rows, 0, 0, len, len + 1, len);
     }
     finish(Ld);
-    cur_cg = level_cg(b);
+    level_shape(b);
     BcrLaunch L = begin(0);
     for (const int2& m : mem) {
       const BcrSub& B = pl->bcr[m.x];
@@ -1117,7 +1130,7 @@ void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
     return;
   }
   if (pl->timing) (void)hipEventRecord(pl->ev0, st);
-  launch_bcr_solve<T>(pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, L.rt, nrhs,
+  launch_bcr_solve<T>(L.kg > 0 ? L.kg : pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, L.rt, nrhs,
                       pl->kmax, pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
   if (pl->timing) {
     (void)hipEventRecord(pl->ev1, st);
@@ -1499,8 +1512,8 @@ int dense_blocks(const dsd_plan* pl, int req) {
   const int lds = device_lds();
   const int kgcap = pl->c64 ? bcr_kg<float>(pl->max_nb, 16) : bcr_kg<double>(pl->max_nb, 16);
   auto need = [&](int mm) {
-    return pl->c64 ? bcr_launch_lds_bytes<float>(pl->max_nb, kgcap, mm, 8, 1)
-                   : bcr_launch_lds_bytes<double>(pl->max_nb, kgcap, mm, 8, 1);
+    return pl->c64 ? bcr_launch_lds_bytes<float>(pl->max_nb, kgcap, mm, 12, 1)
+                   : bcr_launch_lds_bytes<double>(pl->max_nb, kgcap, mm, 12, 1);
   };
   while (m >= 2 && (need(m) > (size_t)lds || (long long)m * pl->max_nb > 2048)) --m;
   return m >= 2 ? m : 0;
@@ -1662,38 +1675,68 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
     const int kk = choose_kg(pl, k);
     if (kk > 0 && std::find(kgs.begin(), kgs.end(), kk) == kgs.end()) kgs.push_back(kk);
   }
-  const int pols[][2] = {{32, 8}, {64, 16}, {16, 4}, {1 << 30, 1 << 30}, {32, 1 << 30}};
-  const int best0_kg = pl->kg, best0_w = pl->cg_wide, best0_m = pl->cg_mid;
+  // shape policies: {cg_wide, cg_mid, wide_cg, wide_rt, mid_cg, mid_rt, deep_cg, deep_rt, dense_cg}
+  const int inf = 1 << 30;
+  const int pols[][9] = {
+      {32, 8, 1, 0, 4, 1, 8, 1, 8},   {32, 8, 1, 0, 2, 0, 4, 0, 8},   {32, 8, 1, 0, 4, 1, 12, 1, 12},
+      {64, 16, 1, 0, 4, 1, 8, 1, 8},  {16, 4, 1, 0, 4, 1, 8, 1, 8},   {32, 8, 2, 0, 4, 1, 8, 1, 8},
+      {64, 8, 1, 0, 4, 1, 12, 1, 12}, {32, 8, 1, 0, 2, 1, 8, 1, 4},   {inf, inf, 1, 0, 1, 0, 1, 0, 8}};
+  auto get = [&](int* v) {
+    const int t[10] = {pl->cg_wide, pl->cg_mid, pl->wide_cg, pl->wide_rt,  pl->mid_cg,
+                       pl->mid_rt,  pl->deep_cg, pl->deep_rt, pl->dense_cg, pl->wide_kg};
+    for (int i = 0; i < 10; ++i) v[i] = t[i];
+  };
+  auto set = [&](const int* v) {
+    pl->cg_wide = v[0]; pl->cg_mid = v[1]; pl->wide_cg = v[2]; pl->wide_rt = v[3]; pl->mid_cg = v[4];
+    pl->mid_rt = v[5]; pl->deep_cg = v[6]; pl->deep_rt = v[7]; pl->dense_cg = v[8]; pl->wide_kg = v[9];
+  };
+  const int best0_kg = pl->kg;
+  int best0[10], bpol[10];
+  get(best0);
+  get(bpol);
   double best = 1e300;
-  int bkg = best0_kg, bw = best0_w, bm = best0_m;
+  int bkg = best0_kg;
   hipEvent_t a = nullptr, b = nullptr;
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
   int rc = 0;
+  // the wide levels may use a wider RHS group than the rest (each wide job
+  // then streams its matrices once for all of them)
+  std::vector<int> wkgs{0};
+  if (pl->solver == 2 && !kgs.empty() && kgs.back() > kgs.front()) wkgs.push_back(kgs.back());
   for (int kg : kgs) {
-    for (const auto& pol : pols) {
-      pl->kg = kg;
-      pl->cg_wide = pol[0];
-      pl->cg_mid = pol[1];
-      if ((rc = build_bcr_jobs(pl)) != 0) break;
-      if ((rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs)) != 0) break;
-      (void)hipEventRecord(a, st);
-      for (int r = 0; r < reps && rc == 0; ++r)
-        rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs);
-      (void)hipEventRecord(b, st);
-      if (rc != 0 || hipEventSynchronize(b) != hipSuccess) { rc = rc ? rc : DSD_EHIP; break; }
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, a, b);
-      if (ms / reps < best) { best = ms / reps; bkg = kg; bw = pol[0]; bm = pol[1]; }
-      if (pl->solver != 2) break;             // the thresholds only shape the reduction
+    for (int wkg : wkgs) {
+      if (wkg != 0 && wkg <= kg) continue;
+      for (const auto& pol : pols) {
+        int v[10];
+        for (int i = 0; i < 9; ++i) v[i] = pol[i];
+        v[9] = wkg;
+        pl->kg = kg;
+        set(v);
+        if ((rc = build_bcr_jobs(pl)) != 0) break;
+        if ((rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs)) != 0) break;
+        (void)hipEventRecord(a, st);
+        for (int r = 0; r < reps && rc == 0; ++r)
+          rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs);
+        (void)hipEventRecord(b, st);
+        if (rc != 0 || hipEventSynchronize(b) != hipSuccess) { rc = rc ? rc : DSD_EHIP; break; }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms / reps < best) {
+          best = ms / reps;
+          bkg = kg;
+          for (int i = 0; i < 10; ++i) bpol[i] = v[i];
+        }
+        if (pl->solver != 2) break;             // the policies only shape the reduction
+      }
+      if (rc != 0) break;
     }
     if (rc != 0) break;
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   pl->kg = rc == 0 ? bkg : best0_kg;
-  pl->cg_wide = rc == 0 ? bw : best0_w;
-  pl->cg_mid = rc == 0 ? bm : best0_m;
+  set(rc == 0 ? bpol : best0);
   const int rc2 = build_bcr_jobs(pl);
   pl->timing = was_timing;
   if (rc != 0) return rc;
@@ -1704,6 +1747,35 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
   if (ms_host) *ms_host = best;
   HIPCHK(hipStreamSynchronize(st));
   return DSD_OK;
+}
+
+int dsd_get_solve_shape(const dsd_plan* pl, int* v) {
+  if (!pl || !v) return DSD_EINVAL;
+  const int t[11] = {pl->kg,     pl->cg_wide, pl->cg_mid,  pl->wide_cg, pl->wide_rt, pl->mid_cg,
+                     pl->mid_rt, pl->deep_cg, pl->deep_rt, pl->dense_cg, pl->wide_kg};
+  for (int i = 0; i < 11; ++i) v[i] = t[i];
+  return DSD_OK;
+}
+
+int dsd_set_solve_shape(dsd_plan* pl, const int* v) {
+  g_detail.clear();
+  if (!pl || !v) { g_detail = "null argument"; return DSD_EINVAL; }
+  auto shape_ok = [](int cg, int rt) { return (rt == 0 && cg >= 1 && cg <= 4) || (rt == 1 && cg >= 1 && cg <= 12); };
+  const int kg = choose_kg(pl, v[0]);
+  const bool wkg_ok = v[10] == 0 || (v[10] >= 1 && choose_kg(pl, v[10]) == v[10]);
+  if (v[0] < 1 || kg != v[0] || v[1] < 1 || v[2] < 1 || !shape_ok(v[3], v[4]) || !shape_ok(v[5], v[6]) ||
+      !shape_ok(v[7], v[8]) || v[9] < 1 || v[9] > 12 || !wkg_ok) {
+    g_detail = "solve shape: RHS per workgroup the plan supports, thresholds >= 1, (cg, rt) with rt 0 "
+               "and cg 1..4 or rt 1 and cg 1..12, dense cg 1..12, wide-level RHS per workgroup 0 or supported";
+    return DSD_EINVAL;
+  }
+  pl->kg = v[0];
+  pl->cg_wide = v[1]; pl->cg_mid = v[2]; pl->wide_cg = v[3]; pl->wide_rt = v[4];
+  pl->mid_cg = v[5]; pl->mid_rt = v[6]; pl->deep_cg = v[7]; pl->deep_rt = v[8]; pl->dense_cg = v[9];
+  pl->wide_kg = v[10];
+  for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);   // tables change
+  pl->graphs.clear();
+  return build_bcr_jobs(pl);
 }
 
 int dsd_subdomain_grid(const dsd_plan* pl, int sub, int* dims, int* g0) {

@@ -139,6 +139,28 @@ def test_autotuned_plan_matches_oracle(prec, tol):
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
     print(f"autotune {prec}: {res}; vs oracle {rel(u, u_ref):.2e}", flush=True)
     assert rel(u, u_ref) < tol
+    # a saved shape applied to a fresh plan reproduces the tuned plan bitwise
+    plan2 = _plan(n, h, om, pml, d, parts, c, prec, k, solver="bcr")
+    plan2.solve_shape = res["shape"]
+    assert plan2.solve_shape == res["shape"]
+    u2 = plan2.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    assert np.array_equal(u2, u)
+
+
+@pytest.mark.parametrize("shape", [(4, 32, 8, 1, 0, 2, 0, 8, 1, 12, 8), (2, 16, 4, 2, 0, 4, 1, 12, 1, 4, 0),
+                                   (8, 1 << 30, 1 << 30, 1, 0, 1, 0, 1, 0, 8, 0),
+                                   (1, 8, 2, 12, 1, 3, 1, 1, 1, 1, 4)])
+def test_solve_shapes_match_oracle(shape):
+    """Every level-shape policy the autotuner may pick solves the same problem."""
+    n, h, om, pml, d, parts, c = _case("rag34")
+    k = 3
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k, solver="bcr")
+    plan.solve_shape = shape
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    u_ref = ddm.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    assert rel(u, u_ref) < 1e-10
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
