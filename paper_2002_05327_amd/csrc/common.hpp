@@ -94,6 +94,9 @@ struct SubDesc {
   int mid;            // block where the two elimination chains meet
 };
 
+// Most incoming transfers of one receiver in one sweep (26 directions in 3D).
+constexpr int MAX_IN_EDGES = 32;
+
 // One incoming transfer of a receiver in one sweep (pull model).
 struct Edge {
   int sender;

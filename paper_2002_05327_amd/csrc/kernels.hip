@@ -1533,20 +1533,38 @@ __device__ inline bool in_box(const Edge& e, const int c[3]) {
 // group of up to PR right-hand sides starting at r0: for every incoming edge
 // whose box holds c, g = -M (beta_t v) evaluated with the sender's stencil and
 // the sender solutions of the sweeps in the edge's mask (Section 2.2).  The
-// stencil weights (coefficient times cutoff) are formed once per group.
-constexpr int PULL_R = 2;
-
+// stencil weights (coefficient times cutoff) are formed once per edge and
+// group; every load of a sweep's solutions is independent of the others (a
+// stencil point off the grid or outside the cutoff reads the centre cell and
+// is dropped), so they are all in flight together.
 template <typename T>
+constexpr int pull_r() { return sizeof(T) == 4 ? 4 : 2; }   // RHS per thread
+
+template <typename T, int NST>
 __global__ __launch_bounds__(256) void k_pull(Problem P, const SubDesc* subs, const int2* members, const Edge* edges,
                        const int2* erange, int nrhs, int kmax, const cpx<T>* vpool,
                        long long pool_stride, const cpx<T>* diag, const cpx<T>* cx,
                        const cpx<T>* cy, const cpx<T>* cz, cpx<T>* rpool) {
   const int2 mb = members[blockIdx.z];
   const int2 er = erange[blockIdx.z];
+  constexpr int PULL_R = pull_r<T>();
   const int r0 = blockIdx.y * PULL_R;
-  if (r0 >= nrhs || er.y <= 0) return;
-  const Edge* E = edges + er.x;
+  if (r0 >= nrhs || er.y <= 0) return;   // uniform over the workgroup
+  // the member's edges and their senders' descriptors, staged in LDS
+  __shared__ Edge E[MAX_IN_EDGES];
+  __shared__ SubDesc SS[MAX_IN_EDGES];
   const int ne = er.y;
+  {
+    constexpr int EW = (int)(sizeof(Edge) / sizeof(int)), SW = (int)(sizeof(SubDesc) / sizeof(int));
+    const int* src = reinterpret_cast<const int*>(edges + er.x);
+    for (int i = threadIdx.x; i < ne * EW; i += blockDim.x) reinterpret_cast<int*>(E)[i] = src[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * SW; i += blockDim.x) {
+      const int e = i / SW, w_ = i - e * SW;
+      reinterpret_cast<int*>(&SS[e])[w_] = reinterpret_cast<const int*>(subs + E[e].sender)[w_];
+    }
+    __syncthreads();
+  }
   int f = blockIdx.x * blockDim.x + threadIdx.x;
   int eidx = -1;
   for (int e = 0; e < ne; ++e) {
@@ -1567,44 +1585,64 @@ __global__ __launch_bounds__(256) void k_pull(Problem P, const SubDesc* subs, co
   cpx<T> acc[PULL_R];
 #pragma unroll
   for (int k = 0; k < PULL_R; ++k) acc[k] = mk((T)0, (T)0);
-  const int nst = P.dim == 3 ? 7 : 5;
   for (int e = eidx; e < ne; ++e) {
     const Edge& ed = E[e];
     if (!in_box<T>(ed, c)) continue;
-    const SubDesc& Sd = subs[ed.sender];
+    const SubDesc& Sd = SS[e];
     const int dm0 = Sd.dims[0], dm1 = Sd.dims[1], dm2 = Sd.dims[2];
     const int cs0 = c[0] + ed.off[0], cs1 = c[1] + ed.off[1], cs2 = c[2] + ed.off[2];
     const long long co = Sd.coef_off + ((long long)cs2 * dm1 + cs1) * dm0 + cs0;
     const long long plane = (long long)dm0 * dm1;
-    const cpx<T>* V = vpool + Sd.vec_off * kmax;
-    for (int st = 0; st < nst; ++st) {
-      // stencil point: 0 centre, 1/2 +-x, 3/4 +-y, 5/6 +-z
+    const long long cc = ((long long)cs2 * dm1 + cs1) * dm0 + cs0;
+    // stencil point st: 0 centre, 1/2 +-x, 3/4 +-y, 5/6 +-z
+    cpx<T> w[NST];
+    long long cell[NST];
+    bool live[NST];
+#pragma unroll
+    for (int st = 0; st < NST; ++st) {
       int p0 = cs0, p1 = cs1, p2 = cs2;
-      cpx<T> a;
-      if (st == 0) { a = diag[co]; }
-      else if (st == 1) { if (cs0 + 1 >= dm0) continue; p0 += 1; a = cx[co]; }
-      else if (st == 2) { if (cs0 <= 0) continue; p0 -= 1; a = cx[co - 1]; }
-      else if (st == 3) { if (cs1 + 1 >= dm1) continue; p1 += 1; a = cy[co]; }
-      else if (st == 4) { if (cs1 <= 0) continue; p1 -= 1; a = cy[co - dm0]; }
-      else if (st == 5) { if (cs2 + 1 >= dm2) continue; p2 += 1; a = cz[co]; }
-      else { if (cs2 <= 0) continue; p2 -= 1; a = cz[co - plane]; }
-      double beta = cutoff(Sd.pt[0], ed.t[0], Sd.ax[0].g0 + p0, P.d) *
-                    cutoff(Sd.pt[1], ed.t[1], Sd.ax[1].g0 + p1, P.d);
-      if (P.dim == 3) beta *= cutoff(Sd.pt[2], ed.t[2], Sd.ax[2].g0 + p2, P.d);
-      if (beta == 0.0) continue;
-      const cpx<T> wgt = (T)beta * a;
-      const long long cell = ((long long)p2 * dm1 + p1) * dm0 + p0;
+      bool ok = true;
+      long long ca = co;
+      const cpx<T>* arr = diag;
+      if (st == 1) { ok = ok && cs0 + 1 < dm0; p0 += 1; arr = cx; }
+      else if (st == 2) { ok = ok && cs0 > 0; p0 -= 1; arr = cx; ca = co - 1; }
+      else if (st == 3) { ok = ok && cs1 + 1 < dm1; p1 += 1; arr = cy; }
+      else if (st == 4) { ok = ok && cs1 > 0; p1 -= 1; arr = cy; ca = co - dm0; }
+      else if (st == 5) { ok = ok && cs2 + 1 < dm2; p2 += 1; arr = cz; }
+      else if (st == 6) { ok = ok && cs2 > 0; p2 -= 1; arr = cz; ca = co - plane; }
+      double beta = 0.0;
+      if (ok) {
+        beta = cutoff(Sd.pt[0], ed.t[0], Sd.ax[0].g0 + p0, P.d) *
+               cutoff(Sd.pt[1], ed.t[1], Sd.ax[1].g0 + p1, P.d);
+        if (NST == 7) beta *= cutoff(Sd.pt[2], ed.t[2], Sd.ax[2].g0 + p2, P.d);
+      }
+      live[st] = ok && beta != 0.0;
+      const cpx<T> a = arr[live[st] ? ca : co];
+      w[st] = (T)beta * a;
+      cell[st] = live[st] ? ((long long)p2 * dm1 + p1) * dm0 + p0 : cc;
+    }
+    // v[k][st] = sum over the masked sweeps of the sender solution at the point
+    cpx<T> v[PULL_R][NST];
+#pragma unroll
+    for (int k = 0; k < PULL_R; ++k)
+#pragma unroll
+      for (int st = 0; st < NST; ++st) v[k][st] = mk((T)0, (T)0);
+    const cpx<T>* V = vpool + Sd.vec_off * kmax;
+    for (int l = 0; l < 8; ++l) {
+      if (!(ed.lmask & (1u << l))) continue;   // uniform over the edge's box
+      const cpx<T>* Vl = V + l * pool_stride;
 #pragma unroll
       for (int k = 0; k < PULL_R; ++k) {
-        const int r = r0 + k;
-        if (r < nrhs) {
-          cpx<T> v = mk((T)0, (T)0);
-          for (int l = 0; l < 8; ++l)
-            if (ed.lmask & (1u << l)) v = v + V[l * pool_stride + (long long)r * Sd.nloc + cell];
-          acc[k] = acc[k] + wgt * v;
-        }
+        const int r = min(r0 + k, nrhs - 1);
+#pragma unroll
+        for (int st = 0; st < NST; ++st) v[k][st] = v[k][st] + Vl[(long long)r * Sd.nloc + cell[st]];
       }
     }
+#pragma unroll
+    for (int k = 0; k < PULL_R; ++k)
+#pragma unroll
+      for (int st = 0; st < NST; ++st)
+        if (live[st]) acc[k] = acc[k] + w[st] * v[k][st];
   }
   const SubDesc& R = subs[mb.x];
   const long long cell = ((long long)c[2] * R.dims[1] + c[1]) * R.dims[0] + c[0];
@@ -1623,9 +1661,14 @@ void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members,
                  const cpx<T>* diag, const cpx<T>* cx, const cpx<T>* cy, const cpx<T>* cz,
                  cpx<T>* rpool, hipStream_t s) {
   if (nmem <= 0 || nrhs <= 0 || max_box_cells <= 0) return;
-  dim3 grid(cdiv_u(max_box_cells, 256), (nrhs + PULL_R - 1) / PULL_R, nmem);
-  hipLaunchKernelGGL(k_pull<T>, grid, dim3(256), 0, s, P, d_subs, d_members, d_edges,
-                     d_edge_range, nrhs, kmax, vpool, pool_stride, diag, cx, cy, cz, rpool);
+  constexpr int PR = pull_r<T>();
+  dim3 grid(cdiv_u(max_box_cells, 256), (nrhs + PR - 1) / PR, nmem);
+  if (P.dim == 3)
+    hipLaunchKernelGGL((k_pull<T, 7>), grid, dim3(256), 0, s, P, d_subs, d_members, d_edges,
+                       d_edge_range, nrhs, kmax, vpool, pool_stride, diag, cx, cy, cz, rpool);
+  else
+    hipLaunchKernelGGL((k_pull<T, 5>), grid, dim3(256), 0, s, P, d_subs, d_members, d_edges,
+                       d_edge_range, nrhs, kmax, vpool, pool_stride, diag, cx, cy, cz, rpool);
 }
 
 // ============================================================================

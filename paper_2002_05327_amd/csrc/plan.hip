@@ -448,6 +448,10 @@ int build_schedule(dsd_plan* pl) {
       jobs2.push_back(make_int4(mb.x, 1, mb.y, 0));
       jobs1.push_back(make_int4(mb.x, 0, mb.y, 0));
       const int2 er = edge_of[(size_t)mb.y * pl->S + mb.x];
+      if (er.y > MAX_IN_EDGES) {
+        g_detail = "internal error: more incoming transfers than the pull kernel stages";
+        return DSD_EINVAL;
+      }
       erange.push_back(er);
       long long box = 0;
       for (int e = er.x; e < er.x + er.y; ++e)
