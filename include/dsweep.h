@@ -223,8 +223,10 @@ const char* dsd_last_error_detail(void);
 /* Kernel timing hooks for measurement: accumulated device time (ms) of the
  * subdomain-solve kernels and their launch count since the last reset, and the
  * algorithmic bytes those launches had to move (factor blocks once per RHS
- * group sharing them, plus the vectors).  Timing uses HIP events on the plan's
- * stream and is active only while enabled. */
+ * group sharing them, plus the vectors).  Timing uses a pair of HIP events
+ * around every solve launch on the plan's stream, recorded without waiting so
+ * that launches stay back to back, and read once per preconditioner
+ * application (which then waits for the stream).  Active only while enabled. */
 int dsd_timing_enable(dsd_plan* plan, int on);
 int dsd_timing_read(dsd_plan* plan, double* solve_ms, long long* solve_launches,
                     double* solve_bytes, double* other_ms);

@@ -178,9 +178,12 @@ struct dsd_plan {
   Buf d_res, d_adj, d_y, d_mpart, d_u;
 
   hipStream_t stream = nullptr;
-  // timing
+  // timing: an event pair around every solve launch, recorded without waiting
+  // (so the launches stay back to back) and read once the application is done
   bool timing = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> tev;
+  size_t tev_used = 0;
   double t_solve_ms = 0, t_other_ms = 0, solve_bytes = 0;
   long long solve_launches = 0;
 
@@ -194,6 +197,7 @@ struct dsd_plan {
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    for (hipEvent_t e : tev) (void)hipEventDestroy(e);
   }
 };
 
@@ -1101,24 +1105,45 @@ int ensure_pools(dsd_plan* pl) {
   return 0;
 }
 
+// Solve-launch timing (timing mode only): mark the start, then the end with
+// the launch's algorithmic bytes; flush reads the pairs after one wait.
+void time_begin(dsd_plan* pl) {
+  if (!pl->timing) return;
+  while (pl->tev.size() < pl->tev_used + 2) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) { pl->timing = false; return; }
+    pl->tev.push_back(e);
+  }
+  (void)hipEventRecord(pl->tev[pl->tev_used], pl->stream);
+}
+void time_end(dsd_plan* pl, double bytes) {
+  if (!pl->timing) return;
+  (void)hipEventRecord(pl->tev[pl->tev_used + 1], pl->stream);
+  pl->tev_used += 2;
+  pl->solve_launches += 1;
+  pl->solve_bytes += bytes;
+}
+void time_flush(dsd_plan* pl) {
+  if (pl->tev_used == 0) return;
+  (void)hipEventSynchronize(pl->tev[pl->tev_used - 1]);
+  for (size_t i = 0; i < pl->tev_used; i += 2) {
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, pl->tev[i], pl->tev[i + 1]);
+    pl->t_solve_ms += ms;
+  }
+  pl->tev_used = 0;
+}
+
 template <typename T>
 void chain_phase(dsd_plan* pl, int phase, const int4* jobs, int njobs, int nrhs, double fbytes,
                  long long blk_cells) {
   hipStream_t st = pl->stream;
-  if (pl->timing) (void)hipEventRecord(pl->ev0, st);
+  time_begin(pl);
   launch_chain<T>(pl->kg, phase, pl->d_subs.as<SubDesc>(), jobs, njobs, nrhs, pl->kmax,
                   pl->max_nb, pl->d_fac.as<cpx<T>>(), pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>(),
                   pl->d_rpool.as<cpx<T>>(), pl->d_vpool.as<cpx<T>>(), pl->sum_nloc * pl->kmax, st);
-  if (pl->timing) {
-    (void)hipEventRecord(pl->ev1, st);
-    (void)hipEventSynchronize(pl->ev1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
-    pl->t_solve_ms += ms;
-    pl->solve_launches += 1;
-    // factor blocks once per launch plus the vectors read and written per RHS
-    pl->solve_bytes += fbytes + (double)blk_cells * nrhs * 2.0 * sizeof(cpx<T>);
-  }
+  // factor blocks once per launch plus the vectors read and written per RHS
+  time_end(pl, fbytes + (double)blk_cells * nrhs * 2.0 * sizeof(cpx<T>));
 }
 
 template <typename T>
@@ -1133,18 +1158,10 @@ void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
                        rpool, vpool, ps, st);
     return;
   }
-  if (pl->timing) (void)hipEventRecord(pl->ev0, st);
+  time_begin(pl);
   launch_bcr_solve<T>(L.kg > 0 ? L.kg : pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, L.rt, nrhs,
                       pl->kmax, pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
-  if (pl->timing) {
-    (void)hipEventRecord(pl->ev1, st);
-    (void)hipEventSynchronize(pl->ev1);
-    float ms = 0;
-    (void)hipEventElapsedTime(&ms, pl->ev0, pl->ev1);
-    pl->t_solve_ms += ms;
-    pl->solve_launches += 1;
-    pl->solve_bytes += L.fbytes + L.vcells * nrhs * (double)sizeof(cpx<T>);
-  }
+  time_end(pl, L.fbytes + L.vcells * nrhs * (double)sizeof(cpx<T>));
 }
 
 template <typename T>
@@ -1184,6 +1201,7 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
   launch_assemble_u<T>(P, pl->d_subs.as<SubDesc>(), pt, pl->L, nrhs, pl->kmax, vpool, pool_stride,
                        u, st);
   HIPCHK(hipGetLastError());
+  time_flush(pl);
   return 0;
 }
 
@@ -1984,6 +2002,7 @@ const char* dsd_last_error_detail(void) { return g_detail.c_str(); }
 
 int dsd_timing_enable(dsd_plan* pl, int on) {
   if (!pl) return DSD_EINVAL;
+  time_flush(pl);
   pl->timing = on != 0;
   pl->t_solve_ms = pl->t_other_ms = pl->solve_bytes = 0;
   pl->solve_launches = 0;
@@ -1993,6 +2012,7 @@ int dsd_timing_enable(dsd_plan* pl, int on) {
 int dsd_timing_read(dsd_plan* pl, double* solve_ms, long long* solve_launches,
                     double* solve_bytes, double* other_ms) {
   if (!pl) return DSD_EINVAL;
+  time_flush(pl);
   if (solve_ms) *solve_ms = pl->t_solve_ms;
   if (solve_launches) *solve_launches = pl->solve_launches;
   if (solve_bytes) *solve_bytes = pl->solve_bytes;
