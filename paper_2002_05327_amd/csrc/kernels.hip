@@ -209,12 +209,28 @@ __global__ __launch_bounds__(1024) void k_invert(const SubDesc* subs, const Fact
     for (int c = tid; c < nb; c += bs)
       rowj[c] = (c == j) ? pinv : a[(long long)c * nb + j] * pinv;
     __syncthreads();
-    const long long ne = (long long)nb * nb;
-    for (long long e = tid; e < ne; e += bs) {
-      const int c = (int)(e / nb), i = (int)(e - (long long)c * nb);
-      if (i == j) a[e] = rowj[c];
-      else if (c == j) a[e] = -(tcol[i] * pinv);
-      else a[e] = a[e] - tcol[i] * rowj[c];
+    // rank-1 update, one column per wave at a time (coalesced, four loads in
+    // flight per lane)
+    for (int c = wid; c < nb; c += nw) {
+      cpx<double>* col = a + (long long)c * nb;
+      const cpx<double> rj = rowj[c];
+      for (int i0 = lane; i0 < nb; i0 += 256) {
+        cpx<double> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          v[u] = i < nb ? col[i] : mk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          if (i < nb) {
+            if (i == j) col[i] = rj;
+            else if (c == j) col[i] = -(tcol[i] * pinv);
+            else col[i] = v[u] - tcol[i] * rj;
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -831,12 +847,28 @@ __global__ __launch_bounds__(1024) void k_bcr_invert(const BcrInvJob* jobs, cpx<
     const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
     for (int c = tid; c < nb; c += bs) rowj[c] = (c == j) ? pinv : a[(long long)c * nb + j] * pinv;
     __syncthreads();
-    const long long ne = (long long)nb * nb;
-    for (long long e = tid; e < ne; e += bs) {
-      const int c = (int)(e / nb), i = (int)(e - (long long)c * nb);
-      if (i == j) a[e] = rowj[c];
-      else if (c == j) a[e] = -(tcol[i] * pinv);
-      else a[e] = a[e] - tcol[i] * rowj[c];
+    // rank-1 update, one column per wave at a time (coalesced, four loads in
+    // flight per lane)
+    for (int c = wid; c < nb; c += nw) {
+      cpx<double>* col = a + (long long)c * nb;
+      const cpx<double> rj = rowj[c];
+      for (int i0 = lane; i0 < nb; i0 += 256) {
+        cpx<double> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          v[u] = i < nb ? col[i] : mk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          if (i < nb) {
+            if (i == j) col[i] = rj;
+            else if (c == j) col[i] = -(tcol[i] * pinv);
+            else col[i] = v[u] - tcol[i] * rj;
+          }
+        }
+      }
     }
     __syncthreads();
   }
