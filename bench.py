@@ -75,10 +75,22 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bcr_c2_traffic.md")
 
 
 def _kernel_source_hash():
+    """sha256 over the source that decides the solve kernel's memory traffic: the
+    kernel and its launchers, and the builder of its job tables and launch shapes."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2002_05327_amd", "csrc")
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2002_05327_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    with open(os.path.join(csrc, "kernels.hip")) as f:
+        k = f.read()
+    a, b = k.index("// ---- solve jobs"), k.index("// a4: local right-hand sides")
+    h.update(k[a:b].encode())
+    with open(os.path.join(csrc, "plan.hip")) as f:
+        p = f.read()
+    a = p.index("void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,\n                    std::vector<BcrLaunch>& out) {")
+    b = p.index("\n}\n", a)
+    h.update(p[a:b].encode())
+    a = p.index("  int cg_wide = ")
+    h.update(p[a:p.index("\n", p.index("int wide_kg", a))].encode())
     return h.hexdigest()
 
 
@@ -94,7 +106,7 @@ def _measured_traffic(workload):
                 if ":" in line and line.startswith("- "):
                     k, v = line[2:].split(":", 1)
                     vals[k.strip()] = v.strip().strip("`")
-        if vals.get("workload") != workload or vals.get("kernels.hip sha256") != _kernel_source_hash():
+        if vals.get("workload") != workload or vals.get("solve-kernel source sha256") != _kernel_source_hash():
             return None
         return float(vals["HBM bytes per dispatch"])
     except (OSError, KeyError, ValueError):
