@@ -1054,7 +1054,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
                                                        const cpx<T>* __restrict__ cpl,
                                                        cpx<T>* __restrict__ rpool,
                                                        cpx<T>* __restrict__ vpool,
-                                                       long long pool_stride) {
+                                                       long long pool_stride, int lds_rg) {
   typedef typename vec2<T>::type V2;
   typedef cpx<T> C;
   typedef BcrTraits<T, KG> TR;
@@ -1313,9 +1313,16 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
   }
   const int orow = row0 + lane;
   if constexpr (MF) {
-    // regroup rows through LDS (the operand area, free once every wave is done)
-    __syncthreads();
-    float* st = reinterpret_cast<float*>(smem_raw) + (long long)rt * 64 * KG * 2;
+    // regroup rows through LDS: with one column group each wave has a region of
+    // its own after the operands (no wait for the other waves); otherwise the
+    // operand area, free once every wave is done
+    float* st;
+    if (CG == 1) {
+      st = reinterpret_cast<float*>(smem_raw + lds_rg) + (long long)rt * 64 * KG * 2;
+    } else {
+      __syncthreads();
+      st = reinterpret_cast<float*>(smem_raw) + (long long)rt * 64 * KG * 2;
+    }
     if (cg == 0) {
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
@@ -1328,7 +1335,15 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
             st[((long long)(j >> 1) * 64 + rl) * 2 + (j & 1)] = acc[rb][jb][r];
           }
     }
-    __syncthreads();
+    if (CG == 1) {
+      // the wave reads back only what it wrote; LDS operations of a wave are
+      // performed in order
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
     if (cg == 0) {
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
@@ -1402,13 +1417,22 @@ static inline void bcr_shape(int max_nb, int cg, int rt, int& RT, int& CG, int& 
 
 // LDS of a launch: the operand sets, reused for the MF row regrouping and the
 // column-group partial sums once every wave is done with the operands.
+// Operand area of a launch (bytes, rounded); with MF and one column group the
+// row-regrouping regions of the row tiles follow it.
+template <typename T>
+static size_t bcr_ops_area(int max_nb, int kg, int nset) {
+  const size_t ops = (size_t)nset * ((max_nb + 3) & ~3) * kg * sizeof(cpx<T>);
+  return (ops + 255) / 256 * 256;
+}
+
 template <typename T>
 size_t bcr_launch_lds_bytes(int max_nb, int kg, int nset, int cg, int rt) {
   int RT, CG, nrg;
   bcr_shape(max_nb, cg, rt, RT, CG, nrg);
-  const size_t ops = (size_t)nset * ((max_nb + 3) & ~3) * kg * sizeof(cpx<T>);
+  const size_t ops = bcr_ops_area<T>(max_nb, kg, nset);
   const size_t stage = (size_t)RT * 64 * kg * sizeof(cpx<T>);
   const bool mf = std::is_same<T, float>::value && kg >= 8;
+  if (mf && CG == 1) return ops + (stage + 255) / 256 * 256;
   const size_t per_lane = mf ? (size_t)16 * (kg / 8) * sizeof(float) : 2 * (size_t)kg * sizeof(T);
   const size_t part = CG > 1 ? (size_t)(CG - 1) * RT * 64 * per_lane : 0;
   size_t b = ops > stage ? ops : stage;
@@ -1443,7 +1467,7 @@ static void launch_bcr_k(const SubDesc* d_subs, const BcrJob* d_jobs, int njobs,
   const size_t lds = bcr_launch_lds_bytes<T>(max_nb, KG, nset, cg, rt);
   hipLaunchKernelGGL((k_bcr<T, KG>), dim3((unsigned)total), dim3(64 * RT * CG), lds, s, d_subs,
                      d_jobs, njobs, G, nrg, RT, CG, nrhs, kmax, fac, cpl, rpool, vpool,
-                     pool_stride);
+                     pool_stride, (int)bcr_ops_area<T>(max_nb, KG, nset));
 }
 
 template <typename T>

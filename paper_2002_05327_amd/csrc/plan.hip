@@ -1722,38 +1722,44 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
   HIPCHK(hipEventCreate(&a));
   HIPCHK(hipEventCreate(&b));
   int rc = 0;
-  // the wide levels may use a wider RHS group than the rest (each wide job
-  // then streams its matrices once for all of them)
-  std::vector<int> wkgs{0};
-  if (pl->solver == 2 && !kgs.empty() && kgs.back() > kgs.front()) wkgs.push_back(kgs.back());
-  for (int kg : kgs) {
-    for (int wkg : wkgs) {
-      if (wkg != 0 && wkg <= kg) continue;
-      for (const auto& pol : pols) {
-        int v[10];
-        for (int i = 0; i < 9; ++i) v[i] = pol[i];
-        v[9] = wkg;
-        pl->kg = kg;
-        set(v);
-        if ((rc = build_bcr_jobs(pl)) != 0) break;
-        if ((rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs)) != 0) break;
-        (void)hipEventRecord(a, st);
-        for (int r = 0; r < reps && rc == 0; ++r)
-          rc = sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs);
-        (void)hipEventRecord(b, st);
-        if (rc != 0 || hipEventSynchronize(b) != hipSuccess) { rc = rc ? rc : DSD_EHIP; break; }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
-        if (ms / reps < best) {
-          best = ms / reps;
-          bkg = kg;
-          for (int i = 0; i < 10; ++i) bpol[i] = v[i];
-        }
-        if (pl->solver != 2) break;             // the policies only shape the reduction
-      }
-      if (rc != 0) break;
+  // one candidate: time `reps` applications after one untimed one
+  auto trial = [&](int kg, const int* v) -> int {
+    pl->kg = kg;
+    set(v);
+    CHK(build_bcr_jobs(pl));
+    CHK(sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs));
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < reps; ++r) CHK(sweep_apply_eager(pl, f.as<cpx<double>>(), u.as<cpx<double>>(), nrhs));
+    (void)hipEventRecord(b, st);
+    if (hipEventSynchronize(b) != hipSuccess) return DSD_EHIP;
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, a, b);
+    if (ms / reps < best) {
+      best = ms / reps;
+      bkg = kg;
+      for (int i = 0; i < 10; ++i) bpol[i] = v[i];
     }
-    if (rc != 0) break;
+    return 0;
+  };
+  // coordinate search: the RHS group width under the current policy, then the
+  // level-shape policies at that width, then a wider RHS group on the wide
+  // levels (each wide job then streams its matrices once for all of them)
+  for (int kg : kgs)
+    if ((rc = trial(kg, best0)) != 0) break;
+  if (rc == 0 && pl->solver == 2) {
+    const int kg1 = bkg;
+    for (const auto& pol : pols) {
+      int v[10];
+      for (int i = 0; i < 9; ++i) v[i] = pol[i];
+      v[9] = 0;
+      if ((rc = trial(kg1, v)) != 0) break;
+    }
+    if (rc == 0 && !kgs.empty() && kgs.back() > kg1) {
+      int v[10];
+      for (int i = 0; i < 10; ++i) v[i] = bpol[i];
+      v[9] = kgs.back();
+      rc = trial(kg1, v);
+    }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
