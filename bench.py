@@ -68,7 +68,7 @@ def _solve_steps(plan, b, tol, maxit, restart, warmup, steps):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     x, its, rel, ok = last
-    return dt, its, rel, ok
+    return dt, its, rel, ok, x[0].cpu().numpy().ravel()
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bcr_c2_traffic.md")
@@ -154,6 +154,24 @@ def _cpu_baseline(w, c, F):
                       f"SuperLU, scipy.sparse and BLAS on one thread"}
 
 
+def _oracle_error(w, c, F, sols):
+    """Relative error of the timed solutions of RHS 0 (at the benchmark's
+    tolerance) against the oracle's global sparse LU solution of the same
+    PML problem (2D workloads up to 2M unknowns; null otherwise)."""
+    N = int(np.prod([k + 2 * w.pml for k in w.n]))
+    if w.dim != 2 or N > 2_000_000:
+        return None
+    from oracle.pml import assemble, global_axes
+    from oracle.sweep import global_solve
+    M = assemble(global_axes(w.n, w.pml, w.h), 1.0 / c ** 2, w.h, w.omega, w.pml)
+    u = global_solve(M, F[0].ravel())
+    out = {"reference": "oracle global sparse LU, RHS 0"}
+    for k, x in sols.items():
+        if x is not None:
+            out[k] = float(np.linalg.norm(x - u) / np.linalg.norm(u))
+    return out
+
+
 def _copy_probe(gib=1.0):
     """A plain device copy of known size, whose FETCH_SIZE / WRITE_SIZE counters
     calibrate the per-dispatch byte counts of the other kernels."""
@@ -197,8 +215,8 @@ def main():
 
     plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph, args.autotune)
     print(f"# c64 factorisation {tf64:.2f} s", file=sys.stderr, flush=True)
-    dt64, its64, rel64, ok64 = _solve_steps(plan64, b, args.tol, args.maxit, args.restart,
-                                            args.warmup, args.steps)
+    dt64, its64, rel64, ok64, x64 = _solve_steps(plan64, b, args.tol, args.maxit, args.restart,
+                                                 args.warmup, args.steps)
     print(f"# c64 solve {dt64 / args.steps * 1e3:.1f} ms/step iters {its64}", file=sys.stderr,
           flush=True)
     roof = _roofline(plan64, b, w.name)
@@ -209,9 +227,9 @@ def main():
     c128 = None
     if not args.no_c128:
         plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph, args.autotune)
-        dt128, its128, rel128, ok128 = _solve_steps(plan128, b, args.tol, args.maxit,
-                                                    args.restart, min(args.warmup, 1),
-                                                    max(1, min(args.steps, 2)))
+        dt128, its128, rel128, ok128, x128 = _solve_steps(plan128, b, args.tol, args.maxit,
+                                                          args.restart, min(args.warmup, 1),
+                                                          max(1, min(args.steps, 2)))
         n128 = max(1, min(args.steps, 2))
         c128 = {"value": round(w.nrhs * n128 / dt128, 3), "unit": "RHS/s",
                 "ms_per_step": round(dt128 / n128 * 1e3, 2), "factor_s": round(tf128, 3),
@@ -222,9 +240,12 @@ def main():
         del plan128
 
     cpu = None
+    err = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         cpu = _cpu_baseline(w, c, F)
+        print("# error against the oracle's global solve ...", file=sys.stderr, flush=True)
+        err = _oracle_error(w, c, F, {"c64": x64, "c128": None if c128 is None else x128})
 
     value = w.nrhs * args.steps / dt64
     out = {
@@ -241,7 +262,7 @@ def main():
                    "global_batch": w.nrhs, "precision": "c64 factors + FP64 refinement"},
         "iters": its64, "max_relres": max(rel64), "converged": ok64,
         "factor_s": round(tf64, 3), "factor_bytes": info64["factor_bytes"],
-        "c128": c128, "roofline": roof, "cpu_baseline": cpu,
+        "c128": c128, "rel_err_vs_oracle": err, "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
