@@ -129,7 +129,8 @@ def _roofline(plan, b, workload):
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": _measured_traffic(workload),
             "kernel": {"bcr": "k_bcr (block cyclic reduction solves)",
-                       "chain": "k_chain (block LDL^T chain solves)"}[plan.local_solver],
+                       "chain": "k_chain (block LDL^T chain solves)",
+                       "chain-steps": "k_bcr (block LDL^T chain steps)"}[plan.local_solver],
             "launches": t["solve_launches"],
             "avg_launch_ms": round(avg_ms, 4), "avg_launch_bytes": round(avg_bytes),
             "traffic_unit": "HBM bytes per dispatch"}

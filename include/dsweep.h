@@ -69,10 +69,13 @@ typedef struct {
   int local_solver;      /* factorisation and solve of the block-tridiagonal subdomain
                             operators: 1: twisted block LDL^T (two Schur-complement
                                chains meeting in the middle block; least memory,
-                               sequential in the blocks);
+                               sequential in the blocks; one workgroup runs a chain);
                             2: block cyclic reduction (about three times the factor
                                memory; every reduction level is one batched launch);
-                            0: 2 unless its factor would exceed 45% of device memory. */
+                            3: the LDL^T chains of 1 with one launch per block step,
+                               every chain of a launch group in it (wide blocks);
+                            0: 2 unless its factor would exceed 45% of device memory,
+                               else 3 for blocks of 512 cells or more, else 1.          */
   int dense_top;         /* block cyclic reduction only: the reduction stops at the first
                             level that has at most this many blocks (at least 2) and
                             applies the precomputed inverse of that reduced system as one
@@ -102,8 +105,9 @@ void dsd_destroy(dsd_plan* plan);
 int dsd_plan_info(const dsd_plan* plan, long long* n_global, int* n_subdomains,
                   long long* factor_bytes, long long* workspace_bytes);
 
-/* Local solver in use: 1 = twisted block LDL^T chains, 2 = block cyclic reduction
- * (dsd_params.local_solver after the automatic choice); negative on a NULL plan. */
+/* Local solver in use: 1 = twisted block LDL^T chains, 2 = block cyclic reduction,
+ * 3 = LDL^T chains with one launch per block step (dsd_params.local_solver after
+ * the automatic choice); negative on a NULL plan. */
 int dsd_plan_local_solver(const dsd_plan* plan);
 
 /* Graph mode: when on, dsd_sweep_apply (and the preconditioner applications

@@ -57,7 +57,7 @@ class Plan:
         p.precision = {"c64": DSD_C64, "c128": DSD_C128}[precision]
         p.max_rhs, p.rhs_per_group = int(max_rhs), int(rhs_per_group)
         p.schedule = {"dag": 0, "sequential": 1}[schedule]
-        p.local_solver = {"auto": 0, "chain": 1, "bcr": 2}[local_solver]
+        p.local_solver = {"auto": 0, "chain": 1, "bcr": 2, "chain-steps": 3}[local_solver]
         p.dense_top = int(dense_top)
         self.params = p
         self.n, self.dim, self.pml, self.omega = tuple(int(k) for k in n), dim, int(pml), omega
@@ -205,7 +205,7 @@ class Plan:
 
     @property
     def local_solver(self) -> str:
-        return {1: "chain", 2: "bcr"}[self._lib.dsd_plan_local_solver(self._h)]
+        return {1: "chain", 2: "bcr", 3: "chain-steps"}[self._lib.dsd_plan_local_solver(self._h)]
 
     def timing(self, on: bool):
         check(self._lib.dsd_timing_enable(self._h, int(bool(on))), "dsd_timing_enable")

@@ -1165,8 +1165,8 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
           if (hl) va[k] = R[ro + (long long)J.nl * nb + i];
           if (hr) vb[k] = R[ro + (long long)J.nr * nb + i];
         } else {
-          va[k] = R[ro + (long long)blk * nb + i];
-          if (mode == BCR_BWD || mode == BCR_BWD0) {
+          if (mode != BCR_CHB) va[k] = R[ro + (long long)blk * nb + i];
+          if (mode == BCR_BWD || mode == BCR_BWD0 || mode == BCR_CHB) {
             if (hl) vb[k] = X[ro + (long long)J.nl * nb + i];
             if (hr) vc[k] = X[ro + (long long)J.nr * nb + i];
           }
@@ -1188,6 +1188,13 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
         if (hr) o[hl ? 2 * ss : ss] = -vc[k];
       } else if (mode == BCR_BWD0) {
         C y = va[k];
+        if (i < nb) {
+          if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * vb[k];
+          if (hr) y = y - Cp[(long long)blk * nb + i] * vc[k];
+        }
+        o[0] = y;
+      } else if (mode == BCR_CHB) {
+        C y = zero;
         if (i < nb) {
           if (hl) y = y - Cp[(long long)(blk - 1) * nb + i] * vb[k];
           if (hr) y = y - Cp[(long long)blk * nb + i] * vc[k];
@@ -1360,6 +1367,7 @@ __global__ __launch_bounds__(64 * BCR_MAXW) void k_bcr(const SubDesc* __restrict
         const long long oo = (long long)rq * nloc + (long long)blk * nb + orow;
         const C out = mk(ar[q], ai[q]);
         if (mode == BCR_KEPT) R[oo] = R[oo] + out;
+        else if (mode == BCR_CHB) X[oo] = X[oo] + out;
         else X[oo] = out;
       }
     }

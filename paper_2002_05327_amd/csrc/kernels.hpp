@@ -92,8 +92,10 @@ enum {
   BCR_BWD0 = 2,   // X_blk = M0 (R_blk - c_{blk-1} X_nl - c_blk X_nr)   (backward, level 0)
   BCR_BWD = 3,    // X_blk = M0 R_blk - M1 X_nl - M2 X_nr               (backward, level >= 1)
   BCR_DFWD = 4,   // R_blk = R_blk - c_{blk-1} X_nl - c_blk X_nr        (forward, level 0)
-  BCR_DENSE = 5   // X_blk = M0 [R_b0; R_b1; ...; R_b(m-1)] with b_q = nl + q nr, m = pad:
+  BCR_DENSE = 5,  // X_blk = M0 [R_b0; R_b1; ...; R_b(m-1)] with b_q = nl + q nr, m = pad:
                   // one nb x (m nb) row block of the inverse of a small reduced system
+  BCR_CHB = 6     // X_blk = X_blk - M0 (c_{blk-1} X_nl)  or  X_blk - M0 (c_blk X_nr):
+                  // a backward step of the block LDL^T chains (one neighbour)
 };
 struct BcrJob {
   int sub, l, blk, mode;

@@ -164,6 +164,10 @@ struct dsd_plan {
   int wide_cg = 1, wide_rt = 0, mid_cg = 4, mid_rt = 1, deep_cg = 8, deep_rt = 1, dense_cg = 8;
   int wide_kg = 0;                // RHS per workgroup on the wide levels (0: kg)
   int dense_max = 0;              // largest reduced system solved densely (0: none)
+  // chain factor solved with one launch per block step (all chains of a
+  // launch group together) instead of one workgroup looping over the blocks
+  bool chain_steps = false;
+  int chain_cg = 3, chain_rt = 0;
   Buf d_bcr_jobs;
   long long sum_nloc = 0, sum_fac = 0;
 
@@ -322,15 +326,24 @@ int sub_index(const dsd_plan* pl, const int* pidx) {
 void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
                     std::vector<BcrLaunch>& out);
 int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs);
+void chain_step_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
+                     std::vector<BcrLaunch>& out);
+// jobs of one launch group (or one subdomain) with the plan's local solver
+void solve_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
+                std::vector<BcrLaunch>& out) {
+  if (pl->solver == 2) bcr_group_jobs(pl, mem, jobs, out);
+  else chain_step_jobs(pl, mem, jobs, out);
+}
 
-// Solve-job tables of the cyclic reduction for every launch group.
+// Solve-job tables of the cyclic reduction (or of the chain block steps) for
+// every launch group.
 int build_bcr_jobs(dsd_plan* pl) {
   pl->bcr_launch.clear();
-  if (pl->solver != 2) return 0;
+  if (pl->solver != 2 && !pl->chain_steps) return 0;
   std::vector<BcrJob> bj;
   for (auto& grp : pl->groups) {
     pl->bcr_launch.emplace_back();
-    bcr_group_jobs(pl, grp, bj, pl->bcr_launch.back());
+    solve_jobs(pl, grp, bj, pl->bcr_launch.back());
   }
   CHK(bcr_check_jobs(pl, bj));
   CHK(upload(pl->d_bcr_jobs, bj));
@@ -915,6 +928,66 @@ void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vecto
   }
 }
 
+// Block steps of the twisted block LDL^T chains, every chain of the launch
+// group in one launch per step (B_k the stored inverse Schur blocks):
+//   forward  w_k = B_k (r_k - c_{k-1} w_{k-1})  (top, k < m)
+//            w_k = B_k (r_k - c_k w_{k+1})      (bottom, k > m)
+//   middle   x_m = B_m (r_m - c_{m-1} w_{m-1} - c_m w_{m+1})
+//   backward x_k = w_k - B_k (c_k x_{k+1})      (top)
+//            x_k = w_k - B_k (c_{k-1} x_{k-1})  (bottom)
+// w and x share the solution pool; a step reads only blocks a previous
+// launch wrote.
+void chain_step_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
+                     std::vector<BcrLaunch>& out) {
+  const double ts = (double)tsize(pl);
+  int T = 0;
+  for (const int2& m : mem) {
+    const SubDesc& S = pl->subs[m.x];
+    T = std::max(T, std::max(S.mid, S.nblk - 1 - S.mid));
+  }
+  auto begin = [&]() {
+    return BcrLaunch{(int)jobs.size(), 0, 0, 1, pl->chain_cg, pl->chain_rt, 0, 0.0, 0.0};
+  };
+  auto finish = [&](BcrLaunch& L) {
+    L.n = (int)jobs.size() - L.off;
+    if (L.n > 0) out.push_back(L);
+  };
+  auto add = [&](BcrLaunch& L, const int2& m, int blk, int mode, int nl, int nr) {
+    const SubDesc& S = pl->subs[m.x];
+    jobs.push_back(BcrJob{m.x, m.y, blk, mode, nl, nr, S.nb, 0,
+                          S.fac_off + (long long)blk * S.nb * S.nb, 0, 0, S.nloc,
+                          S.vec_off * pl->kmax, S.coef_off});
+    const int nvec = 2 + (int)(nl >= 0) + (int)(nr >= 0) + (mode == BCR_CHB ? 1 : 0);
+    L.fbytes += (double)S.nb * S.nb * ts;
+    L.vcells += (double)nvec * S.nb;
+  };
+  for (int t = 0; t < T; ++t) {
+    BcrLaunch L = begin();
+    for (const int2& m : mem) {
+      const SubDesc& S = pl->subs[m.x];
+      if (t < S.mid) add(L, m, t, BCR_BWD0, t > 0 ? t - 1 : -1, -1);
+      const int k = S.nblk - 1 - t;
+      if (k > S.mid) add(L, m, k, BCR_BWD0, -1, k + 1 < S.nblk ? k + 1 : -1);
+    }
+    finish(L);
+  }
+  BcrLaunch Lm = begin();
+  for (const int2& m : mem) {
+    const SubDesc& S = pl->subs[m.x];
+    add(Lm, m, S.mid, BCR_BWD0, S.mid > 0 ? S.mid - 1 : -1, S.mid + 1 < S.nblk ? S.mid + 1 : -1);
+  }
+  finish(Lm);
+  for (int s = 1; s <= T; ++s) {
+    BcrLaunch L = begin();
+    for (const int2& m : mem) {
+      const SubDesc& S = pl->subs[m.x];
+      if (S.mid - s >= 0) add(L, m, S.mid - s, BCR_CHB, -1, S.mid - s + 1);
+      if (S.mid + s < S.nblk) add(L, m, S.mid + s, BCR_CHB, S.mid + s - 1, -1);
+    }
+    finish(L);
+  }
+}
+
 // Host check of a solve-job table against the factor and the subdomain grids.
 int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
   for (const BcrJob& J : jobs) {
@@ -938,6 +1011,9 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
                (J.mode == BCR_DFWD || mat_ok(J.m0));
           break;
         case BCR_BWD: ok = ok && mat_ok(J.m0) && (!hl || mat_ok(J.m1)) && (!hr || mat_ok(J.m2)); break;
+        case BCR_CHB:
+          ok = ok && mat_ok(J.m0) && (hl != hr) && (!hl || J.blk >= 1) && (!hr || J.blk + 1 < S.nblk);
+          break;
         case BCR_DENSE: {
           // blocks nl + q nr, q < pad, of one reduction level; matrix nb x (pad nb)
           const int m = J.pad;
@@ -1181,7 +1257,7 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
                    pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
                    pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
                    pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
-    if (pl->solver == 2) {
+    if (pl->solver == 2 || pl->chain_steps) {
       for (const BcrLaunch& L : pl->bcr_launch[&st_ - pl->steps.data()])
         bcr_phase<T>(pl, pl->d_bcr_jobs.as<BcrJob>(), L, nrhs);
       continue;
@@ -1543,6 +1619,15 @@ int dense_blocks(const dsd_plan* pl, int req) {
 
 int choose_kg(const dsd_plan* pl, int want) {
   const int lds = device_lds();
+  if (pl->chain_steps) {
+    int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
+    auto need = [&](int k) {
+      return pl->c64 ? bcr_launch_lds_bytes<float>(pl->max_nb, k, 1, pl->chain_cg, pl->chain_rt)
+                     : bcr_launch_lds_bytes<double>(pl->max_nb, k, 1, pl->chain_cg, pl->chain_rt);
+    };
+    while (kg > 1 && need(kg) > (size_t)lds) kg >>= 1;
+    return need(kg) > (size_t)lds ? 0 : kg;
+  }
   if (pl->solver == 2) {
     int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
     auto need = [&](int k) {
@@ -1575,10 +1660,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   const dsd_params& q = *params;
   if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
       (q.precision != DSD_C64 && q.precision != DSD_C128) || q.local_solver < 0 ||
-      q.local_solver > 2 || q.schedule < 0 || q.schedule > 1 || q.dense_top < -1 ||
+      q.local_solver > 3 || q.schedule < 0 || q.schedule > 1 || q.dense_top < -1 ||
       q.dense_top > 64) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
-               "local_solver 0..2, schedule 0..1, dense_top -1..64";
+               "local_solver 0..3, schedule 0..1, dense_top -1..64";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)
@@ -1602,7 +1687,7 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
     std::vector<long long> toff(pl->S);
     for (int i = 0; i < pl->S; ++i) toff[i] = pl->subs[i].fac_off;
     const long long tsum = pl->sum_fac;
-    pl->solver = q.local_solver == 1 ? 1 : 2;
+    pl->solver = (q.local_solver == 1 || q.local_solver == 3) ? 1 : 2;
     if (pl->solver == 2) {
       pl->dense_max = dense_blocks(pl, q.dense_top);
       bcr_layout(pl);
@@ -1614,10 +1699,13 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
         pl->sum_fac = tsum;
       }
     }
+    // chain solves: one launch per block step for wide blocks (the 3D planes),
+    // where one workgroup per chain would leave most of the GPU idle
+    pl->chain_steps = pl->solver == 1 && (q.local_solver == 3 || (q.local_solver == 0 && pl->max_nb >= 512));
   }
   if (rc == 0) {
     pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group
-                                               : (pl->solver == 2 ? (pl->c64 ? 8 : 4) : 2));
+                                               : ((pl->solver == 2 || pl->chain_steps) ? (pl->c64 ? 8 : 4) : 2));
     if (pl->kg == 0) {
       g_detail = "subdomain blocks too large for the solve kernel's LDS";
       rc = DSD_EINVAL;
@@ -1663,7 +1751,9 @@ int dsd_plan_info(const dsd_plan* pl, long long* n_global, int* n_subdomains,
   return DSD_OK;
 }
 
-int dsd_plan_local_solver(const dsd_plan* pl) { return pl ? pl->solver : DSD_EINVAL; }
+int dsd_plan_local_solver(const dsd_plan* pl) {
+  return pl ? (pl->chain_steps ? 3 : pl->solver) : DSD_EINVAL;
+}
 
 int dsd_set_graph(dsd_plan* pl, int on) {
   if (!pl) return DSD_EINVAL;
@@ -1827,10 +1917,10 @@ int dsd_local_solve(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, i
   const SubDesc& S = pl->subs[sub];
   const long long off = S.vec_off * pl->kmax;
   hipStream_t st = pl->stream;
-  if (pl->solver == 2) {
+  if (pl->solver == 2 || pl->chain_steps) {
     std::vector<BcrJob> bj;
     pl->bcr_single.clear();
-    bcr_group_jobs(pl, std::vector<int2>{make_int2(sub, 0)}, bj, pl->bcr_single);
+    solve_jobs(pl, std::vector<int2>{make_int2(sub, 0)}, bj, pl->bcr_single);
     CHK(bcr_check_jobs(pl, bj));
     CHK(upload(pl->d_single_job, bj));
     const BcrJob* jb = pl->d_single_job.as<BcrJob>();

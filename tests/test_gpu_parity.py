@@ -25,7 +25,7 @@ def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="aut
                     dense_top=dense_top)
 
 
-SOLVERS = ["bcr", "chain"]
+SOLVERS = ["bcr", "chain", "chain-steps"]
 
 
 def _cuda(x):
@@ -228,7 +228,8 @@ def test_cyclic_reduction_equals_chains(name):
     f = _cuda(sources(n, h, pml, 2))
     a = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="bcr").sweep_apply(f).cpu().numpy()
     b = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain").sweep_apply(f).cpu().numpy()
-    assert rel(a, b) < 1e-12
+    s = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain-steps").sweep_apply(f).cpu().numpy()
+    assert rel(a, b) < 1e-12 and rel(s, b) < 1e-12
 
 
 @pytest.mark.parametrize("dense_top", [-1, 2, 3, 8])
