@@ -46,6 +46,8 @@ def _plan(w, c, prec, kg, graph=False, tune=False):
                     m=m, precision=prec, max_rhs=w.nrhs, rhs_per_group=kg)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    print(f"# {prec} plan ready ({plan.local_solver} local solver): factorisation {dt:.2f} s",
+          file=sys.stderr, flush=True)
     if tune:
         t1 = time.perf_counter()
         res = plan.autotune()

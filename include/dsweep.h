@@ -133,18 +133,19 @@ int dsd_set_graph(dsd_plan* plan, int on);
 int dsd_autotune(dsd_plan* plan, int nrhs, int reps, int* kg_host, int* cg_wide_host,
                  int* cg_mid_host, double* ms_host, void* stream);
 
-/* Launch shape of the subdomain solves as 11 ints: RHS per workgroup, then
+/* Launch shape of the subdomain solves as 13 ints: RHS per workgroup, then
  * the cyclic-reduction level policy: cg_wide, cg_mid (thresholds on the blocks
  * per subdomain left at a level that make it a wide, middle or deep level),
  * (wide_cg, wide_rt), (mid_cg, mid_rt), (deep_cg, deep_rt) (wave groups
  * splitting the columns of a job, 64-row tiles per workgroup: rt 0 = up to 4),
- * dense_cg, and wide_kg (RHS per workgroup on the wide levels; 0 = the first
- * entry).  get writes the plan's current shape (for instance after
- * dsd_autotune); set applies a saved one without timing anything (rt 0 with
- * cg 1..4 or rt 1 with cg 1..12; RHS-per-workgroup entries must be ones the
- * plan supports, else DSD_EINVAL).  set drops captured graphs. */
-int dsd_get_solve_shape(const dsd_plan* plan, int* shape11_host);
-int dsd_set_solve_shape(dsd_plan* plan, const int* shape11_host);
+ * dense_cg, wide_kg (RHS per workgroup on the wide levels; 0 = the first
+ * entry), and (chain_cg, chain_rt) for the chain block steps (local solver 3).
+ * get writes the plan's current shape (for instance after dsd_autotune); set
+ * applies a saved one without timing anything (rt 0 with cg 1..4 or rt 1 with
+ * cg 1..12; RHS-per-workgroup entries must be ones the plan supports, else
+ * DSD_EINVAL).  set drops captured graphs. */
+int dsd_get_solve_shape(const dsd_plan* plan, int* shape13_host);
+int dsd_set_solve_shape(dsd_plan* plan, const int* shape13_host);
 
 /* Local grid of subdomain `sub` (lexicographic index, x part fastest):
  * dims[3] = local cells per axis, g0[3] = global array index of its first cell

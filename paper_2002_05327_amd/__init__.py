@@ -188,15 +188,15 @@ class Plan:
 
     @property
     def solve_shape(self) -> tuple:
-        """Launch shape of the subdomain solves (11 ints: RHS per workgroup, then the
+        """Launch shape of the subdomain solves (13 ints: RHS per workgroup, then the
         cyclic-reduction level policy); set it to reuse an autotuned shape."""
-        v = (C.c_int * 11)()
+        v = (C.c_int * 13)()
         check(self._lib.dsd_get_solve_shape(self._h, v), "dsd_get_solve_shape")
         return tuple(v)
 
     @solve_shape.setter
     def solve_shape(self, shape):
-        v = (C.c_int * 11)(*[int(x) for x in shape])
+        v = (C.c_int * 13)(*[int(x) for x in shape])
         check(self._lib.dsd_set_solve_shape(self._h, v), "dsd_set_solve_shape")
 
     def use_graph(self, on: bool = True):

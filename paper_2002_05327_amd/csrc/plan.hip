@@ -1794,16 +1794,17 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
       {64, 16, 1, 0, 4, 1, 8, 1, 8},  {16, 4, 1, 0, 4, 1, 8, 1, 8},   {32, 8, 2, 0, 4, 1, 8, 1, 8},
       {64, 8, 1, 0, 4, 1, 12, 1, 12}, {32, 8, 1, 0, 2, 1, 8, 1, 4},   {inf, inf, 1, 0, 1, 0, 1, 0, 8}};
   auto get = [&](int* v) {
-    const int t[10] = {pl->cg_wide, pl->cg_mid, pl->wide_cg, pl->wide_rt,  pl->mid_cg,
-                       pl->mid_rt,  pl->deep_cg, pl->deep_rt, pl->dense_cg, pl->wide_kg};
-    for (int i = 0; i < 10; ++i) v[i] = t[i];
+    const int t[12] = {pl->cg_wide, pl->cg_mid,  pl->wide_cg,  pl->wide_rt, pl->mid_cg,   pl->mid_rt,
+                       pl->deep_cg, pl->deep_rt, pl->dense_cg, pl->wide_kg, pl->chain_cg, pl->chain_rt};
+    for (int i = 0; i < 12; ++i) v[i] = t[i];
   };
   auto set = [&](const int* v) {
     pl->cg_wide = v[0]; pl->cg_mid = v[1]; pl->wide_cg = v[2]; pl->wide_rt = v[3]; pl->mid_cg = v[4];
     pl->mid_rt = v[5]; pl->deep_cg = v[6]; pl->deep_rt = v[7]; pl->dense_cg = v[8]; pl->wide_kg = v[9];
+    pl->chain_cg = v[10]; pl->chain_rt = v[11];
   };
   const int best0_kg = pl->kg;
-  int best0[10], bpol[10];
+  int best0[12], bpol[12];
   get(best0);
   get(bpol);
   double best = 1e300;
@@ -1813,7 +1814,13 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
   HIPCHK(hipEventCreate(&b));
   int rc = 0;
   // one candidate: time `reps` applications after one untimed one
+  const int lds_dev = device_lds();
   auto trial = [&](int kg, const int* v) -> int {
+    if (pl->chain_steps) {   // the chain-step launch must fit the LDS at this shape
+      const size_t need = pl->c64 ? bcr_launch_lds_bytes<float>(pl->max_nb, kg, 1, v[10], v[11])
+                                  : bcr_launch_lds_bytes<double>(pl->max_nb, kg, 1, v[10], v[11]);
+      if (need > (size_t)lds_dev) return 0;
+    }
     pl->kg = kg;
     set(v);
     CHK(build_bcr_jobs(pl));
@@ -1827,7 +1834,7 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
     if (ms / reps < best) {
       best = ms / reps;
       bkg = kg;
-      for (int i = 0; i < 10; ++i) bpol[i] = v[i];
+      for (int i = 0; i < 12; ++i) bpol[i] = v[i];
     }
     return 0;
   };
@@ -1839,17 +1846,31 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
   if (rc == 0 && pl->solver == 2) {
     const int kg1 = bkg;
     for (const auto& pol : pols) {
-      int v[10];
+      int v[12];
       for (int i = 0; i < 9; ++i) v[i] = pol[i];
       v[9] = 0;
+      v[10] = best0[10];
+      v[11] = best0[11];
       if ((rc = trial(kg1, v)) != 0) break;
     }
     if (rc == 0 && !kgs.empty() && kgs.back() > kg1) {
-      int v[10];
-      for (int i = 0; i < 10; ++i) v[i] = bpol[i];
+      int v[12];
+      for (int i = 0; i < 12; ++i) v[i] = bpol[i];
       v[9] = kgs.back();
       rc = trial(kg1, v);
     }
+  }
+  if (rc == 0 && pl->chain_steps) {
+    // chain steps: (column groups, row tiles per workgroup) at the best width
+    const int shapes[][2] = {{3, 0}, {2, 0}, {1, 0}, {4, 1}, {8, 1}, {12, 1}};
+    for (int kg : kgs)
+      for (const auto& sh : shapes) {
+        int v[12];
+        for (int i = 0; i < 12; ++i) v[i] = bpol[i];
+        v[10] = sh[0];
+        v[11] = sh[1];
+        if ((rc = trial(kg, v)) != 0) break;
+      }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
@@ -1869,9 +1890,10 @@ int dsd_autotune(dsd_plan* pl, int nrhs, int reps, int* kg_host, int* cg_wide_ho
 
 int dsd_get_solve_shape(const dsd_plan* pl, int* v) {
   if (!pl || !v) return DSD_EINVAL;
-  const int t[11] = {pl->kg,     pl->cg_wide, pl->cg_mid,  pl->wide_cg, pl->wide_rt, pl->mid_cg,
-                     pl->mid_rt, pl->deep_cg, pl->deep_rt, pl->dense_cg, pl->wide_kg};
-  for (int i = 0; i < 11; ++i) v[i] = t[i];
+  const int t[13] = {pl->kg,      pl->cg_wide, pl->cg_mid,   pl->wide_cg, pl->wide_rt,
+                     pl->mid_cg,  pl->mid_rt,  pl->deep_cg,  pl->deep_rt, pl->dense_cg,
+                     pl->wide_kg, pl->chain_cg, pl->chain_rt};
+  for (int i = 0; i < 13; ++i) v[i] = t[i];
   return DSD_OK;
 }
 
@@ -1879,10 +1901,15 @@ int dsd_set_solve_shape(dsd_plan* pl, const int* v) {
   g_detail.clear();
   if (!pl || !v) { g_detail = "null argument"; return DSD_EINVAL; }
   auto shape_ok = [](int cg, int rt) { return (rt == 0 && cg >= 1 && cg <= 4) || (rt == 1 && cg >= 1 && cg <= 12); };
-  const int kg = choose_kg(pl, v[0]);
+  const int c0 = pl->chain_cg, r0 = pl->chain_rt;
+  pl->chain_cg = v[11];
+  pl->chain_rt = v[12];
+  const int kg = shape_ok(v[11], v[12]) ? choose_kg(pl, v[0]) : 0;
   const bool wkg_ok = v[10] == 0 || (v[10] >= 1 && choose_kg(pl, v[10]) == v[10]);
+  pl->chain_cg = c0;
+  pl->chain_rt = r0;
   if (v[0] < 1 || kg != v[0] || v[1] < 1 || v[2] < 1 || !shape_ok(v[3], v[4]) || !shape_ok(v[5], v[6]) ||
-      !shape_ok(v[7], v[8]) || v[9] < 1 || v[9] > 12 || !wkg_ok) {
+      !shape_ok(v[7], v[8]) || v[9] < 1 || v[9] > 12 || !wkg_ok || !shape_ok(v[11], v[12])) {
     g_detail = "solve shape: RHS per workgroup the plan supports, thresholds >= 1, (cg, rt) with rt 0 "
                "and cg 1..4 or rt 1 and cg 1..12, dense cg 1..12, wide-level RHS per workgroup 0 or supported";
     return DSD_EINVAL;
@@ -1891,6 +1918,8 @@ int dsd_set_solve_shape(dsd_plan* pl, const int* v) {
   pl->cg_wide = v[1]; pl->cg_mid = v[2]; pl->wide_cg = v[3]; pl->wide_rt = v[4];
   pl->mid_cg = v[5]; pl->mid_rt = v[6]; pl->deep_cg = v[7]; pl->deep_rt = v[8]; pl->dense_cg = v[9];
   pl->wide_kg = v[10];
+  pl->chain_cg = v[11];
+  pl->chain_rt = v[12];
   for (auto& kv : pl->graphs) (void)hipGraphExecDestroy(kv.second);   // tables change
   pl->graphs.clear();
   return build_bcr_jobs(pl);

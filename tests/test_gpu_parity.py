@@ -125,13 +125,14 @@ def test_sweep_apply_deterministic():
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("solver", ["bcr", "chain-steps"])
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-3)])
-def test_autotuned_plan_matches_oracle(prec, tol):
+def test_autotuned_plan_matches_oracle(prec, tol, solver):
     """The autotuner only picks launch shapes: the tuned plan still matches the oracle."""
     n, h, om, pml, d, parts, c = _case("lay33")
     k = 3
     f = sources(n, h, pml, k)
-    plan = _plan(n, h, om, pml, d, parts, c, prec, k, solver="bcr")
+    plan = _plan(n, h, om, pml, d, parts, c, prec, k, solver=solver)
     res = plan.autotune(reps=1)
     assert res["rhs_per_group"] >= 1 and res["ms_per_application"] > 0
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
@@ -140,23 +141,25 @@ def test_autotuned_plan_matches_oracle(prec, tol):
     print(f"autotune {prec}: {res}; vs oracle {rel(u, u_ref):.2e}", flush=True)
     assert rel(u, u_ref) < tol
     # a saved shape applied to a fresh plan reproduces the tuned plan bitwise
-    plan2 = _plan(n, h, om, pml, d, parts, c, prec, k, solver="bcr")
+    plan2 = _plan(n, h, om, pml, d, parts, c, prec, k, solver=solver)
     plan2.solve_shape = res["shape"]
     assert plan2.solve_shape == res["shape"]
     u2 = plan2.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
     assert np.array_equal(u2, u)
 
 
-@pytest.mark.parametrize("shape", [(4, 32, 8, 1, 0, 2, 0, 8, 1, 12, 8), (2, 16, 4, 2, 0, 4, 1, 12, 1, 4, 0),
-                                   (8, 1 << 30, 1 << 30, 1, 0, 1, 0, 1, 0, 8, 0),
-                                   (1, 8, 2, 12, 1, 3, 1, 1, 1, 1, 4)])
-def test_solve_shapes_match_oracle(shape):
-    """Every level-shape policy the autotuner may pick solves the same problem."""
+@pytest.mark.parametrize("shape", [(4, 32, 8, 1, 0, 2, 0, 8, 1, 12, 8, 3, 0), (2, 16, 4, 2, 0, 4, 1, 12, 1, 4, 0, 12, 1),
+                                   (8, 1 << 30, 1 << 30, 1, 0, 1, 0, 1, 0, 8, 0, 1, 0),
+                                   (1, 8, 2, 12, 1, 3, 1, 1, 1, 1, 4, 4, 1)])
+@pytest.mark.parametrize("solver", ["bcr", "chain-steps"])
+def test_solve_shapes_match_oracle(shape, solver):
+    """Every launch shape the autotuner may pick solves the same problem."""
     n, h, om, pml, d, parts, c = _case("rag34")
     k = 3
     f = sources(n, h, pml, k)
-    plan = _plan(n, h, om, pml, d, parts, c, "c128", k, solver="bcr")
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k, solver=solver)
     plan.solve_shape = shape
+    assert plan.solve_shape == tuple(shape)
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
