@@ -147,118 +147,188 @@ void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jo
                      scratch);
 }
 
-// In-place Gauss-Jordan inversion with partial (row) pivoting of the FP64
-// column-major nb x nb matrix at scratch[cur]; one workgroup per job.  The
-// inverse is then rounded into the factor slot of block k.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_invert(const SubDesc* subs, const FactorJob* jobs,
-                                                 cpx<double>* scratch, cpx<T>* fac, int* err,
-                                                 int* pivbuf, int max_nb) {
-  const FactorJob J = jobs[blockIdx.x];
-  const SubDesc S = subs[J.sub];
-  const int nb = S.nb;
-  cpx<double>* a = scratch + J.cur;
-  extern __shared__ unsigned char smem_raw[];
-  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem_raw);
-  cpx<double>* rowj = tcol + nb;
-  int* piv = pivbuf + (long long)blockIdx.x * max_nb;
+// In-place inversion of the FP64 column-major n x n matrix a by blocked
+// Gauss-Jordan elimination with partial (row) pivoting, one 1024-thread
+// workgroup per matrix.  Panels of GJ_B columns are eliminated column by column
+// (row interchanges applied to whole rows, rank-1 updates to the panel only);
+// the rest of the matrix then takes the panel's transformation at once,
+//   A[i, c] = [i not a pivot row of the panel] A[i, c] + sum_k P[i, k] R[k, c],
+// with P the transformed panel and R the panel's pivot rows (copied to R
+// first), as tiled products through LDS.  The row interchanges are undone as
+// column interchanges at the end.  LDS: tcol and rowj (2 max_n entries), then
+// the product tiles.  Returns nonzero (in thread 0) for a zero pivot.
+constexpr int GJ_B = 32;              // panel width
+constexpr int GJ_TI = 64, GJ_TC = 64; // product tile: rows x columns
+
+__device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv, cpx<double>* R,
+                          unsigned char* smem, const int max_n) {
+  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem);
+  cpx<double>* rowj = tcol + max_n;
+  cpx<double>* Pt = rowj + max_n;           // [GJ_B][GJ_TI]
+  cpx<double>* Rt = Pt + GJ_B * GJ_TI;      // [GJ_TC][GJ_B + 1]
   __shared__ double red_v[16];
   __shared__ int red_i[16];
   __shared__ int s_p;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
   int bad = 0;
-  for (int j = 0; j < nb; ++j) {
-    // pivot: largest |a_ij| for i >= j (ties: smallest i)
-    double bv = -1.0;
-    int bi = nb;
-    for (int i = j + tid; i < nb; i += bs) {
-      double v = abs2(a[(long long)j * nb + i]);
-      if (v > bv) { bv = v; bi = i; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      double ov = __shfl_down(bv, o, 64);
-      int oi = __shfl_down(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double v = red_v[0];
-      int p = red_i[0];
-      for (int w = 1; w < nw; ++w)
-        if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
-      if (!(v > 0.0)) { bad = 1; p = j; }
-      s_p = p;
-      piv[j] = p;
-    }
-    __syncthreads();
-    const int p = s_p;
-    if (p != j) {
-      for (int c = tid; c < nb; c += bs) {
-        cpx<double> t0 = a[(long long)c * nb + j];
-        a[(long long)c * nb + j] = a[(long long)c * nb + p];
-        a[(long long)c * nb + p] = t0;
+  for (int j0 = 0; j0 < n; j0 += GJ_B) {
+    const int j1 = min(n, j0 + GJ_B), bw = j1 - j0;
+    for (int j = j0; j < j1; ++j) {
+      // pivot: largest |a_ij| for i >= j (ties: smallest i)
+      double bv = -1.0;
+      int bi = n;
+      for (int i = j + tid; i < n; i += bs) {
+        const double v = abs2(a[(long long)j * n + i]);
+        if (v > bv) { bv = v; bi = i; }
       }
-    }
-    __syncthreads();
-    for (int i = tid; i < nb; i += bs) tcol[i] = a[(long long)j * nb + i];
-    __syncthreads();
-    const cpx<double> piv_v = tcol[j];
-    const cpx<double> pinv = (abs2(piv_v) > 0.0) ? cdiv(mk(1.0, 0.0), piv_v) : mk(0.0, 0.0);
-    for (int c = tid; c < nb; c += bs)
-      rowj[c] = (c == j) ? pinv : a[(long long)c * nb + j] * pinv;
-    __syncthreads();
-    // rank-1 update, one column per wave at a time (coalesced, four loads in
-    // flight per lane)
-    for (int c = wid; c < nb; c += nw) {
-      cpx<double>* col = a + (long long)c * nb;
-      const cpx<double> rj = rowj[c];
-      for (int i0 = lane; i0 < nb; i0 += 256) {
-        cpx<double> v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 64 * u;
-          v[u] = i < nb ? col[i] : mk(0.0, 0.0);
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_down(bv, o, 64);
+        const int oi = __shfl_down(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double v = red_v[0];
+        int p = red_i[0];
+        for (int w = 1; w < nw; ++w)
+          if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
+        if (!(v > 0.0)) { bad = 1; p = j; }
+        s_p = p;
+        piv[j] = p;
+      }
+      __syncthreads();
+      const int p = s_p;
+      if (p != j) {
+        for (int c = tid; c < n; c += bs) {
+          const cpx<double> t0 = a[(long long)c * n + j];
+          a[(long long)c * n + j] = a[(long long)c * n + p];
+          a[(long long)c * n + p] = t0;
         }
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += bs) tcol[i] = a[(long long)j * n + i];
+      __syncthreads();
+      const cpx<double> pv = tcol[j];
+      const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+      for (int c = j0 + tid; c < j1; c += bs)
+        rowj[c] = (c == j) ? pinv : a[(long long)c * n + j] * pinv;
+      __syncthreads();
+      // rank-1 update of the panel columns, one column per wave
+      for (int c = j0 + wid; c < j1; c += nw) {
+        cpx<double>* col = a + (long long)c * n;
+        const cpx<double> rj = rowj[c];
+        for (int i0 = lane; i0 < n; i0 += 256) {
+          cpx<double> v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 64 * u;
-          if (i < nb) {
-            if (i == j) col[i] = rj;
-            else if (c == j) col[i] = -(tcol[i] * pinv);
-            else col[i] = v[u] - tcol[i] * rj;
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u;
+            v[u] = i < n ? col[i] : mk(0.0, 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + 64 * u;
+            if (i < n) {
+              if (i == j) col[i] = rj;
+              else if (c == j) col[i] = -(tcol[i] * pinv);
+              else col[i] = v[u] - tcol[i] * rj;
+            }
           }
         }
       }
+      __syncthreads();
+    }
+    if (j1 >= n && j0 == 0) continue;   // a single panel covers the matrix
+    // R[c][k] = pivot row j0 + k at column c (all columns; panel ones unused)
+    for (long long e = tid; e < (long long)bw * n; e += bs) {
+      const int c = (int)(e / bw), k = (int)(e - (long long)c * bw);
+      R[(long long)c * GJ_B + k] = a[(long long)c * n + j0 + k];
     }
     __syncthreads();
+    // every column outside the panel: A = [not pivot row] A + P R
+    const int nti = (n + GJ_TI - 1) / GJ_TI, ntc = (n + GJ_TC - 1) / GJ_TC;
+    const int r = tid % GJ_TI, cq = (tid / GJ_TI) * 4;   // 4 output columns per thread
+    for (int tile = 0; tile < nti * ntc; ++tile) {
+      const int i0 = (tile % nti) * GJ_TI, c0 = (tile / nti) * GJ_TC;
+      if (c0 >= j0 && c0 + GJ_TC <= j1) continue;       // tile inside the panel (uniform)
+      for (int e = tid; e < GJ_B * GJ_TI; e += bs) {
+        const int k = e / GJ_TI, rr = e - k * GJ_TI;
+        Pt[e] = (k < bw && i0 + rr < n) ? a[(long long)(j0 + k) * n + i0 + rr] : mk(0.0, 0.0);
+      }
+      for (int e = tid; e < GJ_B * GJ_TC; e += bs) {
+        const int cc = e / GJ_B, k = e - cc * GJ_B;
+        Rt[cc * (GJ_B + 1) + k] = (k < bw && c0 + cc < n) ? R[(long long)(c0 + cc) * GJ_B + k] : mk(0.0, 0.0);
+      }
+      __syncthreads();
+      const int i = i0 + r;
+      const bool prow = i >= j0 && i < j1;
+      bool live[4];
+      cpx<double> acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = c0 + cq + u;
+        live[u] = i < n && c < n && (c < j0 || c >= j1);
+        acc[u] = (live[u] && !prow) ? a[(long long)c * n + i] : mk(0.0, 0.0);
+      }
+      for (int k = 0; k < bw; ++k) {
+        const cpx<double> pk = Pt[k * GJ_TI + r];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = acc[u] + pk * Rt[(cq + u) * (GJ_B + 1) + k];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (live[u]) a[(long long)(c0 + cq + u) * n + i] = acc[u];
+      __syncthreads();
+    }
   }
   // undo the row interchanges as column interchanges, in reverse order
-  for (int j = nb - 1; j >= 0; --j) {
+  for (int j = n - 1; j >= 0; --j) {
     const int p = piv[j];
     if (p != j) {
-      for (int i = tid; i < nb; i += bs) {
-        cpx<double> t0 = a[(long long)j * nb + i];
-        a[(long long)j * nb + i] = a[(long long)p * nb + i];
-        a[(long long)p * nb + i] = t0;
+      for (int i = tid; i < n; i += bs) {
+        const cpx<double> t0 = a[(long long)j * n + i];
+        a[(long long)j * n + i] = a[(long long)p * n + i];
+        a[(long long)p * n + i] = t0;
       }
     }
     __syncthreads();
   }
+  return bad;
+}
+
+size_t gj_lds_bytes(int max_n) {
+  return ((size_t)2 * max_n + (size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
+}
+
+// Inversion of the Schur block at scratch[cur] (one workgroup per job); the
+// inverse is then rounded into the factor slot of block k.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_invert(const SubDesc* subs, const FactorJob* jobs,
+                                                 cpx<double>* scratch, cpx<T>* fac, int* err,
+                                                 int* pivbuf, cpx<double>* rbuf, int max_nb) {
+  const FactorJob J = jobs[blockIdx.x];
+  const SubDesc S = subs[J.sub];
+  const int nb = S.nb;
+  cpx<double>* a = scratch + J.cur;
+  extern __shared__ unsigned char smem_raw[];
+  const int bad = gj_blocked(a, nb, pivbuf + (long long)blockIdx.x * max_nb,
+                             rbuf + (long long)blockIdx.x * GJ_B * max_nb, smem_raw, max_nb);
   cpx<T>* out = fac + S.fac_off + (long long)J.k * nb * nb;
   const long long ne = (long long)nb * nb;
-  for (long long e = tid; e < ne; e += bs) out[e] = cvt<T>(a[e]);
-  if (tid == 0 && bad) err[blockIdx.x] = J.sub + 1;
+  for (long long e = threadIdx.x; e < ne; e += blockDim.x) out[e] = cvt<T>(a[e]);
+  if (threadIdx.x == 0 && bad) err[blockIdx.x] = J.sub + 1;
 }
+
+size_t gj_rbuf_entries(int max_n) { return (size_t)GJ_B * max_n; }
 
 template <typename T>
 void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
-                   cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s) {
+                   cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf,
+                   hipStream_t s) {
   if (njobs <= 0) return;
-  size_t lds = (size_t)max_nb * 2 * sizeof(cpx<double>);
-  hipLaunchKernelGGL(k_invert<T>, dim3(njobs), dim3(1024), lds, s, d_subs, d_jobs, scratch, fac,
-                     d_err, d_piv, max_nb);
+  hipLaunchKernelGGL(k_invert<T>, dim3(njobs), dim3(1024), gj_lds_bytes(max_nb), s, d_subs, d_jobs,
+                     scratch, fac, d_err, d_piv, d_rbuf, max_nb);
 }
 
 // ============================================================================
@@ -790,113 +860,31 @@ void launch_bcr_assemble(const Problem& P, const SubDesc* d_subs, const BcrBlkJo
                      dim3(256), 0, s, P, d_subs, d_jobs, diag, cx, cy, work);
 }
 
-// Gauss-Jordan inversion with partial pivoting, in place, one workgroup per job.
+// Inversion in place (blocked Gauss-Jordan), one workgroup per job; the
+// inverse is rounded into fac[dst] when dst >= 0.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_bcr_invert(const BcrInvJob* jobs, cpx<double>* work,
                                                      cpx<T>* fac, int* err, int* pivbuf,
-                                                     int max_nb) {
+                                                     cpx<double>* rbuf, int max_nb) {
   const BcrInvJob J = jobs[blockIdx.x];
   const int nb = J.nb;
   cpx<double>* a = work + J.src;
   extern __shared__ unsigned char smem_raw[];
-  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem_raw);
-  cpx<double>* rowj = tcol + nb;
-  int* piv = pivbuf + (long long)blockIdx.x * max_nb;
-  __shared__ double red_v[16];
-  __shared__ int red_i[16];
-  __shared__ int s_p;
-  const int tid = threadIdx.x, bs = blockDim.x;
-  const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
-  int bad = 0;
-  for (int j = 0; j < nb; ++j) {
-    double bv = -1.0;
-    int bi = nb;
-    for (int i = j + tid; i < nb; i += bs) {
-      const double v = abs2(a[(long long)j * nb + i]);
-      if (v > bv) { bv = v; bi = i; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_down(bv, o, 64);
-      const int oi = __shfl_down(bi, o, 64);
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
-    if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
-    __syncthreads();
-    if (tid == 0) {
-      double v = red_v[0];
-      int p = red_i[0];
-      for (int w = 1; w < nw; ++w)
-        if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
-      if (!(v > 0.0)) { bad = 1; p = j; }
-      s_p = p;
-      piv[j] = p;
-    }
-    __syncthreads();
-    const int p = s_p;
-    if (p != j) {
-      for (int c = tid; c < nb; c += bs) {
-        const cpx<double> t0 = a[(long long)c * nb + j];
-        a[(long long)c * nb + j] = a[(long long)c * nb + p];
-        a[(long long)c * nb + p] = t0;
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < nb; i += bs) tcol[i] = a[(long long)j * nb + i];
-    __syncthreads();
-    const cpx<double> pv = tcol[j];
-    const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
-    for (int c = tid; c < nb; c += bs) rowj[c] = (c == j) ? pinv : a[(long long)c * nb + j] * pinv;
-    __syncthreads();
-    // rank-1 update, one column per wave at a time (coalesced, four loads in
-    // flight per lane)
-    for (int c = wid; c < nb; c += nw) {
-      cpx<double>* col = a + (long long)c * nb;
-      const cpx<double> rj = rowj[c];
-      for (int i0 = lane; i0 < nb; i0 += 256) {
-        cpx<double> v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 64 * u;
-          v[u] = i < nb ? col[i] : mk(0.0, 0.0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int i = i0 + 64 * u;
-          if (i < nb) {
-            if (i == j) col[i] = rj;
-            else if (c == j) col[i] = -(tcol[i] * pinv);
-            else col[i] = v[u] - tcol[i] * rj;
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
-  for (int j = nb - 1; j >= 0; --j) {
-    const int p = piv[j];
-    if (p != j) {
-      for (int i = tid; i < nb; i += bs) {
-        const cpx<double> t0 = a[(long long)j * nb + i];
-        a[(long long)j * nb + i] = a[(long long)p * nb + i];
-        a[(long long)p * nb + i] = t0;
-      }
-    }
-    __syncthreads();
-  }
+  const int bad = gj_blocked(a, nb, pivbuf + (long long)blockIdx.x * max_nb,
+                             rbuf + (long long)blockIdx.x * GJ_B * max_nb, smem_raw, max_nb);
   if (J.dst >= 0) {
     const long long ne = (long long)nb * nb;
-    for (long long e = tid; e < ne; e += bs) fac[J.dst + e] = cvt<T>(a[e]);
+    for (long long e = threadIdx.x; e < ne; e += blockDim.x) fac[J.dst + e] = cvt<T>(a[e]);
   }
-  if (tid == 0 && bad) err[blockIdx.x] = 1;
+  if (threadIdx.x == 0 && bad) err[blockIdx.x] = 1;
 }
 
 template <typename T>
 void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
-                       cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s) {
+                       cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, hipStream_t s) {
   if (njobs <= 0) return;
-  const size_t lds = (size_t)max_nb * 2 * sizeof(cpx<double>);
-  hipLaunchKernelGGL(k_bcr_invert<T>, dim3(njobs), dim3(1024), lds, s, d_jobs, work, fac, d_err,
-                     d_piv, max_nb);
+  hipLaunchKernelGGL(k_bcr_invert<T>, dim3(njobs), dim3(1024), gj_lds_bytes(max_nb), s, d_jobs,
+                     work, fac, d_err, d_piv, d_rbuf, max_nb);
 }
 
 __global__ void k_bcr_diag_update(Problem P, const SubDesc* subs, const BcrDiagUpd* jobs,
@@ -2110,7 +2098,7 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
 #define DSD_INST(T)                                                                              \
   template void launch_convert<T>(const cpx<double>*, cpx<T>*, long long, hipStream_t);          \
   template void launch_invert<T>(const SubDesc*, const FactorJob*, int, int, cpx<double>*,      \
-                                 cpx<T>*, int*, int*, hipStream_t);                              \
+                                 cpx<T>*, int*, int*, cpx<double>*, hipStream_t);                \
   template void launch_chain<T>(int, int, const SubDesc*, const int4*, int, int, int, int,      \
                                 const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*, long long, \
                                 hipStream_t);                                                    \
@@ -2126,7 +2114,7 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
                                      int, int, const cpx<T>*, long long, cpx<double>*,           \
                                      hipStream_t);                                               \
   template void launch_bcr_invert<T>(const BcrInvJob*, int, int, cpx<double>*, cpx<T>*, int*,  \
-                                     int*, hipStream_t);                                         \
+                                     int*, cpx<double>*, hipStream_t);                           \
   template void launch_bcr_copy<T>(const BcrCopyJob*, int, int, const cpx<double>*, cpx<T>*,    \
                                    hipStream_t);                                                 \
   template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int, int,\

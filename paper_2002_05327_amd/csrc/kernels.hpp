@@ -36,9 +36,14 @@ void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jo
                   int max_nb, const cpx<double>* diag, const cpx<double>* cx,
                   const cpx<double>* cy, const cpx<double>* cz, cpx<double>* scratch,
                   hipStream_t s);
+// Inversions (blocked Gauss-Jordan, FP64): d_piv holds max_nb ints and d_rbuf
+// gj_rbuf_entries(max_nb) complex entries per job of the launch.
 template <typename T>
 void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
-                   cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s);
+                   cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf,
+                   hipStream_t s);
+size_t gj_rbuf_entries(int max_n);
+size_t gj_lds_bytes(int max_n);   // dynamic LDS of an inversion launch
 
 // ---- a3: subdomain solves (block-tridiagonal chains); phase 0 fwd, 1 mid, 2 bwd.
 // A job is {subdomain, half (0 top / 1 bottom), sweep, unused}; the right-hand
@@ -76,7 +81,7 @@ void launch_bcr_assemble(const Problem& P, const SubDesc* d_subs, const BcrBlkJo
                          const cpx<double>* cy, cpx<double>* work, hipStream_t s);
 template <typename T>
 void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
-                       cpx<T>* fac, int* d_err, int* d_piv, hipStream_t s);
+                       cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, hipStream_t s);
 void launch_bcr_diag_update(const Problem& P, const SubDesc* d_subs, const BcrDiagUpd* d_jobs,
                             int njobs, int max_nb, const cpx<double>* cy, const cpx<double>* cz,
                             cpx<double>* work, hipStream_t s);

@@ -596,18 +596,20 @@ int bcr_factor(dsd_plan* pl) {
   const long long budget = std::min<long long>((long long)(freeb / 2), 48LL << 30);
   int batch = (int)std::max<long long>(1, budget / ((per_sub + dn2) * (long long)sizeof(cpx<double>)));
   batch = std::min(batch, pl->S);
-  Buf work, derr, dpiv, dj, dwork, dpivd;
+  Buf work, derr, dpiv, drbuf, dj, dwork, dpivd, drbufd;
   CHK(work.alloc((size_t)batch * per_sub * sizeof(cpx<double>)));
   if (dn_max > 0) {
     CHK(dwork.alloc((size_t)batch * dn2 * sizeof(cpx<double>)));
     CHK(dpivd.alloc((size_t)batch * dn_max * sizeof(int)));
+    CHK(drbufd.alloc((size_t)batch * gj_rbuf_entries((int)dn_max) * sizeof(cpx<double>)));
   }
   long long ninv = 0;
   for (const SubDesc& S : pl->subs) ninv += S.nblk + 1;
   CHK(derr.alloc((size_t)ninv * sizeof(int)));
   HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)ninv * sizeof(int), st));
-  const int maxinv = batch * (int)half;
+  const int maxinv = std::min(batch * (int)half, 2048);   // inversions per launch
   CHK(dpiv.alloc((size_t)maxinv * pl->max_nb * sizeof(int)));
+  CHK(drbuf.alloc((size_t)maxinv * gj_rbuf_entries(pl->max_nb) * sizeof(cpx<double>)));
   cpx<double>* W = work.as<cpx<double>>();
   const cpx<double>* c64d[4] = {pl->d_lcoef64[0].as<cpx<double>>(), pl->d_lcoef64[1].as<cpx<double>>(),
                                 pl->d_lcoef64[2].as<cpx<double>>(), pl->d_lcoef64[3].as<cpx<double>>()};
@@ -744,11 +746,11 @@ int bcr_factor(dsd_plan* pl) {
         launch_bcr_dense_build(ddj, (int)dns.size(), (int)dn_max, W, DW, st);
         if (pl->c64) {
           launch_bcr_invert<float>(dij, (int)dinv.size(), (int)dn_max, DW, pl->d_fac.as<cpx<float>>(),
-                                   derr.as<int>() + err_off, dpivd.as<int>(), st);
+                                   derr.as<int>() + err_off, dpivd.as<int>(), drbufd.as<cpx<double>>(), st);
           launch_bcr_dense_store<float>(ddj, (int)dns.size(), (int)dn_max, DW, pl->d_fac.as<cpx<float>>(), st);
         } else {
           launch_bcr_invert<double>(dij, (int)dinv.size(), (int)dn_max, DW, pl->d_fac.as<cpx<double>>(),
-                                    derr.as<int>() + err_off, dpivd.as<int>(), st);
+                                    derr.as<int>() + err_off, dpivd.as<int>(), drbufd.as<cpx<double>>(), st);
           launch_bcr_dense_store<double>(ddj, (int)dns.size(), (int)dn_max, DW,
                                          pl->d_fac.as<cpx<double>>(), st);
         }
@@ -761,11 +763,11 @@ int bcr_factor(dsd_plan* pl) {
         const int n = std::min(maxinv, (int)inv.size() - i0);
         if (pl->c64)
           launch_bcr_invert<float>(dj.as<BcrInvJob>() + i0, n, pl->max_nb, W, pl->d_fac.as<cpx<float>>(),
-                                   derr.as<int>() + err_off, dpiv.as<int>(), st);
+                                   derr.as<int>() + err_off, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
         else
           launch_bcr_invert<double>(dj.as<BcrInvJob>() + i0, n, pl->max_nb, W,
                                     pl->d_fac.as<cpx<double>>(), derr.as<int>() + err_off,
-                                    dpiv.as<int>(), st);
+                                    dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
         err_off += n;
       }
       HIPCHK(hipGetLastError());
@@ -1146,6 +1148,8 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
   int maxjobs = 0;
   for (int t = 0; t <= maxlen; ++t) maxjobs = std::max(maxjobs, job_off[t + 1] - job_off[t]);
   CHK(dpiv.alloc((size_t)maxjobs * pl->max_nb * sizeof(int)));
+  Buf drbuf;
+  CHK(drbuf.alloc((size_t)maxjobs * gj_rbuf_entries(pl->max_nb) * sizeof(cpx<double>)));
   for (int t = 0; t <= maxlen; ++t) {
     const int j0 = job_off[t], nj = job_off[t + 1] - j0;
     const FactorJob* jp = djobs.as<FactorJob>() + j0;
@@ -1156,11 +1160,11 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
     if (pl->c64)
       launch_invert<float>(pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
                            scratch.as<cpx<double>>(), pl->d_fac.as<cpx<float>>(),
-                           derr.as<int>() + j0, dpiv.as<int>(), st);
+                           derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
     else
       launch_invert<double>(pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
                             scratch.as<cpx<double>>(), pl->d_fac.as<cpx<double>>(),
-                            derr.as<int>() + j0, dpiv.as<int>(), st);
+                            derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
     HIPCHK(hipGetLastError());
   }
   std::vector<int> herr(all.size());
@@ -1603,7 +1607,8 @@ int device_lds() {
 
 // Largest reduced system (in blocks) the cyclic reduction solves densely: the
 // requested bound (default 8), lowered until the dense solve launch fits the
-// LDS at the widest RHS group the plan may use, and its order m nb <= 2048.
+// LDS at the widest RHS group the plan may use, its order m nb <= 2048, and
+// its inversion fits the LDS.
 int dense_blocks(const dsd_plan* pl, int req) {
   if (req < 0) return 0;
   int m = req > 0 ? req : 8;
@@ -1613,7 +1618,9 @@ int dense_blocks(const dsd_plan* pl, int req) {
     return pl->c64 ? bcr_launch_lds_bytes<float>(pl->max_nb, kgcap, mm, 12, 1)
                    : bcr_launch_lds_bytes<double>(pl->max_nb, kgcap, mm, 12, 1);
   };
-  while (m >= 2 && (need(m) > (size_t)lds || (long long)m * pl->max_nb > 2048)) --m;
+  while (m >= 2 && (need(m) > (size_t)lds || (long long)m * pl->max_nb > 2048 ||
+                    gj_lds_bytes(m * pl->max_nb) > (size_t)lds))
+    --m;
   return m >= 2 ? m : 0;
 }
 
@@ -1708,6 +1715,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
                                                : ((pl->solver == 2 || pl->chain_steps) ? (pl->c64 ? 8 : 4) : 2));
     if (pl->kg == 0) {
       g_detail = "subdomain blocks too large for the solve kernel's LDS";
+      rc = DSD_EINVAL;
+    }
+    if (rc == 0 && gj_lds_bytes(pl->max_nb) > (size_t)device_lds()) {
+      g_detail = "subdomain blocks too large for the inversion kernel's LDS";
       rc = DSD_EINVAL;
     }
   }
