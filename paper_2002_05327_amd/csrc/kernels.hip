@@ -154,9 +154,11 @@ void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jo
 // the rest of the matrix then takes the panel's transformation at once,
 //   A[i, c] = [i not a pivot row of the panel] A[i, c] + sum_k P[i, k] R[k, c],
 // with P the transformed panel and R the panel's pivot rows (copied to R
-// first), as tiled products through LDS.  The row interchanges are undone as
-// column interchanges at the end.  LDS: tcol and rowj (2 max_n entries), then
-// the product tiles.  Returns nonzero (in thread 0) for a zero pivot.
+// first), as 64 x 64 tiled products on the FP64 matrix cores with operands
+// staged in LDS.  The row interchanges are undone as column interchanges at
+// the end.  LDS: tcol and rowj (2 max_n entries), then the product tiles.
+// Returns nonzero (in thread 0) for a zero pivot.
+typedef double gj_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GJ_B = 32;              // panel width
 constexpr int GJ_TI = 64, GJ_TC = 64; // product tile: rows x columns
 
@@ -246,9 +248,15 @@ __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv,
       R[(long long)c * GJ_B + k] = a[(long long)c * n + j0 + k];
     }
     __syncthreads();
-    // every column outside the panel: A = [not pivot row] A + P R
+    // every column outside the panel: A = [not pivot row] A + P R, on the FP64
+    // matrix cores.  Wave w owns the 16 x 16 block at rows 16 (w % 4), columns
+    // 16 (w / 4) of the 64 x 64 tile; v_mfma_f64_16x16x4f64 takes A as lane l =
+    // (row l % 16, k l / 16), B as (k l / 16, column l % 16), and returns lane l,
+    // item j = (row 4 j + l / 16, column l % 16).  A complex product is four
+    // real ones: Re += Re P Re R - Im P Im R, Im += Re P Im R + Im P Re R.
     const int nti = (n + GJ_TI - 1) / GJ_TI, ntc = (n + GJ_TC - 1) / GJ_TC;
-    const int r = tid % GJ_TI, cq = (tid / GJ_TI) * 4;   // 4 output columns per thread
+    const int sr = (wid & 3) * 16, sc = (wid >> 2) * 16;
+    const int l16 = lane & 15, l4 = lane >> 4;
     for (int tile = 0; tile < nti * ntc; ++tile) {
       const int i0 = (tile % nti) * GJ_TI, c0 = (tile / nti) * GJ_TC;
       if (c0 >= j0 && c0 + GJ_TC <= j1) continue;       // tile inside the panel (uniform)
@@ -261,24 +269,31 @@ __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv,
         Rt[cc * (GJ_B + 1) + k] = (k < bw && c0 + cc < n) ? R[(long long)(c0 + cc) * GJ_B + k] : mk(0.0, 0.0);
       }
       __syncthreads();
-      const int i = i0 + r;
-      const bool prow = i >= j0 && i < j1;
-      bool live[4];
-      cpx<double> acc[4];
+      const int c = c0 + sc + l16;                       // this lane's output column
+      const bool ccol = c < n && (c < j0 || c >= j1);
+      const int ib = i0 + sr + l4;                       // this lane's rows: ib + 4 j
+      gj_f64x4 cr, ci;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int c = c0 + cq + u;
-        live[u] = i < n && c < n && (c < j0 || c >= j1);
-        acc[u] = (live[u] && !prow) ? a[(long long)c * n + i] : mk(0.0, 0.0);
+      for (int j = 0; j < 4; ++j) {
+        const int i = ib + 4 * j;
+        const bool ld = ccol && i < n && (i < j0 || i >= j1);
+        const cpx<double> v = ld ? a[(long long)c * n + i] : mk(0.0, 0.0);
+        cr[j] = v.re;
+        ci[j] = v.im;
       }
-      for (int k = 0; k < bw; ++k) {
-        const cpx<double> pk = Pt[k * GJ_TI + r];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] = acc[u] + pk * Rt[(cq + u) * (GJ_B + 1) + k];
+      for (int kk = 0; kk < bw; kk += 4) {
+        const cpx<double> pa = Pt[(kk + l4) * GJ_TI + sr + l16];
+        const cpx<double> rb = Rt[(sc + l16) * (GJ_B + 1) + kk + l4];
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.re, rb.re, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.re, rb.im, ci, 0, 0, 0);
+        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa.im, rb.im, cr, 0, 0, 0);
+        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.im, rb.re, ci, 0, 0, 0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (live[u]) a[(long long)(c0 + cq + u) * n + i] = acc[u];
+      for (int j = 0; j < 4; ++j) {
+        const int i = ib + 4 * j;
+        if (ccol && i < n) a[(long long)c * n + i] = mk(cr[j], ci[j]);
+      }
       __syncthreads();
     }
   }
