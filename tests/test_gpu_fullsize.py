@@ -125,8 +125,8 @@ def _fwi_setup(n_cells, parts, nsrc, nrec):
 def test_c5_fwi_gradient_by_finite_differences():
     """Full FWI workload (512^2, 8x8, 64 shots, 128 receivers): the adjoint
     gradient behind HelmholtzMisfit (complex64 factors + FP64 refinement)
-    against central differences of the misfit along two seeded smooth
-    directions (plain complex128 path, solves at 1e-12)."""
+    against central differences of the misfit along eight seeded smooth
+    directions, seeds 100-107 (plain complex128 path, solves at 1e-12)."""
     import synth
     import paper_2002_05327_amd as dsw
     w0 = synth.workload("c5")
@@ -153,7 +153,7 @@ def test_c5_fwi_gradient_by_finite_differences():
     J = dsw.HelmholtzMisfit.apply(mt, f_t, rec_t, d_obs, dict(precision="c64", **kw), 1e-10, 300)
     J.backward()
     g = mt.grad.cpu().numpy()
-    for p in synth.smooth_directions(w.n[0], w.n[1], 2, seed=100):
+    for p in synth.smooth_directions(w.n[0], w.n[1], 8, seed=100):
         eps = 1e-4 * np.linalg.norm(m0) / np.linalg.norm(p)
         fd = (misfit(m0 + eps * p, d_obs) - misfit(m0 - eps * p, d_obs)) / (2 * eps)
         an = float(np.sum(g * p))
