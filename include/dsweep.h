@@ -235,6 +235,12 @@ const char* dsd_last_error_detail(void);
 int dsd_timing_enable(dsd_plan* plan, int on);
 int dsd_timing_read(dsd_plan* plan, double* solve_ms, long long* solve_launches,
                     double* solve_bytes, double* other_ms);
+/* The algorithmic flops of the same launches since the last reset: 8 real
+ * flops per complex factor entry and right-hand side (each factor block applied
+ * to every right-hand side of the call).  With dsd_timing_read's bytes this
+ * places the solves against the matrix-core roof when the right-hand-side
+ * count makes them compute bound.  DSD_EINVAL for a null argument. */
+int dsd_timing_flops(dsd_plan* plan, double* solve_flops);
 
 #ifdef __cplusplus
 }

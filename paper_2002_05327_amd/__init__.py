@@ -214,7 +214,10 @@ class Plan:
         ms, n, b, o = C.c_double(), C.c_longlong(), C.c_double(), C.c_double()
         check(self._lib.dsd_timing_read(self._h, C.byref(ms), C.byref(n), C.byref(b),
                                         C.byref(o)), "dsd_timing_read")
-        return {"solve_ms": ms.value, "solve_launches": n.value, "solve_bytes": b.value}
+        fl = C.c_double()
+        check(self._lib.dsd_timing_flops(self._h, C.byref(fl)), "dsd_timing_flops")
+        return {"solve_ms": ms.value, "solve_launches": n.value, "solve_bytes": b.value,
+                "solve_flops": fl.value}
 
 
 class HelmholtzMisfit(torch.autograd.Function):

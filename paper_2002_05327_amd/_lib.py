@@ -53,6 +53,7 @@ EXPORTS = {
     "dsd_timing_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "dsd_timing_read": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_longlong),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "dsd_timing_flops": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
 }
 
 _lib = None

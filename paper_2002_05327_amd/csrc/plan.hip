@@ -188,7 +188,7 @@ struct dsd_plan {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> tev;
   size_t tev_used = 0;
-  double t_solve_ms = 0, t_other_ms = 0, solve_bytes = 0;
+  double t_solve_ms = 0, t_other_ms = 0, solve_bytes = 0, solve_flops = 0;
   long long solve_launches = 0;
 
   // captured preconditioner applications, keyed by (f, u, nrhs)
@@ -1196,12 +1196,13 @@ void time_begin(dsd_plan* pl) {
   }
   (void)hipEventRecord(pl->tev[pl->tev_used], pl->stream);
 }
-void time_end(dsd_plan* pl, double bytes) {
+void time_end(dsd_plan* pl, double bytes, double flops) {
   if (!pl->timing) return;
   (void)hipEventRecord(pl->tev[pl->tev_used + 1], pl->stream);
   pl->tev_used += 2;
   pl->solve_launches += 1;
   pl->solve_bytes += bytes;
+  pl->solve_flops += flops;
 }
 void time_flush(dsd_plan* pl) {
   if (pl->tev_used == 0) return;
@@ -1222,8 +1223,10 @@ void chain_phase(dsd_plan* pl, int phase, const int4* jobs, int njobs, int nrhs,
   launch_chain<T>(pl->kg, phase, pl->d_subs.as<SubDesc>(), jobs, njobs, nrhs, pl->kmax,
                   pl->max_nb, pl->d_fac.as<cpx<T>>(), pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>(),
                   pl->d_rpool.as<cpx<T>>(), pl->d_vpool.as<cpx<T>>(), pl->sum_nloc * pl->kmax, st);
-  // factor blocks once per launch plus the vectors read and written per RHS
-  time_end(pl, fbytes + (double)blk_cells * nrhs * 2.0 * sizeof(cpx<T>));
+  // factor blocks once per launch plus the vectors read and written per RHS;
+  // 8 real flops per complex factor entry and right-hand side
+  time_end(pl, fbytes + (double)blk_cells * nrhs * 2.0 * sizeof(cpx<T>),
+           fbytes / sizeof(cpx<T>) * nrhs * 8.0);
 }
 
 template <typename T>
@@ -1241,7 +1244,8 @@ void bcr_phase(dsd_plan* pl, const BcrJob* jobs, const BcrLaunch& L, int nrhs) {
   time_begin(pl);
   launch_bcr_solve<T>(L.kg > 0 ? L.kg : pl->kg, pl->d_subs.as<SubDesc>(), jobs + L.off, L.n, L.nset, L.cg, L.rt, nrhs,
                       pl->kmax, pl->max_nb, pl->d_fac.as<cpx<T>>(), cpl, rpool, vpool, ps, st);
-  time_end(pl, L.fbytes + L.vcells * nrhs * (double)sizeof(cpx<T>));
+  time_end(pl, L.fbytes + L.vcells * nrhs * (double)sizeof(cpx<T>),
+           L.fbytes / sizeof(cpx<T>) * nrhs * 8.0);
 }
 
 template <typename T>
@@ -2140,7 +2144,7 @@ int dsd_timing_enable(dsd_plan* pl, int on) {
   if (!pl) return DSD_EINVAL;
   time_flush(pl);
   pl->timing = on != 0;
-  pl->t_solve_ms = pl->t_other_ms = pl->solve_bytes = 0;
+  pl->t_solve_ms = pl->t_other_ms = pl->solve_bytes = pl->solve_flops = 0;
   pl->solve_launches = 0;
   return DSD_OK;
 }
@@ -2153,6 +2157,13 @@ int dsd_timing_read(dsd_plan* pl, double* solve_ms, long long* solve_launches,
   if (solve_launches) *solve_launches = pl->solve_launches;
   if (solve_bytes) *solve_bytes = pl->solve_bytes;
   if (other_ms) *other_ms = pl->t_other_ms;
+  return DSD_OK;
+}
+
+int dsd_timing_flops(dsd_plan* pl, double* solve_flops) {
+  if (!pl || !solve_flops) return DSD_EINVAL;
+  time_flush(pl);
+  *solve_flops = pl->solve_flops;
   return DSD_OK;
 }
 
