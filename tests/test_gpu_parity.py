@@ -321,3 +321,29 @@ def test_fwi_gradient_matches_oracle():
         eg = rel(g.cpu().numpy(), g_ref)
         print(f"fwi {prec}: misfit rel {abs(J - J_ref) / J_ref:.2e} grad rel {eg:.2e}")
         assert abs(J - J_ref) / J_ref < bound and eg < bound * 10
+
+
+@pytest.mark.parametrize("solver", SOLVERS)
+def test_timing_hooks_bytes_and_flops(solver):
+    """The measurement hooks behind bench.py's roofline, over one application:
+    launches and device time are positive; the flops (8 per complex factor
+    entry and right-hand side) scale exactly with the right-hand-side count,
+    the bytes only through their vector part, so 2 B(4) - B(8) is the factor
+    bytes F and the flops at 4 RHS are 4 F."""
+    n, h, om, pml, d, parts, c = _case("lay33")
+    plan = _plan(n, h, om, pml, d, parts, c, "c64", 8, solver=solver)
+    reads = {}
+    for k in (4, 8):
+        f = _cuda(sources(n, h, pml, k))
+        plan.timing(True)
+        plan.sweep_apply(f)
+        torch.cuda.synchronize()
+        reads[k] = plan.timing_read()
+        plan.timing(False)
+    a, b = reads[4], reads[8]
+    assert a["solve_launches"] == b["solve_launches"] > 0
+    assert a["solve_ms"] > 0 and b["solve_ms"] > 0
+    assert b["solve_flops"] == pytest.approx(2 * a["solve_flops"], rel=1e-12)
+    fac = 2 * a["solve_bytes"] - b["solve_bytes"]
+    assert fac > 0
+    assert a["solve_flops"] == pytest.approx(4 * fac, rel=1e-9)
