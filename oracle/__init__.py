@@ -16,6 +16,9 @@ paper by eye:
   * :mod:`oracle.sweep`     -- sweep orders, Rules 3.1/3.2/4.1/4.2, Algorithms 3.1/4.1
   * :mod:`oracle.krylov`    -- flexible GMRES with the DDM as right preconditioner
                                 (Remark 1 of Section 4, Section 5.2)
+  * :mod:`oracle.analytic`  -- free-space solutions of the Gaussian sources of the
+                                constant-medium accuracy tests (Section 5.1,
+                                Tables 1 and 2) and the L2 error against them
   * :mod:`oracle.fwi`       -- misfit and adjoint gradient w.r.t. 1/c^2
                                 (Remark 2 of Section 4 motivates it; no formula in
                                 the paper, so the adjoint is derived from the
