@@ -195,6 +195,21 @@ int dsd_apply_operator(dsd_plan* plan, const double* x_dev, double* y_dev, int n
 int dsd_gmres_solve(dsd_plan* plan, const double* b_dev, double* x_dev, int nrhs, double tol,
                     int maxit, int restart, int* iters_host, double* relres_host, void* stream);
 
+/*
+ * The diagonal sweeps as a stand-alone iterative solver (Section 5.2, the
+ * three-layer residual-decay test): x_0 = 0, x_{k+1} = x_k + DDM(f - M x_k)
+ * with DDM = dsd_sweep_apply in the plan precision and the residual in FP64.
+ *   f_dev, x_dev     : [nrhs][N_g] complex128, must not alias (x overwritten).
+ *   iters            : sweep applications (>= 0).
+ *   relres_hist_host : [iters + 1][nrhs] ||f - M x_k|| / ||f|| for k = 0..iters
+ *                      (1 at k = 0; 0 for a zero right-hand side).
+ * Synchronises the stream after every iteration (the history is host data).
+ * DSD_EINVAL for a bad pointer, nrhs outside 1..max_rhs or iters < 0;
+ * DSD_ENOTFINITE for a non-finite right-hand side or residual.
+ */
+int dsd_ddm_iterate(dsd_plan* plan, const double* f_dev, double* x_dev, int nrhs, int iters,
+                    double* relres_hist_host, void* stream);
+
 /* Solve the adjoint system M^H x = b with the same factors; M is complex
  * symmetric, so x = conj(M^{-1} conj(b)).  Arguments as dsd_gmres_solve. */
 int dsd_adjoint_solve(dsd_plan* plan, const double* b_dev, double* x_dev, int nrhs, double tol,

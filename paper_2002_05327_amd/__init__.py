@@ -142,6 +142,16 @@ class Plan:
         """Solve M x = b; returns (x, iterations per RHS, true relres per RHS, converged)."""
         return self._krylov(self._lib.dsd_gmres_solve, b, tol, maxit, restart, "dsd_gmres_solve")
 
+    def ddm_iterate(self, f: torch.Tensor, iters: int):
+        """The sweeps as a stand-alone iterative solver: x_{k+1} = x_k + DDM(f - M x_k)
+        from x_0 = 0; returns (x, relative residual history of shape (iters + 1, k))."""
+        k = self._batch(f, "f")
+        x = torch.empty_like(f)
+        hist = (C.c_double * ((int(iters) + 1) * k))()
+        check(self._lib.dsd_ddm_iterate(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(x.data_ptr()),
+                                        k, int(iters), hist, _stream_ptr()), "dsd_ddm_iterate")
+        return x, [list(hist[i * k:(i + 1) * k]) for i in range(int(iters) + 1)]
+
     def adjoint_solve(self, b: torch.Tensor, tol: float = 1e-6, maxit: int = 100,
                       restart: int = 0):
         """Solve M^H x = b with the same factors."""

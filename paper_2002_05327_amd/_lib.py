@@ -40,6 +40,8 @@ EXPORTS = {
     "dsd_gmres_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
                                   C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double),
                                   C.c_void_p]),
+    "dsd_ddm_iterate": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                  C.POINTER(C.c_double), C.c_void_p]),
     "dsd_adjoint_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
                                     C.c_int, C.c_int, C.POINTER(C.c_int),
                                     C.POINTER(C.c_double), C.c_void_p]),

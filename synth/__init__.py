@@ -99,6 +99,23 @@ def layered_medium(nx: int, ny: int, seed: int = 0, n_interfaces: int = 5,
     return np.ascontiguousarray(c)
 
 
+def three_layer_medium(nx: int, ny: int, speeds=(1.0, 2.0, 1.0),
+                       cuts=(0.25, 0.75)) -> np.ndarray:
+    """Three horizontal layers on [0,1]^2 (y = depth as a fraction of the domain),
+    speeds top to bottom, interfaces at the depth fractions ``cuts``; (ny, nx)."""
+    y = (np.arange(ny) + 0.5) / ny
+    col = np.where(y < cuts[0], speeds[0], np.where(y < cuts[1], speeds[1], speeds[2]))
+    return np.repeat(col[:, None], nx, axis=1).astype(np.float64)
+
+
+def point_source(nx: int, ny: int, h: float, pml: int, x: float, y: float) -> np.ndarray:
+    """Unit-mass discrete delta (1/h^2 in the cell holding (x, y)) on the global
+    grid with the PML, shape (ny + 2 pml, nx + 2 pml), complex128."""
+    f = np.zeros((ny + 2 * pml, nx + 2 * pml), np.complex128)
+    f[pml + int(y / h), pml + int(x / h)] = 1.0 / h ** 2
+    return f
+
+
 def grf_medium_3d(n: int, seed: int = 0, mean: float = 2.0, std: float = 0.2,
                   corr_cells: float = 16.0) -> np.ndarray:
     """Smooth Gaussian random field c[iz, iy, ix] with the given mean and std."""

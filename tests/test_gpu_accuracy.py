@@ -112,3 +112,33 @@ def test_table3_gmres_iterations(mesh):
     print(f"Table 3 {n}^2 {P}x{P} omega/2pi={fr}: {iters[0]} iterations "
           f"(relres {relres[0]:.1e}), paper {iters_paper}", flush=True)
     assert ok and iters[0] == iters_paper
+
+
+def test_three_layer_residual_decay_shape():
+    """The shape of Section 5.2's three-layer test on the GPU (complex64 sweeps,
+    FP64 residual, the sweeps as a stand-alone solver): with every subdomain
+    interface inside the middle layer (speeds 1, 2, 1; interfaces at depths
+    1/4 and 3/4), the per-iteration residual ratio of the 3x3 and 6x6 partitions
+    equals the two-subdomain (1x2) ratio, the optimal rate, within 10%; all are
+    near the normal-incidence round-trip reflection 1/9."""
+    import synth
+    import paper_2002_05327_amd as dsw
+    N, freq, pml, d = 384, 12, 16, 6
+    h, om = 1.0 / N, 2 * np.pi * freq
+    c = synth.three_layer_medium(N, N)
+    m = torch.from_numpy(1.0 / c ** 2).cuda()
+    rates = {}
+    for parts in [(1, 2), (3, 3), (6, 6)]:
+        f = synth.point_source(N, N, h, pml, 0.25 / parts[0], (1.0 / 3.0) / parts[1])
+        plan = dsw.Plan(n=(N, N), h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m,
+                        precision="c64", max_rhs=1)
+        x, hist = plan.ddm_iterate(torch.from_numpy(f[None]).cuda(), 8)
+        plan.close()
+        hist = [v[0] for v in hist]
+        rates[parts] = (hist[7] / hist[2]) ** (1.0 / 5)
+        print(f"three layers {N}^2 {parts}: history {['%.2e' % v for v in hist]}, "
+              f"ratio {rates[parts]:.4f}", flush=True)
+    r12 = rates[(1, 2)]
+    assert 0.08 < r12 < 0.14
+    for p in [(3, 3), (6, 6)]:
+        assert abs(rates[p] - r12) < 0.1 * r12

@@ -347,3 +347,43 @@ def test_timing_hooks_bytes_and_flops(solver):
     fac = 2 * a["solve_bytes"] - b["solve_bytes"]
     assert fac > 0
     assert a["solve_flops"] == pytest.approx(4 * fac, rel=1e-9)
+
+
+def _three_layer_case(N, freq, parts):
+    import synth
+    pml, d = 8, 4
+    h, om = 1.0 / N, 2 * np.pi * freq
+    c = synth.three_layer_medium(N, N)
+    f = synth.point_source(N, N, h, pml, 0.25 / parts[0], (1.0 / 3.0) / parts[1])
+    return (N, N), h, om, pml, d, c, f
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+@pytest.mark.parametrize("parts", [(1, 2), (3, 3)])
+def test_ddm_iterate_matches_oracle(parts, prec):
+    """dsd_ddm_iterate (the sweeps as a stand-alone solver, Section 5.2) against
+    the oracle's iteration on the three-layer case: the residual history
+    (complex128: entry by entry; complex64: the first two iterations to the
+    single-precision sweep error) and the iterate, which converges to the
+    global solution in either precision because the residual is FP64."""
+    from oracle.krylov import ddm_iterate
+    n, h, om, pml, d, c, f = _three_layer_case(64, 4, parts)
+    M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml)
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
+    iters = 10
+    x_ref, hist_ref = ddm_iterate(lambda v: M @ v, ddm.apply, f.ravel(), iters)
+    plan = _plan(n, h, om, pml, d, parts, c, prec, 1)
+    x, hist = plan.ddm_iterate(_cuda(f[None]), iters)
+    hist = [v[0] for v in hist]
+    u = global_solve(M, f.ravel())
+    ex = rel(x.cpu().numpy().ravel(), u)
+    print(f"{parts} {prec}: history {['%.3e' % v for v in hist]}; iterate vs global {ex:.2e}")
+    assert hist[0] == 1.0
+    if prec == "c128":
+        for a, b in zip(hist, hist_ref):
+            assert abs(a - b) <= 1e-12 + 1e-7 * b
+        assert rel(x.cpu().numpy().ravel(), x_ref) < 1e-10
+    else:
+        for a, b in zip(hist[1:3], hist_ref[1:3]):
+            assert abs(a - b) <= 1e-3 * b
+    assert hist[-1] < 1e-8 and ex < 1e-7
