@@ -83,6 +83,11 @@ typedef struct {
                             0: the library's bound (8, lowered to fit the solve kernel's
                             LDS and an order of at most 2048); -1: reduce to one block.
                             Valid range -1..64.                                          */
+  int sweep_order;       /* 3D sweep order (Section 4.1): 0 the order (Sorder3D) -- the 2D
+                            order with +z, then with -z; 1 the other order given there,
+                            along which the L1 distance from (+1,+1,+1) never decreases.
+                            Transfers are routed by Rules 4.1/4.2 over the chosen order.
+                            2D has one order (must be 0).                               */
 } dsd_params;
 
 /*

@@ -38,10 +38,20 @@ from .pml import assemble, global_axes
 ORDER_2D = [(1, 1), (-1, 1), (1, -1), (-1, -1)]
 ORDER_3D = [(1, 1, 1), (-1, 1, 1), (1, -1, 1), (-1, -1, 1),
             (1, 1, -1), (-1, 1, -1), (1, -1, -1), (-1, -1, -1)]
+# the other 3D order of Section 4.1: the L1 distance of each direction from the
+# first one never decreases along the list
+ORDER_3D_L1 = [(1, 1, 1), (-1, 1, 1), (1, -1, 1), (1, 1, -1),
+               (-1, -1, 1), (-1, 1, -1), (1, -1, -1), (-1, -1, -1)]
 
 
-def sweep_order(dim: int) -> List[Tuple[int, ...]]:
-    return ORDER_2D if dim == 2 else ORDER_3D
+def sweep_order(dim: int, variant: int = 0) -> List[Tuple[int, ...]]:
+    """variant 0: (Sorder3D) (the 2D order in 3D, +z then -z); variant 1 (3D
+    only): the L1-monotone order."""
+    if dim == 2:
+        if variant != 0:
+            raise ValueError("2D has one sweep order")
+        return ORDER_2D
+    return ORDER_3D_L1 if variant == 1 else ORDER_3D
 
 
 def similar(t: Sequence[int], D: Sequence[int]) -> bool:
@@ -68,10 +78,10 @@ def excluded(t: Sequence[int], D1: Sequence[int], D2: Sequence[int]) -> bool:
     return False
 
 
-def route(l: int, t: Sequence[int], dim: int) -> Optional[int]:
+def route(l: int, t: Sequence[int], dim: int, variant: int = 0) -> Optional[int]:
     """Smallest sweep l' >= l in which a transfer of direction t generated in
     sweep l may be used (Algorithm 3.1 / 4.1), or None (dropped)."""
-    order = sweep_order(dim)
+    order = sweep_order(dim, variant)
     for lp in range(l, len(order)):
         if similar(t, order[lp]) and not excluded(t, order[l], order[lp]):
             return lp
@@ -117,7 +127,7 @@ class DiagonalSweepDDM:
     """
 
     def __init__(self, n, h, omega, pml, d, parts, m_phys, mode="real",
-                 sigma0_delta=60.0):
+                 sigma0_delta=60.0, order_variant=0):
         if mode not in ("real", "exact"):
             raise ValueError(mode)
         self.mode = mode
@@ -127,7 +137,8 @@ class DiagonalSweepDDM:
         self.gshape = tuple(ax.n for ax in reversed(self.gaxes))
         self.N = int(np.prod(self.gshape))
         self.M = assemble(self.gaxes, m_phys, h, omega, pml, sigma0_delta).tocsc()
-        self.order = sweep_order(self.dim)
+        self.variant = order_variant
+        self.order = sweep_order(self.dim, order_variant)
         self.dirs = directions(self.dim)
         self.spaces: Dict[Tuple[int, ...], LocalSpace] = {}
         if mode == "exact":
@@ -234,7 +245,7 @@ class DiagonalSweepDDM:
                         nb = tuple(i + ti for i, ti in zip(sub, t))
                         if not self.part.exists(nb):
                             continue
-                        lp = route(l, t, self.dim)
+                        lp = route(l, t, self.dim, self.variant)
                         if lp is None:
                             continue
                         gv, box = self.transfer(sub, t, v)

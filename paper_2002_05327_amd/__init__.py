@@ -42,7 +42,8 @@ class Plan:
     def __init__(self, n: Sequence[int], h: float, omega: float, pml: int, overlap: int,
                  parts: Sequence[int], m: torch.Tensor, precision: str = "c64",
                  max_rhs: int = 1, rhs_per_group: int = 0, sigma0_delta: float = 60.0,
-                 schedule: str = "dag", local_solver: str = "auto", dense_top: int = 0):
+                 schedule: str = "dag", local_solver: str = "auto", dense_top: int = 0,
+                 sweep_order: str = "default"):
         self._lib = _lib.load()
         dim = len(n)
         if dim not in (2, 3) or len(parts) != dim:
@@ -59,6 +60,7 @@ class Plan:
         p.schedule = {"dag": 0, "sequential": 1}[schedule]
         p.local_solver = {"auto": 0, "chain": 1, "bcr": 2, "chain-steps": 3}[local_solver]
         p.dense_top = int(dense_top)
+        p.sweep_order = {"default": 0, "l1": 1}[sweep_order]
         self.params = p
         self.n, self.dim, self.pml, self.omega = tuple(int(k) for k in n), dim, int(pml), omega
         self.precision, self.max_rhs = precision, int(max_rhs)

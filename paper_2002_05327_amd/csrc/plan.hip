@@ -36,12 +36,18 @@ thread_local std::string g_detail;
   } while (0)
 
 // ---------------------------------------------------------------- sweep rules
-// Sweep directions: Section 3 (2D order) and (Sorder3D) of Section 4.1.
+// Sweep directions: Section 3 (2D order) and (Sorder3D) of Section 4.1, or
+// (3D, variant 1) the other order given there, along which the L1 distance
+// from the first direction never decreases.
 const int ORDER2[4][3] = {{1, 1, 0}, {-1, 1, 0}, {1, -1, 0}, {-1, -1, 0}};
 const int ORDER3[8][3] = {{1, 1, 1},  {-1, 1, 1},  {1, -1, 1},  {-1, -1, 1},
                           {1, 1, -1}, {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
+const int ORDER3_L1[8][3] = {{1, 1, 1},   {-1, 1, 1},  {1, -1, 1},  {1, 1, -1},
+                             {-1, -1, 1}, {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
 
-const int* sweep_dir(int dim, int l) { return dim == 2 ? ORDER2[l] : ORDER3[l]; }
+const int* sweep_dir(int dim, int variant, int l) {
+  return dim == 2 ? ORDER2[l] : (variant == 1 ? ORDER3_L1[l] : ORDER3[l]);
+}
 
 // Rule 3.1 (t.D > 0) / Rule 4.1 (t.D > 0 and every t_k D_k >= 0)
 bool similar(int dim, const int* t, const int* D) {
@@ -69,10 +75,11 @@ bool barred(int dim, const int* t, const int* D1, const int* D2) {
 }
 
 // Sweep (>= l) that uses a transfer of direction t generated in sweep l; -1 if dropped.
-int route(int dim, int l, const int* t) {
+int route(int dim, int variant, int l, const int* t) {
   const int L = 1 << dim;
   for (int lp = l; lp < L; ++lp)
-    if (similar(dim, t, sweep_dir(dim, lp)) && !barred(dim, t, sweep_dir(dim, l), sweep_dir(dim, lp)))
+    if (similar(dim, t, sweep_dir(dim, variant, lp)) &&
+        !barred(dim, t, sweep_dir(dim, variant, l), sweep_dir(dim, variant, lp)))
       return lp;
   return -1;
 }
@@ -380,7 +387,7 @@ int build_schedule(dsd_plan* pl) {
         if (sid < 0) continue;
         unsigned mask = 0;
         for (int lg = 0; lg <= l; ++lg)
-          if (route(dim, lg, t) == l) mask |= 1u << lg;
+          if (route(dim, q.sweep_order, lg, t) == l) mask |= 1u << lg;
         if (!mask) continue;
         const SubDesc& Sd = pl->subs[sid];
         Edge e{};
@@ -423,7 +430,7 @@ int build_schedule(dsd_plan* pl) {
   std::vector<int> level((size_t)L * pl->S, 0);
   std::vector<std::vector<int2>> groups;
   for (int l = 0; l < L; ++l) {
-    const int* D = sweep_dir(dim, l);
+    const int* D = sweep_dir(dim, pl->prm.sweep_order, l);
     std::vector<std::vector<int>> steps(nsteps);
     for (int sid = 0; sid < pl->S; ++sid) {
       const SubDesc& S = pl->subs[sid];
@@ -1672,9 +1679,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
       (q.precision != DSD_C64 && q.precision != DSD_C128) || q.local_solver < 0 ||
       q.local_solver > 3 || q.schedule < 0 || q.schedule > 1 || q.dense_top < -1 ||
-      q.dense_top > 64) {
+      q.dense_top > 64 || q.sweep_order < 0 || q.sweep_order > 1 ||
+      (q.sweep_order == 1 && q.dim != 3)) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
-               "local_solver 0..3, schedule 0..1, dense_top -1..64";
+               "local_solver 0..3, schedule 0..1, dense_top -1..64, sweep_order 0..1 (1: 3D only)";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)

@@ -387,3 +387,24 @@ def test_ddm_iterate_matches_oracle(parts, prec):
         for a, b in zip(hist[1:3], hist_ref[1:3]):
             assert abs(a - b) <= 1e-3 * b
     assert hist[-1] < 1e-8 and ex < 1e-7
+
+
+@pytest.mark.parametrize("name", ["d3", "wide3"])
+def test_sweep_apply_3d_l1_order_matches_oracle(name):
+    """The other 3D sweep order of Section 4.1 (L1 distance from the first
+    direction non-decreasing): GPU sweeps (complex128) against the oracle's
+    real mode with the same order, and different from the default order."""
+    import paper_2002_05327_amd as dsw
+    n, h, om, pml, d, parts, c = _case(name)
+    k = 2
+    f = sources(n, h, pml, k)
+    m = torch.from_numpy(slowness2(c)).cuda()
+    plan = dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision="c128",
+                    max_rhs=k, sweep_order="l1")
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c), order_variant=1)
+    u_ref = ddm.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    u0 = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c)).apply(f.reshape(k, -1).T).T
+    e = rel(u, u_ref)
+    print(f"{name}: GPU l1-order sweep vs oracle {e:.2e}; default vs l1 order {rel(u0, u_ref):.2e}")
+    assert e < 1e-10 and rel(u0, u_ref) > 1e-8

@@ -53,12 +53,16 @@ def test_exact_mode_reproduces_global_solution_2d(parts, n, medium):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("parts,n", [((2, 2, 2), (12, 12, 12)), ((3, 3, 2), (12, 12, 9))])
-def test_exact_mode_reproduces_global_solution_3d(parts, n):
+def test_exact_mode_reproduces_global_solution_3d(parts, n, variant):
+    """Both 3D sweep orders of Section 4.1 ((Sorder3D) and the L1-monotone one),
+    with transfers routed by Rules 4.1/4.2 over the order in use."""
     h, om, pml, d = 1 / n[0], 2 * np.pi * 2, 3, 3
     c = 1 + 0.5 * np.random.default_rng(3).random(n[::-1])
     f = embed_physical(np.random.default_rng(1).standard_normal(n[::-1]), pml).ravel()
-    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c), mode="exact")
+    ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c), mode="exact",
+                           order_variant=variant)
     assert _rel(ddm.apply(f), global_solve(ddm.M, f)) < 1e-12
 
 
