@@ -13,7 +13,8 @@ paper by eye:
                                 (Section 2.1, eq. (eq:sigma), (eq:PML), (eq:PMLprofile))
   * :mod:`oracle.partition` -- checkerboard partition, extended subdomains,
                                 index-form cutoffs and truncations (Section 2.2)
-  * :mod:`oracle.sweep`     -- sweep orders, Rules 3.1/3.2/4.1/4.2, Algorithms 3.1/4.1
+  * :mod:`oracle.sweep`     -- sweep orders, Rules 3.1/3.2/4.1/4.2, Algorithms 3.1/4.1,
+                                and the additive DDM it re-orders (Algorithms 2.1/2.2)
   * :mod:`oracle.krylov`    -- flexible GMRES with the DDM as right preconditioner
                                 (Remark 1 of Section 4, Section 5.2)
   * :mod:`oracle.analytic`  -- free-space solutions of the Gaussian sources of the

@@ -23,7 +23,7 @@ import pytest
 from oracle.krylov import fgmres
 from oracle.partition import directions
 from oracle.pml import embed_physical, slowness2
-from oracle.sweep import (DiagonalSweepDDM, global_solve, route, step_groups, step_of,
+from oracle.sweep import (AdditiveDDM, DiagonalSweepDDM, global_solve, route, step_groups, step_of,
                           sweep_order)
 import synth
 
@@ -247,3 +247,19 @@ def test_fgmres_with_ddm_converges_to_global_solution():
     lu = spla.splu(ddm.M.tocsc())
     x1, it1, _ = fgmres(lambda v: ddm.M @ v, lu.solve, f, tol=1e-12, maxit=5)
     assert it1 == 1 and _rel(x1, lu.solve(f)) < 1e-12
+
+
+@pytest.mark.parametrize("n,parts,pml,d", [((48, 44), (3, 3), 6, 4), ((60, 52), (4, 3), 6, 4),
+                                           ((14, 13, 12), (2, 2, 2), 3, 3)])
+@pytest.mark.parametrize("med", ["const", "random"])
+def test_additive_ddm_exact_mode_reproduces_global_solution(n, parts, pml, d, med):
+    """Algorithms 2.1 / 2.2 (the additive overlapping DDM of Section 2) in exact
+    mode: the discrete counterpart of its exactness result, for any medium with
+    the index-form cutoffs."""
+    h = 1 / n[0]
+    om = 2 * np.pi * (3 if len(n) == 2 else 1.5)
+    rng = np.random.default_rng(3)
+    c = np.ones(n[::-1]) if med == "const" else 1 + 0.5 * rng.random(n[::-1])
+    f = embed_physical(np.random.default_rng(1).standard_normal(n[::-1]), pml).ravel()
+    a = AdditiveDDM(n, h, om, pml, d, parts, slowness2(c), mode="exact")
+    assert _rel(a.apply(f), global_solve(a.M, f)) < 1e-12
