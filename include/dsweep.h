@@ -65,7 +65,12 @@ typedef struct {
   int schedule;          /* 0: launch every solve as soon as the solves it depends on
                                are done (dependency levels of Algorithms 3.1 / 4.1);
                             1: the anti-diagonal steps of each sweep in order.  Both
-                               give identical results.                                  */
+                               give identical results.
+                            2: instead of the sweeps, the additive overlapping DDM they
+                               re-order (Section 2, Algorithms 2.1 / 2.2): every
+                               subdomain solves at each of the sum(N_a - 1) + 1 steps,
+                               with the transfers of all its neighbours from earlier
+                               steps; the same local solves, transfers and assembly. */
   int local_solver;      /* factorisation and solve of the block-tridiagonal subdomain
                             operators: 1: twisted block LDL^T (two Schur-complement
                                chains meeting in the middle block; least memory,

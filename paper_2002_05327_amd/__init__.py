@@ -57,7 +57,7 @@ class Plan:
         p.sigma0_delta = float(sigma0_delta)
         p.precision = {"c64": DSD_C64, "c128": DSD_C128}[precision]
         p.max_rhs, p.rhs_per_group = int(max_rhs), int(rhs_per_group)
-        p.schedule = {"dag": 0, "sequential": 1}[schedule]
+        p.schedule = {"dag": 0, "sequential": 1, "additive": 2}[schedule]
         p.local_solver = {"auto": 0, "chain": 1, "bcr": 2, "chain-steps": 3}[local_solver]
         p.dense_top = int(dense_top)
         p.sweep_order = {"default": 0, "l1": 1}[sweep_order]

@@ -1552,14 +1552,16 @@ void launch_bcr_dense_store(const BcrDenseJob* d_jobs, int njobs, int max_n,
 }
 
 // ============================================================================
-// a4: local right-hand sides.  init: r^1 = f on own cells (first sweep), 0
+// a4: local right-hand sides.  init: r = f on own cells for the members in
+// slot src_slot (the first sweep; the first step of the additive DDM), 0
 // otherwise.  pull: every receiver cell sums, in a fixed edge order, the
 // transferred sources Psi_t(v) = -M_sender(beta_t v) of the edges whose box
 // holds it; each cell is written by exactly one thread (no atomics).
 // ============================================================================
 template <typename T>
 __global__ __launch_bounds__(256) void k_init_rhs(Problem P, const SubDesc* subs, const int2* members, int nrhs, int kmax,
-                           const cpx<double>* f, cpx<T>* rpool, long long pool_stride) {
+                           const cpx<double>* f, cpx<T>* rpool, long long pool_stride,
+                           int src_slot) {
   const int2 mb = members[blockIdx.y];
   const SubDesc& S = subs[mb.x];
   const int nloc = (int)S.nloc;
@@ -1567,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_init_rhs(Problem P, const SubDesc* subs
   if (c >= nloc) return;
   cpx<T>* R = rpool + (long long)mb.y * pool_stride + S.vec_off * kmax + c;
   long long gf = -1;
-  if (mb.y == 0) {   // first sweep: f on the subdomain's own cells
+  if (mb.y == src_slot) {   // the slot that takes f on the subdomain's own cells
     const int nx = S.dims[0], ny = S.dims[1];
     const int ix = c % nx, q = c / nx;
     const int iy = q % ny, iz = q / ny;
@@ -1583,11 +1585,11 @@ __global__ __launch_bounds__(256) void k_init_rhs(Problem P, const SubDesc* subs
 template <typename T>
 void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
                      long long max_nloc, int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool,
-                     long long pool_stride, hipStream_t s) {
+                     long long pool_stride, int src_slot, hipStream_t s) {
   if (nmem <= 0 || nrhs <= 0) return;
   dim3 grid(cdiv_u(max_nloc, 256), nmem);
   hipLaunchKernelGGL(k_init_rhs<T>, grid, dim3(256), 0, s, P, d_subs, d_members, nrhs, kmax, f,
-                     rpool, pool_stride);
+                     rpool, pool_stride, src_slot);
 }
 
 template <typename T>
@@ -1739,12 +1741,15 @@ void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members,
 }
 
 // ============================================================================
-// a5: u_DDM = sum_sub beta_{0;sub} sum_l v_sub^l, FP64, pulled per global cell
-// from the (at most two per axis) subdomains whose cutoff support covers it.
+// a5: u_DDM = sum_sub beta_{0;sub} sum_l v_sub^l over the slots l in
+// [slot0, slot0 + nslots), FP64, pulled per global cell from the (at most two
+// per axis) subdomains whose cutoff support covers it; written, or added to u
+// (accumulate: the additive DDM adds every step's solutions).
 // ============================================================================
 template <typename T>
 __global__ __launch_bounds__(256) void k_assemble_u(Problem P, const SubDesc* subs, PartTables pt,
-                                                    int nsweeps, int nrhs, int kmax,
+                                                    int slot0, int nslots, int accumulate,
+                                                    int nrhs, int kmax,
                                                     const cpx<T>* __restrict__ vpool,
                                                     long long pool_stride,
                                                     cpx<double>* __restrict__ u) {
@@ -1808,20 +1813,31 @@ __global__ __launch_bounds__(256) void k_assemble_u(Problem P, const SubDesc* su
       if (wc[k] == 0.0) continue;
       const long long o = base[k] + (long long)r * nl[k];
       cpx<double> v = mk(0.0, 0.0);
-      for (int l = 0; l < nsweeps; ++l) v = v + cvt<double>(vpool[l * pool_stride + o]);
+      for (int l = slot0; l < slot0 + nslots; ++l) v = v + cvt<double>(vpool[l * pool_stride + o]);
       acc = acc + wc[k] * v;
     }
-    u[(long long)r * P.N + gflat] = acc;
+    const long long uo = (long long)r * P.N + gflat;
+    u[uo] = accumulate ? u[uo] + acc : acc;
   }
   (void)nc;
 }
 
 template <typename T>
-void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int nsweeps,
-                       int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
-                       cpx<double>* u, hipStream_t s) {
+void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int slot0,
+                       int nslots, int accumulate, int nrhs, int kmax, const cpx<T>* vpool,
+                       long long pool_stride, cpx<double>* u, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble_u<T>, dim3(cdiv_u(P.N, 256)), dim3(256), 0, s, P, d_subs, pt,
-                     nsweeps, nrhs, kmax, vpool, pool_stride, u);
+                     slot0, nslots, accumulate, nrhs, kmax, vpool, pool_stride, u);
+}
+
+template <typename T>
+__global__ void k_zero(cpx<T>* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = mk((T)0, (T)0);
+}
+template <typename T>
+void launch_zero(cpx<T>* p, long long n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_zero<T>, dim3(cdiv_u(n, 256)), dim3(256), 0, s, p, n);
 }
 
 template <typename T>
@@ -2119,14 +2135,15 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
                                 hipStream_t);                                                    \
   template size_t chain_lds_bytes<T>(int, int);                                                 \
   template void launch_init_rhs<T>(const Problem&, const SubDesc*, const int2*, int, long long, \
-                                   int, int, const cpx<double>*, cpx<T>*, long long,             \
+                                   int, int, const cpx<double>*, cpx<T>*, long long, int,        \
                                    hipStream_t);                                                 \
+  template void launch_zero<T>(cpx<T>*, long long, hipStream_t);                                \
   template void launch_pull<T>(const Problem&, const SubDesc*, const int2*, int, const Edge*,   \
                                const int2*, long long, int, int, const cpx<T>*, long long,       \
                                const cpx<T>*, const cpx<T>*, const cpx<T>*, const cpx<T>*,       \
                                cpx<T>*, hipStream_t);                                            \
   template void launch_assemble_u<T>(const Problem&, const SubDesc*, const PartTables&, int,    \
-                                     int, int, const cpx<T>*, long long, cpx<double>*,           \
+                                     int, int, int, int, const cpx<T>*, long long, cpx<double>*, \
                                      hipStream_t);                                               \
   template void launch_bcr_invert<T>(const BcrInvJob*, int, int, cpx<double>*, cpx<T>*, int*,  \
                                      int*, cpx<double>*, hipStream_t);                           \

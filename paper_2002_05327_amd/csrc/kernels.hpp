@@ -161,7 +161,7 @@ void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* wo
 template <typename T>
 void launch_init_rhs(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
                      long long max_nloc, int nrhs, int kmax, const cpx<double>* f, cpx<T>* rpool,
-                     long long pool_stride, hipStream_t s);
+                     long long pool_stride, int src_slot, hipStream_t s);
 template <typename T>
 void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members, int nmem,
                  const Edge* d_edges, const int2* d_edge_range, long long max_box_cells,
@@ -171,9 +171,12 @@ void launch_pull(const Problem& P, const SubDesc* d_subs, const int2* d_members,
 
 // ---- a5: u_DDM = sum_sub beta_0 sum_l v_sub^l (FP64, pull over global cells)
 template <typename T>
-void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int nsweeps,
-                       int nrhs, int kmax, const cpx<T>* vpool, long long pool_stride,
-                       cpx<double>* u, hipStream_t s);
+void launch_assemble_u(const Problem& P, const SubDesc* d_subs, const PartTables& pt, int slot0,
+                       int nslots, int accumulate, int nrhs, int kmax, const cpx<T>* vpool,
+                       long long pool_stride, cpx<double>* u, hipStream_t s);
+// p[0, n) = 0 (a kernel, so that graph captures hold no memset node)
+template <typename T>
+void launch_zero(cpx<T>* p, long long n, hipStream_t s);
 
 // local solve entry point helpers: complex128 <-> plan precision on one subdomain
 template <typename T>

@@ -154,6 +154,7 @@ struct dsd_plan {
   int dim = 2, L = 4, nsteps = 0, S = 0, kmax = 1, kg = 2, max_nb = 0;
   bool c64 = true;
   bool sequential = false;      // anti-diagonal steps in order instead of DAG launch groups
+  bool additive = false;        // the additive DDM (every subdomain at every step)
   std::vector<SubDesc> subs;
   std::vector<AxisPart> parts[3];
   std::vector<StepTab> steps;   // launch groups, in order
@@ -360,6 +361,12 @@ int build_bcr_jobs(dsd_plan* pl) {
 int build_schedule(dsd_plan* pl) {
   const int dim = pl->dim, L = pl->L;
   const dsd_params& q = pl->prm;
+  // additive DDM (Algorithms 2.1 / 2.2): every subdomain at every step; step s
+  // keeps its solutions in slot (s - 1) mod (dim + 1), which holds them while
+  // steps s + 1 .. s + dim read them (a neighbour at L1 distance |t| reads the
+  // solution of step s - |t|)
+  const bool additive = pl->additive;
+  const int Ls = additive ? dim + 1 : L;
   int nsteps = 1;
   for (int a = 0; a < dim; ++a) nsteps += q.parts[a] - 1;
   pl->nsteps = nsteps;
@@ -376,7 +383,7 @@ int build_schedule(dsd_plan* pl) {
         tdirs.push_back(tz);
       }
   const int ndir = (int)tdirs.size() / 3;
-  for (int l = 0; l < L; ++l)
+  for (int l = 0; l < Ls; ++l)
     for (int rid = 0; rid < pl->S; ++rid) {
       const SubDesc& R = pl->subs[rid];
       const int start = (int)edges.size();
@@ -386,8 +393,13 @@ int build_schedule(dsd_plan* pl) {
         const int sid = sub_index(pl, sp);
         if (sid < 0) continue;
         unsigned mask = 0;
-        for (int lg = 0; lg <= l; ++lg)
-          if (route(dim, q.sweep_order, lg, t) == l) mask |= 1u << lg;
+        if (additive) {
+          const int dist = std::abs(t[0]) + std::abs(t[1]) + std::abs(t[2]);
+          mask = 1u << (((l - dist) % Ls + Ls) % Ls);
+        } else {
+          for (int lg = 0; lg <= l; ++lg)
+            if (route(dim, q.sweep_order, lg, t) == l) mask |= 1u << lg;
+        }
         if (!mask) continue;
         const SubDesc& Sd = pl->subs[sid];
         Edge e{};
@@ -429,7 +441,12 @@ int build_schedule(dsd_plan* pl) {
   // schedules give identical results.
   std::vector<int> level((size_t)L * pl->S, 0);
   std::vector<std::vector<int2>> groups;
-  for (int l = 0; l < L; ++l) {
+  if (additive)
+    for (int st = 0; st < nsteps; ++st) {
+      groups.emplace_back();
+      for (int sid = 0; sid < pl->S; ++sid) groups.back().push_back(make_int2(sid, st % Ls));
+    }
+  for (int l = 0; l < (additive ? 0 : L); ++l) {
     const int* D = sweep_dir(dim, pl->prm.sweep_order, l);
     std::vector<std::vector<int>> steps(nsteps);
     for (int sid = 0; sid < pl->S; ++sid) {
@@ -1263,34 +1280,43 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
   const long long pool_stride = pl->sum_nloc * pl->kmax;
   cpx<T>* rpool = pl->d_rpool.as<cpx<T>>();
   cpx<T>* vpool = pl->d_vpool.as<cpx<T>>();
-  for (const StepTab& st_ : pl->steps) {
-    if (st_.nmem == 0) continue;
-    const int2* mem = pl->d_members.as<int2>() + st_.mem_off;
-    launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, nrhs, pl->kmax,
-                       f, rpool, pool_stride, st);
-    launch_pull<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, pl->d_edges.as<Edge>(),
-                   pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
-                   pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
-                   pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
-    if (pl->solver == 2 || pl->chain_steps) {
-      for (const BcrLaunch& L : pl->bcr_launch[&st_ - pl->steps.data()])
-        bcr_phase<T>(pl, pl->d_bcr_jobs.as<BcrJob>(), L, nrhs);
-      continue;
-    }
-    const int4* j2 = pl->d_jobs2.as<int4>() + st_.job_off;
-    const int4* j1 = pl->d_jobs1.as<int4>() + st_.mem_off;
-    chain_phase<T>(pl, 0, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
-    chain_phase<T>(pl, 1, j1, st_.nmem, nrhs, st_.fac_bytes_mid, st_.blk_cells_mid);
-    chain_phase<T>(pl, 2, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
-  }
   PartTables pt;
   for (int a = 0; a < 3; ++a) {
     pt.part_of[a] = pl->d_part_of[a].as<int>();
     pt.parts[a] = pl->d_axparts[a].as<AxisPart>();
     pt.P[a] = (int)pl->parts[a].size();
   }
-  launch_assemble_u<T>(P, pl->d_subs.as<SubDesc>(), pt, pl->L, nrhs, pl->kmax, vpool, pool_stride,
-                       u, st);
+  // additive DDM: the solution slots of steps before the first start at zero
+  // (their transfers are read before any step has written them)
+  const int Ls = pl->additive ? pl->dim + 1 : pl->L;
+  if (pl->additive) launch_zero<T>(vpool, (long long)Ls * pool_stride, st);
+  for (size_t gi = 0; gi < pl->steps.size(); ++gi) {
+    const StepTab& st_ = pl->steps[gi];
+    if (st_.nmem == 0) continue;
+    const int2* mem = pl->d_members.as<int2>() + st_.mem_off;
+    const int src_slot = pl->additive ? (gi == 0 ? 0 : -1) : 0;
+    launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, nrhs, pl->kmax,
+                       f, rpool, pool_stride, src_slot, st);
+    launch_pull<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, pl->d_edges.as<Edge>(),
+                   pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
+                   pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
+                   pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
+    if (pl->solver == 2 || pl->chain_steps) {
+      for (const BcrLaunch& L : pl->bcr_launch[gi]) bcr_phase<T>(pl, pl->d_bcr_jobs.as<BcrJob>(), L, nrhs);
+    } else {
+      const int4* j2 = pl->d_jobs2.as<int4>() + st_.job_off;
+      const int4* j1 = pl->d_jobs1.as<int4>() + st_.mem_off;
+      chain_phase<T>(pl, 0, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
+      chain_phase<T>(pl, 1, j1, st_.nmem, nrhs, st_.fac_bytes_mid, st_.blk_cells_mid);
+      chain_phase<T>(pl, 2, j2, 2 * st_.nmem, nrhs, st_.fac_bytes_fb, st_.blk_cells_fb);
+    }
+    if (pl->additive)   // u_DDM += sum_sub beta_0 u^s (step gi's slot)
+      launch_assemble_u<T>(P, pl->d_subs.as<SubDesc>(), pt, (int)(gi % Ls), 1, gi > 0 ? 1 : 0,
+                           nrhs, pl->kmax, vpool, pool_stride, u, st);
+  }
+  if (!pl->additive)
+    launch_assemble_u<T>(P, pl->d_subs.as<SubDesc>(), pt, 0, pl->L, 0, nrhs, pl->kmax, vpool,
+                         pool_stride, u, st);
   HIPCHK(hipGetLastError());
   time_flush(pl);
   return 0;
@@ -1678,11 +1704,11 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   const dsd_params& q = *params;
   if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
       (q.precision != DSD_C64 && q.precision != DSD_C128) || q.local_solver < 0 ||
-      q.local_solver > 3 || q.schedule < 0 || q.schedule > 1 || q.dense_top < -1 ||
+      q.local_solver > 3 || q.schedule < 0 || q.schedule > 2 || q.dense_top < -1 ||
       q.dense_top > 64 || q.sweep_order < 0 || q.sweep_order > 1 ||
       (q.sweep_order == 1 && q.dim != 3)) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
-               "local_solver 0..3, schedule 0..1, dense_top -1..64, sweep_order 0..1 (1: 3D only)";
+               "local_solver 0..3, schedule 0..2, dense_top -1..64, sweep_order 0..1 (1: 3D only)";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)
@@ -1700,6 +1726,7 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   pl->stream = (hipStream_t)stream;
   int rc = build_partition(pl);
   pl->sequential = q.schedule == 1;
+  pl->additive = q.schedule == 2;
   if (rc == 0) {
     // local solver: block cyclic reduction unless its factor (about three
     // times the chain factor) would take more than 45% of the device memory

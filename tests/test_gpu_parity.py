@@ -408,3 +408,24 @@ def test_sweep_apply_3d_l1_order_matches_oracle(name):
     e = rel(u, u_ref)
     print(f"{name}: GPU l1-order sweep vs oracle {e:.2e}; default vs l1 order {rel(u0, u_ref):.2e}")
     assert e < 1e-10 and rel(u0, u_ref) > 1e-8
+
+
+@pytest.mark.parametrize("solver", ["bcr", "chain"])
+@pytest.mark.parametrize("name", ["lay33", "rag34", "d3"])
+def test_additive_ddm_matches_oracle(name, solver):
+    """schedule="additive" (Algorithms 2.1 / 2.2 of Section 2 on the same
+    kernels) against the oracle's additive DDM in real mode (complex128), and
+    FGMRES with it as the preconditioner converges to the global solution."""
+    from oracle.sweep import AdditiveDDM
+    n, h, om, pml, d, parts, c = _case(name)
+    k = 2
+    f = sources(n, h, pml, k)
+    plan = _plan(n, h, om, pml, d, parts, c, "c128", k, schedule="additive", solver=solver)
+    add = AdditiveDDM(n, h, om, pml, d, parts, slowness2(c))
+    u_ref = add.apply(f.reshape(k, -1).T).T
+    u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
+    e = rel(u, u_ref)
+    x, iters, relres, ok = plan.gmres(_cuda(f), tol=1e-10, maxit=60)
+    ex = rel(x.cpu().numpy().reshape(k, -1), global_solve(add.M, f.reshape(k, -1).T).T)
+    print(f"{name} {solver}: additive DDM vs oracle {e:.2e}; FGMRES {iters} its, vs global {ex:.2e}")
+    assert e < 1e-10 and ok and ex < 1e-8
