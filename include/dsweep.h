@@ -178,8 +178,10 @@ int dsd_local_solve(dsd_plan* plan, int sub, const double* r_dev, double* u_dev,
  * (schedule 1), as soon as its sources exist; the source-transfer operator Psi passes the
  * cutoff-weighted sources to the neighbours (Section 2.2) routed by Rules
  * 3.1/3.2 (4.1/4.2), and u_DDM = sum beta_{0;ij} u_ij (eq. (eq:sumdiag2D),
- * (eq:sumdiag3D)) is accumulated in FP64.
- *   f_dev, u_dev : [nrhs][N_g] complex128; nrhs <= max_rhs.
+ * (eq:sumdiag3D)) is accumulated in FP64.  With schedule 2 the same operators
+ * run the additive DDM of Section 2 instead (every subdomain at every step).
+ *   f_dev, u_dev : [nrhs][N_g] complex128; nrhs in 1..max_rhs (else DSD_EINVAL).
+ *                  They may alias: f is read before u is first written.
  */
 int dsd_sweep_apply(dsd_plan* plan, const double* f_dev, double* u_dev, int nrhs, void* stream);
 

@@ -3,6 +3,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -38,3 +40,46 @@ def test_oracle_is_not_imported_by_the_product():
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", txt, re.M), fn
                 assert "oracle/" not in txt, fn
+
+
+def _params(**kw):
+    from paper_2002_05327_amd import _lib
+    p = _lib.Params()
+    p.dim, p.h, p.pml, p.overlap, p.sigma0_delta = 2, 1 / 64, 8, 4, 60.0
+    p.n[0], p.n[1], p.n[2] = 64, 64, 1
+    p.parts[0], p.parts[1], p.parts[2] = 2, 2, 1
+    p.precision, p.max_rhs = 2, 1
+    for k, v in kw.items():
+        if k in ("n", "parts"):
+            for a, x in enumerate(v):
+                getattr(p, k)[a] = x
+        else:
+            setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("bad", [dict(dim=4), dict(overlap=2), dict(pml=-1), dict(h=0.0),
+                                 dict(precision=7), dict(local_solver=5), dict(schedule=3),
+                                 dict(dense_top=-2), dict(sweep_order=1),
+                                 dict(parts=(65, 2, 1)), dict(n=(0, 64, 1)), "omega"])
+def test_plan_create_rejects_bad_parameters_without_gpu(bad):
+    """Parameter validation answers DSD_EINVAL with a message before any device
+    work (so it runs without a GPU); the medium pointer is never read."""
+    from paper_2002_05327_amd import _lib
+    lib = _lib.load()
+    p = _params() if bad == "omega" else _params(**bad)
+    omega = 0.0 if bad == "omega" else 2 * 3.141592653589793 * 4
+    h = ctypes.c_void_p()
+    rc = lib.dsd_plan_create(ctypes.byref(p), omega, ctypes.c_void_p(16), None, ctypes.byref(h))
+    assert rc == -1 and not h.value
+    assert lib.dsd_last_error_detail().decode()
+
+
+def test_entry_points_reject_a_null_plan_without_gpu():
+    from paper_2002_05327_amd import _lib
+    lib = _lib.load()
+    one = ctypes.c_void_p(16)
+    assert lib.dsd_sweep_apply(None, one, one, 1, None) == -1
+    assert lib.dsd_apply_operator(None, one, one, 1, None) == -1
+    assert lib.dsd_ddm_iterate(None, one, one, 1, 1, (ctypes.c_double * 2)(), None) == -1
+    assert lib.dsd_timing_flops(None, (ctypes.c_double * 1)()) == -1
