@@ -968,10 +968,11 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZGemmJob* jobs, cpx<double>
   const cpx<double>* __restrict__ A = W + J.a;
   const cpx<double>* __restrict__ B = W + J.b;
   cpx<double>* C = W + J.c;
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  cpx<double> acc[2][2];
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c) acc[r][c] = mk(0.0, 0.0);
+  // FP64 matrix cores: wave w owns the 16 x 16 block at (16 (w % 2), 16 (w / 2))
+  // of the 32 x 32 tile (lane layout as in the Gauss-Jordan update)
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int sr = (w & 1) * 16, sc = (w >> 1) * 16, l16 = lane & 15, l4 = lane >> 4;
+  gj_f64x4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < nb; k0 += 16) {
     for (int e = tid; e < 512; e += 256) {
       int mm, kk;
@@ -988,26 +989,26 @@ __global__ __launch_bounds__(256) void k_zgemm(const ZGemmJob* jobs, cpx<double>
       Bs[kk][nn] = u;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      const cpx<double> a0 = As[kk][2 * tx], a1 = As[kk][2 * tx + 1];
-      const cpx<double> b0 = Bs[kk][2 * ty], b1 = Bs[kk][2 * ty + 1];
-      acc[0][0] = acc[0][0] + a0 * b0;
-      acc[1][0] = acc[1][0] + a1 * b0;
-      acc[0][1] = acc[0][1] + a0 * b1;
-      acc[1][1] = acc[1][1] + a1 * b1;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const cpx<double> av = As[kk + l4][sr + l16];
+      const cpx<double> bv = Bs[kk + l4][sc + l16];
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.re, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.re, bv.im, ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.im, bv.im, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(av.im, bv.re, ci, 0, 0, 0);
     }
     __syncthreads();
   }
-  for (int r = 0; r < 2; ++r)
-    for (int c = 0; c < 2; ++c) {
-      const int m = tm + 2 * tx + r, n = tn + 2 * ty + c;
-      if (m < nb && n < nb) {
-        const long long o = (long long)n * nb + m;
-        const cpx<double> v = mk(J.alpha * acc[r][c].re, J.alpha * acc[r][c].im);
-        C[o] = J.beta ? C[o] + v : v;
-      }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int m = tm + sr + 4 * j + l4, n = tn + sc + l16;
+    if (m < nb && n < nb) {
+      const long long o = (long long)n * nb + m;
+      const cpx<double> v = mk(J.alpha * cr[j], J.alpha * ci[j]);
+      C[o] = J.beta ? C[o] + v : v;
     }
+  }
 }
 
 void launch_zgemm(const ZGemmJob* d_jobs, int njobs, int max_nb, cpx<double>* work, hipStream_t s) {
