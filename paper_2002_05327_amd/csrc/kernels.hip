@@ -162,142 +162,149 @@ typedef double gj_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GJ_B = 32;              // panel width
 constexpr int GJ_TI = 64, GJ_TC = 64; // product tile: rows x columns
 
-__device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv, cpx<double>* R,
-                          unsigned char* smem, const int max_n) {
-  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem);
-  cpx<double>* rowj = tcol + max_n;
-  cpx<double>* Pt = rowj + max_n;           // [GJ_B][GJ_TI]
-  cpx<double>* Rt = Pt + GJ_B * GJ_TI;      // [GJ_TC][GJ_B + 1]
+// One panel [j0, j1) of the elimination: its columns one by one (pivot search
+// over rows >= j, whole-row interchange, rank-1 update of the panel columns),
+// then, unless the panel is the whole matrix, R = the panel's pivot rows.
+// 1024 threads; returns nonzero (in thread 0) for a zero pivot.
+__device__ __forceinline__ int gj_panel(cpx<double>* a, const int n, const int j0, int* piv,
+                                        cpx<double>* R, cpx<double>* tcol, cpx<double>* rowj) {
   __shared__ double red_v[16];
   __shared__ int red_i[16];
   __shared__ int s_p;
   const int tid = threadIdx.x, bs = blockDim.x;
   const int lane = tid & 63, wid = tid >> 6, nw = bs >> 6;
+  const int j1 = min(n, j0 + GJ_B), bw = j1 - j0;
   int bad = 0;
-  for (int j0 = 0; j0 < n; j0 += GJ_B) {
-    const int j1 = min(n, j0 + GJ_B), bw = j1 - j0;
-    for (int j = j0; j < j1; ++j) {
-      // pivot: largest |a_ij| for i >= j (ties: smallest i)
-      double bv = -1.0;
-      int bi = n;
-      for (int i = j + tid; i < n; i += bs) {
-        const double v = abs2(a[(long long)j * n + i]);
-        if (v > bv) { bv = v; bi = i; }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_down(bv, o, 64);
-        const int oi = __shfl_down(bi, o, 64);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
-      if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
-      __syncthreads();
-      if (tid == 0) {
-        double v = red_v[0];
-        int p = red_i[0];
-        for (int w = 1; w < nw; ++w)
-          if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
-        if (!(v > 0.0)) { bad = 1; p = j; }
-        s_p = p;
-        piv[j] = p;
-      }
-      __syncthreads();
-      const int p = s_p;
-      if (p != j) {
-        for (int c = tid; c < n; c += bs) {
-          const cpx<double> t0 = a[(long long)c * n + j];
-          a[(long long)c * n + j] = a[(long long)c * n + p];
-          a[(long long)c * n + p] = t0;
-        }
-      }
-      __syncthreads();
-      for (int i = tid; i < n; i += bs) tcol[i] = a[(long long)j * n + i];
-      __syncthreads();
-      const cpx<double> pv = tcol[j];
-      const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
-      for (int c = j0 + tid; c < j1; c += bs)
-        rowj[c] = (c == j) ? pinv : a[(long long)c * n + j] * pinv;
-      __syncthreads();
-      // rank-1 update of the panel columns, one column per wave
-      for (int c = j0 + wid; c < j1; c += nw) {
-        cpx<double>* col = a + (long long)c * n;
-        const cpx<double> rj = rowj[c];
-        for (int i0 = lane; i0 < n; i0 += 256) {
-          cpx<double> v[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + 64 * u;
-            v[u] = i < n ? col[i] : mk(0.0, 0.0);
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + 64 * u;
-            if (i < n) {
-              if (i == j) col[i] = rj;
-              else if (c == j) col[i] = -(tcol[i] * pinv);
-              else col[i] = v[u] - tcol[i] * rj;
-            }
-          }
-        }
-      }
-      __syncthreads();
+  for (int j = j0; j < j1; ++j) {
+    // pivot: largest |a_ij| for i >= j (ties: smallest i)
+    double bv = -1.0;
+    int bi = n;
+    for (int i = j + tid; i < n; i += bs) {
+      const double v = abs2(a[(long long)j * n + i]);
+      if (v > bv) { bv = v; bi = i; }
     }
-    if (j1 >= n && j0 == 0) continue;   // a single panel covers the matrix
-    // R[c][k] = pivot row j0 + k at column c (all columns; panel ones unused)
-    for (long long e = tid; e < (long long)bw * n; e += bs) {
-      const int c = (int)(e / bw), k = (int)(e - (long long)c * bw);
-      R[(long long)c * GJ_B + k] = a[(long long)c * n + j0 + k];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_down(bv, o, 64);
+      const int oi = __shfl_down(bi, o, 64);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wid] = bv; red_i[wid] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double v = red_v[0];
+      int p = red_i[0];
+      for (int w = 1; w < nw; ++w)
+        if (red_v[w] > v || (red_v[w] == v && red_i[w] < p)) { v = red_v[w]; p = red_i[w]; }
+      if (!(v > 0.0)) { bad = 1; p = j; }
+      s_p = p;
+      piv[j] = p;
     }
     __syncthreads();
-    // every column outside the panel: A = [not pivot row] A + P R, on the FP64
-    // matrix cores.  Wave w owns the 16 x 16 block at rows 16 (w % 4), columns
-    // 16 (w / 4) of the 64 x 64 tile; v_mfma_f64_16x16x4f64 takes A as lane l =
-    // (row l % 16, k l / 16), B as (k l / 16, column l % 16), and returns lane l,
-    // item j = (row 4 j + l / 16, column l % 16).  A complex product is four
-    // real ones: Re += Re P Re R - Im P Im R, Im += Re P Im R + Im P Re R.
-    const int nti = (n + GJ_TI - 1) / GJ_TI, ntc = (n + GJ_TC - 1) / GJ_TC;
-    const int sr = (wid & 3) * 16, sc = (wid >> 2) * 16;
-    const int l16 = lane & 15, l4 = lane >> 4;
-    for (int tile = 0; tile < nti * ntc; ++tile) {
-      const int i0 = (tile % nti) * GJ_TI, c0 = (tile / nti) * GJ_TC;
-      if (c0 >= j0 && c0 + GJ_TC <= j1) continue;       // tile inside the panel (uniform)
-      for (int e = tid; e < GJ_B * GJ_TI; e += bs) {
-        const int k = e / GJ_TI, rr = e - k * GJ_TI;
-        Pt[e] = (k < bw && i0 + rr < n) ? a[(long long)(j0 + k) * n + i0 + rr] : mk(0.0, 0.0);
+    const int p = s_p;
+    if (p != j) {
+      for (int c = tid; c < n; c += bs) {
+        const cpx<double> t0 = a[(long long)c * n + j];
+        a[(long long)c * n + j] = a[(long long)c * n + p];
+        a[(long long)c * n + p] = t0;
       }
-      for (int e = tid; e < GJ_B * GJ_TC; e += bs) {
-        const int cc = e / GJ_B, k = e - cc * GJ_B;
-        Rt[cc * (GJ_B + 1) + k] = (k < bw && c0 + cc < n) ? R[(long long)(c0 + cc) * GJ_B + k] : mk(0.0, 0.0);
-      }
-      __syncthreads();
-      const int c = c0 + sc + l16;                       // this lane's output column
-      const bool ccol = c < n && (c < j0 || c >= j1);
-      const int ib = i0 + sr + l4;                       // this lane's rows: ib + 4 j
-      gj_f64x4 cr, ci;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int i = ib + 4 * j;
-        const bool ld = ccol && i < n && (i < j0 || i >= j1);
-        const cpx<double> v = ld ? a[(long long)c * n + i] : mk(0.0, 0.0);
-        cr[j] = v.re;
-        ci[j] = v.im;
-      }
-      for (int kk = 0; kk < bw; kk += 4) {
-        const cpx<double> pa = Pt[(kk + l4) * GJ_TI + sr + l16];
-        const cpx<double> rb = Rt[(sc + l16) * (GJ_B + 1) + kk + l4];
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.re, rb.re, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.re, rb.im, ci, 0, 0, 0);
-        cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa.im, rb.im, cr, 0, 0, 0);
-        ci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.im, rb.re, ci, 0, 0, 0);
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int i = ib + 4 * j;
-        if (ccol && i < n) a[(long long)c * n + i] = mk(cr[j], ci[j]);
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    for (int i = tid; i < n; i += bs) tcol[i] = a[(long long)j * n + i];
+    __syncthreads();
+    const cpx<double> pv = tcol[j];
+    const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+    for (int c = j0 + tid; c < j1; c += bs)
+      rowj[c] = (c == j) ? pinv : a[(long long)c * n + j] * pinv;
+    __syncthreads();
+    // rank-1 update of the panel columns, one column per wave
+    for (int c = j0 + wid; c < j1; c += nw) {
+      cpx<double>* col = a + (long long)c * n;
+      const cpx<double> rj = rowj[c];
+      for (int i0 = lane; i0 < n; i0 += 256) {
+        cpx<double> v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          v[u] = i < n ? col[i] : mk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + 64 * u;
+          if (i < n) {
+            if (i == j) col[i] = rj;
+            else if (c == j) col[i] = -(tcol[i] * pinv);
+            else col[i] = v[u] - tcol[i] * rj;
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
-  // undo the row interchanges as column interchanges, in reverse order
+  if (j1 >= n && j0 == 0) return bad;   // a single panel covers the matrix
+  // R[c][k] = pivot row j0 + k at column c (all columns; panel ones unused)
+  for (long long e = tid; e < (long long)bw * n; e += bs) {
+    const int c = (int)(e / bw), k = (int)(e - (long long)c * bw);
+    R[(long long)c * GJ_B + k] = a[(long long)c * n + j0 + k];
+  }
+  __syncthreads();
+  return bad;
+}
+
+// One 64 x 64 tile (rows i0.., columns c0..) of the update of every column
+// outside the panel, A = [not pivot row] A + P R, on the FP64 matrix cores
+// (1024 threads).  Wave w owns the 16 x 16 block at rows 16 (w % 4), columns
+// 16 (w / 4) of the tile; v_mfma_f64_16x16x4f64 takes A as lane l =
+// (row l % 16, k l / 16), B as (k l / 16, column l % 16), and returns lane l,
+// item j = (row 4 j + l / 16, column l % 16).  A complex product is four real
+// ones: Re += Re P Re R - Im P Im R, Im += Re P Im R + Im P Re R.
+__device__ __forceinline__ void gj_tile(cpx<double>* a, const int n, const int j0, const int j1,
+                                        const cpx<double>* R, cpx<double>* Pt, cpx<double>* Rt,
+                                        const int i0, const int c0) {
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int bw = j1 - j0;
+  const int sr = (wid & 3) * 16, sc = (wid >> 2) * 16;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  for (int e = tid; e < GJ_B * GJ_TI; e += bs) {
+    const int k = e / GJ_TI, rr = e - k * GJ_TI;
+    Pt[e] = (k < bw && i0 + rr < n) ? a[(long long)(j0 + k) * n + i0 + rr] : mk(0.0, 0.0);
+  }
+  for (int e = tid; e < GJ_B * GJ_TC; e += bs) {
+    const int cc = e / GJ_B, k = e - cc * GJ_B;
+    Rt[cc * (GJ_B + 1) + k] = (k < bw && c0 + cc < n) ? R[(long long)(c0 + cc) * GJ_B + k] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int c = c0 + sc + l16;                       // this lane's output column
+  const bool ccol = c < n && (c < j0 || c >= j1);
+  const int ib = i0 + sr + l4;                       // this lane's rows: ib + 4 j
+  gj_f64x4 cr, ci;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = ib + 4 * j;
+    const bool ld = ccol && i < n && (i < j0 || i >= j1);
+    const cpx<double> v = ld ? a[(long long)c * n + i] : mk(0.0, 0.0);
+    cr[j] = v.re;
+    ci[j] = v.im;
+  }
+  for (int kk = 0; kk < bw; kk += 4) {
+    const cpx<double> pa = Pt[(kk + l4) * GJ_TI + sr + l16];
+    const cpx<double> rb = Rt[(sc + l16) * (GJ_B + 1) + kk + l4];
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.re, rb.re, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.re, rb.im, ci, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa.im, rb.im, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.im, rb.re, ci, 0, 0, 0);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int i = ib + 4 * j;
+    if (ccol && i < n) a[(long long)c * n + i] = mk(cr[j], ci[j]);
+  }
+  __syncthreads();
+}
+
+// The row interchanges undone as column interchanges, in reverse order.
+__device__ __forceinline__ void gj_unpermute(cpx<double>* a, const int n, const int* piv) {
+  const int tid = threadIdx.x, bs = blockDim.x;
   for (int j = n - 1; j >= 0; --j) {
     const int p = piv[j];
     if (p != j) {
@@ -309,11 +316,118 @@ __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv,
     }
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv, cpx<double>* R,
+                                          unsigned char* smem, const int max_n) {
+  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem);
+  cpx<double>* rowj = tcol + max_n;
+  cpx<double>* Pt = rowj + max_n;           // [GJ_B][GJ_TI]
+  cpx<double>* Rt = Pt + GJ_B * GJ_TI;      // [GJ_TC][GJ_B + 1]
+  int bad = 0;
+  for (int j0 = 0; j0 < n; j0 += GJ_B) {
+    const int j1 = min(n, j0 + GJ_B);
+    bad |= gj_panel(a, n, j0, piv, R, tcol, rowj);
+    if (j1 >= n && j0 == 0) continue;
+    const int nti = (n + GJ_TI - 1) / GJ_TI, ntc = (n + GJ_TC - 1) / GJ_TC;
+    for (int tile = 0; tile < nti * ntc; ++tile) {
+      const int i0 = (tile % nti) * GJ_TI, c0 = (tile / nti) * GJ_TC;
+      if (c0 >= j0 && c0 + GJ_TC <= j1) continue;       // tile inside the panel (uniform)
+      gj_tile(a, n, j0, j1, R, Pt, Rt, i0, c0);
+    }
+  }
+  gj_unpermute(a, n, piv);
   return bad;
 }
 
 size_t gj_lds_bytes(int max_n) {
   return ((size_t)2 * max_n + (size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
+}
+
+// Split form for launches with few large matrices (the fused kernel would leave
+// most compute units idle): per panel, one launch eliminates the panel of every
+// matrix (one workgroup each) and one launch updates all tiles of all matrices
+// (one workgroup per tile); a last launch undoes the interchanges and writes the
+// inverse.  Every element goes through the same operations in the same order as
+// in the fused kernel, so both forms give identical results.
+struct GjView {
+  cpx<double>* a;
+  long long out;   // factor offset of the rounded inverse (-1: none)
+  int n;
+  int errval;      // written to err[job] for a zero pivot
+};
+__device__ inline GjView gj_view(const BcrInvJob* jobs, const SubDesc*, cpx<double>* base, int i) {
+  const BcrInvJob J = jobs[i];
+  return GjView{base + J.src, J.dst, J.nb, 1};
+}
+__device__ inline GjView gj_view(const FactorJob* jobs, const SubDesc* subs, cpx<double>* base,
+                                 int i) {
+  const FactorJob J = jobs[i];
+  const SubDesc& S = subs[J.sub];
+  return GjView{base + J.cur, S.fac_off + (long long)J.k * S.nb * S.nb, S.nb, J.sub + 1};
+}
+
+template <typename JOB>
+__global__ __launch_bounds__(1024) void k_gj_panel(const JOB* jobs, const SubDesc* subs,
+                                                   cpx<double>* base, int* pivbuf,
+                                                   cpx<double>* rbuf, int* err, int j0, int max_n) {
+  const GjView V = gj_view(jobs, subs, base, blockIdx.x);
+  if (j0 >= V.n) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem_raw);
+  const int bad = gj_panel(V.a, V.n, j0, pivbuf + (long long)blockIdx.x * max_n,
+                           rbuf + (long long)blockIdx.x * GJ_B * max_n, tcol, tcol + max_n);
+  if (threadIdx.x == 0 && bad) err[blockIdx.x] = V.errval;
+}
+
+template <typename JOB>
+__global__ __launch_bounds__(1024) void k_gj_update(const JOB* jobs, const SubDesc* subs,
+                                                    cpx<double>* base, const cpx<double>* rbuf,
+                                                    int j0, int max_n) {
+  const GjView V = gj_view(jobs, subs, base, blockIdx.y);
+  const int n = V.n, j1 = min(n, j0 + GJ_B);
+  if (j0 >= n || (j1 >= n && j0 == 0)) return;
+  const int nti = (n + GJ_TI - 1) / GJ_TI, ntc = (n + GJ_TC - 1) / GJ_TC;
+  const int tile = blockIdx.x;
+  if (tile >= nti * ntc) return;
+  const int i0 = (tile % nti) * GJ_TI, c0 = (tile / nti) * GJ_TC;
+  if (c0 >= j0 && c0 + GJ_TC <= j1) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<double>* Pt = reinterpret_cast<cpx<double>*>(smem_raw);
+  gj_tile(V.a, n, j0, j1, rbuf + (long long)blockIdx.y * GJ_B * max_n, Pt, Pt + GJ_B * GJ_TI, i0, c0);
+}
+
+template <typename T, typename JOB>
+__global__ __launch_bounds__(1024) void k_gj_finish(const JOB* jobs, const SubDesc* subs,
+                                                    cpx<double>* base, const int* pivbuf,
+                                                    cpx<T>* fac, int max_n) {
+  const GjView V = gj_view(jobs, subs, base, blockIdx.x);
+  gj_unpermute(V.a, V.n, pivbuf + (long long)blockIdx.x * max_n);
+  if (V.out >= 0) {
+    const long long ne = (long long)V.n * V.n;
+    for (long long e = threadIdx.x; e < ne; e += blockDim.x) fac[V.out + e] = cvt<T>(V.a[e]);
+  }
+}
+
+// The split form pays when the launch has fewer matrices than compute units
+// and each matrix has many tiles.
+static inline bool gj_use_split(int njobs, int max_n) { return njobs < 256 && max_n > 256; }
+
+template <typename T, typename JOB>
+static void launch_gj_split(const JOB* d_jobs, const SubDesc* d_subs, int njobs, int max_n,
+                            cpx<double>* base, cpx<T>* fac, int* d_err, int* d_piv,
+                            cpx<double>* d_rbuf, hipStream_t s) {
+  const int nt = (max_n + GJ_TI - 1) / GJ_TI;
+  const size_t lds_panel = (size_t)2 * max_n * sizeof(cpx<double>);
+  const size_t lds_tile = ((size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
+  for (int j0 = 0; j0 < max_n; j0 += GJ_B) {
+    hipLaunchKernelGGL(k_gj_panel<JOB>, dim3(njobs), dim3(1024), lds_panel, s, d_jobs, d_subs, base,
+                       d_piv, d_rbuf, d_err, j0, max_n);
+    hipLaunchKernelGGL(k_gj_update<JOB>, dim3(nt * nt, njobs), dim3(1024), lds_tile, s, d_jobs,
+                       d_subs, base, d_rbuf, j0, max_n);
+  }
+  hipLaunchKernelGGL((k_gj_finish<T, JOB>), dim3(njobs), dim3(1024), 0, s, d_jobs, d_subs, base,
+                     d_piv, fac, max_n);
 }
 
 // Inversion of the Schur block at scratch[cur] (one workgroup per job); the
@@ -342,6 +456,10 @@ void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, in
                    cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf,
                    hipStream_t s) {
   if (njobs <= 0) return;
+  if (gj_use_split(njobs, max_nb)) {
+    launch_gj_split<T, FactorJob>(d_jobs, d_subs, njobs, max_nb, scratch, fac, d_err, d_piv, d_rbuf, s);
+    return;
+  }
   hipLaunchKernelGGL(k_invert<T>, dim3(njobs), dim3(1024), gj_lds_bytes(max_nb), s, d_subs, d_jobs,
                      scratch, fac, d_err, d_piv, d_rbuf, max_nb);
 }
@@ -898,6 +1016,10 @@ template <typename T>
 void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
                        cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, hipStream_t s) {
   if (njobs <= 0) return;
+  if (gj_use_split(njobs, max_nb)) {
+    launch_gj_split<T, BcrInvJob>(d_jobs, nullptr, njobs, max_nb, work, fac, d_err, d_piv, d_rbuf, s);
+    return;
+  }
   hipLaunchKernelGGL(k_bcr_invert<T>, dim3(njobs), dim3(1024), gj_lds_bytes(max_nb), s, d_jobs,
                      work, fac, d_err, d_piv, d_rbuf, max_nb);
 }
