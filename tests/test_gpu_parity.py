@@ -410,7 +410,7 @@ def test_sweep_apply_3d_l1_order_matches_oracle(name):
     assert e < 1e-10 and rel(u0, u_ref) > 1e-8
 
 
-@pytest.mark.parametrize("solver", ["bcr", "chain"])
+@pytest.mark.parametrize("solver", SOLVERS)
 @pytest.mark.parametrize("name", ["lay33", "rag34", "d3"])
 def test_additive_ddm_matches_oracle(name, solver):
     """schedule="additive" (Algorithms 2.1 / 2.2 of Section 2 on the same
