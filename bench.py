@@ -175,7 +175,20 @@ def _cpu_baseline(w, c, F):
     return {"value": round(1.0 / dt, 5), "unit": "RHS/s", "cores": 1, "kind": "oracle",
             "sample": f"1 of the {w.nrhs} RHS, FGMRES to 1e-6 ({its} iterations, relres "
                       f"{hist[-1]:.1e}) in {dt:.1f} s; local factorisations excluded; "
-                      f"SuperLU, scipy.sparse and BLAS on one thread"}
+                      f"SuperLU, scipy.sparse and BLAS on one thread",
+            "host_cpu": _host_cpu(), "host_logical_cpus": os.cpu_count()}
+
+
+def _host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo; empty if unavailable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def _oracle_error(w, c, F, sols):
