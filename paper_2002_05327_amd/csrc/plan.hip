@@ -1289,14 +1289,27 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
   // additive DDM: the solution slots of steps before the first start at zero
   // (their transfers are read before any step has written them)
   const int Ls = pl->additive ? pl->dim + 1 : pl->L;
-  if (pl->additive) launch_zero<T>(vpool, (long long)Ls * pool_stride, st);
+  if (pl->additive) {
+    launch_zero<T>(vpool, (long long)Ls * pool_stride, st);
+  } else {
+    // every (sweep, subdomain) solve has a right-hand-side slot of its own, so
+    // all of them are initialised up front in one launch (f in the first
+    // sweep's slots, 0 elsewhere) and each launch group only adds its transfers
+    long long nmem = 0, max_nloc = 0;
+    for (const StepTab& t : pl->steps) {
+      nmem += t.nmem;
+      max_nloc = std::max(max_nloc, t.max_nloc);
+    }
+    launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), pl->d_members.as<int2>(), (int)nmem, max_nloc,
+                       nrhs, pl->kmax, f, rpool, pool_stride, 0, st);
+  }
   for (size_t gi = 0; gi < pl->steps.size(); ++gi) {
     const StepTab& st_ = pl->steps[gi];
     if (st_.nmem == 0) continue;
     const int2* mem = pl->d_members.as<int2>() + st_.mem_off;
-    const int src_slot = pl->additive ? (gi == 0 ? 0 : -1) : 0;
-    launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, nrhs, pl->kmax,
-                       f, rpool, pool_stride, src_slot, st);
+    if (pl->additive)   // the slots rotate: each step starts from f (step 1) or 0
+      launch_init_rhs<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, st_.max_nloc, nrhs, pl->kmax,
+                         f, rpool, pool_stride, gi == 0 ? 0 : -1, st);
     launch_pull<T>(P, pl->d_subs.as<SubDesc>(), mem, st_.nmem, pl->d_edges.as<Edge>(),
                    pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
                    pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
