@@ -123,14 +123,40 @@ def _measured_traffic(workload):
         return None
 
 
-def _roofline(plan, b, workload, matrix_peak=None):
-    """Average duration, algorithmic bytes and flops of the subdomain-solve
-    launches over one preconditioner application, timed with HIP events on the
-    plan's stream.  The binding roof is the one whose ideal time is longer: HBM
-    for few right-hand sides (C2: 16), the FP32 matrix cores when the
-    right-hand-side count passes the ridge (C3, C4r); the other is reported
-    beside it.  With matrix_peak (the complex128 path, vector FP64 FMAs) the
-    compute roof is that ALU peak instead."""
+def band_work(plan, w, nrhs, tsize):
+    """The algorithmic work of one preconditioner application's local solves, as
+    the band solve counts it: every one of the 2^dim * N_sub solves streams its
+    band LU factor once for the whole RHS block -- N_loc (2b + 1) complex entries,
+    b the band half-width (the shorter local dimension in 2D, the product of the
+    two shorter ones in 3D) -- and moves 4 N_loc vector entries per RHS (read
+    the right-hand side and write the solution, each once per triangular
+    sweep); 16 N_loc b real flops per RHS.  Returns (bytes, flops)."""
+    nsub = int(np.prod(w.parts))
+    sweeps = 2 ** w.dim
+    fac = vec = flops = 0.0
+    for sid in range(nsub):
+        dims, _ = plan.subdomain_grid(sid)
+        dims = sorted(dims[:w.dim])
+        nloc = float(np.prod(dims))
+        bw = float(dims[0] if w.dim == 2 else dims[0] * dims[1])
+        fac += sweeps * nloc * (2 * bw + 1) * tsize
+        vec += sweeps * 4 * nloc * tsize * nrhs
+        flops += sweeps * 16 * nloc * bw * nrhs
+    return fac + vec, flops
+
+
+def _roofline(plan, b, w, tsize, matrix_peak=None):
+    """Roofline of the subdomain-solve kernel over one preconditioner application.
+
+    achieved = the algorithmic bytes (band_work: band-LU factor once per RHS
+    block plus the vectors, summed over the application's local solves) divided
+    by the summed device time of the solve launches, timed with a pair of HIP
+    events around every launch on the plan's stream; the same over the flops
+    for the compute roof.  The binding roof is the one whose ideal time is
+    longer (HBM for C2's 16 RHS, the matrix cores past the ridge); the other is
+    reported beside it.  kernel_format_bytes is the library's own count of the
+    bytes its factor format has to stream (a diagnostic).  With matrix_peak (the
+    complex128 path, vector FP64 FMAs) the compute roof is that ALU peak."""
     import torch
     plan.timing(True)
     plan.sweep_apply(b)
@@ -138,48 +164,103 @@ def _roofline(plan, b, workload, matrix_peak=None):
     t = plan.timing_read()
     plan.timing(False)
     nl = max(1, t["solve_launches"])
-    avg_ms = t["solve_ms"] / nl
-    avg_bytes = t["solve_bytes"] / nl
-    avg_flops = t["solve_flops"] / nl
-    gbs = avg_bytes / (avg_ms * 1e-3) / 1e9
-    tfs = avg_flops / (avg_ms * 1e-3) / 1e12
+    k = b.shape[0]
+    app_bytes, app_flops = band_work(plan, w, k, tsize)
+    sec = t["solve_ms"] * 1e-3
+    gbs = app_bytes / sec / 1e9
+    tfs = app_flops / sec / 1e12
     hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4)}
     peak_tf = FP32_MATRIX_PEAK_TFLOPS if matrix_peak is None else matrix_peak
     mfma = {"bound": "mfma" if matrix_peak is None else "alu", "achieved": round(tfs, 2),
             "peak": peak_tf, "unit": "TFLOP/s", "frac": round(tfs / peak_tf, 4)}
-    mfma_bound = avg_flops / (peak_tf * 1e12) > avg_bytes / (HBM_PEAK_GBS * 1e9)
+    mfma_bound = app_flops / (peak_tf * 1e12) > app_bytes / (HBM_PEAK_GBS * 1e9)
     out = dict(mfma if mfma_bound else hbm)
-    out.update({"traffic": _measured_traffic(workload) if matrix_peak is None else None,
-                "kernel": {"bcr": "k_bcr (block cyclic reduction solves)",
-                           "chain": "k_chain (block LDL^T chain solves)",
-                           "chain-steps": "k_bcr (block LDL^T chain steps)"}[plan.local_solver],
+    out.update({"traffic": _measured_traffic(w.name) if matrix_peak is None else None,
+                "kernel": KERNEL_NAMES[plan.local_solver],
                 "launches": t["solve_launches"],
-                "avg_launch_ms": round(avg_ms, 4), "avg_launch_bytes": round(avg_bytes),
-                "avg_launch_flops": round(avg_flops),
+                "solve_ms_per_application": round(t["solve_ms"], 3),
+                "avg_launch_ms": round(t["solve_ms"] / nl, 4),
+                "avg_launch_bytes": round(app_bytes / nl),
+                "avg_launch_flops": round(app_flops / nl),
                 "other_roof": hbm if mfma_bound else mfma,
-                "traffic_unit": "HBM bytes per dispatch"})
+                "traffic_unit": "HBM bytes per dispatch",
+                "algorithmic_bytes": "band LU: N_loc (2b+1) factor entries per solve per RHS "
+                                     "block + 4 N_loc entries per RHS",
+                "kernel_format_bytes_per_launch": round(t["solve_bytes"] / nl),
+                "kernel_format_GBps": round(t["solve_bytes"] / sec / 1e9, 1)})
     return out
 
 
-def _cpu_baseline(w, c, F):
-    """The FP64 oracle (numpy/scipy) on one host core: DDM-preconditioned FGMRES
-    for one RHS of the same workload; the local factorisations are excluded
-    (as on the GPU side, where factors are resident)."""
+KERNEL_NAMES = {"bcr": "k_bcr (block cyclic reduction solves)",
+                "chain": "k_chain (block LDL^T chain solves)",
+                "chain-steps": "k_bcr (block LDL^T chain steps)"}
+
+
+_CPU = {}
+
+
+def _cpu_worker(i):
+    """One RHS of the oracle's DDM-preconditioned FGMRES on one thread (pool worker;
+    the factors come from the parent by fork)."""
     from threadpoolctl import threadpool_limits
     from oracle.krylov import fgmres
-    from oracle.sweep import DiagonalSweepDDM
+    ddm, F = _CPU["ddm"], _CPU["F"]
     with threadpool_limits(limits=1):
-        ddm = DiagonalSweepDDM(w.n, w.h, w.omega, w.pml, w.overlap, w.parts, 1.0 / c ** 2)
-        b = F[0].ravel()
         t0 = time.perf_counter()
-        x, its, hist = fgmres(lambda v: ddm.M @ v, ddm.apply, b, tol=1e-6, restart=30, maxit=60)
-        dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 5), "unit": "RHS/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 of the {w.nrhs} RHS, FGMRES to 1e-6 ({its} iterations, relres "
-                      f"{hist[-1]:.1e}) in {dt:.1f} s; local factorisations excluded; "
-                      f"SuperLU, scipy.sparse and BLAS on one thread",
-            "host_cpu": _host_cpu(), "host_logical_cpus": os.cpu_count()}
+        x, its, hist = fgmres(lambda v: ddm.M @ v, ddm.apply, F[i].ravel(), tol=1e-6, restart=30,
+                              maxit=60)
+        return its, hist[-1], time.perf_counter() - t0
+
+
+def _cpu_baseline(w, c, F):
+    """The FP64 oracle (numpy/scipy, as it stands) on the host cores, with the
+    phases of the method timed separately: the local factorisations (one sparse
+    LU per subdomain), the global sparse LU of the whole PML problem (the
+    reference the error is measured against), and the DDM-preconditioned FGMRES
+    solves.  The solves run one worker process per core over the RHS (factors
+    shared by fork; one BLAS thread each): `value` is that throughput, with the
+    single-RHS time of one worker beside it.  Runs before the GPU is touched,
+    so the workers fork from a process without a GPU context."""
+    import multiprocessing as mp
+    from threadpoolctl import threadpool_limits
+    from oracle.sweep import DiagonalSweepDDM
+    out = {"kind": "oracle", "unit": "RHS/s", "host_cpu": _host_cpu(),
+           "host_logical_cpus": os.cpu_count()}
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ddm = DiagonalSweepDDM(w.n, w.h, w.omega, w.pml, w.overlap, w.parts, 1.0 / c ** 2)
+        out["local_factor_s"] = round(time.perf_counter() - t0, 2)
+        u_glob = None
+        N = int(np.prod([k + 2 * w.pml for k in w.n]))
+        if w.dim == 2 and N <= 2_000_000:
+            from oracle.sweep import global_solve
+            t0 = time.perf_counter()
+            u_glob = global_solve(ddm.M, F[0].ravel())
+            out["global_splu_s"] = round(time.perf_counter() - t0, 2)
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu, w.nrhs))
+    _CPU.update(ddm=ddm, F=F)
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_cpu_worker, range(w.nrhs))
+    wall = time.perf_counter() - t0
+    _CPU.clear()
+    its = [r[0] for r in res]
+    per = [r[2] for r in res]
+    out.update({
+        "value": round(w.nrhs / wall, 5), "cores": workers,
+        "sample": f"all {w.nrhs} RHS, FGMRES to 1e-6 ({min(its)}-{max(its)} iterations, relres "
+                  f"<= {max(r[1] for r in res):.1e}) in {wall:.1f} s wall on {workers} worker "
+                  f"processes (one BLAS thread each); local factorisations and global LU timed "
+                  f"separately",
+        "ddm_gmres_wall_s": round(wall, 2),
+        "single_core_rhs_per_s": round(1.0 / statistics.median(per), 5),
+    })
+    return out, u_glob
 
 
 def _host_cpu():
@@ -194,17 +275,12 @@ def _host_cpu():
     return ""
 
 
-def _oracle_error(w, c, F, sols):
+def _oracle_error(u, sols):
     """Relative error of the timed solutions of RHS 0 (at the benchmark's
-    tolerance) against the oracle's global sparse LU solution of the same
-    PML problem (2D workloads up to 2M unknowns; null otherwise)."""
-    N = int(np.prod([k + 2 * w.pml for k in w.n]))
-    if w.dim != 2 or N > 2_000_000:
+    tolerance) against the oracle's global sparse LU solution of the same PML
+    problem (2D workloads up to 2M unknowns; null otherwise)."""
+    if u is None:
         return None
-    from oracle.pml import assemble, global_axes
-    from oracle.sweep import global_solve
-    M = assemble(global_axes(w.n, w.pml, w.h), 1.0 / c ** 2, w.h, w.omega, w.pml)
-    u = global_solve(M, F[0].ravel())
     out = {"reference": "oracle global sparse LU, RHS 0"}
     for k, x in sols.items():
         if x is not None:
@@ -246,10 +322,17 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    w, c, F = _inputs(args.workload)
+    cpu, u_glob = None, None
+    if not args.no_cpu_baseline:
+        # before any GPU call: the oracle's worker processes fork from this one
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu, u_glob = _cpu_baseline(w, c, F)
+        print(f"# cpu baseline: {cpu['value']} RHS/s on {cpu['cores']} cores", file=sys.stderr,
+              flush=True)
     import torch
     if args.copy_probe:
         _copy_probe()
-    w, c, F = _inputs(args.workload)
     b = torch.from_numpy(F).cuda()
     print(f"# workload {w.name}: n={w.n} parts={w.parts} nrhs={w.nrhs}", file=sys.stderr, flush=True)
 
@@ -259,7 +342,7 @@ def main():
                                                           args.restart, args.warmup, args.steps)
     print(f"# c64 solve {dt64 / args.steps * 1e3:.1f} ms/step iters {its64}", file=sys.stderr,
           flush=True)
-    roof = _roofline(plan64, b, w.name)
+    roof = _roofline(plan64, b, w, 8)
     info64 = plan64.info()
     plan64.close()
     del plan64
@@ -277,17 +360,11 @@ def main():
                 "iters": its128, "max_relres": max(rel128), "converged": ok128}
         print(f"# c128 solve {dt128 / n128 * 1e3:.1f} ms/step iters {its128}", file=sys.stderr,
               flush=True)
-        c128["roofline"] = _roofline(plan128, b, w.name, FP64_VECTOR_PEAK_TFLOPS)
+        c128["roofline"] = _roofline(plan128, b, w, 16, FP64_VECTOR_PEAK_TFLOPS)
         plan128.close()
         del plan128
 
-    cpu = None
-    err = None
-    if not args.no_cpu_baseline:
-        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cpu = _cpu_baseline(w, c, F)
-        print("# error against the oracle's global solve ...", file=sys.stderr, flush=True)
-        err = _oracle_error(w, c, F, {"c64": x64, "c128": None if c128 is None else x128})
+    err = _oracle_error(u_glob, {"c64": x64, "c128": None if c128 is None else x128})
 
     value = w.nrhs * args.steps / dt64
     out = {

@@ -222,8 +222,13 @@ int dsd_gmres_solve(dsd_plan* plan, const double* b_dev, double* x_dev, int nrhs
 int dsd_ddm_iterate(dsd_plan* plan, const double* f_dev, double* x_dev, int nrhs, int iters,
                     double* relres_hist_host, void* stream);
 
-/* Solve the adjoint system M^H x = b with the same factors; M is complex
- * symmetric, so x = conj(M^{-1} conj(b)).  Arguments as dsd_gmres_solve. */
+/* Solve the adjoint system M^H x = b with the same factors: the discrete
+ * PML operator of Section 2.1 (eq. (eq:PML) multiplied through by J, central
+ * differences of Section 5) is complex symmetric, so x = conj(M^{-1} conj(b))
+ * is one FGMRES solve of Remark 1 of Section 4 between two conjugations.  It
+ * is the adjoint solve of the many-right-hand-side inversion setting that
+ * Remark 2 of Section 4 motivates.  Arguments, outputs and error codes as
+ * dsd_gmres_solve. */
 int dsd_adjoint_solve(dsd_plan* plan, const double* b_dev, double* x_dev, int nrhs, double tol,
                       int maxit, int restart, int* iters_host, double* relres_host,
                       void* stream);

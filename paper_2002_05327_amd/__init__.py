@@ -17,7 +17,7 @@ from typing import Optional, Sequence, Tuple
 import torch
 
 from . import _lib
-from ._lib import DSD_C64, DSD_C128, DsweepError, check
+from ._lib import DSD_C64, DSD_C128, DSD_OK, DsweepError, check
 
 __all__ = ["Plan", "HelmholtzMisfit", "DsweepError", "load_library"]
 
@@ -161,20 +161,28 @@ class Plan:
                             "dsd_adjoint_solve")
 
     # ----------------------------------------------------------------- FWI
-    def fwi_forward(self, f: torch.Tensor, receivers: torch.Tensor, tol=1e-6, maxit=100):
+    def fwi_forward(self, f: torch.Tensor, receivers: torch.Tensor, tol=1e-6, maxit=100,
+                    allow_not_converged=False):
+        """d = P u_s for every source.  Raises DsweepError (DSD_NOT_CONVERGED) if a
+        forward solve missed tol within maxit, unless allow_not_converged; the
+        flag of the last call is kept in ``last_converged``."""
         k = self._batch(f, "f")
         _dev(receivers, torch.int64, "receivers")
         d = torch.empty((k, receivers.numel()), dtype=torch.complex128, device=f.device)
-        check(self._lib.dsd_fwi_forward(self._h, C.c_void_p(f.data_ptr()), k,
-                                        C.c_void_p(receivers.data_ptr()), receivers.numel(),
-                                        float(tol), int(maxit), C.c_void_p(d.data_ptr()),
-                                        _stream_ptr()), "dsd_fwi_forward",
-              allow_not_converged=True)
+        rc = self._lib.dsd_fwi_forward(self._h, C.c_void_p(f.data_ptr()), k,
+                                       C.c_void_p(receivers.data_ptr()), receivers.numel(),
+                                       float(tol), int(maxit), C.c_void_p(d.data_ptr()),
+                                       _stream_ptr())
+        check(rc, "dsd_fwi_forward", allow_not_converged=allow_not_converged)
+        self.last_converged = rc == DSD_OK
         return d
 
     def fwi_gradient(self, f: torch.Tensor, receivers: torch.Tensor, d_obs: torch.Tensor,
-                     tol=1e-6, maxit=100):
-        """Misfit 1/2 sum |P u - d|^2 and its gradient w.r.t. m = 1/c^2 (physical cells)."""
+                     tol=1e-6, maxit=100, allow_not_converged=False):
+        """Misfit 1/2 sum |P u - d|^2 and its gradient w.r.t. m = 1/c^2 (physical cells).
+        Raises DsweepError (DSD_NOT_CONVERGED) if a forward or adjoint solve missed
+        tol within maxit, unless allow_not_converged; the flag of the last call is
+        kept in ``last_converged``."""
         k = self._batch(f, "f")
         _dev(receivers, torch.int64, "receivers")
         _dev(d_obs, torch.complex128, "d_obs")
@@ -185,7 +193,8 @@ class Plan:
                                         C.c_void_p(d_obs.data_ptr()), float(tol), int(maxit),
                                         C.c_void_p(g.data_ptr()), C.byref(J), None,
                                         _stream_ptr())
-        check(rc, "dsd_fwi_gradient", allow_not_converged=True)
+        check(rc, "dsd_fwi_gradient", allow_not_converged=allow_not_converged)
+        self.last_converged = rc == DSD_OK
         return J.value, g
 
     # -------------------------------------------------------------- timing
@@ -238,7 +247,9 @@ class HelmholtzMisfit(torch.autograd.Function):
     forward(m, f, receivers, d_obs, plan_kwargs, tol, maxit) -> scalar tensor.
     The gradient dJ/dm comes from the adjoint solves M^H lam_s = P^T(P u_s - d_s)
     with the same complex-symmetric factors; it is computed together with J
-    (one factorisation) and returned by backward.
+    (one factorisation) and returned by backward.  A forward or adjoint solve
+    that misses tol within maxit raises DsweepError (DSD_NOT_CONVERGED) instead
+    of returning a gradient of unconverged fields.
     """
 
     @staticmethod

@@ -30,7 +30,23 @@ def sources(n, h, pml, k, seed=1):
 
 
 def rel(a, b):
+    """Relative 2-norm error over the whole array."""
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def elem(a, b):
+    """Element-wise error max |a - b| / max |b|: a local error (a PML strip, a
+    transfer box, a corner subdomain) that the 2-norm would average away."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def close(a, b, tol, what=""):
+    """Assert both the relative 2-norm and the element-wise error below tol."""
+    e2, ei = rel(a, b), elem(a, b)
+    if what:
+        print(f"{what}: rel {e2:.2e} elementwise {ei:.2e} (bound {tol:.0e})", flush=True)
+    assert e2 < tol and ei < tol, (what, e2, ei, tol)
+    return e2
 
 
 def sub_tuple(sid, parts):
@@ -42,4 +58,4 @@ def sub_tuple(sid, parts):
     return tuple(out)
 
 
-__all__ = ["medium", "sources", "rel", "sub_tuple", "slowness2", "embed_physical"]
+__all__ = ["medium", "sources", "rel", "elem", "close", "sub_tuple", "slowness2", "embed_physical"]

@@ -10,15 +10,17 @@ global solution); 2240^2, 80^3 and 96^3 have factors that fit the GPU only in
 complex64, so they run FGMRES with FP64 refinement to a relative residual of
 1e-12.  The free-space solution and the error norm are the oracle's.
 
-Reading for Table 2: its errors are those of the source amplitude
-64 kappa^3 / pi^5, a factor pi^(-1/2) below the printed 64 kappa^3 / pi^(9/2)
-(which gives unit mass, as the 2D source does).  With unit mass the errors at
-80^3 and 96^3 are 4.738e-2 and 3.218e-2: sqrt(pi) = 1.7725 times the printed
-2.67e-2 and 1.82e-2 (ratios 1.775 and 1.768), with the printed rate (2.1).
-The error is linear in the amplitude, so the scaled source reproduces both
-rows.  The 128^3 and 160^3 rows need inversions of planes larger than the
-inversion kernel's LDS holds, and Table 1's 4480^2 and 6720^2 rows factors
-larger than one GPU's memory.
+Table 2 is checked against the oracle, not against the printed digits.  With
+the source as printed (64 kappa^3 / pi^(9/2), unit mass like the 2D source) the
+oracle's own discrete solution of the same problem (separable direct solve,
+residual <= 5e-10; ``tests/golden/table2_oracle.json``, written by
+``make_table2_oracle.py`` from ``oracle/`` alone) has L2 errors 4.738e-2 and
+3.218e-2 at 80^3 and 96^3: a constant factor 1.77 above the printed 2.67e-2
+and 1.82e-2, at the printed rate.  The GPU errors must equal the oracle's to
+1e-4 relative; agreement with Table 2's printed values is unpinned.  The
+128^3 and 160^3 rows need inversions of planes larger than the inversion
+kernel's LDS holds, and Table 1's 4480^2 and 6720^2 rows factors larger than
+one GPU's memory.
 """
 import json
 import os
@@ -33,6 +35,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "accuracy_tables.json")
+ORACLE2 = os.path.join(os.path.dirname(__file__), "golden", "table2_oracle.json")
 
 
 def _row(table, mesh):
@@ -51,9 +54,8 @@ def _problem(tab, mesh):
     c = (np.arange(n) + 0.5) * h
     coords = np.meshgrid(*([c] * dim), indexing="ij")       # slowest axis first
     r = np.sqrt(sum((g - x0[dim - 1 - k]) ** 2 for k, g in enumerate(coords)))
-    amp = 1.0 if dim == 2 else 1.0 / np.sqrt(np.pi)          # Table 2 reading (module doc)
-    f = np.pad(amp * gaussian_source(kappa, dim, r), pml).astype(np.complex128)
-    return dim, kappa, h, n, pml, x0, f, amp
+    f = np.pad(gaussian_source(kappa, dim, r), pml).astype(np.complex128)
+    return dim, kappa, h, n, pml, x0, f
 
 
 @pytest.mark.parametrize("table,mesh,overlap,prec", [
@@ -66,7 +68,7 @@ def _problem(tab, mesh):
 def test_accuracy_table_row(table, mesh, overlap, prec):
     import paper_2002_05327_amd as dsw
     tab, row = _row(table, mesh)
-    dim, kappa, h, n, pml, x0, f, amp = _problem(tab, mesh)
+    dim, kappa, h, n, pml, x0, f = _problem(tab, mesh)
     m = torch.ones((n,) * dim, dtype=torch.float64, device="cuda")
     print(f"{table} {mesh}^{dim}: n={n} pml={pml} parts={tab['parts']} {prec}", flush=True)
     plan = dsw.Plan(n=(n,) * dim, h=h, omega=kappa, pml=pml, overlap=overlap,
@@ -80,9 +82,15 @@ def test_accuracy_table_row(table, mesh, overlap, prec):
     plan.close()
     sl = (slice(pml, pml + n),) * dim
     u = u.cpu().numpy()[0][sl]
-    e = l2_error(u / amp, h, x0, kappa) * amp             # free-space solution scales with f
+    e = l2_error(u, h, x0, kappa)
     print(f"{table} {mesh}^{dim}: L2 error {e:.4e}, paper {row[2]:.2e}", flush=True)
-    assert f"{e:.2e}" == f"{row[2]:.2e}"
+    if dim == 2:
+        assert f"{e:.2e}" == f"{row[2]:.2e}"
+    else:
+        ref = json.load(open(ORACLE2))["rows"][str(mesh)]["l2_error"]
+        print(f"{table} {mesh}^{dim}: oracle L2 error {ref:.6e}, GPU/oracle - 1 = "
+              f"{e / ref - 1:.1e}; GPU / printed = {e / row[2]:.4f}", flush=True)
+        assert abs(e / ref - 1) < 1e-4
 
 
 @pytest.mark.parametrize("mesh", [600, 1200, 2400, 4800])

@@ -10,7 +10,7 @@ direct adjoint on a 128 x 128 downsample.
 import numpy as np
 import pytest
 
-from _cases import rel
+from _cases import close, rel, sub_tuple
 
 pytestmark = pytest.mark.gpu
 
@@ -54,8 +54,7 @@ def test_c2_solutions_against_oracle_operator_and_global_lu():
         plan = _plan(w, c, prec)
         y = plan.apply_operator(torch.from_numpy(x).cuda()).cpu().numpy().reshape(2, -1)
         y_ref = (M @ x.reshape(2, -1).T).T
-        print(f"c2 {prec}: operator vs oracle {rel(y, y_ref):.2e}", flush=True)
-        assert rel(y, y_ref) < 1e-13
+        close(y, y_ref, 1e-13, f"c2 {prec}: operator vs oracle")
         sol, iters, relres, ok = plan.gmres(b, tol=1e-6, maxit=100, restart=30)
         assert ok
         X = sol.cpu().numpy().reshape(shape[0], -1)
@@ -67,10 +66,8 @@ def test_c2_solutions_against_oracle_operator_and_global_lu():
         # one RHS driven further: error against the global sparse direct solve
         tight = 1e-11 if prec == "c64" else 1e-13
         s0, it0, rr0, ok0 = plan.gmres(b[:1].contiguous(), tol=tight, maxit=200, restart=30)
-        e = rel(s0.cpu().numpy().ravel(), u_ref)
-        print(f"c2 {prec}: RHS 0 at relres {rr0[0]:.1e} ({it0[0]} its): error vs global LU {e:.2e}",
-              flush=True)
-        assert e < tol_err
+        close(s0.cpu().numpy().ravel(), u_ref, tol_err,
+              f"c2 {prec}: RHS 0 at relres {rr0[0]:.1e} ({it0[0]} its) vs global LU")
         plan.close()
 
 
@@ -83,7 +80,7 @@ def test_c3_solutions_against_oracle_operator():
     plan = _plan(w, c, "c64")
     x = np.random.default_rng(6).standard_normal(F.shape[1:]) + 0j
     y = plan.apply_operator(torch.from_numpy(x[None]).cuda()).cpu().numpy().ravel()
-    assert rel(y, M @ x.ravel()) < 1e-13
+    close(y, M @ x.ravel(), 1e-13, "c3 operator vs oracle")
     sol, iters, relres, ok = plan.gmres(torch.from_numpy(F).cuda(), tol=1e-6, maxit=100, restart=30)
     assert ok
     X = sol.cpu().numpy().reshape(F.shape[0], -1)
@@ -103,12 +100,66 @@ def test_c2_sweep_matches_oracle_sweep():
     ddm = DiagonalSweepDDM(w.n, w.h, w.omega, w.pml, w.overlap, w.parts, 1.0 / c ** 2)
     u_ref = ddm.apply(F[0].ravel())
     f = torch.from_numpy(F[:2].copy()).cuda()
-    for prec, tol in [("c128", 1e-10), ("c64", 1e-3)]:
+    for prec, tol in [("c128", 1e-10), ("c64", 1e-4)]:
         plan = _plan(w, c, prec)
         u = plan.sweep_apply(f).cpu().numpy().reshape(2, -1)
-        print(f"c2 sweep {prec}: vs oracle {rel(u[0], u_ref):.2e}", flush=True)
-        assert rel(u[0], u_ref) < tol
+        close(u[0], u_ref, tol, f"c2 sweep {prec} vs oracle")
         plan.close()
+
+
+def test_c3_sweep_matches_oracle_sweep():
+    """One application of the diagonal sweeps on C3's uneven 16 x 16 partition
+    (RHS 0, complex64 as bench.py runs it), against the oracle's sequential
+    sweep with real local PML solves (256 local sparse LUs)."""
+    from oracle.sweep import DiagonalSweepDDM
+    w, c, F = _workload("c3")
+    ddm = DiagonalSweepDDM(w.n, w.h, w.omega, w.pml, w.overlap, w.parts, 1.0 / c ** 2)
+    u_ref = ddm.apply(F[0].ravel())
+    plan = _plan(w, c, "c64")
+    u = plan.sweep_apply(torch.from_numpy(F[:1].copy()).cuda()).cpu().numpy().ravel()
+    close(u, u_ref, 1e-4, "c3 sweep c64 vs oracle")
+    plan.close()
+
+
+def test_c4r_solutions_and_local_solves_against_oracle():
+    """C4r (80^3, 4x4x4, 32 RHS, complex64 + FP64 refinement, as bench.py
+    --workload c4r runs it): every RHS meets the FP64 true residual 1e-6 under
+    the oracle's operator, and the local solves of an interior and a corner
+    subdomain equal the oracle's local sparse LU (complex64 2e-4, complex128
+    1e-11)."""
+    import scipy.sparse.linalg as spla
+    from oracle.partition import Partition
+    from oracle.pml import assemble
+    w, c, F = _workload("c4r")
+    M = _oracle_operator(w, c)
+    b = torch.from_numpy(F).cuda()
+    plan = _plan(w, c, "c64")
+    sol, iters, relres, ok = plan.gmres(b, tol=1e-6, maxit=100, restart=30)
+    assert ok
+    X = sol.cpu().numpy().reshape(F.shape[0], -1)
+    B = F.reshape(F.shape[0], -1)
+    rr = np.linalg.norm((M @ X.T).T - B, axis=1) / np.linalg.norm(B, axis=1)
+    print(f"c4r: iterations {min(iters)}-{max(iters)}; oracle-operator residual max {rr.max():.2e}",
+          flush=True)
+    assert rr.max() <= 1.0e-6 * 1.001
+    part = Partition(w.n, w.parts, w.pml, w.overlap, w.h)
+    corner, interior = 0, 1 + 4 + 16          # parts (0,0,0) and (1,1,1)
+    cases = []
+    rng = np.random.default_rng(11)
+    for sid in (corner, interior):
+        axes = part.local_axes(sub_tuple(sid, w.parts))
+        shape = tuple(ax.n for ax in reversed(axes))
+        Ml = assemble(axes, 1.0 / c ** 2, w.h, w.omega, w.pml).tocsc()
+        r = rng.standard_normal((2, Ml.shape[0])) + 1j * rng.standard_normal((2, Ml.shape[0]))
+        cases.append((sid, shape, r, spla.splu(Ml).solve(r.T).T))
+    for prec, tol in [("c64", 2e-4), ("c128", 1e-11)]:
+        if prec == "c128":
+            plan.close()
+            plan = _plan(w, c, "c128", max_rhs=2)
+        for sid, shape, r, u_ref in cases:
+            u = plan.local_solve(sid, torch.from_numpy(r.reshape((2,) + shape)).cuda())
+            close(u.cpu().numpy().reshape(2, -1), u_ref, tol, f"c4r {prec} local solve sub {sid}")
+    plan.close()
 
 
 def _fwi_setup(n_cells, parts, nsrc, nrec):
@@ -184,7 +235,6 @@ def test_fwi_gradient_against_global_direct_adjoint_128():
                                  torch.from_numpy(np.ascontiguousarray(d_obs.T)).cuda(),
                                  tol=tol, maxit=300)
         plan.close()
-        eg = rel(g.cpu().numpy(), g_ref)
-        print(f"fwi 128 {prec}: misfit rel {abs(J - J_ref) / J_ref:.2e} gradient rel {eg:.2e}",
-              flush=True)
-        assert abs(J - J_ref) / J_ref < bound and eg < bound
+        print(f"fwi 128 {prec}: misfit rel {abs(J - J_ref) / J_ref:.2e}", flush=True)
+        assert abs(J - J_ref) / J_ref < bound
+        close(g.cpu().numpy(), g_ref, bound, f"fwi 128 {prec} gradient")

@@ -1,14 +1,18 @@
 """GPU parity: every entry point of libdsweep.so against the FP64 CPU oracle.
 
-Tolerances: complex128 path 1e-10 relative (1e-12 for a single local solve),
+Tolerances: complex128 path 1e-10 relative (1e-11 for a single local solve),
 complex64 path bounded by the single-precision rounding of the factors
-(a few 1e-6 per local solve), FP64 operator 1e-14.
+(a few 1e-6 per local solve, 1e-4 for a sweep application), FP64 operator
+1e-14.  Every comparison bounds both the relative 2-norm error and the
+element-wise error max |u - u_ref| / max |u_ref| (``close``), so an error
+confined to a PML strip, a transfer box or one subdomain cannot hide in the
+norm of the whole grid.
 """
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from _cases import embed_physical, medium, rel, slowness2, sources, sub_tuple
+from _cases import close, embed_physical, medium, rel, slowness2, sources, sub_tuple
 from oracle.pml import assemble, global_axes
 from oracle.sweep import DiagonalSweepDDM, global_solve
 
@@ -68,8 +72,7 @@ def test_local_solve_matches_oracle(name, prec, solver):
         u_ref = sp.solve(r.T).T
         u = plan.local_solve(sid, _cuda(r.reshape((k,) + sp.shape))).cpu().numpy().reshape(k, -1)
         tol = 1e-11 if prec == "c128" else 2e-4
-        print(f"{name} {prec} {solver} sub {sid}: rel err {rel(u, u_ref):.2e}", flush=True)
-        assert rel(u, u_ref) < tol
+        close(u, u_ref, tol, f"{name} {prec} {solver} sub {sid}")
 
 
 @pytest.mark.parametrize("name", ["lay33", "d3"])
@@ -81,7 +84,7 @@ def test_operator_matches_oracle(name):
     x = rng.standard_normal((2,) + plan.gshape) + 1j * rng.standard_normal((2,) + plan.gshape)
     y = plan.apply_operator(_cuda(x)).cpu().numpy()
     y_ref = (M @ x.reshape(2, -1).T).T.reshape(y.shape)
-    assert rel(y, y_ref) < 1e-14
+    close(y, y_ref, 1e-14, f"{name} operator")
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -98,7 +101,7 @@ def test_sweep_apply_c128_matches_oracle_real_mode(name, solver):
     e = rel(u, u_ref)
     print(f"{name} {solver}: GPU c128 sweep vs oracle {e:.2e}; DDM vs global solve "
           f"{rel(u_ref, global_solve(ddm.M, f.reshape(k, -1).T).T):.2e}", flush=True)
-    assert e < 1e-10
+    close(u, u_ref, 1e-10, f"{name} {solver} c128 sweep")
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -111,9 +114,7 @@ def test_sweep_apply_c64_close_to_oracle(name, solver):
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
-    e = rel(u, u_ref)
-    print(f"{name} {solver}: GPU c64 sweep vs oracle {e:.2e}", flush=True)
-    assert e < 1e-3
+    close(u, u_ref, 1e-4, f"{name} {solver} c64 sweep")
 
 
 def test_sweep_apply_deterministic():
@@ -126,7 +127,7 @@ def test_sweep_apply_deterministic():
 
 
 @pytest.mark.parametrize("solver", ["bcr", "chain-steps"])
-@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-4)])
 def test_autotuned_plan_matches_oracle(prec, tol, solver):
     """The autotuner only picks launch shapes: the tuned plan still matches the oracle."""
     n, h, om, pml, d, parts, c = _case("lay33")
@@ -138,8 +139,7 @@ def test_autotuned_plan_matches_oracle(prec, tol, solver):
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
-    print(f"autotune {prec}: {res}; vs oracle {rel(u, u_ref):.2e}", flush=True)
-    assert rel(u, u_ref) < tol
+    close(u, u_ref, tol, f"autotune {prec}: {res}")
     # a saved shape applied to a fresh plan reproduces the tuned plan bitwise
     plan2 = _plan(n, h, om, pml, d, parts, c, prec, k, solver=solver)
     plan2.solve_shape = res["shape"]
@@ -163,7 +163,7 @@ def test_solve_shapes_match_oracle(shape, solver):
     ddm = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
-    assert rel(u, u_ref) < 1e-10
+    close(u, u_ref, 1e-10, f"shape {shape} {solver}")
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -210,7 +210,7 @@ def test_rhs_grouping_does_not_change_result(kg, solver):
     f = _cuda(sources(n, h, pml, k))
     ref = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=1, solver=solver).sweep_apply(f)
     got = _plan(n, h, om, pml, d, parts, c, "c128", k, kg=kg, solver=solver).sweep_apply(f)
-    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-13
+    close(got.cpu().numpy(), ref.cpu().numpy(), 1e-13, f"kg {kg} {solver}")
 
 
 @pytest.mark.parametrize("kg", [2, 4, 8])
@@ -221,7 +221,7 @@ def test_rhs_grouping_c64_matrix_core_path(kg):
     f = _cuda(sources(n, h, pml, k))
     ref = _plan(n, h, om, pml, d, parts, c, "c64", k, kg=2, solver="bcr").sweep_apply(f)
     got = _plan(n, h, om, pml, d, parts, c, "c64", k, kg=kg, solver="bcr").sweep_apply(f)
-    assert rel(got.cpu().numpy(), ref.cpu().numpy()) < 1e-6
+    close(got.cpu().numpy(), ref.cpu().numpy(), 1e-6, f"c64 kg {kg}")
 
 
 @pytest.mark.parametrize("name", ["lay33", "rag34", "d3"])
@@ -232,7 +232,8 @@ def test_cyclic_reduction_equals_chains(name):
     a = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="bcr").sweep_apply(f).cpu().numpy()
     b = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain").sweep_apply(f).cpu().numpy()
     s = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain-steps").sweep_apply(f).cpu().numpy()
-    assert rel(a, b) < 1e-12 and rel(s, b) < 1e-12
+    close(a, b, 1e-12, f"{name} reduction vs chains")
+    close(s, b, 1e-12, f"{name} chain steps vs chains")
 
 
 @pytest.mark.parametrize("dense_top", [-1, 2, 3, 8])
@@ -252,12 +253,11 @@ def test_dense_top_level_matches_oracle(name, dense_top):
         r = rng.standard_normal((k, sp.N)) + 1j * rng.standard_normal((k, sp.N))
         u_ref = sp.solve(r.T).T
         u = plan.local_solve(sid, _cuda(r.reshape((k,) + sp.shape))).cpu().numpy().reshape(k, -1)
-        print(f"{name} dense_top={dense_top} sub {sid}: rel err {rel(u, u_ref):.2e}", flush=True)
-        assert rel(u, u_ref) < 1e-11
+        close(u, u_ref, 1e-11, f"{name} dense_top={dense_top} sub {sid}")
     f = sources(n, h, pml, k)
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
-    assert rel(u, u_ref) < 1e-10
+    close(u, u_ref, 1e-10, f"{name} dense_top={dense_top} sweep")
 
 
 @pytest.mark.parametrize("prec,tol,bound", [("c128", 1e-12, 1e-10), ("c64", 1e-11, 1e-8)])
@@ -273,7 +273,7 @@ def test_gmres_matches_global_solve(prec, tol, bound):
     true_res = [np.linalg.norm(f[i].ravel() - M @ xg[i]) / np.linalg.norm(f[i]) for i in range(k)]
     print(f"{prec}: iters {its} relres {res} true {true_res} err {rel(xg, x_ref):.2e}", flush=True)
     assert ok and max(true_res) <= tol * 1.01
-    assert rel(xg, x_ref) < bound
+    close(xg, x_ref, bound, f"{prec} FGMRES vs global LU")
 
 
 def test_gmres_c1_reaches_global_solution():
@@ -284,8 +284,9 @@ def test_gmres_c1_reaches_global_solution():
     x, its, res, ok = plan.gmres(_cuda(f.astype(complex)), tol=1e-13, maxit=40)
     M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml)
     x_ref = global_solve(M, f.reshape(-1))
-    print(f"c1 gmres iters {its} relres {res} err {rel(x.cpu().numpy().ravel(), x_ref):.2e}")
-    assert ok and rel(x.cpu().numpy().ravel(), x_ref) < 1e-10
+    print(f"c1 gmres iters {its} relres {res}")
+    assert ok
+    close(x.cpu().numpy().ravel(), x_ref, 1e-10, "c1 FGMRES vs global LU")
 
 
 def test_adjoint_solve():
@@ -296,7 +297,8 @@ def test_adjoint_solve():
     y, _, _, ok = plan.adjoint_solve(_cuda(f), tol=1e-12, maxit=80)
     M = assemble(global_axes(n, pml, h), slowness2(c), h, om, pml).tocsc()
     y_ref = spla.splu(M.conj().T.tocsc()).solve(f.reshape(k, -1).T).T
-    assert ok and rel(y.cpu().numpy().reshape(k, -1), y_ref) < 1e-10
+    assert ok
+    close(y.cpu().numpy().reshape(k, -1), y_ref, 1e-10, "adjoint solve")
 
 
 def test_fwi_gradient_matches_oracle():
@@ -318,9 +320,9 @@ def test_fwi_gradient_matches_oracle():
     for prec, tol, bound in [("c128", 1e-12, 1e-8), ("c64", 1e-11, 1e-7)]:
         plan = _plan(n, h, om, pml, d, parts, c0, prec, 4)
         J, g = plan.fwi_gradient(_cuda(f), rec, _cuda(d_obs.T.copy()), tol=tol, maxit=80)
-        eg = rel(g.cpu().numpy(), g_ref)
-        print(f"fwi {prec}: misfit rel {abs(J - J_ref) / J_ref:.2e} grad rel {eg:.2e}")
-        assert abs(J - J_ref) / J_ref < bound and eg < bound * 10
+        print(f"fwi {prec}: misfit rel {abs(J - J_ref) / J_ref:.2e}")
+        assert abs(J - J_ref) / J_ref < bound
+        close(g.cpu().numpy(), g_ref, bound * 10, f"fwi {prec} gradient")
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -382,7 +384,7 @@ def test_ddm_iterate_matches_oracle(parts, prec):
     if prec == "c128":
         for a, b in zip(hist, hist_ref):
             assert abs(a - b) <= 1e-12 + 1e-7 * b
-        assert rel(x.cpu().numpy().ravel(), x_ref) < 1e-10
+        close(x.cpu().numpy().ravel(), x_ref, 1e-10, f"{parts} iterate")
     else:
         for a, b in zip(hist[1:3], hist_ref[1:3]):
             assert abs(a - b) <= 1e-3 * b
@@ -405,9 +407,9 @@ def test_sweep_apply_3d_l1_order_matches_oracle(name):
     u_ref = ddm.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
     u0 = DiagonalSweepDDM(n, h, om, pml, d, parts, slowness2(c)).apply(f.reshape(k, -1).T).T
-    e = rel(u, u_ref)
-    print(f"{name}: GPU l1-order sweep vs oracle {e:.2e}; default vs l1 order {rel(u0, u_ref):.2e}")
-    assert e < 1e-10 and rel(u0, u_ref) > 1e-8
+    print(f"{name}: default vs l1 order {rel(u0, u_ref):.2e}")
+    close(u, u_ref, 1e-10, f"{name} l1-order sweep")
+    assert rel(u0, u_ref) > 1e-8
 
 
 @pytest.mark.parametrize("solver", SOLVERS)
@@ -424,8 +426,9 @@ def test_additive_ddm_matches_oracle(name, solver):
     add = AdditiveDDM(n, h, om, pml, d, parts, slowness2(c))
     u_ref = add.apply(f.reshape(k, -1).T).T
     u = plan.sweep_apply(_cuda(f)).cpu().numpy().reshape(k, -1)
-    e = rel(u, u_ref)
+    close(u, u_ref, 1e-10, f"{name} {solver} additive DDM")
     x, iters, relres, ok = plan.gmres(_cuda(f), tol=1e-10, maxit=60)
-    ex = rel(x.cpu().numpy().reshape(k, -1), global_solve(add.M, f.reshape(k, -1).T).T)
-    print(f"{name} {solver}: additive DDM vs oracle {e:.2e}; FGMRES {iters} its, vs global {ex:.2e}")
-    assert e < 1e-10 and ok and ex < 1e-8
+    print(f"{name} {solver}: FGMRES {iters} its")
+    assert ok
+    close(x.cpu().numpy().reshape(k, -1), global_solve(add.M, f.reshape(k, -1).T).T, 1e-8,
+          f"{name} {solver} additive FGMRES vs global")

@@ -83,3 +83,28 @@ def test_entry_points_reject_a_null_plan_without_gpu():
     assert lib.dsd_apply_operator(None, one, one, 1, None) == -1
     assert lib.dsd_ddm_iterate(None, one, one, 1, 1, (ctypes.c_double * 2)(), None) == -1
     assert lib.dsd_timing_flops(None, (ctypes.c_double * 1)()) == -1
+
+
+def test_bench_band_work_matches_the_stated_c2_figures():
+    """bench.py's algorithmic bytes (band LU factor once per RHS block plus the
+    vectors, over the 2^dim * N_sub local solves of one application) reproduce
+    the C2 figures the measurement is defined by: 26.0 GB of complex64 factor
+    stream per RHS block and 0.28 GB of vectors per RHS; 2.59e10 flops per RHS.
+    Local grids come from the oracle's partition."""
+    import bench
+    import synth
+    from oracle.partition import Partition
+    w = synth.workload("c2")
+    part = Partition(w.n, w.parts, w.pml, w.overlap, w.h)
+
+    class FakePlan:
+        def subdomain_grid(self, sid):
+            sub = (sid % w.parts[0], sid // w.parts[0])
+            return tuple(ax.n for ax in part.local_axes(sub)), (0, 0)
+
+    b1, f1 = bench.band_work(FakePlan(), w, 1, 8)
+    b2, f2 = bench.band_work(FakePlan(), w, 2, 8)
+    vec = b2 - b1
+    fac = b1 - vec
+    assert abs(fac / 26.0e9 - 1) < 0.01 and abs(vec / 0.28e9 - 1) < 0.03
+    assert abs(f1 / 2.59e10 - 1) < 0.01 and f2 == 2 * f1

@@ -87,3 +87,32 @@ def test_second_order_convergence_at_lower_frequency():
     ratios = [errs[i] / errs[i + 1] for i in range(2)]
     print("errors", errs, "ratios", ratios)
     assert all(3.9 < q < 4.2 for q in ratios)
+
+
+def test_table2_oracle_values_and_printed_rate():
+    """Table 2 (Section 5.1, 3D): tests/golden/table2_oracle.json holds the
+    oracle's L2 errors at 80^3 and 96^3 with the printed unit-mass source (the
+    values the GPU is held to).  They are reproduced here from oracle/ alone
+    (separable direct solve, residual under the sparse operator <= 1e-9), and
+    their ratio equals the printed ratio 2.67e-2 / 1.82e-2 within 1%: the
+    printed rate is matched, the printed level is a constant 1.77 times
+    lower, so parity with the printed values is unpinned."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_table2_oracle import table2_problem
+    from oracle.separable import residual, solve_constant
+    tab = json.load(open(GOLDEN))["table2_3d"]
+    stored = json.load(open(os.path.join(os.path.dirname(GOLDEN), "table2_oracle.json")))["rows"]
+    errs = {}
+    for mesh in (80, 96):
+        dim, kappa, h, n, pml, x0, f = table2_problem(tab, mesh)
+        u = solve_constant((n,) * dim, h, kappa, pml, 1.0, f.ravel())
+        M = assemble(global_axes((n,) * dim, pml, h), np.ones((n,) * dim), h, kappa, pml)
+        assert residual(M, u, f.ravel()) < 1e-9
+        sl = (slice(pml, pml + n),) * dim
+        errs[mesh] = l2_error(u.reshape(f.shape)[sl], h, x0, kappa)
+        assert abs(errs[mesh] / stored[str(mesh)]["l2_error"] - 1) < 1e-10
+    printed = {r[0]: r[2] for r in tab["rows"]}
+    assert abs((errs[80] / errs[96]) / (printed[80] / printed[96]) - 1) < 0.01
+    print("oracle / printed:", {k: errs[k] / printed[k] for k in errs})
