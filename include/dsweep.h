@@ -172,6 +172,28 @@ int dsd_local_solve(dsd_plan* plan, int sub, const double* r_dev, double* u_dev,
                     void* stream);
 
 /*
+ * Allocation-free variant of dsd_local_solve, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts and results as
+ * dsd_local_solve (the same kernels), but its working memory -- the packed
+ * right-hand sides and solutions of the call in the plan precision,
+ * 2 x N_loc x nrhs values, each half rounded up to 256 bytes -- lives in a
+ * static device array of DSD_NOALLOC_SCRATCH_BYTES per GPU (held by every GPU
+ * the library runs on until the process ends), and the job tables were built
+ * with the plan.  The call allocates, frees and uploads nothing and does not
+ * synchronise: it is ordered on `stream` like the other calls.  Every call on
+ * one GPU shares that GPU's array and nothing in it needs to start at zero
+ * (every value is written before it is read); calls that overlap on one GPU
+ * (other streams, other threads, other plans on the same device) race on it
+ * and must be serialised by the caller.
+ * DSD_EINVAL for a bad argument, for a current device other than the plan's,
+ * or when 2 x N_loc x nrhs values exceed DSD_NOALLOC_SCRATCH_BYTES.
+ */
+#define DSD_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int dsd_local_solve_noalloc(dsd_plan* plan, int sub, const double* r_dev, double* u_dev,
+                            int nrhs, void* stream);
+
+/*
  * One application of the diagonal-sweeping DDM (Algorithm 3.1 in 2D, 4.1 in
  * 3D): 2^dim sweeps; every subdomain solve is launched, batched with all other
  * solves of its dependency level (schedule 0) or of its anti-diagonal step

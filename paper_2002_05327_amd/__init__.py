@@ -115,6 +115,19 @@ class Plan:
               "dsd_local_solve")
         return u
 
+    def local_solve_noalloc(self, sub: int, r: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+        """dsd_local_solve_noalloc: the same local solve with the library's static
+        device scratch (no allocation in the call); the caller passes the output."""
+        dims, _ = self.subdomain_grid(sub)
+        _dev(r, torch.complex128, "r")
+        _dev(u, torch.complex128, "u")
+        if tuple(r.shape[1:]) != tuple(reversed(dims)) or u.shape != r.shape:
+            raise ValueError(f"r and u must have shape (nrhs, *{tuple(reversed(dims))})")
+        check(self._lib.dsd_local_solve_noalloc(self._h, int(sub), C.c_void_p(r.data_ptr()),
+                                                C.c_void_p(u.data_ptr()), r.shape[0],
+                                                _stream_ptr()), "dsd_local_solve_noalloc")
+        return u
+
     def sweep_apply(self, f: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         k = self._batch(f, "f")
         u = torch.empty_like(f) if out is None else out

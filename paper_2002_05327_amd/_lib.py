@@ -7,6 +7,7 @@ LIB_PATH = os.path.join(_HERE, "libdsweep.so")
 
 DSD_OK, DSD_NOT_CONVERGED = 0, 1
 DSD_C64, DSD_C128 = 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20   # DSD_NOALLOC_SCRATCH_BYTES of include/dsweep.h
 
 
 class Params(C.Structure):
@@ -36,6 +37,8 @@ EXPORTS = {
                                      C.POINTER(C.c_int)]),
     "dsd_local_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                   C.c_void_p]),
+    "dsd_local_solve_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                          C.c_void_p]),
     "dsd_sweep_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "dsd_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]),
     "dsd_gmres_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,

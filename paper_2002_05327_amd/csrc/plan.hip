@@ -8,6 +8,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <vector>
 
@@ -161,7 +162,13 @@ struct dsd_plan {
   int solver = 2;               // 1: twisted block LDL^T chains, 2: block cyclic reduction
   std::vector<BcrSub> bcr;
   std::vector<std::vector<BcrLaunch>> bcr_launch;   // per launch group
-  std::vector<BcrLaunch> bcr_single;                // dsd_local_solve (jobs in d_single_job)
+  // local-solve tables of every subdomain (dsd_local_solve and its
+  // allocation-free variant): job tables addressing a subdomain's vectors from
+  // offset 0 (vbase = 0, and descriptors with vec_off = 0), so one table serves
+  // the plan's pools and the static scratch alike
+  std::vector<std::vector<BcrLaunch>> local_launch;  // per subdomain, offsets into d_local_jobs
+  int device = 0;
+  void* scratch = nullptr;        // this device's allocation-free scratch (see below)
   std::vector<std::vector<int2>> groups;            // launch groups: {subdomain, sweep}
   // launch shape of a reduction level: (wide_cg, wide_rt) column groups and
   // row tiles per workgroup while >= cg_wide blocks per subdomain remain at the
@@ -182,7 +189,7 @@ struct dsd_plan {
   Buf d_subs, d_m, d_gcoef[4], d_lcoef64[4], d_lcoefT[4], d_fac;
   Buf d_rpool, d_vpool, d_members, d_jobs2, d_jobs1, d_edges, d_erange;
   Buf d_part_of[3], d_axparts[3];
-  Buf d_single_job, d_single_mem;
+  Buf d_subs_local, d_local_jobs;
   // Krylov workspace
   Buf d_V, d_Z, d_w, d_r, d_xa, d_ba, d_part, d_h1, d_h2, d_hn, d_scal, d_idx, d_coef;
   int kr_restart = 0, kr_k = 0;
@@ -333,7 +340,7 @@ int sub_index(const dsd_plan* pl, const int* pidx) {
 
 void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
                     std::vector<BcrLaunch>& out);
-int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs);
+int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs, bool local = false);
 void chain_step_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
                      std::vector<BcrLaunch>& out);
 // jobs of one launch group (or one subdomain) with the plan's local solver
@@ -839,6 +846,40 @@ int bcr_factor(dsd_plan* pl) {
 
 // Solve launches of one launch group (members {subdomain, sweep}): the forward
 // reduction levels, then the backward substitution from the top level down.
+// Local-solve tables of every subdomain, built once with the plan (the
+// allocation-free local solve must not upload anything): the solve jobs of
+// {subdomain, sweep 0} with vbase = 0, and descriptors with vec_off = 0 for the
+// kernels that address vectors through them, so that the caller hands the
+// subdomain's vector slice (plan pool or static scratch) as the pool base.
+int resolve_scratch(int dev, void** out);   // the allocation-free local solve's scratch
+
+int build_local_tables(dsd_plan* pl) {
+  std::vector<SubDesc> sl = pl->subs;
+  for (SubDesc& S : sl) S.vec_off = 0;
+  CHK(upload(pl->d_subs_local, sl));
+  pl->local_launch.assign(pl->S, {});
+  if (pl->solver != 2 && !pl->chain_steps) {
+    // chains: per subdomain {sub, top half}, {sub, bottom half} (forward and
+    // backward phases) and {sub, middle} (the middle block)
+    std::vector<int4> cj;
+    for (int s = 0; s < pl->S; ++s) {
+      cj.push_back(make_int4(s, 0, 0, 0));
+      cj.push_back(make_int4(s, 1, 0, 0));
+      cj.push_back(make_int4(s, 0, 0, 0));
+    }
+    return upload(pl->d_local_jobs, cj);
+  }
+  std::vector<BcrJob> bj;
+  for (int s = 0; s < pl->S; ++s) {
+    const size_t first = bj.size();
+    solve_jobs(pl, std::vector<int2>{make_int2(s, 0)}, bj, pl->local_launch[s]);
+    for (size_t i = first; i < bj.size(); ++i) bj[i].vbase = 0;
+  }
+  CHK(bcr_check_jobs(pl, bj, true));
+  CHK(upload(pl->d_local_jobs, bj));
+  return 0;
+}
+
 void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,
                     std::vector<BcrLaunch>& out) {
   int maxtop = 0;
@@ -1015,13 +1056,13 @@ void chain_step_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vect
 }
 
 // Host check of a solve-job table against the factor and the subdomain grids.
-int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs) {
+int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs, bool local) {
   for (const BcrJob& J : jobs) {
     bool ok = J.sub >= 0 && J.sub < pl->S && J.l >= 0 && J.l < pl->L;
     if (ok) {
       const SubDesc& S = pl->subs[J.sub];
       const long long nb2 = (long long)S.nb * S.nb;
-      if (J.nb != S.nb || J.nloc != S.nloc || J.vbase != S.vec_off * pl->kmax ||
+      if (J.nb != S.nb || J.nloc != S.nloc || J.vbase != (local ? 0 : S.vec_off * pl->kmax) ||
           J.cbase != S.coef_off)
         ok = false;
       auto blk_ok = [&](int b) { return b >= 0 && b < S.nblk; };
@@ -1707,6 +1748,92 @@ int choose_kg(const dsd_plan* pl, int want) {
 }  // namespace
 
 // ============================================================================ C ABI
+namespace {
+
+// One subdomain's local solve on R (right-hand sides; the reduction overwrites
+// them) and X (solution), both [nrhs][N_loc] in the plan precision from offset
+// 0, with the plan's local-solve tables.  Nothing is allocated or uploaded;
+// the launches are timed (timing mode) only when `timed`.
+template <typename T>
+void local_solve_launches(dsd_plan* pl, int sub, cpx<T>* R, cpx<T>* X, int nrhs, bool timed) {
+  hipStream_t st = pl->stream;
+  const SubDesc* dsub = pl->d_subs_local.as<SubDesc>();
+  const cpx<T>* cpl = pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>();
+  const cpx<T>* fac = pl->d_fac.as<cpx<T>>();
+  if (pl->solver == 2 || pl->chain_steps) {
+    const BcrJob* jobs = pl->d_local_jobs.as<BcrJob>();
+    for (const BcrLaunch& L : pl->local_launch[sub]) {
+      if (L.dfwd) {
+        launch_bcr_dfwd<T>(dsub, jobs + L.off, L.n, nrhs, pl->kmax, pl->max_nb, cpl, R, X, 0, st);
+        continue;
+      }
+      if (timed) time_begin(pl);
+      launch_bcr_solve<T>(L.kg > 0 ? L.kg : pl->kg, dsub, jobs + L.off, L.n, L.nset, L.cg, L.rt,
+                          nrhs, pl->kmax, pl->max_nb, fac, cpl, R, X, 0, st);
+      if (timed)
+        time_end(pl, L.fbytes + L.vcells * nrhs * (double)sizeof(cpx<T>),
+                 L.fbytes / sizeof(cpx<T>) * nrhs * 8.0);
+    }
+    return;
+  }
+  // chains: phase 0 and 2 run the two halves {sub, 0}, {sub, 1}; phase 1 the middle block
+  const int4* jobs = pl->d_local_jobs.as<int4>() + 3 * (long long)sub;
+  for (int ph = 0; ph < 3; ++ph) {
+    if (timed) time_begin(pl);
+    launch_chain<T>(pl->kg, ph, dsub, jobs + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2, nrhs, pl->kmax,
+                    pl->max_nb, fac, cpl, R, X, 0, st);
+    if (timed) time_end(pl, 0, 0);
+  }
+}
+
+template <typename T>
+void local_solve_any(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, int nrhs,
+                     cpx<T>* R, cpx<T>* X, bool timed) {
+  const SubDesc& S = pl->subs[sub];
+  launch_pack_local<T>((const cpx<double>*)r_dev, R, S.nloc, nrhs, pl->kmax, pl->stream);
+  local_solve_launches<T>(pl, sub, R, X, nrhs, timed);
+  launch_unpack_local<T>(X, (cpx<double>*)u_dev, S.nloc, nrhs, pl->kmax, pl->stream);
+}
+
+}  // namespace
+
+// ------------------------------------------------- allocation-free local solve
+// Working memory of dsd_local_solve_noalloc: the packed right-hand sides and
+// solutions of one call in the plan precision.  Every GPU the library runs on
+// holds its own copy of this array until the process ends; host code never
+// uses the array's name (a host-side stand-in), only the device address that
+// hipGetSymbolAddress returns for the current device, resolved once per device
+// when the first plan is created on it.
+static __device__ __align__(256) unsigned char scratch[DSD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (resolved once per device).
+int resolve_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    g_detail = "device index beyond the scratch table";
+    return DSD_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      g_detail = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return DSD_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+}  // namespace
+
 extern "C" {
 
 int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev, void* stream,
@@ -1777,6 +1904,12 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   if (rc == 0) rc = upload(pl->d_subs, pl->subs);
   if (rc == 0) rc = assemble_and_factor(pl, m_dev);
   if (rc == 0) rc = build_schedule(pl);
+  if (rc == 0) rc = build_local_tables(pl);
+  if (rc == 0 && hipGetDevice(&pl->device) != hipSuccess) {
+    g_detail = "hipGetDevice failed";
+    rc = DSD_EHIP;
+  }
+  if (rc == 0) rc = resolve_scratch(pl->device, &pl->scratch);
   if (rc == 0 && (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess)) {
     g_detail = "hipEventCreate failed";
     rc = DSD_EHIP;
@@ -2006,54 +2139,48 @@ int dsd_local_solve(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, i
   }
   pl->stream = (hipStream_t)stream;
   CHK(ensure_pools(pl));
-  const SubDesc& S = pl->subs[sub];
-  const long long off = S.vec_off * pl->kmax;
-  hipStream_t st = pl->stream;
-  if (pl->solver == 2 || pl->chain_steps) {
-    std::vector<BcrJob> bj;
-    pl->bcr_single.clear();
-    solve_jobs(pl, std::vector<int2>{make_int2(sub, 0)}, bj, pl->bcr_single);
-    CHK(bcr_check_jobs(pl, bj));
-    CHK(upload(pl->d_single_job, bj));
-    const BcrJob* jb = pl->d_single_job.as<BcrJob>();
-    if (pl->c64) {
-      launch_pack_local<float>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<float>>() + off,
-                               S.nloc, nrhs, pl->kmax, st);
-      for (const BcrLaunch& L : pl->bcr_single) bcr_phase<float>(pl, jb, L, nrhs);
-      launch_unpack_local<float>(pl->d_vpool.as<cpx<float>>() + off, (cpx<double>*)u_dev, S.nloc,
-                                 nrhs, pl->kmax, st);
-    } else {
-      launch_pack_local<double>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<double>>() + off,
-                                S.nloc, nrhs, pl->kmax, st);
-      for (const BcrLaunch& L : pl->bcr_single) bcr_phase<double>(pl, jb, L, nrhs);
-      launch_unpack_local<double>(pl->d_vpool.as<cpx<double>>() + off, (cpx<double>*)u_dev,
-                                  S.nloc, nrhs, pl->kmax, st);
-    }
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(st));
-    return DSD_OK;
-  }
-  std::vector<int4> jobs = {make_int4(sub, 0, 0, 0), make_int4(sub, 1, 0, 0),
-                            make_int4(sub, 0, 0, 0)};
-  CHK(upload(pl->d_single_job, jobs));
-  const int4* jb = pl->d_single_job.as<int4>();
-  if (pl->c64) {
-    launch_pack_local<float>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<float>>() + off, S.nloc,
-                             nrhs, pl->kmax, st);
-    for (int ph = 0; ph < 3; ++ph)
-      chain_phase<float>(pl, ph, jb + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2, nrhs, 0, 0);
-    launch_unpack_local<float>(pl->d_vpool.as<cpx<float>>() + off, (cpx<double>*)u_dev, S.nloc,
-                               nrhs, pl->kmax, st);
-  } else {
-    launch_pack_local<double>((const cpx<double>*)r_dev, pl->d_rpool.as<cpx<double>>() + off,
-                              S.nloc, nrhs, pl->kmax, st);
-    for (int ph = 0; ph < 3; ++ph)
-      chain_phase<double>(pl, ph, jb + (ph == 1 ? 2 : 0), ph == 1 ? 1 : 2, nrhs, 0, 0);
-    launch_unpack_local<double>(pl->d_vpool.as<cpx<double>>() + off, (cpx<double>*)u_dev, S.nloc,
-                                nrhs, pl->kmax, st);
-  }
+  const long long off = pl->subs[sub].vec_off * pl->kmax;
+  if (pl->c64)
+    local_solve_any<float>(pl, sub, r_dev, u_dev, nrhs, pl->d_rpool.as<cpx<float>>() + off,
+                           pl->d_vpool.as<cpx<float>>() + off, true);
+  else
+    local_solve_any<double>(pl, sub, r_dev, u_dev, nrhs, pl->d_rpool.as<cpx<double>>() + off,
+                            pl->d_vpool.as<cpx<double>>() + off, true);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
+  time_flush(pl);
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return DSD_OK;
+}
+
+int dsd_local_solve_noalloc(dsd_plan* pl, int sub, const double* r_dev, double* u_dev,
+                            int nrhs, void* stream) {
+  g_detail.clear();
+  if (!pl || sub < 0 || sub >= pl->S || nrhs <= 0 || nrhs > pl->kmax || !r_dev || !u_dev) {
+    g_detail = "local_solve_noalloc: bad subdomain, nrhs or pointer";
+    return DSD_EINVAL;
+  }
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != pl->device || !pl->scratch) {
+    g_detail = "local_solve_noalloc: the current device is not the plan's device";
+    return DSD_EINVAL;
+  }
+  const size_t part = align256((size_t)pl->subs[sub].nloc * nrhs * tsize(pl));
+  if (2 * part > (size_t)DSD_NOALLOC_SCRATCH_BYTES) {
+    g_detail = "local_solve_noalloc: 2 x N_loc x nrhs values (" + std::to_string(2 * part) +
+               " bytes) exceed the static scratch of " +
+               std::to_string((long long)DSD_NOALLOC_SCRATCH_BYTES) + " bytes";
+    return DSD_EINVAL;
+  }
+  pl->stream = (hipStream_t)stream;
+  unsigned char* base = static_cast<unsigned char*>(pl->scratch);
+  if (pl->c64)
+    local_solve_any<float>(pl, sub, r_dev, u_dev, nrhs, reinterpret_cast<cpx<float>*>(base),
+                           reinterpret_cast<cpx<float>*>(base + part), false);
+  else
+    local_solve_any<double>(pl, sub, r_dev, u_dev, nrhs, reinterpret_cast<cpx<double>*>(base),
+                            reinterpret_cast<cpx<double>*>(base + part), false);
+  HIPCHK(hipGetLastError());
   return DSD_OK;
 }
 

@@ -108,3 +108,10 @@ def test_bench_band_work_matches_the_stated_c2_figures():
     fac = b1 - vec
     assert abs(fac / 26.0e9 - 1) < 0.01 and abs(vec / 0.28e9 - 1) < 0.03
     assert abs(f1 / 2.59e10 - 1) < 0.01 and f2 == 2 * f1
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    from paper_2002_05327_amd import _lib
+    hdr = open(os.path.join(ROOT, "include", "dsweep.h")).read()
+    m = re.search(r"#define DSD_NOALLOC_SCRATCH_BYTES \((\d+)LL << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
