@@ -79,6 +79,11 @@ typedef struct {
                                memory; every reduction level is one batched launch);
                             3: the LDL^T chains of 1 with one launch per block step,
                                every chain of a launch group in it (wide blocks);
+                            4: nested dissection (multifrontal): recursive bisection of
+                               the subdomain box, the Schur complements of the
+                               separators stored inverted, the separators above a
+                               depth applied as one dense inverse, one workgroup per
+                               remaining subtree (about a quarter of the band factor);
                             0: 2 unless its factor would exceed 45% of device memory,
                                else 3 for blocks of 512 cells or more, else 1.          */
   int dense_top;         /* block cyclic reduction only: the reduction stops at the first
@@ -93,6 +98,11 @@ typedef struct {
                             along which the L1 distance from (+1,+1,+1) never decreases.
                             Transfers are routed by Rules 4.1/4.2 over the chosen order.
                             2D has one order (must be 0).                               */
+  int nd_leaf;           /* nested dissection: boxes of at most this many cells are not
+                            bisected further (0: 16)                                   */
+  int nd_top_cells;      /* nested dissection: the separators of the shallowest depths
+                            whose cells total at most this many form the dense top
+                            (0: 1200; at most 5000)                                    */
 } dsd_params;
 
 /*
@@ -116,8 +126,8 @@ int dsd_plan_info(const dsd_plan* plan, long long* n_global, int* n_subdomains,
                   long long* factor_bytes, long long* workspace_bytes);
 
 /* Local solver in use: 1 = twisted block LDL^T chains, 2 = block cyclic reduction,
- * 3 = LDL^T chains with one launch per block step (dsd_params.local_solver after
- * the automatic choice); negative on a NULL plan. */
+ * 3 = LDL^T chains with one launch per block step, 4 = nested dissection
+ * (dsd_params.local_solver after the automatic choice); negative on a NULL plan. */
 int dsd_plan_local_solver(const dsd_plan* plan);
 
 /* Graph mode: when on, dsd_sweep_apply (and the preconditioner applications

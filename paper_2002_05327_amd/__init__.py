@@ -43,7 +43,7 @@ class Plan:
                  parts: Sequence[int], m: torch.Tensor, precision: str = "c64",
                  max_rhs: int = 1, rhs_per_group: int = 0, sigma0_delta: float = 60.0,
                  schedule: str = "dag", local_solver: str = "auto", dense_top: int = 0,
-                 sweep_order: str = "default"):
+                 sweep_order: str = "default", nd_leaf: int = 0, nd_top_cells: int = 0):
         self._lib = _lib.load()
         dim = len(n)
         if dim not in (2, 3) or len(parts) != dim:
@@ -58,9 +58,10 @@ class Plan:
         p.precision = {"c64": DSD_C64, "c128": DSD_C128}[precision]
         p.max_rhs, p.rhs_per_group = int(max_rhs), int(rhs_per_group)
         p.schedule = {"dag": 0, "sequential": 1, "additive": 2}[schedule]
-        p.local_solver = {"auto": 0, "chain": 1, "bcr": 2, "chain-steps": 3}[local_solver]
+        p.local_solver = {"auto": 0, "chain": 1, "bcr": 2, "chain-steps": 3, "nd": 4}[local_solver]
         p.dense_top = int(dense_top)
         p.sweep_order = {"default": 0, "l1": 1}[sweep_order]
+        p.nd_leaf, p.nd_top_cells = int(nd_leaf), int(nd_top_cells)
         self.params = p
         self.n, self.dim, self.pml, self.omega = tuple(int(k) for k in n), dim, int(pml), omega
         self.precision, self.max_rhs = precision, int(max_rhs)
@@ -239,7 +240,8 @@ class Plan:
 
     @property
     def local_solver(self) -> str:
-        return {1: "chain", 2: "bcr", 3: "chain-steps"}[self._lib.dsd_plan_local_solver(self._h)]
+        return {1: "chain", 2: "bcr", 3: "chain-steps",
+                4: "nd"}[self._lib.dsd_plan_local_solver(self._h)]
 
     def timing(self, on: bool):
         check(self._lib.dsd_timing_enable(self._h, int(bool(on))), "dsd_timing_enable")

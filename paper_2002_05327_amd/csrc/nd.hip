@@ -1,0 +1,789 @@
+// Nested-dissection (multifrontal) local solver: symbolic analysis of a local
+// grid shape (host), factorisation kernels (FP64) and the subtree / dense-top
+// solve kernels (plan precision).  The layout of the tables is described in
+// nd.hpp.
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
+#include "nd.hpp"
+
+namespace dsd {
+
+static inline unsigned nd_cdiv(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+// ============================================================================
+// Analysis (host)
+// ============================================================================
+namespace {
+
+struct NdBuilder {
+  int dim;
+  int dims[3];
+  int leaf_max;
+  std::vector<NdNode>* nodes;
+
+  int index(int x, int y, int z) const { return x + dims[0] * (y + dims[1] * z); }
+
+  void box(const int* lo, const int* hi, std::vector<int>& out) const {
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) out.push_back(index(x, y, z));
+  }
+
+  // Node of box [lo, hi) and (recursively, first) its children; returns its id.
+  int build(const int* lo, const int* hi, int depth) {
+    int ext[3], a = 0;
+    long long vol = 1;
+    for (int k = 0; k < 3; ++k) {
+      ext[k] = hi[k] - lo[k];
+      vol *= ext[k];
+    }
+    for (int k = 1; k < dim; ++k)
+      if (ext[k] > ext[a]) a = k;
+    NdNode n;
+    for (int k = 0; k < 3; ++k) {
+      n.lo[k] = lo[k];
+      n.hi[k] = hi[k];
+    }
+    n.depth = depth;
+    if (vol <= leaf_max || ext[a] < 3) {
+      box(lo, hi, n.sep);
+    } else {
+      const int mid = lo[a] + ext[a] / 2;
+      int h1[3] = {hi[0], hi[1], hi[2]}, l2[3] = {lo[0], lo[1], lo[2]};
+      h1[a] = mid;
+      l2[a] = mid + 1;
+      n.child[0] = build(lo, h1, depth + 1);
+      n.child[1] = build(l2, hi, depth + 1);
+      int sl[3] = {lo[0], lo[1], lo[2]}, sh[3] = {hi[0], hi[1], hi[2]};
+      sl[a] = mid;
+      sh[a] = mid + 1;
+      box(sl, sh, n.sep);
+    }
+    // boundary: the cells just outside every face of the box
+    for (int k = 0; k < dim; ++k)
+      for (int side = 0; side < 2; ++side) {
+        const int c = side == 0 ? lo[k] - 1 : hi[k];
+        if (c < 0 || c >= dims[k]) continue;
+        int fl[3] = {lo[0], lo[1], lo[2]}, fh[3] = {hi[0], hi[1], hi[2]};
+        fl[k] = c;
+        fh[k] = c + 1;
+        box(fl, fh, n.bnd);
+      }
+    std::sort(n.bnd.begin(), n.bnd.end());
+    nodes->push_back(std::move(n));
+    const int id = (int)nodes->size() - 1;
+    for (int c : (*nodes)[id].child)
+      if (c >= 0) (*nodes)[c].parent = id;
+    return id;
+  }
+};
+
+}  // namespace
+
+NdShape nd_analyse(int dim, const int* dims, int leaf_max, int ntop_max) {
+  NdShape S;
+  S.dim = dim;
+  for (int k = 0; k < 3; ++k) S.dims[k] = k < dim ? dims[k] : 1;
+  NdBuilder b{dim, {S.dims[0], S.dims[1], S.dims[2]}, std::max(1, leaf_max), &S.nodes};
+  const int lo[3] = {0, 0, 0};
+  b.build(lo, S.dims, 0);
+  // dense top: the deepest depth whose separators (with all above) fit ntop_max
+  int maxd = 0;
+  for (const NdNode& n : S.nodes) maxd = std::max(maxd, n.depth);
+  std::vector<long long> at(maxd + 1, 0);
+  for (const NdNode& n : S.nodes) at[n.depth] += (long long)n.sep.size();
+  long long cum = 0;
+  S.dtop = 0;
+  for (int d = 0; d <= maxd; ++d) {
+    if (cum + at[d] > ntop_max) break;
+    cum += at[d];
+    S.dtop = d + 1;
+  }
+  const int N = (int)S.nodes.size();
+  for (int i = 0; i < N; ++i) {
+    NdNode& n = S.nodes[i];
+    n.top = n.depth < S.dtop;
+    if (n.top) S.top_cells.insert(S.top_cells.end(), n.sep.begin(), n.sep.end());
+  }
+  for (int i = 0; i < N; ++i) {
+    NdNode& n = S.nodes[i];
+    if (!n.top && (n.parent < 0 || S.nodes[n.parent].top)) {
+      n.subtree = (int)S.roots.size();
+      n.level = 0;
+      S.roots.push_back(i);
+    }
+  }
+  // parents come after their children in postorder: walk backwards
+  for (int i = N - 1; i >= 0; --i) {
+    NdNode& n = S.nodes[i];
+    if (n.top) continue;
+    if (n.subtree < 0) {
+      n.subtree = S.nodes[n.parent].subtree;
+      n.level = S.nodes[n.parent].level + 1;
+    }
+    S.nlev = std::max(S.nlev, n.level + 1);
+  }
+  long long fo = 0, uo = 0;
+  for (NdNode& n : S.nodes) {
+    if (n.top) continue;
+    const long long ns = (long long)n.sep.size(), nb = (long long)n.bnd.size();
+    n.fac = fo;
+    fo += nb * ns + ns * (ns + nb);
+    n.upd = uo;
+    uo += nb;
+    S.max_ns = std::max(S.max_ns, (int)ns);
+    S.max_nbd = std::max(S.max_nbd, (int)nb);
+    S.max_nf = std::max(S.max_nf, (int)(ns + nb));
+  }
+  S.top_fac = fo;
+  S.fac_entries = fo + (long long)S.ntop() * S.ntop();
+  S.upd_entries = uo;
+  return S;
+}
+
+bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>& nodes,
+                      std::vector<int>& cells, std::vector<int>& maps, std::vector<int>& src,
+                      std::vector<int>& lev, std::vector<int>& levnodes) {
+  const int dim2 = 2 * S.dim;
+  const int N = (int)S.nodes.size();
+  const long long ncell = (long long)S.dims[0] * S.dims[1] * S.dims[2];
+  tab.node0 = (int)nodes.size();
+  std::vector<int> pos(ncell, -1);
+  for (int i = 0; i < N; ++i) {
+    const NdNode& n = S.nodes[i];
+    NdNodeDev d{};
+    d.ns = (int)n.sep.size();
+    d.nbd = (int)n.bnd.size();
+    d.cell = (int)cells.size();
+    cells.insert(cells.end(), n.sep.begin(), n.sep.end());
+    cells.insert(cells.end(), n.bnd.begin(), n.bnd.end());
+    d.map = (int)maps.size();
+    d.ch0 = n.child[0] >= 0 && !n.top ? tab.node0 + n.child[0] : -1;
+    d.ch1 = n.child[1] >= 0 && !n.top ? tab.node0 + n.child[1] : -1;
+    d.fac = n.fac;
+    d.upd = n.upd;
+    const int nf = d.ns + d.nbd;
+    maps.insert(maps.end(), (size_t)2 * nf, -1);
+    if (!n.top) {
+      // front position of every cell of this node's front
+      for (int p = 0; p < nf; ++p) pos[p < d.ns ? n.sep[p] : n.bnd[p - d.ns]] = p;
+      for (int c = 0; c < 2; ++c) {
+        if (n.child[c] < 0) continue;
+        const std::vector<int>& cb = S.nodes[n.child[c]].bnd;
+        for (int i2 = 0; i2 < (int)cb.size(); ++i2) {
+          const int p = pos[cb[i2]];
+          if (p < 0) return false;   // a child's boundary must lie in the parent's front
+          maps[d.map + 2 * p + c] = i2;
+        }
+      }
+      for (int p = 0; p < nf; ++p) pos[p < d.ns ? n.sep[p] : n.bnd[p - d.ns]] = -1;
+    }
+    nodes.push_back(d);
+  }
+  // top cells and the subtree-root updates that land on each of them
+  tab.top_cell = (int)cells.size();
+  cells.insert(cells.end(), S.top_cells.begin(), S.top_cells.end());
+  tab.top_src = (int)src.size();
+  const int ntop = S.ntop();
+  src.insert(src.end(), (size_t)ntop * dim2 * 2, -1);
+  for (int p = 0; p < ntop; ++p) pos[S.top_cells[p]] = p;
+  for (int r : S.roots) {
+    const std::vector<int>& rb = S.nodes[r].bnd;
+    for (int i = 0; i < (int)rb.size(); ++i) {
+      const int p = pos[rb[i]];
+      if (p < 0) return false;       // a subtree root's boundary must lie in the top
+      int k = 0;
+      while (k < dim2 && src[tab.top_src + (p * dim2 + k) * 2] >= 0) ++k;
+      if (k == dim2) return false;
+      src[tab.top_src + (p * dim2 + k) * 2] = r;
+      src[tab.top_src + (p * dim2 + k) * 2 + 1] = i;
+    }
+  }
+  // level lists of every subtree
+  tab.lev0.clear();
+  tab.nlev.clear();
+  for (size_t s = 0; s < S.roots.size(); ++s) {
+    int nl = 0;
+    for (const NdNode& n : S.nodes)
+      if (n.subtree == (int)s) nl = std::max(nl, n.level + 1);
+    tab.lev0.push_back((int)lev.size());
+    tab.nlev.push_back(nl);
+    for (int l = 0; l < nl; ++l) {
+      lev.push_back((int)levnodes.size());
+      for (int i = 0; i < N; ++i)
+        if (S.nodes[i].subtree == (int)s && S.nodes[i].level == l) levnodes.push_back(tab.node0 + i);
+    }
+    lev.push_back((int)levnodes.size());
+  }
+  return true;
+}
+
+// ============================================================================
+// Solve kernels
+// ============================================================================
+constexpr int ND_W = 4;     // waves per subtree workgroup
+constexpr int ND_TW = 4;    // waves per dense-top workgroup
+
+__device__ __forceinline__ void nd_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// XCD-aware order (grid a multiple of 8): consecutive tasks share an L2.
+__device__ __forceinline__ int nd_task(int b, int total) {
+  const int per = total >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// Forward pass of one subtree for KG right-hand sides, leaves to root:
+// front = (r on S, 0 on B) + children's updates; f_S back into R; u_B = front_B - L f_S.
+// Levels with at least ND_W nodes give every wave its own nodes; smaller levels
+// build their fronts first and share the 64-row passes over all waves.
+template <typename T, int KG>
+__global__ __launch_bounds__(64 * ND_W) void k_nd_fwd(
+    const NdSubJob* __restrict__ jobs, int njobs, int G, const NdNodeDev* __restrict__ nodes,
+    const int* __restrict__ lev, const int* __restrict__ levnodes, const int* __restrict__ cells,
+    const int* __restrict__ maps, const cpx<T>* __restrict__ fac, cpx<T>* __restrict__ rpool,
+    cpx<T>* __restrict__ upool, long long pool_stride, int nrhs, int kmax, int region) {
+  typedef cpx<T> C;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int job = Lg / G, g = Lg - (Lg / G) * G;
+  if (job >= njobs) return;
+  const NdSubJob J = jobs[job];
+  C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ U = upool + J.ubase;
+  const C* __restrict__ F = fac + J.fac;
+  const long long nloc = J.nloc;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const C zero = mk((T)0, (T)0);
+  const int q0 = g * KG;
+
+  auto build = [&](const NdNodeDev& N, C* fr) {
+    const int nf = N.ns + N.nbd;
+    const int* fc = cells + N.cell;
+    const int* mp = maps + N.map;
+    const long long u0 = N.ch0 >= 0 ? nodes[N.ch0].upd : -1;
+    const long long u1 = N.ch1 >= 0 ? nodes[N.ch1].upd : -1;
+    for (int e = lane; e < nf * KG; e += 64) {
+      const int p = e / KG, q = e - (e / KG) * KG, rq = q0 + q;
+      C v = zero;
+      if (rq < nrhs) {
+        if (p < N.ns) v = R[(long long)rq * nloc + fc[p]];
+        if (u0 >= 0) {
+          const int i = mp[2 * p];
+          if (i >= 0) v = v + U[(u0 + i) * kmax + rq];
+        }
+        if (u1 >= 0) {
+          const int i = mp[2 * p + 1];
+          if (i >= 0) v = v + U[(u1 + i) * kmax + rq];
+        }
+        if (p < N.ns) R[(long long)rq * nloc + fc[p]] = v;
+      }
+      fr[e] = v;
+    }
+  };
+  auto rows = [&](const NdNodeDev& N, const C* fr, int i0) {
+    const int i = i0 + lane;
+    if (i >= N.nbd) return;
+    const C* __restrict__ L = F + N.fac;
+    C acc[KG];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) acc[q] = fr[(N.ns + i) * KG + q];
+    for (int j = 0; j < N.ns; ++j) {
+      const C a = L[(long long)j * N.nbd + i];
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        const C y = fr[j * KG + q];
+        acc[q].re = fma(-a.re, y.re, acc[q].re);
+        acc[q].re = fma(a.im, y.im, acc[q].re);
+        acc[q].im = fma(-a.re, y.im, acc[q].im);
+        acc[q].im = fma(-a.im, y.re, acc[q].im);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+      if (q0 + q < nrhs) U[(N.upd + i) * kmax + q0 + q] = acc[q];
+  };
+  for (int l = J.nlev - 1; l >= 0; --l) {
+    const int n0 = lev[J.lev0 + l], nn = lev[J.lev0 + l + 1] - n0;
+    if (nn >= ND_W) {
+      C* fr = lds + (long long)w * region;
+      for (int k = w; k < nn; k += ND_W) {
+        const NdNodeDev N = nodes[levnodes[n0 + k]];
+        build(N, fr);
+        nd_wave_sync();
+        for (int i0 = 0; i0 < N.nbd; i0 += 64) rows(N, fr, i0);
+        nd_wave_sync();
+      }
+    } else {
+      if (w < nn) build(nodes[levnodes[n0 + w]], lds + (long long)w * region);
+      __syncthreads();
+      int it = 0;
+      for (int k = 0; k < nn; ++k) {
+        const NdNodeDev N = nodes[levnodes[n0 + k]];
+        for (int i0 = 0; i0 < N.nbd; i0 += 64, ++it)
+          if (it % ND_W == w) rows(N, lds + (long long)k * region, i0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward pass of one subtree, root to leaves: x_S = K [f_S; -x_B] with
+// K = [P | L^T] (ns x nf), f_S from R, x_B from X (ancestors, or the top).
+template <typename T, int KG>
+__global__ __launch_bounds__(64 * ND_W) void k_nd_bwd(
+    const NdSubJob* __restrict__ jobs, int njobs, int G, const NdNodeDev* __restrict__ nodes,
+    const int* __restrict__ lev, const int* __restrict__ levnodes, const int* __restrict__ cells,
+    const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ xpool,
+    long long pool_stride, int nrhs, int kmax, int region) {
+  typedef cpx<T> C;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int job = Lg / G, g = Lg - (Lg / G) * G;
+  if (job >= njobs) return;
+  const NdSubJob J = jobs[job];
+  const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
+  const C* __restrict__ F = fac + J.fac;
+  const long long nloc = J.nloc;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const C zero = mk((T)0, (T)0);
+  const int q0 = g * KG;
+  (void)kmax;
+
+  auto build = [&](const NdNodeDev& N, C* v) {
+    const int nf = N.ns + N.nbd;
+    const int* fc = cells + N.cell;
+    for (int e = lane; e < nf * KG; e += 64) {
+      const int p = e / KG, q = e - (e / KG) * KG, rq = q0 + q;
+      C x = zero;
+      if (rq < nrhs) x = p < N.ns ? R[(long long)rq * nloc + fc[p]] : -X[(long long)rq * nloc + fc[p]];
+      v[e] = x;
+    }
+  };
+  auto rows = [&](const NdNodeDev& N, const C* v, int i0) {
+    const int i = i0 + lane;
+    if (i >= N.ns) return;
+    const int nf = N.ns + N.nbd;
+    const C* __restrict__ K = F + N.fac + (long long)N.nbd * N.ns;
+    C acc[KG];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) acc[q] = zero;
+    for (int j = 0; j < nf; ++j) {
+      const C a = K[(long long)j * N.ns + i];
+#pragma unroll
+      for (int q = 0; q < KG; ++q) fma_acc(acc[q], a, v[j * KG + q]);
+    }
+    const int cell = cells[N.cell + i];
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+      if (q0 + q < nrhs) X[(long long)(q0 + q) * nloc + cell] = acc[q];
+  };
+  for (int l = 0; l < J.nlev; ++l) {
+    const int n0 = lev[J.lev0 + l], nn = lev[J.lev0 + l + 1] - n0;
+    if (nn >= ND_W) {
+      C* v = lds + (long long)w * region;
+      for (int k = w; k < nn; k += ND_W) {
+        const NdNodeDev N = nodes[levnodes[n0 + k]];
+        build(N, v);
+        nd_wave_sync();
+        for (int i0 = 0; i0 < N.ns; i0 += 64) rows(N, v, i0);
+        nd_wave_sync();
+      }
+    } else {
+      if (w < nn) build(nodes[levnodes[n0 + w]], lds + (long long)w * region);
+      __syncthreads();
+      int it = 0;
+      for (int k = 0; k < nn; ++k) {
+        const NdNodeDev N = nodes[levnodes[n0 + k]];
+        for (int i0 = 0; i0 < N.ns; i0 += 64, ++it)
+          if (it % ND_W == w) rows(N, lds + (long long)k * region, i0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Dense top: rows [64 tile, 64 tile + 64) of x_top = P_top g, g = r_top plus
+// the subtree roots' updates; the waves split the columns (each gathers its
+// own columns of g into LDS) and meet in LDS for the sum, in wave order.
+template <typename T, int KG>
+__global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
+    const NdTopJob* __restrict__ jobs, int njobs, int G, int ntiles,
+    const NdNodeDev* __restrict__ nodes, const int* __restrict__ cells,
+    const int* __restrict__ srcs, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
+    const cpx<T>* __restrict__ upool, cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs,
+    int kmax, int cwmax) {
+  typedef cpx<T> C;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int per = G * ntiles;
+  const int job = Lg / per;
+  if (job >= njobs) return;
+  const int rem = Lg - job * per;
+  const int g = rem / ntiles, tile = rem - (rem / ntiles) * ntiles;
+  const NdTopJob J = jobs[job];
+  const int ntop = J.ntop;
+  if (tile * 64 >= ntop) return;
+  const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
+  const C* __restrict__ U = upool + J.ubase;
+  const C* __restrict__ P = fac + J.fac;
+  const int* tc = cells + J.cell;
+  const int* sr = srcs + J.src;
+  const long long nloc = J.nloc;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const C zero = mk((T)0, (T)0);
+  const int q0 = g * KG;
+  const int cw = (ntop + ND_TW - 1) / ND_TW;
+  const int c0 = min(ntop, w * cw), c1 = min(ntop, c0 + cw);
+  C* gl = lds + (long long)w * cwmax * KG;
+  for (int e = lane; e < (c1 - c0) * KG; e += 64) {
+    const int j = c0 + e / KG, q = e - (e / KG) * KG, rq = q0 + q;
+    C v = zero;
+    if (rq < nrhs) {
+      v = R[(long long)rq * nloc + tc[j]];
+      for (int k = 0; k < J.dim2; ++k) {
+        const int r = sr[(j * J.dim2 + k) * 2];
+        if (r < 0) break;
+        const long long o = nodes[J.node0 + r].upd + sr[(j * J.dim2 + k) * 2 + 1];
+        v = v + U[o * kmax + rq];
+      }
+    }
+    gl[e] = v;
+  }
+  nd_wave_sync();
+  const int i = tile * 64 + lane;
+  C acc[KG];
+#pragma unroll
+  for (int q = 0; q < KG; ++q) acc[q] = zero;
+  if (i < ntop) {
+    for (int j = c0; j < c1; ++j) {
+      const C a = P[(long long)j * ntop + i];
+#pragma unroll
+      for (int q = 0; q < KG; ++q) fma_acc(acc[q], a, gl[(j - c0) * KG + q]);
+    }
+  }
+  C* part = lds + (long long)ND_TW * cwmax * KG;
+  if (w > 0) {
+#pragma unroll
+    for (int q = 0; q < KG; ++q) part[((w - 1) * KG + q) * 64 + lane] = acc[q];
+  }
+  __syncthreads();
+  if (w == 0 && i < ntop) {
+    for (int o = 1; o < ND_TW; ++o)
+#pragma unroll
+      for (int q = 0; q < KG; ++q) acc[q] = acc[q] + part[((o - 1) * KG + q) * 64 + lane];
+    const int cell = tc[i];
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+      if (q0 + q < nrhs) X[(long long)(q0 + q) * nloc + cell] = acc[q];
+  }
+}
+
+template <typename T>
+size_t nd_sub_lds_bytes(int max_nf, int kg) {
+  return (size_t)ND_W * std::max(1, max_nf) * kg * sizeof(cpx<T>);
+}
+
+static size_t nd_top_lds_bytes(size_t ts, int max_ntop, int kg) {
+  const int cw = (max_ntop + ND_TW - 1) / ND_TW;
+  return ((size_t)ND_TW * cw + (size_t)(ND_TW - 1) * 64) * kg * ts;
+}
+
+template <typename T>
+int nd_kg(int max_nf, int kg, size_t lds_cap) {
+  int k = 16;
+  while (k > kg && k > 1) k >>= 1;
+  while (k > 1 && nd_sub_lds_bytes<T>(max_nf, k) > lds_cap) k >>= 1;
+  return nd_sub_lds_bytes<T>(max_nf, k) <= lds_cap ? k : 0;
+}
+
+static unsigned nd_grid(long long tasks) { return (unsigned)(((tasks + 7) / 8) * 8); }
+
+template <typename T, int KG>
+static void launch_fwd_k(const NdSubJob* jobs, int njobs, const NdNodeDev* nodes, const int* lev,
+                         const int* levnodes, const int* cells, const int* maps, const cpx<T>* fac,
+                         cpx<T>* rpool, cpx<T>* upool, long long ps, int nrhs, int kmax,
+                         int max_nf, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  hipLaunchKernelGGL((k_nd_fwd<T, KG>), dim3(nd_grid((long long)njobs * G)), dim3(64 * ND_W),
+                     nd_sub_lds_bytes<T>(max_nf, KG), s, jobs, njobs, G, nodes, lev, levnodes,
+                     cells, maps, fac, rpool, upool, ps, nrhs, kmax, max_nf * KG);
+}
+
+template <typename T>
+void launch_nd_fwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nodes,
+                   const int* lev, const int* levnodes, const int* cells, const int* maps,
+                   const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool, long long pool_stride,
+                   int nrhs, int kmax, int max_nf, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0) return;
+#define ND_FWD(K) launch_fwd_k<T, K>(jobs, njobs, nodes, lev, levnodes, cells, maps, fac, rpool, \
+                                     upool, pool_stride, nrhs, kmax, max_nf, s)
+  switch (kg) {
+    case 16: ND_FWD(16); break;
+    case 8: ND_FWD(8); break;
+    case 4: ND_FWD(4); break;
+    case 2: ND_FWD(2); break;
+    default: ND_FWD(1); break;
+  }
+#undef ND_FWD
+}
+
+template <typename T, int KG>
+static void launch_bwd_k(const NdSubJob* jobs, int njobs, const NdNodeDev* nodes, const int* lev,
+                         const int* levnodes, const int* cells, const cpx<T>* fac,
+                         const cpx<T>* rpool, cpx<T>* xpool, long long ps, int nrhs, int kmax,
+                         int max_nf, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  hipLaunchKernelGGL((k_nd_bwd<T, KG>), dim3(nd_grid((long long)njobs * G)), dim3(64 * ND_W),
+                     nd_sub_lds_bytes<T>(max_nf, KG), s, jobs, njobs, G, nodes, lev, levnodes,
+                     cells, fac, rpool, xpool, ps, nrhs, kmax, max_nf * KG);
+}
+
+template <typename T>
+void launch_nd_bwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nodes,
+                   const int* lev, const int* levnodes, const int* cells, const cpx<T>* fac,
+                   const cpx<T>* rpool, cpx<T>* xpool, long long pool_stride, int nrhs, int kmax,
+                   int max_nf, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0) return;
+#define ND_BWD(K) launch_bwd_k<T, K>(jobs, njobs, nodes, lev, levnodes, cells, fac, rpool, xpool, \
+                                     pool_stride, nrhs, kmax, max_nf, s)
+  switch (kg) {
+    case 16: ND_BWD(16); break;
+    case 8: ND_BWD(8); break;
+    case 4: ND_BWD(4); break;
+    case 2: ND_BWD(2); break;
+    default: ND_BWD(1); break;
+  }
+#undef ND_BWD
+}
+
+template <typename T, int KG>
+static void launch_top_k(const NdTopJob* jobs, int njobs, const NdNodeDev* nodes, const int* cells,
+                         const int* src, const cpx<T>* fac, const cpx<T>* rpool,
+                         const cpx<T>* upool, cpx<T>* xpool, long long ps, int nrhs, int kmax,
+                         int max_ntop, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  const int ntiles = (max_ntop + 63) / 64;
+  const int cwmax = (max_ntop + ND_TW - 1) / ND_TW;
+  hipLaunchKernelGGL((k_nd_top<T, KG>), dim3(nd_grid((long long)njobs * G * ntiles)),
+                     dim3(64 * ND_TW), nd_top_lds_bytes(sizeof(cpx<T>), max_ntop, KG), s, jobs,
+                     njobs, G, ntiles, nodes, cells, src, fac, rpool, upool, xpool, ps, nrhs, kmax,
+                     cwmax);
+}
+
+template <typename T>
+void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const NdNodeDev* nodes,
+                   const int* cells, const int* src, const cpx<T>* fac, const cpx<T>* rpool,
+                   const cpx<T>* upool, cpx<T>* xpool, long long pool_stride, int nrhs, int kmax,
+                   int max_ntop, hipStream_t s) {
+  if (njobs <= 0 || nrhs <= 0 || max_ntop <= 0) return;
+  // the largest RHS group (<= kg) whose gathered columns fit the LDS
+  int k = 16;
+  while (k > kg && k > 1) k >>= 1;
+  while (k > 1 && nd_top_lds_bytes(sizeof(cpx<T>), max_ntop, k) > 160 * 1024) k >>= 1;
+#define ND_TOP(K) launch_top_k<T, K>(jobs, njobs, nodes, cells, src, fac, rpool, upool, xpool, \
+                                     pool_stride, nrhs, kmax, max_ntop, s)
+  switch (k) {
+    case 16: ND_TOP(16); break;
+    case 8: ND_TOP(8); break;
+    case 4: ND_TOP(4); break;
+    case 2: ND_TOP(2); break;
+    default: ND_TOP(1); break;
+  }
+#undef ND_TOP
+}
+
+// LDS needed by the dense top for a given RHS group (1 if even that does not fit)
+size_t nd_top_lds_need(size_t ts, int max_ntop) { return nd_top_lds_bytes(ts, max_ntop, 1); }
+
+// ============================================================================
+// Factorisation kernels (FP64)
+// ============================================================================
+// Entry (ci, cj) of the J-scaled local operator: the diagonal, or the face
+// coupling stored at the lower-indexed cell of a neighbour pair.
+__device__ inline cpx<double> nd_coef(int ci, int cj, const int* dims, long long coef,
+                                      const cpx<double>* diag, const cpx<double>* cx,
+                                      const cpx<double>* cy, const cpx<double>* cz) {
+  if (ci == cj) return diag[coef + ci];
+  const int lo = min(ci, cj), d = max(ci, cj) - lo;
+  const int nx = dims[0], ny = dims[1];
+  if (d == 1 && lo % nx != nx - 1) return cx[coef + lo];
+  if (d == nx && (lo / nx) % ny != ny - 1) return cy[coef + lo];
+  if (d == nx * ny) return cz[coef + lo];
+  return mk(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(256) void k_nd_front(const NdFrontJob* __restrict__ jobs,
+                                                  const NdNodeDev* __restrict__ nodes,
+                                                  const int* __restrict__ cells,
+                                                  const int* __restrict__ maps,
+                                                  const cpx<double>* diag, const cpx<double>* cx,
+                                                  const cpx<double>* cy, const cpx<double>* cz,
+                                                  cpx<double>* W) {
+  const NdFrontJob J = jobs[blockIdx.y];
+  const NdNodeDev N = nodes[J.node];
+  const int nf = N.ns + N.nbd;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)nf * nf) return;
+  const int p = (int)(e % nf), q = (int)(e / nf);
+  const int* fc = cells + N.cell;
+  cpx<double> v = mk(0.0, 0.0);
+  if (p < N.ns || q < N.ns) v = nd_coef(fc[p], fc[q], J.dims, J.coef, diag, cx, cy, cz);
+  const int* mp = maps + N.map;
+  if (N.ch0 >= 0) {
+    const int i = mp[2 * p], j = mp[2 * q];
+    if (i >= 0 && j >= 0) {
+      const NdNodeDev C0 = nodes[N.ch0];
+      const int f0 = C0.ns + C0.nbd;
+      v = v + W[J.F0 + (C0.ns + i) + (long long)(C0.ns + j) * f0];
+    }
+  }
+  if (N.ch1 >= 0) {
+    const int i = mp[2 * p + 1], j = mp[2 * q + 1];
+    if (i >= 0 && j >= 0) {
+      const NdNodeDev C1 = nodes[N.ch1];
+      const int f1 = C1.ns + C1.nbd;
+      v = v + W[J.F1 + (C1.ns + i) + (long long)(C1.ns + j) * f1];
+    }
+  }
+  W[J.F + p + (long long)q * nf] = v;
+}
+
+void launch_nd_front(const NdFrontJob* jobs, int njobs, int max_nf, const NdNodeDev* nodes,
+                     const int* cells, const int* maps, const cpx<double>* diag,
+                     const cpx<double>* cx, const cpx<double>* cy, const cpx<double>* cz,
+                     cpx<double>* work, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_nd_front, dim3(nd_cdiv((long long)max_nf * max_nf, 256), njobs), dim3(256),
+                     0, s, jobs, nodes, cells, maps, diag, cx, cy, cz, work);
+}
+
+__global__ __launch_bounds__(256) void k_nd_top_asm(const NdTopAsmJob* __restrict__ jobs,
+                                                    const NdNodeDev* __restrict__ nodes,
+                                                    const int* __restrict__ cells,
+                                                    const int* __restrict__ srcs,
+                                                    const long long* __restrict__ fo,
+                                                    const cpx<double>* diag, const cpx<double>* cx,
+                                                    const cpx<double>* cy, const cpx<double>* cz,
+                                                    cpx<double>* W) {
+  const NdTopAsmJob J = jobs[blockIdx.y];
+  const int n = J.ntop;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int p = (int)(e % n), q = (int)(e / n);
+  const int* tc = cells + J.cell;
+  const int* sr = srcs + J.src;
+  cpx<double> v = nd_coef(tc[p], tc[q], J.dims, J.coef, diag, cx, cy, cz);
+  // update matrices of the subtree roots whose boundaries hold both cells
+  for (int a = 0; a < J.dim2; ++a) {
+    const int rp = sr[(p * J.dim2 + a) * 2];
+    if (rp < 0) break;
+    for (int b = 0; b < J.dim2; ++b) {
+      const int rq = sr[(q * J.dim2 + b) * 2];
+      if (rq < 0) break;
+      if (rq != rp) continue;
+      const NdNodeDev N = nodes[J.node0 + rp];
+      const int nf = N.ns + N.nbd;
+      const int i = sr[(p * J.dim2 + a) * 2 + 1], j = sr[(q * J.dim2 + b) * 2 + 1];
+      v = v + W[fo[J.fo + rp] + (N.ns + i) + (long long)(N.ns + j) * nf];
+    }
+  }
+  W[J.T + p + (long long)q * n] = v;
+}
+
+void launch_nd_top_asm(const NdTopAsmJob* jobs, int njobs, int max_ntop, const NdNodeDev* nodes,
+                       const int* cells, const int* src, const long long* fo,
+                       const cpx<double>* diag, const cpx<double>* cx, const cpx<double>* cy,
+                       const cpx<double>* cz, cpx<double>* work, hipStream_t s) {
+  if (njobs <= 0 || max_ntop <= 0) return;
+  hipLaunchKernelGGL(k_nd_top_asm, dim3(nd_cdiv((long long)max_ntop * max_ntop, 256), njobs),
+                     dim3(256), 0, s, jobs, nodes, cells, src, fo, diag, cx, cy, cz, work);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_copy(const NdCopyJob* __restrict__ jobs, cpx<double>* W,
+                                                 cpx<T>* fac) {
+  const NdCopyJob J = jobs[blockIdx.y];
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)J.rows * J.cols) return;
+  const int i = (int)(e % J.rows), j = (int)(e / J.rows);
+  const long long s = J.trans ? J.src + j + (long long)i * J.ld_src : J.src + i + (long long)j * J.ld_src;
+  const long long d = J.dst + i + (long long)j * J.ld_dst;
+  if (J.to_fac) fac[d] = cvt<T>(W[s]);
+  else W[d] = W[s];
+}
+
+template <typename T>
+void launch_nd_copy(const NdCopyJob* jobs, int njobs, int max_rows, int max_cols,
+                    cpx<double>* work, cpx<T>* fac, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_nd_copy<T>, dim3(nd_cdiv((long long)max_rows * max_cols, 256), njobs),
+                     dim3(256), 0, s, jobs, work, fac);
+}
+
+// C = beta C + alpha A B on 16 x 16 output tiles, 16-deep slices of A and B staged in LDS.
+__global__ __launch_bounds__(256) void k_nd_gemm(const NdGemmJob* __restrict__ jobs,
+                                                 cpx<double>* W) {
+  const NdGemmJob J = jobs[blockIdx.z];
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  if (i0 >= J.m || j0 >= J.n) return;
+  __shared__ cpx<double> As[16][17], Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  cpx<double> acc = mk(0.0, 0.0);
+  for (int k0 = 0; k0 < J.k; k0 += 16) {
+    As[ty][tx] = (i0 + tx < J.m && k0 + ty < J.k)
+                     ? W[J.a + (i0 + tx) + (long long)(k0 + ty) * J.lda] : mk(0.0, 0.0);
+    Bs[ty][tx] = (k0 + tx < J.k && j0 + ty < J.n)
+                     ? W[J.b + (k0 + tx) + (long long)(j0 + ty) * J.ldb] : mk(0.0, 0.0);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) fma_acc(acc, As[kk][tx], Bs[ty][kk]);
+    __syncthreads();
+  }
+  const int i = i0 + tx, j = j0 + ty;
+  if (i < J.m && j < J.n) {
+    const long long o = J.c + i + (long long)j * J.ldc;
+    const cpx<double> r = J.alpha * acc;
+    W[o] = J.beta ? W[o] + r : r;
+  }
+}
+
+void launch_nd_gemm(const NdGemmJob* jobs, int njobs, int max_m, int max_n, cpx<double>* work,
+                    hipStream_t s) {
+  if (njobs <= 0 || max_m <= 0 || max_n <= 0) return;
+  hipLaunchKernelGGL(k_nd_gemm, dim3(nd_cdiv(max_m, 16), nd_cdiv(max_n, 16), njobs), dim3(256), 0,
+                     s, jobs, work);
+}
+
+#define ND_INST(T)                                                                              \
+  template void launch_nd_fwd<T>(int, const NdSubJob*, int, const NdNodeDev*, const int*,        \
+                                 const int*, const int*, const int*, const cpx<T>*, cpx<T>*,      \
+                                 cpx<T>*, long long, int, int, int, hipStream_t);                \
+  template void launch_nd_bwd<T>(int, const NdSubJob*, int, const NdNodeDev*, const int*,        \
+                                 const int*, const int*, const cpx<T>*, const cpx<T>*, cpx<T>*,   \
+                                 long long, int, int, int, hipStream_t);                         \
+  template void launch_nd_top<T>(int, const NdTopJob*, int, const NdNodeDev*, const int*,        \
+                                 const int*, const cpx<T>*, const cpx<T>*, const cpx<T>*,         \
+                                 cpx<T>*, long long, int, int, int, hipStream_t);                \
+  template size_t nd_sub_lds_bytes<T>(int, int);                                                 \
+  template int nd_kg<T>(int, int, size_t);                                                       \
+  template void launch_nd_copy<T>(const NdCopyJob*, int, int, int, cpx<double>*, cpx<T>*,       \
+                                  hipStream_t);
+
+ND_INST(float)
+ND_INST(double)
+
+}  // namespace dsd

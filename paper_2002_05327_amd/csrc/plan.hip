@@ -14,6 +14,7 @@
 
 #include "dsweep.h"
 #include "kernels.hpp"
+#include "nd.hpp"
 
 using namespace dsd;
 
@@ -190,6 +191,24 @@ struct dsd_plan {
   Buf d_rpool, d_vpool, d_members, d_jobs2, d_jobs1, d_edges, d_erange;
   Buf d_part_of[3], d_axparts[3];
   Buf d_subs_local, d_local_jobs;
+  // nested dissection (solver 4): shapes, device tables, per launch group jobs
+  struct NdLaunch {
+    int sub_off = 0, nsub = 0;   // subtree jobs (d_nd_sub)
+    int top_off = 0, ntop = 0;   // dense-top jobs (d_nd_top)
+    int max_nf = 0, max_ntop = 0;
+    double fwd_bytes = 0, bwd_bytes = 0, top_bytes = 0;   // factor bytes of each launch
+    double cells = 0;            // local cells of the members (vector traffic per RHS)
+    long long upd = 0;           // update-vector entries per RHS of the members
+  };
+  std::vector<NdShape> nd_shapes;
+  std::vector<NdShapeTab> nd_tabs;
+  std::vector<int> nd_shape_of;                      // per subdomain
+  std::vector<NdLaunch> nd_launch;                   // per launch group
+  std::vector<NdLaunch> nd_local;                    // per subdomain (local solves)
+  Buf d_nd_nodes, d_nd_cells, d_nd_maps, d_nd_src, d_nd_lev, d_nd_levnodes;
+  Buf d_nd_sub, d_nd_top, d_upool;
+  long long nd_upd_max = 0;                          // entries per RHS of the update pool
+  int nd_max_nf = 0, nd_max_ntop = 0;
   // Krylov workspace
   Buf d_V, d_Z, d_w, d_r, d_xa, d_ba, d_part, d_h1, d_h2, d_hn, d_scal, d_idx, d_coef;
   int kr_restart = 0, kr_k = 0;
@@ -350,10 +369,13 @@ void solve_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<Bc
   else chain_step_jobs(pl, mem, jobs, out);
 }
 
-// Solve-job tables of the cyclic reduction (or of the chain block steps) for
-// every launch group.
+int build_nd_jobs(dsd_plan* pl);
+
+// Solve-job tables of the cyclic reduction (or of the chain block steps, or
+// of the nested dissection) for every launch group.
 int build_bcr_jobs(dsd_plan* pl) {
   pl->bcr_launch.clear();
+  if (pl->solver == 4) return build_nd_jobs(pl);
   if (pl->solver != 2 && !pl->chain_steps) return 0;
   std::vector<BcrJob> bj;
   for (auto& grp : pl->groups) {
@@ -858,6 +880,7 @@ int build_local_tables(dsd_plan* pl) {
   for (SubDesc& S : sl) S.vec_off = 0;
   CHK(upload(pl->d_subs_local, sl));
   pl->local_launch.assign(pl->S, {});
+  if (pl->solver == 4) return 0;   // nested dissection: nd_local (build_nd_jobs)
   if (pl->solver != 2 && !pl->chain_steps) {
     // chains: per subdomain {sub, top half}, {sub, bottom half} (forward and
     // backward phases) and {sub, middle} (the middle block)
@@ -1100,6 +1123,361 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs, bool loc
   return 0;
 }
 
+// ------------------------------------------- nested dissection (local solver 4)
+// Analysis of every distinct local grid shape, the factor layout (per
+// subdomain: the nodes' L and K blocks, then P_top) and the device tables.
+int nd_setup(dsd_plan* pl) {
+  const dsd_params& q = pl->prm;
+  const int leaf = q.nd_leaf > 0 ? q.nd_leaf : 16;
+  const int ntop_max = q.nd_top_cells > 0 ? q.nd_top_cells : 1200;
+  std::map<std::tuple<int, int, int>, int> shape_id;
+  pl->nd_shapes.clear();
+  pl->nd_shape_of.assign(pl->S, 0);
+  for (int s = 0; s < pl->S; ++s) {
+    const SubDesc& S = pl->subs[s];
+    const auto key = std::make_tuple(S.dims[0], S.dims[1], S.dims[2]);
+    auto it = shape_id.find(key);
+    if (it == shape_id.end()) {
+      it = shape_id.emplace(key, (int)pl->nd_shapes.size()).first;
+      pl->nd_shapes.push_back(nd_analyse(pl->dim, S.dims, leaf, ntop_max));
+    }
+    pl->nd_shape_of[s] = it->second;
+  }
+  std::vector<NdNodeDev> nodes;
+  std::vector<int> cells, maps, src, lev, levnodes;
+  pl->nd_tabs.assign(pl->nd_shapes.size(), NdShapeTab{});
+  pl->nd_max_nf = pl->nd_max_ntop = 0;
+  for (size_t k = 0; k < pl->nd_shapes.size(); ++k) {
+    const NdShape& sh = pl->nd_shapes[k];
+    if (!nd_append_tables(sh, pl->nd_tabs[k], nodes, cells, maps, src, lev, levnodes)) {
+      g_detail = "internal error: nested-dissection tables inconsistent";
+      return DSD_EINVAL;
+    }
+    pl->nd_max_nf = std::max(pl->nd_max_nf, sh.max_nf);
+    pl->nd_max_ntop = std::max(pl->nd_max_ntop, sh.ntop());
+  }
+  if (pl->nd_max_ntop > 5000) {
+    g_detail = "nested dissection: dense top above 5000 cells (lower nd_top_cells)";
+    return DSD_EINVAL;
+  }
+  long long foff = 0;
+  for (int s = 0; s < pl->S; ++s) {
+    pl->subs[s].fac_off = foff;
+    foff += pl->nd_shapes[pl->nd_shape_of[s]].fac_entries;
+  }
+  pl->sum_fac = foff;
+  CHK(upload(pl->d_nd_nodes, nodes));
+  CHK(upload(pl->d_nd_cells, cells));
+  CHK(upload(pl->d_nd_maps, maps));
+  CHK(upload(pl->d_nd_src, src));
+  CHK(upload(pl->d_nd_lev, lev));
+  CHK(upload(pl->d_nd_levnodes, levnodes));
+  return 0;
+}
+
+// Solve jobs of a set of members {subdomain, sweep slot}: every subtree of
+// every member, and every member's dense top.  Update vectors of member i
+// start at the sum of the earlier members' (entries x kmax).  With `local`
+// the vectors are addressed from offset 0 (vbase = 0) and kmax is the call's
+// right-hand-side count (passed at launch), so ubase is in entries per RHS.
+void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
+                   std::vector<NdSubJob>& sj, std::vector<NdTopJob>& tj, dsd_plan::NdLaunch& L) {
+  const double ts = (double)tsize(pl);
+  L = dsd_plan::NdLaunch{};
+  L.sub_off = (int)sj.size();
+  L.top_off = (int)tj.size();
+  long long ubase = 0;
+  for (const int2& m : mem) {
+    const SubDesc& S = pl->subs[m.x];
+    const int k = pl->nd_shape_of[m.x];
+    const NdShape& sh = pl->nd_shapes[k];
+    const NdShapeTab& tb = pl->nd_tabs[k];
+    const long long vb = local ? 0 : S.vec_off * pl->kmax;
+    const long long ub = local ? ubase : ubase * pl->kmax;
+    for (size_t r = 0; r < sh.roots.size(); ++r) {
+      NdSubJob J{};
+      J.sub = m.x;
+      J.l = m.y;
+      J.lev0 = tb.lev0[r];
+      J.nlev = tb.nlev[r];
+      J.nloc = S.nloc;
+      J.fac = S.fac_off;
+      J.vbase = vb;
+      J.ubase = ub;
+      sj.push_back(J);
+    }
+    if (sh.ntop() > 0) {
+      NdTopJob T{};
+      T.ntop = sh.ntop();
+      T.dim2 = 2 * pl->dim;
+      T.cell = tb.top_cell;
+      T.src = tb.top_src;
+      T.nloc = S.nloc;
+      T.fac = S.fac_off + sh.top_fac;
+      T.vbase = vb;
+      T.ubase = ub;
+      T.l = m.y;
+      T.node0 = tb.node0;
+      tj.push_back(T);
+    }
+    for (const NdNode& n : sh.nodes) {
+      if (n.top) continue;
+      const double ns = (double)n.sep.size(), nb = (double)n.bnd.size();
+      L.fwd_bytes += nb * ns * ts;
+      L.bwd_bytes += ns * (ns + nb) * ts;
+    }
+    L.top_bytes += (double)sh.ntop() * sh.ntop() * ts;
+    L.cells += (double)S.nloc;
+    L.max_nf = std::max(L.max_nf, sh.max_nf);
+    L.max_ntop = std::max(L.max_ntop, sh.ntop());
+    ubase += sh.upd_entries;
+  }
+  L.nsub = (int)sj.size() - L.sub_off;
+  L.ntop = (int)tj.size() - L.top_off;
+  L.upd = ubase;
+}
+
+// Job tables of every launch group and of every subdomain's local solve.
+int build_nd_jobs(dsd_plan* pl) {
+  std::vector<NdSubJob> sj;
+  std::vector<NdTopJob> tj;
+  pl->nd_launch.assign(pl->groups.size(), dsd_plan::NdLaunch{});
+  pl->nd_upd_max = 0;
+  for (size_t g = 0; g < pl->groups.size(); ++g) {
+    nd_group_jobs(pl, pl->groups[g], false, sj, tj, pl->nd_launch[g]);
+    pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_launch[g].upd);
+  }
+  pl->nd_local.assign(pl->S, dsd_plan::NdLaunch{});
+  for (int s = 0; s < pl->S; ++s) {
+    nd_group_jobs(pl, std::vector<int2>{make_int2(s, 0)}, true, sj, tj, pl->nd_local[s]);
+    pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_local[s].upd);
+  }
+  CHK(upload(pl->d_nd_sub, sj));
+  CHK(upload(pl->d_nd_top, tj));
+  return 0;
+}
+
+// Factorisation, bottom-up by depth over all subdomains of a chunk (FP64
+// fronts): assemble every front (original couplings of its separator plus the
+// children's update matrices), invert F_SS (Gauss-Jordan, partial pivoting),
+// L = F_BS P and the update F_BB -= L F_SB, and round L and K = [P | L^T] into
+// the factors; then assemble the dense top from the subtree roots' updates,
+// invert it and round it into the factors.
+int nd_factor(dsd_plan* pl) {
+  hipStream_t st = pl->stream;
+  CHK(pl->d_fac.alloc((size_t)pl->sum_fac * tsize(pl)));
+  const cpx<double>* cf[4] = {pl->d_lcoef64[0].as<cpx<double>>(), pl->d_lcoef64[1].as<cpx<double>>(),
+                              pl->d_lcoef64[2].as<cpx<double>>(), pl->d_lcoef64[3].as<cpx<double>>()};
+  // FP64 work per subdomain: every front, and the top matrix
+  std::vector<long long> fwork(pl->S, 0);
+  int maxdepth = 0;
+  for (int s = 0; s < pl->S; ++s) {
+    const NdShape& sh = pl->nd_shapes[pl->nd_shape_of[s]];
+    for (const NdNode& n : sh.nodes) {
+      maxdepth = std::max(maxdepth, n.depth);
+      if (!n.top) fwork[s] += (long long)(n.sep.size() + n.bnd.size()) * (n.sep.size() + n.bnd.size());
+    }
+    fwork[s] += (long long)sh.ntop() * sh.ntop();
+  }
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  const double budget = 0.4 * (double)fr / sizeof(cpx<double>);
+  int s0 = 0;
+  while (s0 < pl->S) {
+    // chunk [s0, s1): fronts and tops of its subdomains, plus per-level S and L blocks
+    int s1 = s0;
+    double need = 0;
+    while (s1 < pl->S && s1 - s0 < 255 && (s1 == s0 || need + 2.0 * fwork[s1] < budget)) {
+      need += 2.0 * fwork[s1];
+      ++s1;
+    }
+    // offsets: fronts of (sub, node), then the tops
+    std::vector<long long> fo;          // per (sub in chunk, node of its shape); -1 for top nodes
+    std::vector<int> fo_base(s1 - s0);
+    std::vector<long long> toff(s1 - s0);
+    long long w = 0;
+    for (int s = s0; s < s1; ++s) {
+      const NdShape& sh = pl->nd_shapes[pl->nd_shape_of[s]];
+      fo_base[s - s0] = (int)fo.size();
+      for (const NdNode& n : sh.nodes) {
+        if (n.top) {
+          fo.push_back(-1);
+          continue;
+        }
+        fo.push_back(w);
+        w += (long long)(n.sep.size() + n.bnd.size()) * (n.sep.size() + n.bnd.size());
+      }
+    }
+    for (int s = s0; s < s1; ++s) {
+      const NdShape& sh = pl->nd_shapes[pl->nd_shape_of[s]];
+      toff[s - s0] = w;
+      w += (long long)sh.ntop() * sh.ntop();
+    }
+    // per-level S (ns x ns) and L (nbd x ns) blocks: the largest level of the chunk
+    long long lvl_max = 0;
+    for (int d = 0; d <= maxdepth; ++d) {
+      long long e = 0;
+      for (int s = s0; s < s1; ++s)
+        for (const NdNode& n : pl->nd_shapes[pl->nd_shape_of[s]].nodes)
+          if (!n.top && n.depth == d)
+            e += (long long)n.sep.size() * (n.sep.size() + n.bnd.size());
+      lvl_max = std::max(lvl_max, e);
+    }
+    const long long sl_base = w;
+    w += lvl_max;
+    Buf work, dfo, derr, dpiv, drbuf, dj1, dj2, dj3, dj4;
+    CHK(work.alloc((size_t)w * sizeof(cpx<double>)));
+    CHK(upload(dfo, fo));
+    cpx<double>* W = work.as<cpx<double>>();
+    const NdNodeDev* dn = pl->d_nd_nodes.as<NdNodeDev>();
+    for (int d = maxdepth; d >= 0; --d) {
+      std::vector<NdFrontJob> fj;
+      std::vector<NdCopyJob> cj, sj;
+      std::vector<BcrInvJob> ij;
+      std::vector<NdGemmJob> g1, g2;
+      int max_nf = 0, max_ns = 0, max_nbd = 0;
+      long long so = sl_base;
+      for (int s = s0; s < s1; ++s) {
+        const int k = pl->nd_shape_of[s];
+        const NdShape& sh = pl->nd_shapes[k];
+        const SubDesc& S = pl->subs[s];
+        for (size_t i = 0; i < sh.nodes.size(); ++i) {
+          const NdNode& n = sh.nodes[i];
+          if (n.top || n.depth != d) continue;
+          const int ns = (int)n.sep.size(), nbd = (int)n.bnd.size(), nf = ns + nbd;
+          max_nf = std::max(max_nf, nf);
+          max_ns = std::max(max_ns, ns);
+          max_nbd = std::max(max_nbd, nbd);
+          const long long F = fo[fo_base[s - s0] + i];
+          NdFrontJob J{};
+          J.node = pl->nd_tabs[k].node0 + (int)i;
+          for (int a = 0; a < 3; ++a) J.dims[a] = S.dims[a];
+          J.coef = S.coef_off;
+          J.F = F;
+          J.F0 = n.child[0] >= 0 ? fo[fo_base[s - s0] + n.child[0]] : -1;
+          J.F1 = n.child[1] >= 0 ? fo[fo_base[s - s0] + n.child[1]] : -1;
+          fj.push_back(J);
+          const long long Sb = so, Lb = so + (long long)ns * ns;
+          so += (long long)ns * nf;
+          cj.push_back(NdCopyJob{ns, ns, nf, ns, 0, 0, F, Sb});
+          ij.push_back(BcrInvJob{ns, 0, Sb, -1});
+          g1.push_back(NdGemmJob{nbd, ns, ns, nf, ns, nbd, 0, 0, 1.0, F + ns, Sb, Lb});
+          g2.push_back(NdGemmJob{nbd, nbd, ns, nbd, nf, nf, 1, 0, -1.0, Lb,
+                                 F + (long long)ns * nf, F + ns + (long long)ns * nf});
+          const long long fb = S.fac_off + n.fac;
+          sj.push_back(NdCopyJob{nbd, ns, nbd, nbd, 0, 1, Lb, fb});
+          sj.push_back(NdCopyJob{ns, ns, ns, ns, 0, 1, Sb, fb + (long long)nbd * ns});
+          sj.push_back(NdCopyJob{ns, nbd, nbd, ns, 1, 1, Lb, fb + (long long)nbd * ns + (long long)ns * ns});
+        }
+      }
+      if (fj.empty()) continue;
+      const int nj = (int)fj.size();
+      CHK(upload(dj1, fj));
+      launch_nd_front(dj1.as<NdFrontJob>(), nj, max_nf, dn, pl->d_nd_cells.as<int>(),
+                      pl->d_nd_maps.as<int>(), cf[0], cf[1], cf[2], cf[3], W, st);
+      CHK(upload(dj2, cj));
+      if (pl->c64) launch_nd_copy<float>(dj2.as<NdCopyJob>(), nj, max_ns, max_ns, W, pl->d_fac.as<cpx<float>>(), st);
+      else launch_nd_copy<double>(dj2.as<NdCopyJob>(), nj, max_ns, max_ns, W, pl->d_fac.as<cpx<double>>(), st);
+      CHK(upload(dj3, ij));
+      CHK(derr.alloc((size_t)nj * sizeof(int)));
+      HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)nj * sizeof(int), st));
+      // inversions in launches of at most 255 (the split form serves large orders)
+      const int step = 255;
+      CHK(dpiv.alloc((size_t)std::min(nj, step) * max_ns * sizeof(int)));
+      CHK(drbuf.alloc((size_t)std::min(nj, step) * gj_rbuf_entries(max_ns) * sizeof(cpx<double>)));
+      for (int j0 = 0; j0 < nj; j0 += step) {
+        const int n = std::min(step, nj - j0);
+        if (pl->c64)
+          launch_bcr_invert<float>(dj3.as<BcrInvJob>() + j0, n, max_ns, W, pl->d_fac.as<cpx<float>>(),
+                                   derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+        else
+          launch_bcr_invert<double>(dj3.as<BcrInvJob>() + j0, n, max_ns, W, pl->d_fac.as<cpx<double>>(),
+                                    derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+      }
+      HIPCHK(hipGetLastError());
+      CHK(upload(dj4, g1));
+      launch_nd_gemm(dj4.as<NdGemmJob>(), nj, max_nbd, max_ns, W, st);
+      Buf dg2;
+      CHK(upload(dg2, g2));
+      launch_nd_gemm(dg2.as<NdGemmJob>(), nj, max_nbd, max_nbd, W, st);
+      Buf ds;
+      CHK(upload(ds, sj));
+      const int mr = std::max(max_nbd, max_ns), mc = std::max(max_nbd, max_ns);
+      if (pl->c64) launch_nd_copy<float>(ds.as<NdCopyJob>(), (int)sj.size(), mr, mc, W, pl->d_fac.as<cpx<float>>(), st);
+      else launch_nd_copy<double>(ds.as<NdCopyJob>(), (int)sj.size(), mr, mc, W, pl->d_fac.as<cpx<double>>(), st);
+      HIPCHK(hipGetLastError());
+      std::vector<int> herr(nj);
+      HIPCHK(hipMemcpyAsync(herr.data(), derr.p, nj * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int j = 0; j < nj; ++j)
+        if (herr[j]) {
+          g_detail = "singular separator block in a nested-dissection front (depth " +
+                     std::to_string(d) + ")";
+          return DSD_EPIVOT;
+        }
+    }
+    // dense tops of the chunk
+    std::vector<NdTopAsmJob> tj;
+    std::vector<BcrInvJob> ti;
+    std::vector<NdCopyJob> tc;
+    int max_top = 0;
+    for (int s = s0; s < s1; ++s) {
+      const int k = pl->nd_shape_of[s];
+      const NdShape& sh = pl->nd_shapes[k];
+      const int nt = sh.ntop();
+      if (nt == 0) continue;
+      const SubDesc& S = pl->subs[s];
+      NdTopAsmJob J{};
+      J.ntop = nt;
+      J.dim2 = 2 * pl->dim;
+      J.cell = pl->nd_tabs[k].top_cell;
+      J.src = pl->nd_tabs[k].top_src;
+      for (int a = 0; a < 3; ++a) J.dims[a] = S.dims[a];
+      J.fo = fo_base[s - s0];
+      J.node0 = pl->nd_tabs[k].node0;
+      J.coef = S.coef_off;
+      J.T = toff[s - s0];
+      tj.push_back(J);
+      ti.push_back(BcrInvJob{nt, 0, toff[s - s0], -1});
+      tc.push_back(NdCopyJob{nt, nt, nt, nt, 0, 1, toff[s - s0], S.fac_off + sh.top_fac});
+      max_top = std::max(max_top, nt);
+    }
+    if (!tj.empty()) {
+      const int nj = (int)tj.size();
+      CHK(upload(dj1, tj));
+      launch_nd_top_asm(dj1.as<NdTopAsmJob>(), nj, max_top, dn, pl->d_nd_cells.as<int>(),
+                        pl->d_nd_src.as<int>(), dfo.as<long long>(), cf[0], cf[1], cf[2], cf[3], W,
+                        st);
+      CHK(upload(dj3, ti));
+      CHK(derr.alloc((size_t)nj * sizeof(int)));
+      HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)nj * sizeof(int), st));
+      CHK(dpiv.alloc((size_t)nj * max_top * sizeof(int)));
+      CHK(drbuf.alloc((size_t)nj * gj_rbuf_entries(max_top) * sizeof(cpx<double>)));
+      if (pl->c64)
+        launch_bcr_invert<float>(dj3.as<BcrInvJob>(), nj, max_top, W, pl->d_fac.as<cpx<float>>(),
+                                 derr.as<int>(), dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+      else
+        launch_bcr_invert<double>(dj3.as<BcrInvJob>(), nj, max_top, W, pl->d_fac.as<cpx<double>>(),
+                                  derr.as<int>(), dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+      CHK(upload(dj2, tc));
+      if (pl->c64) launch_nd_copy<float>(dj2.as<NdCopyJob>(), nj, max_top, max_top, W, pl->d_fac.as<cpx<float>>(), st);
+      else launch_nd_copy<double>(dj2.as<NdCopyJob>(), nj, max_top, max_top, W, pl->d_fac.as<cpx<double>>(), st);
+      HIPCHK(hipGetLastError());
+      std::vector<int> herr(nj);
+      HIPCHK(hipMemcpyAsync(herr.data(), derr.p, nj * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int j = 0; j < nj; ++j)
+        if (herr[j]) {
+          g_detail = "singular dense top in a nested-dissection factorisation";
+          return DSD_EPIVOT;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    s0 = s1;
+  }
+  return 0;
+}
+
 int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
   hipStream_t st = pl->stream;
   const Problem& P = pl->P;
@@ -1151,6 +1529,7 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
   }
   HIPCHK(hipGetLastError());
 
+  if (pl->solver == 4) return nd_factor(pl);
   if (pl->solver == 2) return bcr_factor(pl);
   // ---- factorisation: chains of Schur complements towards the middle block
   CHK(pl->d_fac.alloc((size_t)pl->sum_fac * tsize(pl)));
@@ -1247,6 +1626,7 @@ int ensure_pools(dsd_plan* pl) {
   if (pl->d_rpool.p) return 0;
   CHK(pl->d_rpool.alloc((size_t)pl->L * pl->sum_nloc * pl->kmax * tsize(pl)));
   CHK(pl->d_vpool.alloc((size_t)pl->L * pl->sum_nloc * pl->kmax * tsize(pl)));
+  if (pl->solver == 4) CHK(pl->d_upool.alloc((size_t)pl->nd_upd_max * pl->kmax * tsize(pl)));
   return 0;
 }
 
@@ -1278,6 +1658,36 @@ void time_flush(dsd_plan* pl) {
     pl->t_solve_ms += ms;
   }
   pl->tev_used = 0;
+}
+
+// The nested-dissection solves of one launch (a launch group's members or
+// one subdomain): forward subtree passes, the dense tops, backward passes.
+// Timed launches carry their factor bytes plus the vectors (read and write of
+// the members' local cells per RHS) and 8 flops per factor entry and RHS.
+template <typename T>
+void nd_phase(dsd_plan* pl, const dsd_plan::NdLaunch& L, cpx<T>* R, cpx<T>* X, cpx<T>* U,
+              long long pool_stride, int nrhs, int kmax, bool timed) {
+  hipStream_t st = pl->stream;
+  const NdSubJob* sj = pl->d_nd_sub.as<NdSubJob>() + L.sub_off;
+  const NdTopJob* tj = pl->d_nd_top.as<NdTopJob>() + L.top_off;
+  const NdNodeDev* nodes = pl->d_nd_nodes.as<NdNodeDev>();
+  const cpx<T>* fac = pl->d_fac.as<cpx<T>>();
+  const double ts = (double)sizeof(cpx<T>), vec = 2.0 * L.cells * nrhs * ts;
+  if (timed) time_begin(pl);
+  launch_nd_fwd<T>(pl->kg, sj, L.nsub, nodes, pl->d_nd_lev.as<int>(), pl->d_nd_levnodes.as<int>(),
+                   pl->d_nd_cells.as<int>(), pl->d_nd_maps.as<int>(), fac, R, U, pool_stride, nrhs,
+                   kmax, L.max_nf, st);
+  if (timed) time_end(pl, L.fwd_bytes + vec, L.fwd_bytes / ts * nrhs * 8.0);
+  if (L.ntop > 0) {
+    if (timed) time_begin(pl);
+    launch_nd_top<T>(pl->kg, tj, L.ntop, nodes, pl->d_nd_cells.as<int>(), pl->d_nd_src.as<int>(),
+                     fac, R, U, X, pool_stride, nrhs, kmax, L.max_ntop, st);
+    if (timed) time_end(pl, L.top_bytes + vec, L.top_bytes / ts * nrhs * 8.0);
+  }
+  if (timed) time_begin(pl);
+  launch_nd_bwd<T>(pl->kg, sj, L.nsub, nodes, pl->d_nd_lev.as<int>(), pl->d_nd_levnodes.as<int>(),
+                   pl->d_nd_cells.as<int>(), fac, R, X, pool_stride, nrhs, kmax, L.max_nf, st);
+  if (timed) time_end(pl, L.bwd_bytes + vec, L.bwd_bytes / ts * nrhs * 8.0);
 }
 
 template <typename T>
@@ -1355,7 +1765,10 @@ int sweep_apply_t(dsd_plan* pl, const cpx<double>* f, cpx<double>* u, int nrhs) 
                    pl->d_erange.as<int2>() + st_.er_off, st_.max_box, nrhs, pl->kmax, vpool,
                    pool_stride, pl->d_lcoefT[0].as<cpx<T>>(), pl->d_lcoefT[1].as<cpx<T>>(),
                    pl->d_lcoefT[2].as<cpx<T>>(), pl->d_lcoefT[3].as<cpx<T>>(), rpool, st);
-    if (pl->solver == 2 || pl->chain_steps) {
+    if (pl->solver == 4) {
+      nd_phase<T>(pl, pl->nd_launch[gi], rpool, vpool, pl->d_upool.as<cpx<T>>(), pool_stride, nrhs,
+                  pl->kmax, true);
+    } else if (pl->solver == 2 || pl->chain_steps) {
       for (const BcrLaunch& L : pl->bcr_launch[gi]) bcr_phase<T>(pl, pl->d_bcr_jobs.as<BcrJob>(), L, nrhs);
     } else {
       const int4* j2 = pl->d_jobs2.as<int4>() + st_.job_off;
@@ -1717,6 +2130,9 @@ int dense_blocks(const dsd_plan* pl, int req) {
 
 int choose_kg(const dsd_plan* pl, int want) {
   const int lds = device_lds();
+  if (pl->solver == 4)
+    return pl->c64 ? nd_kg<float>(pl->nd_max_nf, want, (size_t)lds)
+                   : nd_kg<double>(pl->nd_max_nf, want, (size_t)lds);
   if (pl->chain_steps) {
     int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
     auto need = [&](int k) {
@@ -1755,8 +2171,13 @@ namespace {
 // 0, with the plan's local-solve tables.  Nothing is allocated or uploaded;
 // the launches are timed (timing mode) only when `timed`.
 template <typename T>
-void local_solve_launches(dsd_plan* pl, int sub, cpx<T>* R, cpx<T>* X, int nrhs, bool timed) {
+void local_solve_launches(dsd_plan* pl, int sub, cpx<T>* R, cpx<T>* X, cpx<T>* U, int nrhs,
+                          bool timed) {
   hipStream_t st = pl->stream;
+  if (pl->solver == 4) {   // update vectors: entries x nrhs from U
+    nd_phase<T>(pl, pl->nd_local[sub], R, X, U, 0, nrhs, nrhs, timed);
+    return;
+  }
   const SubDesc* dsub = pl->d_subs_local.as<SubDesc>();
   const cpx<T>* cpl = pl->d_lcoefT[pl->dim == 2 ? 2 : 3].as<cpx<T>>();
   const cpx<T>* fac = pl->d_fac.as<cpx<T>>();
@@ -1788,10 +2209,10 @@ void local_solve_launches(dsd_plan* pl, int sub, cpx<T>* R, cpx<T>* X, int nrhs,
 
 template <typename T>
 void local_solve_any(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, int nrhs,
-                     cpx<T>* R, cpx<T>* X, bool timed) {
+                     cpx<T>* R, cpx<T>* X, cpx<T>* U, bool timed) {
   const SubDesc& S = pl->subs[sub];
   launch_pack_local<T>((const cpx<double>*)r_dev, R, S.nloc, nrhs, pl->kmax, pl->stream);
-  local_solve_launches<T>(pl, sub, R, X, nrhs, timed);
+  local_solve_launches<T>(pl, sub, R, X, U, nrhs, timed);
   launch_unpack_local<T>(X, (cpx<double>*)u_dev, S.nloc, nrhs, pl->kmax, pl->stream);
 }
 
@@ -1844,11 +2265,13 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   const dsd_params& q = *params;
   if ((q.dim != 2 && q.dim != 3) || q.overlap < 3 || q.pml < 0 || !(q.h > 0) || !(omega > 0) ||
       (q.precision != DSD_C64 && q.precision != DSD_C128) || q.local_solver < 0 ||
-      q.local_solver > 3 || q.schedule < 0 || q.schedule > 2 || q.dense_top < -1 ||
+      q.local_solver > 4 || q.schedule < 0 || q.schedule > 2 || q.dense_top < -1 ||
       q.dense_top > 64 || q.sweep_order < 0 || q.sweep_order > 1 ||
-      (q.sweep_order == 1 && q.dim != 3)) {
+      (q.sweep_order == 1 && q.dim != 3) || q.nd_leaf < 0 || q.nd_top_cells < 0 ||
+      q.nd_top_cells > 5000) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
-               "local_solver 0..3, schedule 0..2, dense_top -1..64, sweep_order 0..1 (1: 3D only)";
+               "local_solver 0..4, schedule 0..2, dense_top -1..64, sweep_order 0..1 (1: 3D only), "
+               "nd_leaf >= 0, nd_top_cells 0..5000";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)
@@ -1874,6 +2297,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
     for (int i = 0; i < pl->S; ++i) toff[i] = pl->subs[i].fac_off;
     const long long tsum = pl->sum_fac;
     pl->solver = (q.local_solver == 1 || q.local_solver == 3) ? 1 : 2;
+    if (q.local_solver == 4) {
+      pl->solver = 4;
+      rc = nd_setup(pl);
+    }
     if (pl->solver == 2) {
       pl->dense_max = dense_blocks(pl, q.dense_top);
       bcr_layout(pl);
@@ -1890,13 +2317,18 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
     pl->chain_steps = pl->solver == 1 && (q.local_solver == 3 || (q.local_solver == 0 && pl->max_nb >= 512));
   }
   if (rc == 0) {
-    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group
-                                               : ((pl->solver == 2 || pl->chain_steps) ? (pl->c64 ? 8 : 4) : 2));
+    const int kdef = pl->solver == 4 ? 8 : ((pl->solver == 2 || pl->chain_steps) ? (pl->c64 ? 8 : 4) : 2);
+    pl->kg = choose_kg(pl, q.rhs_per_group > 0 ? q.rhs_per_group : kdef);
     if (pl->kg == 0) {
       g_detail = "subdomain blocks too large for the solve kernel's LDS";
       rc = DSD_EINVAL;
     }
-    if (rc == 0 && gj_lds_bytes(pl->max_nb) > (size_t)device_lds()) {
+    if (rc == 0 && pl->solver == 4 &&
+        nd_top_lds_need(tsize(pl), pl->nd_max_ntop) > (size_t)device_lds()) {
+      g_detail = "nested dissection: dense top too large for the top kernel's LDS";
+      rc = DSD_EINVAL;
+    }
+    if (rc == 0 && pl->solver != 4 && gj_lds_bytes(pl->max_nb) > (size_t)device_lds()) {
       g_detail = "subdomain blocks too large for the inversion kernel's LDS";
       rc = DSD_EINVAL;
     }
@@ -2142,10 +2574,11 @@ int dsd_local_solve(dsd_plan* pl, int sub, const double* r_dev, double* u_dev, i
   const long long off = pl->subs[sub].vec_off * pl->kmax;
   if (pl->c64)
     local_solve_any<float>(pl, sub, r_dev, u_dev, nrhs, pl->d_rpool.as<cpx<float>>() + off,
-                           pl->d_vpool.as<cpx<float>>() + off, true);
+                           pl->d_vpool.as<cpx<float>>() + off, pl->d_upool.as<cpx<float>>(), true);
   else
     local_solve_any<double>(pl, sub, r_dev, u_dev, nrhs, pl->d_rpool.as<cpx<double>>() + off,
-                            pl->d_vpool.as<cpx<double>>() + off, true);
+                            pl->d_vpool.as<cpx<double>>() + off, pl->d_upool.as<cpx<double>>(),
+                            true);
   HIPCHK(hipGetLastError());
   time_flush(pl);
   HIPCHK(hipStreamSynchronize(pl->stream));
@@ -2166,9 +2599,10 @@ int dsd_local_solve_noalloc(dsd_plan* pl, int sub, const double* r_dev, double* 
     return DSD_EINVAL;
   }
   const size_t part = align256((size_t)pl->subs[sub].nloc * nrhs * tsize(pl));
-  if (2 * part > (size_t)DSD_NOALLOC_SCRATCH_BYTES) {
-    g_detail = "local_solve_noalloc: 2 x N_loc x nrhs values (" + std::to_string(2 * part) +
-               " bytes) exceed the static scratch of " +
+  const size_t upart = pl->solver == 4 ? align256((size_t)pl->nd_local[sub].upd * nrhs * tsize(pl)) : 0;
+  if (2 * part + upart > (size_t)DSD_NOALLOC_SCRATCH_BYTES) {
+    g_detail = "local_solve_noalloc: the call's working values (" +
+               std::to_string(2 * part + upart) + " bytes) exceed the static scratch of " +
                std::to_string((long long)DSD_NOALLOC_SCRATCH_BYTES) + " bytes";
     return DSD_EINVAL;
   }
@@ -2176,10 +2610,12 @@ int dsd_local_solve_noalloc(dsd_plan* pl, int sub, const double* r_dev, double* 
   unsigned char* base = static_cast<unsigned char*>(pl->scratch);
   if (pl->c64)
     local_solve_any<float>(pl, sub, r_dev, u_dev, nrhs, reinterpret_cast<cpx<float>*>(base),
-                           reinterpret_cast<cpx<float>*>(base + part), false);
+                           reinterpret_cast<cpx<float>*>(base + part),
+                           reinterpret_cast<cpx<float>*>(base + 2 * part), false);
   else
     local_solve_any<double>(pl, sub, r_dev, u_dev, nrhs, reinterpret_cast<cpx<double>*>(base),
-                            reinterpret_cast<cpx<double>*>(base + part), false);
+                            reinterpret_cast<cpx<double>*>(base + part),
+                            reinterpret_cast<cpx<double>*>(base + 2 * part), false);
   HIPCHK(hipGetLastError());
   return DSD_OK;
 }

@@ -94,7 +94,7 @@ def test_bad_batches_are_refused_and_the_plan_stays_usable():
     close(g.cpu().numpy().reshape(2, -1), u_ref, 1e-10, "in-place sweep")
 
 
-SOLVERS = ["bcr", "chain", "chain-steps"]
+SOLVERS = ["bcr", "chain", "chain-steps", "nd"]
 
 
 def test_not_converged_outputs_are_valid():

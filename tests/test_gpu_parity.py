@@ -29,7 +29,7 @@ def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="aut
                     dense_top=dense_top)
 
 
-SOLVERS = ["bcr", "chain", "chain-steps"]
+SOLVERS = ["bcr", "chain", "chain-steps", "nd"]
 
 
 def _cuda(x):
@@ -126,7 +126,7 @@ def test_sweep_apply_deterministic():
     assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("solver", ["bcr", "chain-steps"])
+@pytest.mark.parametrize("solver", ["bcr", "chain-steps", "nd"])
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("c64", 1e-4)])
 def test_autotuned_plan_matches_oracle(prec, tol, solver):
     """The autotuner only picks launch shapes: the tuned plan still matches the oracle."""
@@ -226,14 +226,16 @@ def test_rhs_grouping_c64_matrix_core_path(kg):
 
 @pytest.mark.parametrize("name", ["lay33", "rag34", "d3"])
 def test_cyclic_reduction_equals_chains(name):
-    """Both local solvers invert the same subdomain operators (complex128)."""
+    """Every local solver inverts the same subdomain operators (complex128)."""
     n, h, om, pml, d, parts, c = _case(name)
     f = _cuda(sources(n, h, pml, 2))
     a = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="bcr").sweep_apply(f).cpu().numpy()
     b = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain").sweep_apply(f).cpu().numpy()
     s = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="chain-steps").sweep_apply(f).cpu().numpy()
+    e = _plan(n, h, om, pml, d, parts, c, "c128", 2, solver="nd").sweep_apply(f).cpu().numpy()
     close(a, b, 1e-12, f"{name} reduction vs chains")
     close(s, b, 1e-12, f"{name} chain steps vs chains")
+    close(e, b, 1e-12, f"{name} nested dissection vs chains")
 
 
 @pytest.mark.parametrize("dense_top", [-1, 2, 3, 8])

@@ -21,7 +21,7 @@ def _plan(n, h, om, pml, d, parts, c, prec, k, solver):
                     max_rhs=k, local_solver=solver)
 
 
-@pytest.mark.parametrize("solver", ["bcr", "chain", "chain-steps"])
+@pytest.mark.parametrize("solver", ["bcr", "chain", "chain-steps", "nd"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_noalloc_local_solve_equals_local_solve(solver, prec):
     n, h, om, pml, d, parts = (61, 70), 1 / 61, 2 * np.pi * 4, 6, 4, (3, 4)
