@@ -41,14 +41,15 @@ def _inputs(name):
     return w, c, F
 
 
-def _plan(w, c, prec, kg, graph=False, tune=False):
+def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_top=0):
     import torch
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(1.0 / c ** 2).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     plan = dsw.Plan(n=w.n, h=w.h, omega=w.omega, pml=w.pml, overlap=w.overlap, parts=w.parts,
-                    m=m, precision=prec, max_rhs=w.nrhs, rhs_per_group=kg)
+                    m=m, precision=prec, max_rhs=w.nrhs, rhs_per_group=kg, local_solver=solver,
+                    nd_leaf=nd_leaf, nd_top_cells=nd_top)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"# {prec} plan ready ({plan.local_solver} local solver): factorisation {dt:.2f} s",
@@ -81,21 +82,30 @@ def _solve_steps(plan, b, tol, maxit, restart, warmup, steps):
     return dt, its, rel, ok, x[0].cpu().numpy().ravel(), step_ms
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bcr_c2_traffic.md")
+TRAFFIC_FILES = {"bcr": os.path.join(ROOT, "profiles", "k_bcr_c2_traffic.md"),
+                 "nd": os.path.join(ROOT, "profiles", "k_nd_c2_traffic.md")}
 
 
-def _kernel_source_hash():
-    """sha256 over the source that decides the solve kernel's memory traffic: the
-    kernel and its launchers, and the builder of its job tables and launch shapes."""
+def _kernel_source_hash(solver="bcr"):
+    """sha256 over the source that decides the solve kernels' memory traffic: the
+    kernels and their launchers, and the builder of their job tables and launch
+    shapes."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2002_05327_amd", "csrc")
     h = hashlib.sha256()
+    with open(os.path.join(csrc, "plan.hip")) as f:
+        p = f.read()
+    if solver == "nd":
+        with open(os.path.join(csrc, "nd.hip")) as f:
+            k = f.read()
+        h.update(k[k.index("// Solve kernels"):k.index("// Factorisation kernels")].encode())
+        a = p.index("void nd_group_jobs(")
+        h.update(p[a:p.index("\n}\n", a)].encode())
+        return h.hexdigest()
     with open(os.path.join(csrc, "kernels.hip")) as f:
         k = f.read()
     a, b = k.index("// ---- solve jobs"), k.index("// a4: local right-hand sides")
     h.update(k[a:b].encode())
-    with open(os.path.join(csrc, "plan.hip")) as f:
-        p = f.read()
     a = p.index("void bcr_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, std::vector<BcrJob>& jobs,\n                    std::vector<BcrLaunch>& out) {")
     b = p.index("\n}\n", a)
     h.update(p[a:b].encode())
@@ -104,19 +114,22 @@ def _kernel_source_hash():
     return h.hexdigest()
 
 
-def _measured_traffic(workload):
+def _measured_traffic(workload, solver):
     """HBM bytes per solve-kernel dispatch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE passes, each scaled by what the counter
     reads for a 1 GiB device copy); None when the summary was taken on another
     workload or before the kernels last changed."""
+    if solver not in TRAFFIC_FILES:
+        return None
     try:
         vals = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILES[solver]) as f:
             for line in f:
                 if ":" in line and line.startswith("- "):
                     k, v = line[2:].split(":", 1)
                     vals[k.strip()] = v.strip().strip("`")
-        if vals.get("workload") != workload or vals.get("solve-kernel source sha256") != _kernel_source_hash():
+        if vals.get("workload") != workload or \
+                vals.get("solve-kernel source sha256") != _kernel_source_hash(solver):
             return None
         return float(vals["HBM bytes per dispatch"])
     except (OSError, KeyError, ValueError):
@@ -176,7 +189,7 @@ def _roofline(plan, b, w, tsize, matrix_peak=None):
             "peak": peak_tf, "unit": "TFLOP/s", "frac": round(tfs / peak_tf, 4)}
     mfma_bound = app_flops / (peak_tf * 1e12) > app_bytes / (HBM_PEAK_GBS * 1e9)
     out = dict(mfma if mfma_bound else hbm)
-    out.update({"traffic": _measured_traffic(w.name) if matrix_peak is None else None,
+    out.update({"traffic": _measured_traffic(w.name, plan.local_solver) if matrix_peak is None else None,
                 "kernel": KERNEL_NAMES[plan.local_solver],
                 "launches": t["solve_launches"],
                 "solve_ms_per_application": round(t["solve_ms"], 3),
@@ -194,7 +207,8 @@ def _roofline(plan, b, w, tsize, matrix_peak=None):
 
 KERNEL_NAMES = {"bcr": "k_bcr (block cyclic reduction solves)",
                 "chain": "k_chain (block LDL^T chain solves)",
-                "chain-steps": "k_bcr (block LDL^T chain steps)"}
+                "chain-steps": "k_bcr (block LDL^T chain steps)",
+                "nd": "k_nd_fwd + k_nd_top + k_nd_bwd (nested-dissection solves)"}
 
 
 _CPU = {}
@@ -310,6 +324,9 @@ def main():
     ap.add_argument("--maxit", type=int, default=60)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--kg", type=int, default=0, help="RHS per workgroup in the block solves")
+    ap.add_argument("--solver", default="auto", help="local solver: auto, nd, bcr, chain, chain-steps")
+    ap.add_argument("--nd-leaf", type=int, default=0, help="nested dissection: leaf box cells (0: library)")
+    ap.add_argument("--nd-top", type=int, default=0, help="nested dissection: dense-top cells (0: library)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the solve-launch shapes first (reported separately)")
     ap.add_argument("--graph", action="store_true",
@@ -336,7 +353,8 @@ def main():
     b = torch.from_numpy(F).cuda()
     print(f"# workload {w.name}: n={w.n} parts={w.parts} nrhs={w.nrhs}", file=sys.stderr, flush=True)
 
-    plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph, args.autotune)
+    plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph, args.autotune, args.solver,
+                         args.nd_leaf, args.nd_top)
     print(f"# c64 factorisation {tf64:.2f} s", file=sys.stderr, flush=True)
     dt64, its64, rel64, ok64, x64, steps64 = _solve_steps(plan64, b, args.tol, args.maxit,
                                                           args.restart, args.warmup, args.steps)
@@ -349,7 +367,8 @@ def main():
 
     c128 = None
     if not args.no_c128:
-        plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph, args.autotune)
+        plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph, args.autotune, args.solver,
+                               args.nd_leaf, args.nd_top)
         n128 = max(1, min(args.steps, 5))
         dt128, its128, rel128, ok128, x128, steps128 = _solve_steps(
             plan128, b, args.tol, args.maxit, args.restart, min(args.warmup, 1), n128)

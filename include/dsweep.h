@@ -99,7 +99,7 @@ typedef struct {
                             Transfers are routed by Rules 4.1/4.2 over the chosen order.
                             2D has one order (must be 0).                               */
   int nd_leaf;           /* nested dissection: boxes of at most this many cells are not
-                            bisected further (0: 16)                                   */
+                            bisected further (0: 128)                                  */
   int nd_top_cells;      /* nested dissection: the separators of the shallowest depths
                             whose cells total at most this many form the dense top
                             (0: 1200; at most 5000)                                    */

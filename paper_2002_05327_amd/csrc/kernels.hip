@@ -2061,16 +2061,18 @@ __global__ __launch_bounds__(256) void k_mdot(const cpx<double>* V, int nv, cons
   const int r = blockIdx.y;
   const int b = blockIdx.x;
   const cpx<double>* wr = w + (long long)r * N;
-  for (int i0 = 0; i0 < nv; i0 += 4) {
-    cpx<double> acc[4];
-    for (int t = 0; t < 4; ++t) acc[t] = mk(0.0, 0.0);
+  // eight basis vectors per pass over w (one pass for the first eight Arnoldi steps)
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    cpx<double> acc[8];
+    for (int t = 0; t < 8; ++t) acc[t] = mk(0.0, 0.0);
     for (long long c = (long long)b * blockDim.x + threadIdx.x; c < N;
          c += (long long)nblk * blockDim.x) {
       const cpx<double> wv = wr[c];
-      for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
         if (i0 + t < nv) fma_acc(acc[t], conj(V[((long long)(i0 + t) * nrhs + r) * N + c]), wv);
     }
-    for (int t = 0; t < 4 && i0 + t < nv; ++t) {
+    for (int t = 0; t < 8 && i0 + t < nv; ++t) {
       cpx<double> s = block_sum(acc[t], sh);
       if (threadIdx.x == 0) part[((long long)(i0 + t) * nrhs + r) * nblk + b] = s;
     }
@@ -2151,6 +2153,14 @@ __global__ void k_scatter_rhs(const cpx<double>* src, const int* idx, cpx<double
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (c < N) dst[(long long)idx[r] * N + c] = src[(long long)r * N + c];
+}
+__global__ void k_zero_rhs(cpx<double>* dst, const int* idx, long long N) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < N) dst[(long long)idx[blockIdx.y] * N + c] = mk(0.0, 0.0);
+}
+void launch_zero_rhs(cpx<double>* dst, const int* idx, int nsel, long long N, hipStream_t s) {
+  if (nsel <= 0) return;
+  hipLaunchKernelGGL(k_zero_rhs, dim3(cdiv_u(N, 256), nsel), dim3(256), 0, s, dst, idx, N);
 }
 void launch_gather_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst, int nsel,
                        long long N, hipStream_t s) {

@@ -206,6 +206,8 @@ void launch_scale(const cpx<double>* src, const double* scal, cpx<double>* dst, 
 void launch_sub(const cpx<double>* a, const cpx<double>* b, cpx<double>* y, long long n,
                 hipStream_t s);
 void launch_conj(const cpx<double>* a, cpx<double>* y, long long n, hipStream_t s);
+// dst[idx[r]] = 0 for r < nsel (rows of N entries)
+void launch_zero_rhs(cpx<double>* dst, const int* idx, int nsel, long long N, hipStream_t s);
 // gather / scatter RHS subsets: dst[r] = src[idx[r]] (and the reverse)
 void launch_gather_rhs(const cpx<double>* src, const int* idx, cpx<double>* dst, int nsel,
                        long long N, hipStream_t s);

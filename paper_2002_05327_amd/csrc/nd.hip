@@ -143,9 +143,12 @@ NdShape nd_analyse(int dim, const int* dims, int leaf_max, int ntop_max) {
   return S;
 }
 
+constexpr int ND_TW = 8;    // waves per dense-top workgroup
+
 bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>& nodes,
-                      std::vector<int>& cells, std::vector<int>& maps, std::vector<int>& src,
-                      std::vector<int>& lev, std::vector<int>& levnodes) {
+                      std::vector<int>& cells, std::vector<int>& maps, std::vector<int>& umaps,
+                      std::vector<int>& src, std::vector<int>& usrc, std::vector<int>& lev,
+                      std::vector<int>& levmax, std::vector<int>& levnodes) {
   const int dim2 = 2 * S.dim;
   const int N = (int)S.nodes.size();
   const long long ncell = (long long)S.dims[0] * S.dims[1] * S.dims[2];
@@ -166,6 +169,7 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
     d.upd = n.upd;
     const int nf = d.ns + d.nbd;
     maps.insert(maps.end(), (size_t)2 * nf, -1);
+    umaps.insert(umaps.end(), (size_t)2 * nf, -1);
     if (!n.top) {
       // front position of every cell of this node's front
       for (int p = 0; p < nf; ++p) pos[p < d.ns ? n.sep[p] : n.bnd[p - d.ns]] = p;
@@ -176,6 +180,7 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
           const int p = pos[cb[i2]];
           if (p < 0) return false;   // a child's boundary must lie in the parent's front
           maps[d.map + 2 * p + c] = i2;
+          umaps[d.map + 2 * p + c] = (int)(S.nodes[n.child[c]].upd + i2);
         }
       }
       for (int p = 0; p < nf; ++p) pos[p < d.ns ? n.sep[p] : n.bnd[p - d.ns]] = -1;
@@ -201,7 +206,13 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
       src[tab.top_src + (p * dim2 + k) * 2 + 1] = i;
     }
   }
-  // level lists of every subtree
+  tab.top_usrc = (int)usrc.size();
+  for (int p = 0; p < ntop; ++p)
+    for (int k = 0; k < dim2; ++k) {
+      const int r = src[tab.top_src + (p * dim2 + k) * 2];
+      usrc.push_back(r < 0 ? -1 : (int)(S.nodes[r].upd + src[tab.top_src + (p * dim2 + k) * 2 + 1]));
+    }
+  // level lists of every subtree and the largest front of each level
   tab.lev0.clear();
   tab.nlev.clear();
   for (size_t s = 0; s < S.roots.size(); ++s) {
@@ -212,10 +223,16 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
     tab.nlev.push_back(nl);
     for (int l = 0; l < nl; ++l) {
       lev.push_back((int)levnodes.size());
+      int mx = 0;
       for (int i = 0; i < N; ++i)
-        if (S.nodes[i].subtree == (int)s && S.nodes[i].level == l) levnodes.push_back(tab.node0 + i);
+        if (S.nodes[i].subtree == (int)s && S.nodes[i].level == l) {
+          levnodes.push_back(tab.node0 + i);
+          mx = std::max(mx, (int)(S.nodes[i].sep.size() + S.nodes[i].bnd.size()));
+        }
+      levmax.push_back(mx);
     }
     lev.push_back((int)levnodes.size());
+    levmax.push_back(0);
   }
   return true;
 }
@@ -223,8 +240,9 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
 // ============================================================================
 // Solve kernels
 // ============================================================================
-constexpr int ND_W = 4;     // waves per subtree workgroup
-constexpr int ND_TW = 4;    // waves per dense-top workgroup
+// Lanes take (row, right-hand side) pairs: 64 / KG rows of one node per pass,
+// so the small separators of the deep levels still fill the wave; gathers
+// take one front position per lane (index loads once, then KG data loads).
 
 __device__ __forceinline__ void nd_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -238,189 +256,460 @@ __device__ __forceinline__ int nd_task(int b, int total) {
   return (b & 7) * per + (b >> 3);
 }
 
-// Forward pass of one subtree for KG right-hand sides, leaves to root:
-// front = (r on S, 0 on B) + children's updates; f_S back into R; u_B = front_B - L f_S.
-// Levels with at least ND_W nodes give every wave its own nodes; smaller levels
-// build their fronts first and share the 64-row passes over all waves.
-template <typename T, int KG>
-__global__ __launch_bounds__(64 * ND_W) void k_nd_fwd(
-    const NdSubJob* __restrict__ jobs, int njobs, int G, const NdNodeDev* __restrict__ nodes,
-    const int* __restrict__ lev, const int* __restrict__ levnodes, const int* __restrict__ cells,
-    const int* __restrict__ maps, const cpx<T>* __restrict__ fac, cpx<T>* __restrict__ rpool,
-    cpx<T>* __restrict__ upool, long long pool_stride, int nrhs, int kmax, int region) {
+// Dot products of the node kernels: acc -= (or +=) sum_j A[j * lda] y[j * KG],
+// the matrix column loads issued eight at a time and one batch ahead of the
+// FMAs that use them (so a row's loads are in flight together).
+template <typename T, int KG, bool SUB>
+__device__ __forceinline__ void nd_dot(cpx<T>& acc, const cpx<T>* __restrict__ A, long long lda,
+                                       const cpx<T>* y, int n) {
   typedef cpx<T> C;
-  const int Lg = nd_task(blockIdx.x, gridDim.x);
-  const int job = Lg / G, g = Lg - (Lg / G) * G;
-  if (job >= njobs) return;
-  const NdSubJob J = jobs[job];
-  C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
-  C* __restrict__ U = upool + J.ubase;
-  const C* __restrict__ F = fac + J.fac;
-  const long long nloc = J.nloc;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const C zero = mk((T)0, (T)0);
-  const int q0 = g * KG;
-
-  auto build = [&](const NdNodeDev& N, C* fr) {
-    const int nf = N.ns + N.nbd;
-    const int* fc = cells + N.cell;
-    const int* mp = maps + N.map;
-    const long long u0 = N.ch0 >= 0 ? nodes[N.ch0].upd : -1;
-    const long long u1 = N.ch1 >= 0 ? nodes[N.ch1].upd : -1;
-    for (int e = lane; e < nf * KG; e += 64) {
-      const int p = e / KG, q = e - (e / KG) * KG, rq = q0 + q;
-      C v = zero;
-      if (rq < nrhs) {
-        if (p < N.ns) v = R[(long long)rq * nloc + fc[p]];
-        if (u0 >= 0) {
-          const int i = mp[2 * p];
-          if (i >= 0) v = v + U[(u0 + i) * kmax + rq];
-        }
-        if (u1 >= 0) {
-          const int i = mp[2 * p + 1];
-          if (i >= 0) v = v + U[(u1 + i) * kmax + rq];
-        }
-        if (p < N.ns) R[(long long)rq * nloc + fc[p]] = v;
+  constexpr int B = 8;
+  C a[B], b[B];
+  auto load = [&](C (&buf)[B], int j0) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) buf[u] = A[(long long)min(j0 + u, n - 1) * lda];
+  };
+  auto use = [&](const C (&buf)[B], int j0) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (j0 + u >= n) break;
+      const C m = buf[u], v = y[(j0 + u) * KG];
+      if (SUB) {
+        acc.re = fma(-m.re, v.re, acc.re);
+        acc.re = fma(m.im, v.im, acc.re);
+        acc.im = fma(-m.re, v.im, acc.im);
+        acc.im = fma(-m.im, v.re, acc.im);
+      } else {
+        fma_acc(acc, m, v);
       }
-      fr[e] = v;
     }
   };
-  auto rows = [&](const NdNodeDev& N, const C* fr, int i0) {
-    const int i = i0 + lane;
-    if (i >= N.nbd) return;
-    const C* __restrict__ L = F + N.fac;
-    C acc[KG];
-#pragma unroll
-    for (int q = 0; q < KG; ++q) acc[q] = fr[(N.ns + i) * KG + q];
-    for (int j = 0; j < N.ns; ++j) {
-      const C a = L[(long long)j * N.nbd + i];
-#pragma unroll
-      for (int q = 0; q < KG; ++q) {
-        const C y = fr[j * KG + q];
-        acc[q].re = fma(-a.re, y.re, acc[q].re);
-        acc[q].re = fma(a.im, y.im, acc[q].re);
-        acc[q].im = fma(-a.re, y.im, acc[q].im);
-        acc[q].im = fma(-a.im, y.re, acc[q].im);
-      }
+  if (n <= 0) return;
+  load(a, 0);
+  for (int j0 = 0; j0 < n; j0 += 2 * B) {
+    if (j0 + B < n) load(b, j0 + B);
+    use(a, j0);
+    if (j0 + B < n) {
+      if (j0 + 2 * B < n) load(a, j0 + 2 * B);
+      use(b, j0 + B);
     }
-#pragma unroll
-    for (int q = 0; q < KG; ++q)
-      if (q0 + q < nrhs) U[(N.upd + i) * kmax + q0 + q] = acc[q];
-  };
-  for (int l = J.nlev - 1; l >= 0; --l) {
-    const int n0 = lev[J.lev0 + l], nn = lev[J.lev0 + l + 1] - n0;
-    if (nn >= ND_W) {
-      C* fr = lds + (long long)w * region;
-      for (int k = w; k < nn; k += ND_W) {
-        const NdNodeDev N = nodes[levnodes[n0 + k]];
-        build(N, fr);
-        nd_wave_sync();
-        for (int i0 = 0; i0 < N.nbd; i0 += 64) rows(N, fr, i0);
-        nd_wave_sync();
-      }
-    } else {
-      if (w < nn) build(nodes[levnodes[n0 + w]], lds + (long long)w * region);
-      __syncthreads();
-      int it = 0;
-      for (int k = 0; k < nn; ++k) {
-        const NdNodeDev N = nodes[levnodes[n0 + k]];
-        for (int i0 = 0; i0 < N.nbd; i0 += 64, ++it)
-          if (it % ND_W == w) rows(N, lds + (long long)k * region, i0);
-      }
-    }
-    __syncthreads();
   }
 }
 
-// Backward pass of one subtree, root to leaves: x_S = K [f_S; -x_B] with
-// K = [P | L^T] (ns x nf), f_S from R, x_B from X (ancestors, or the top).
-template <typename T, int KG>
-__global__ __launch_bounds__(64 * ND_W) void k_nd_bwd(
-    const NdSubJob* __restrict__ jobs, int njobs, int G, const NdNodeDev* __restrict__ nodes,
-    const int* __restrict__ lev, const int* __restrict__ levnodes, const int* __restrict__ cells,
-    const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ xpool,
-    long long pool_stride, int nrhs, int kmax, int region) {
+// Lanes over rows: acc[q] -= (or +=) sum_{j in [c0, c1)} A[j * lda] y[j * KG + q]
+// for all KG right-hand sides; the column loads (64 consecutive rows, one
+// load per column) issued eight at a time, one batch ahead of their FMAs.
+template <typename T, int KG, bool SUB>
+__device__ __forceinline__ void nd_dot_rows(cpx<T> (&acc)[KG], const cpx<T>* __restrict__ A,
+                                            long long lda, const cpx<T>* y, int c0, int c1) {
   typedef cpx<T> C;
-  const int Lg = nd_task(blockIdx.x, gridDim.x);
-  const int job = Lg / G, g = Lg - (Lg / G) * G;
-  if (job >= njobs) return;
-  const NdSubJob J = jobs[job];
-  const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
-  C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
-  const C* __restrict__ F = fac + J.fac;
-  const long long nloc = J.nloc;
-  extern __shared__ unsigned char smem_raw[];
-  C* lds = reinterpret_cast<C*>(smem_raw);
-  const int lane = threadIdx.x & 63;
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const C zero = mk((T)0, (T)0);
-  const int q0 = g * KG;
-  (void)kmax;
+  constexpr int B = 8;
+  C a[B], b[B];
+  const int n = c1 - c0;
+  if (n <= 0) return;
+  auto load = [&](C (&buf)[B], int j0) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) buf[u] = A[(long long)(c0 + min(j0 + u, n - 1)) * lda];
+  };
+  auto use = [&](const C (&buf)[B], int j0) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (j0 + u >= n) break;
+      const C m = buf[u];
+      const C* yj = y + (c0 + j0 + u) * KG;
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        const C v = yj[q];
+        if (SUB) {
+          acc[q].re = fma(-m.re, v.re, acc[q].re);
+          acc[q].re = fma(m.im, v.im, acc[q].re);
+          acc[q].im = fma(-m.re, v.im, acc[q].im);
+          acc[q].im = fma(-m.im, v.re, acc[q].im);
+        } else {
+          fma_acc(acc[q], m, v);
+        }
+      }
+    }
+  };
+  load(a, 0);
+  for (int j0 = 0; j0 < n; j0 += 2 * B) {
+    if (j0 + B < n) load(b, j0 + B);
+    use(a, j0);
+    if (j0 + B < n) {
+      if (j0 + 2 * B < n) load(a, j0 + 2 * B);
+      use(b, j0 + B);
+    }
+  }
+}
 
-  auto build = [&](const NdNodeDev& N, C* v) {
-    const int nf = N.ns + N.nbd;
-    const int* fc = cells + N.cell;
-    for (int e = lane; e < nf * KG; e += 64) {
-      const int p = e / KG, q = e - (e / KG) * KG, rq = q0 + q;
-      C x = zero;
-      if (rq < nrhs) x = p < N.ns ? R[(long long)rq * nloc + fc[p]] : -X[(long long)rq * nloc + fc[p]];
-      v[e] = x;
-    }
-  };
-  auto rows = [&](const NdNodeDev& N, const C* v, int i0) {
-    const int i = i0 + lane;
-    if (i >= N.ns) return;
-    const int nf = N.ns + N.nbd;
-    const C* __restrict__ K = F + N.fac + (long long)N.nbd * N.ns;
-    C acc[KG];
+// ---- complex64 on the FP32 matrix cores (v_mfma_f32_16x16x4f32): a wave
+// computes a 64-row tile (four 16-row blocks) against KG = 8 JB right-hand
+// sides.  Lane l holds A[16 rb + l % 16][k = l / 16] of a 4-column chunk and
+// B[k][n = l % 16] with n = 2 q + (re/im): Re(A) against [Re y_q, Im y_q] and
+// Im(A) against [-Im y_q, Re y_q] give [Re (A y)_q, Im (A y)_q].  Output
+// acc[rb][jb][r] = row 16 rb + 4 (l / 16) + r, column n = l % 16 of block jb.
+typedef float nd_mf4 __attribute__((ext_vector_type(4)));
+
+template <int JB>
+__device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<float>* __restrict__ A,
+                                             long long lda, int nrows, const cpx<float>* y,
+                                             int c0, int c1, int lane) {
+  typedef cpx<float> C;
+  constexpr int KG = 8 * JB;
+  constexpr int CH = 4;                      // 4-column chunks per batch of loads
+  const int lr = lane & 15, lk = lane >> 4, n = lane & 15, qn = n >> 1;
+  const bool im = n & 1;
+  const C zero = mk(0.0f, 0.0f);
+  C a[CH][4], b[CH][4];
+  auto load = [&](C (&buf)[CH][4], int j0) {
 #pragma unroll
-    for (int q = 0; q < KG; ++q) acc[q] = zero;
-    for (int j = 0; j < nf; ++j) {
-      const C a = K[(long long)j * N.ns + i];
+    for (int c = 0; c < CH; ++c) {
+      const int col = j0 + 4 * c + lk;
+      const bool cv = col < c1;
 #pragma unroll
-      for (int q = 0; q < KG; ++q) fma_acc(acc[q], a, v[j * KG + q]);
-    }
-    const int cell = cells[N.cell + i];
-#pragma unroll
-    for (int q = 0; q < KG; ++q)
-      if (q0 + q < nrhs) X[(long long)(q0 + q) * nloc + cell] = acc[q];
-  };
-  for (int l = 0; l < J.nlev; ++l) {
-    const int n0 = lev[J.lev0 + l], nn = lev[J.lev0 + l + 1] - n0;
-    if (nn >= ND_W) {
-      C* v = lds + (long long)w * region;
-      for (int k = w; k < nn; k += ND_W) {
-        const NdNodeDev N = nodes[levnodes[n0 + k]];
-        build(N, v);
-        nd_wave_sync();
-        for (int i0 = 0; i0 < N.ns; i0 += 64) rows(N, v, i0);
-        nd_wave_sync();
+      for (int rb = 0; rb < 4; ++rb) {
+        const int row = 16 * rb + lr;
+        buf[c][rb] = (cv && row < nrows) ? A[(long long)col * lda + row] : zero;
       }
-    } else {
-      if (w < nn) build(nodes[levnodes[n0 + w]], lds + (long long)w * region);
+    }
+  };
+  auto use = [&](const C (&buf)[CH][4], int j0) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (j0 + 4 * c >= c1) break;            // wave-uniform
+      const int col = j0 + 4 * c + lk;
+      float bre[JB], bim[JB];
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) {
+        const C yv = col < c1 ? y[col * KG + jb * 8 + qn] : zero;
+        bre[jb] = im ? yv.im : yv.re;
+        bim[jb] = im ? yv.re : -yv.im;
+      }
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(buf[c][rb].re, bre[jb], acc[rb][jb], 0, 0, 0);
+          acc[rb][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(buf[c][rb].im, bim[jb], acc[rb][jb], 0, 0, 0);
+        }
+    }
+  };
+  if (c1 <= c0) return;
+  constexpr int STEP = 4 * CH;
+  load(a, c0);
+  for (int j0 = c0; j0 < c1; j0 += 2 * STEP) {
+    if (j0 + STEP < c1) load(b, j0 + STEP);
+    use(a, j0);
+    if (j0 + STEP < c1) {
+      if (j0 + 2 * STEP < c1) load(a, j0 + 2 * STEP);
+      use(b, j0 + STEP);
+    }
+  }
+}
+
+// The complex outputs of a wave's MFMA tile: the (re, im) halves of a value sit
+// in neighbouring lanes; they meet through the wave's LDS staging area st
+// (64 x KG complex) and come back as row `lane`, all KG right-hand sides.
+template <int JB>
+__device__ __forceinline__ void nd_mfma_out(const nd_mf4 (&acc)[4][JB], float* st, int lane,
+                                            cpx<float> (&out)[8 * JB]) {
+  constexpr int KG = 8 * JB;
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rl = 16 * rb + 4 * (lane >> 4) + r;
+        const int nn = jb * 16 + (lane & 15);
+        st[((nn >> 1) * 64 + rl) * 2 + (nn & 1)] = acc[rb][jb][r];
+      }
+  nd_wave_sync();
+#pragma unroll
+  for (int q = 0; q < KG; ++q) out[q] = mk(st[(q * 64 + lane) * 2], st[(q * 64 + lane) * 2 + 1]);
+}
+
+// One level of the forward pass: one workgroup per (node, group of KG
+// right-hand sides); front = (r on S, 0 on B) + children's updates (built by
+// all waves, one front position per thread), f_S back into R, then the
+// waves share the row passes of u_B = front_B - L f_S.
+// With npw > 1 every wave of the workgroup runs a node of its own (the small
+// nodes of the deep levels: fewer, fuller workgroups) and only waits for itself.
+template <typename T, int KG>
+__global__ __launch_bounds__(512) void k_nd_lvl_fwd(
+    const NdLvlJob* __restrict__ jobs, int njobs, int G, int npw, int region, int TT, int CG,
+    const int* __restrict__ cells, const int* __restrict__ umaps, const cpx<T>* __restrict__ fac,
+    cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ upool, long long pool_stride, int nrhs,
+    int kmax) {
+  typedef cpx<T> C;
+  constexpr int RPP = 64 / KG;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int grp = Lg / G, g = Lg - (Lg / G) * G;
+  int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63;
+  int w = __builtin_amdgcn_readfirstlane(tid >> 6), W = nt >> 6;
+  extern __shared__ unsigned char smem_raw[];
+  C* fr = reinterpret_cast<C*>(smem_raw);
+  int job = grp;
+  if (npw > 1) {              // one node per wave: the wave is the workgroup
+    job = grp * npw + w;
+    fr += (long long)w * region;
+    tid = lane;
+    nt = 64;
+    w = 0;
+    W = 1;
+  }
+  if (job >= njobs) return;
+  const NdLvlJob J = jobs[job];
+  C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ U = upool + J.ubase;
+  const long long nloc = J.nloc;
+  const C zero = mk((T)0, (T)0);
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
+  const int ns = J.ns, nbd = J.nbd, nf = ns + nbd;
+  {
+    const int* fc = cells + J.cell;
+    const int* um = umaps + J.umap;
+    for (int p = tid; p < nf; p += nt) {
+      const int i0 = um[2 * p], i1 = um[2 * p + 1];
+      const bool own = p < ns;
+      const int cell = own ? fc[p] : 0;
+      const C* U0 = U + (long long)i0 * kmax + q0;
+      const C* U1 = U + (long long)i1 * kmax + q0;
+      C* Rc = R + (long long)q0 * nloc + cell;
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        C v = zero;
+        if (q < nq) {
+          if (own) v = Rc[(long long)q * nloc];
+          if (i0 >= 0) v = v + U0[q];
+          if (i1 >= 0) v = v + U1[q];
+          if (own) Rc[(long long)q * nloc] = v;
+        }
+        fr[p * KG + q] = v;
+      }
+    }
+  }
+  if (npw > 1) nd_wave_sync();
+  else __syncthreads();
+  const C* __restrict__ L = fac + J.fac;
+  if (npw > 1) {
+    // (row, right-hand side) lanes: 64 / KG rows per pass
+    const int qq = lane % KG, rr = lane / KG;
+    for (int i0 = 0; i0 < nbd; i0 += RPP) {
+      const int i = i0 + rr;
+      if (i >= nbd) continue;
+      C acc = fr[(ns + i) * KG + qq];
+      nd_dot<T, KG, true>(acc, L + i, nbd, fr + qq, ns);
+      if (qq < nq) U[(J.upd + i) * kmax + q0 + qq] = acc;
+    }
+    return;
+  }
+  (void)W;
+  // lanes over rows: wave w takes row tile w % TT and column group w / TT
+  const int t = w % TT, cgi = w / TT;
+  const int cw = (ns + CG - 1) / CG;
+  const int c0 = min(ns, cgi * cw), c1 = min(ns, c0 + cw);
+  const int i = t * 64 + lane;
+  const bool live = i < nbd;
+  if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
+    constexpr int JB = KG / 8;
+    nd_mf4 macc[4][JB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
+    if (t * 64 < nbd) nd_mfma_rows<JB>(macc, L + t * 64, nbd, nbd - t * 64, fr, c0, c1, lane);
+    float* pf = reinterpret_cast<float*>(fr + region);
+    if (CG > 1) {
+      if (cgi > 0) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              pf[((((cgi - 1) * TT + t) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane] = macc[rb][jb][r];
+      }
       __syncthreads();
-      int it = 0;
-      for (int k = 0; k < nn; ++k) {
-        const NdNodeDev N = nodes[levnodes[n0 + k]];
-        for (int i0 = 0; i0 < N.ns; i0 += 64, ++it)
-          if (it % ND_W == w) rows(N, lds + (long long)k * region, i0);
-      }
+      if (cgi > 0) return;
+      for (int o = 1; o < CG; ++o)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              macc[rb][jb][r] += pf[((((o - 1) * TT + t) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
+    }
+    C out[KG];
+    nd_mfma_out<JB>(macc, pf + (long long)t * 64 * KG * 2, lane, out);
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < KG; ++q)
+        if (q < nq) U[(J.upd + i) * kmax + q0 + q] = fr[(ns + i) * KG + q] - out[q];
+    }
+    return;
+  }
+  C acc[KG];
+#pragma unroll
+  for (int q = 0; q < KG; ++q) acc[q] = (cgi == 0 && live) ? fr[(ns + i) * KG + q] : zero;
+  if (live) nd_dot_rows<T, KG, true>(acc, L + i, nbd, fr, c0, c1);
+  C* part = fr + region;
+  if (CG > 1) {
+    if (cgi > 0) {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) part[(((cgi - 1) * TT + t) * KG + q) * 64 + lane] = acc[q];
     }
     __syncthreads();
+    if (cgi > 0) return;
+    for (int o = 1; o < CG; ++o)
+#pragma unroll
+      for (int q = 0; q < KG; ++q) acc[q] = acc[q] + part[(((o - 1) * TT + t) * KG + q) * 64 + lane];
+  }
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+      if (q < nq) U[(J.upd + i) * kmax + q0 + q] = acc[q];
+  }
+}
+
+// One level of the backward pass: x_S = K [f_S; -x_B] with K = [P | L^T]
+// (ns x nf), f_S from R, x_B from X (ancestors, or the dense top).
+template <typename T, int KG>
+__global__ __launch_bounds__(512) void k_nd_lvl_bwd(
+    const NdLvlJob* __restrict__ jobs, int njobs, int G, int npw, int region, int TT, int CG,
+    const int* __restrict__ cells, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
+    cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs) {
+  typedef cpx<T> C;
+  constexpr int RPP = 64 / KG;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int grp = Lg / G, g = Lg - (Lg / G) * G;
+  int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63;
+  int w = __builtin_amdgcn_readfirstlane(tid >> 6), W = nt >> 6;
+  extern __shared__ unsigned char smem_raw[];
+  C* v = reinterpret_cast<C*>(smem_raw);
+  int job = grp;
+  if (npw > 1) {
+    job = grp * npw + w;
+    v += (long long)w * region;
+    tid = lane;
+    nt = 64;
+    w = 0;
+    W = 1;
+  }
+  if (job >= njobs) return;
+  const NdLvlJob J = jobs[job];
+  const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
+  const long long nloc = J.nloc;
+  const C zero = mk((T)0, (T)0);
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
+  const int ns = J.ns, nbd = J.nbd, nf = ns + nbd;
+  const int* fc = cells + J.cell;
+  for (int p = tid; p < nf; p += nt) {
+    const bool own = p < ns;
+    const long long c = (long long)q0 * nloc + fc[p];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      C x = zero;
+      if (q < nq) x = own ? R[c + (long long)q * nloc] : -X[c + (long long)q * nloc];
+      v[p * KG + q] = x;
+    }
+  }
+  if (npw > 1) nd_wave_sync();
+  else __syncthreads();
+  const C* __restrict__ K = fac + J.fac + (long long)nbd * ns;
+  if (npw > 1) {
+    const int qq = lane % KG, rr = lane / KG;
+    for (int i0 = 0; i0 < ns; i0 += RPP) {
+      const int i = i0 + rr;
+      if (i >= ns) continue;
+      C acc = zero;
+      nd_dot<T, KG, false>(acc, K + i, ns, v + qq, nf);
+      if (qq < nq) X[(long long)(q0 + qq) * nloc + fc[i]] = acc;
+    }
+    return;
+  }
+  (void)W;
+  const int t = w % TT, cgi = w / TT;
+  const int cw = (nf + CG - 1) / CG;
+  const int c0 = min(nf, cgi * cw), c1 = min(nf, c0 + cw);
+  const int i = t * 64 + lane;
+  const bool live = i < ns;
+  if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
+    constexpr int JB = KG / 8;
+    nd_mf4 macc[4][JB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
+    if (t * 64 < ns) nd_mfma_rows<JB>(macc, K + t * 64, ns, ns - t * 64, v, c0, c1, lane);
+    float* pf = reinterpret_cast<float*>(v + region);
+    if (CG > 1) {
+      if (cgi > 0) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              pf[((((cgi - 1) * TT + t) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane] = macc[rb][jb][r];
+      }
+      __syncthreads();
+      if (cgi > 0) return;
+      for (int o = 1; o < CG; ++o)
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              macc[rb][jb][r] += pf[((((o - 1) * TT + t) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
+    }
+    C out[KG];
+    nd_mfma_out<JB>(macc, pf + (long long)t * 64 * KG * 2, lane, out);
+    if (live) {
+      const int cell = fc[i];
+#pragma unroll
+      for (int q = 0; q < KG; ++q)
+        if (q < nq) X[(long long)(q0 + q) * nloc + cell] = out[q];
+    }
+    return;
+  }
+  C acc[KG];
+#pragma unroll
+  for (int q = 0; q < KG; ++q) acc[q] = zero;
+  if (live) nd_dot_rows<T, KG, false>(acc, K + i, ns, v, c0, c1);
+  C* part = v + region;
+  if (CG > 1) {
+    if (cgi > 0) {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) part[(((cgi - 1) * TT + t) * KG + q) * 64 + lane] = acc[q];
+    }
+    __syncthreads();
+    if (cgi > 0) return;
+    for (int o = 1; o < CG; ++o)
+#pragma unroll
+      for (int q = 0; q < KG; ++q) acc[q] = acc[q] + part[(((o - 1) * TT + t) * KG + q) * 64 + lane];
+  }
+  if (live) {
+    const int cell = fc[i];
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+      if (q < nq) X[(long long)(q0 + q) * nloc + cell] = acc[q];
   }
 }
 
 // Dense top: rows [64 tile, 64 tile + 64) of x_top = P_top g, g = r_top plus
 // the subtree roots' updates; the waves split the columns (each gathers its
-// own columns of g into LDS) and meet in LDS for the sum, in wave order.
+// own columns of g into LDS, one column per lane) and meet in LDS for the
+// sum, in wave order.
 template <typename T, int KG>
 __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
-    const NdTopJob* __restrict__ jobs, int njobs, int G, int ntiles,
-    const NdNodeDev* __restrict__ nodes, const int* __restrict__ cells,
-    const int* __restrict__ srcs, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
+    const NdTopJob* __restrict__ jobs, int njobs, int G, int ntiles, const int* __restrict__ cells,
+    const int* __restrict__ usrc, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
     const cpx<T>* __restrict__ upool, cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs,
     int kmax, int cwmax) {
   typedef cpx<T> C;
@@ -438,41 +727,107 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
   const C* __restrict__ U = upool + J.ubase;
   const C* __restrict__ P = fac + J.fac;
   const int* tc = cells + J.cell;
-  const int* sr = srcs + J.src;
+  const int* us = usrc + J.usrc;
   const long long nloc = J.nloc;
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const C zero = mk((T)0, (T)0);
-  const int q0 = g * KG;
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int cw = (ntop + ND_TW - 1) / ND_TW;
   const int c0 = min(ntop, w * cw), c1 = min(ntop, c0 + cw);
   C* gl = lds + (long long)w * cwmax * KG;
-  for (int e = lane; e < (c1 - c0) * KG; e += 64) {
-    const int j = c0 + e / KG, q = e - (e / KG) * KG, rq = q0 + q;
-    C v = zero;
-    if (rq < nrhs) {
-      v = R[(long long)rq * nloc + tc[j]];
-      for (int k = 0; k < J.dim2; ++k) {
-        const int r = sr[(j * J.dim2 + k) * 2];
-        if (r < 0) break;
-        const long long o = nodes[J.node0 + r].upd + sr[(j * J.dim2 + k) * 2 + 1];
-        v = v + U[o * kmax + rq];
+  for (int j = c0 + lane; j < c1; j += 64) {
+    int o[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o[k] = k < J.dim2 ? us[j * J.dim2 + k] : -1;
+    const C* Rc = R + (long long)q0 * nloc + tc[j];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      C v = zero;
+      if (q < nq) {
+        v = Rc[(long long)q * nloc];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (o[k] >= 0) v = v + U[(long long)o[k] * kmax + q0 + q];
       }
+      gl[(j - c0) * KG + q] = v;
     }
-    gl[e] = v;
   }
   nd_wave_sync();
   const int i = tile * 64 + lane;
+  if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
+    constexpr int JB = KG / 8;
+    nd_mf4 macc[4][JB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
+    // gl holds this wave's columns c0..c1 from its start: shift y so that y[col] = gl[col - c0]
+    nd_mfma_rows<JB>(macc, P + tile * 64 + (long long)c0 * ntop, ntop, ntop - tile * 64, gl - 0,
+                     0, c1 - c0, lane);
+    float* pf = reinterpret_cast<float*>(lds + (long long)ND_TW * cwmax * KG);
+    if (w > 0) {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            pf[(((w - 1) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane] = macc[rb][jb][r];
+    }
+    __syncthreads();
+    if (w > 0) return;
+    for (int o = 1; o < ND_TW; ++o)
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            macc[rb][jb][r] += pf[(((o - 1) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
+    C out[KG];
+    nd_mfma_out<JB>(macc, pf, lane, out);
+    if (i < ntop) {
+      const int cell = tc[i];
+#pragma unroll
+      for (int q = 0; q < KG; ++q)
+        if (q < nq) X[(long long)(q0 + q) * nloc + cell] = out[q];
+    }
+    return;
+  }
   C acc[KG];
 #pragma unroll
   for (int q = 0; q < KG; ++q) acc[q] = zero;
   if (i < ntop) {
-    for (int j = c0; j < c1; ++j) {
-      const C a = P[(long long)j * ntop + i];
+    // column loads eight at a time, one batch ahead of the FMAs that use them
+    constexpr int B = 8;
+    C a[B], b[B];
+    const C* __restrict__ Pi = P + i;
+    const int n = c1 - c0;
+    auto load = [&](C (&buf)[B], int j0) {
 #pragma unroll
-      for (int q = 0; q < KG; ++q) fma_acc(acc[q], a, gl[(j - c0) * KG + q]);
+      for (int u = 0; u < B; ++u) buf[u] = Pi[(long long)(c0 + min(j0 + u, n - 1)) * ntop];
+    };
+    auto use = [&](const C (&buf)[B], int j0) {
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        if (j0 + u >= n) break;
+#pragma unroll
+        for (int q = 0; q < KG; ++q) fma_acc(acc[q], buf[u], gl[(j0 + u) * KG + q]);
+      }
+    };
+    if (n > 0) {
+      load(a, 0);
+      for (int j0 = 0; j0 < n; j0 += 2 * B) {
+        if (j0 + B < n) load(b, j0 + B);
+        use(a, j0);
+        if (j0 + B < n) {
+          if (j0 + 2 * B < n) load(a, j0 + 2 * B);
+          use(b, j0 + B);
+        }
+      }
     }
   }
   C* part = lds + (long long)ND_TW * cwmax * KG;
@@ -488,13 +843,13 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
     const int cell = tc[i];
 #pragma unroll
     for (int q = 0; q < KG; ++q)
-      if (q0 + q < nrhs) X[(long long)(q0 + q) * nloc + cell] = acc[q];
+      if (q < nq) X[(long long)(q0 + q) * nloc + cell] = acc[q];
   }
 }
 
 template <typename T>
-size_t nd_sub_lds_bytes(int max_nf, int kg) {
-  return (size_t)ND_W * std::max(1, max_nf) * kg * sizeof(cpx<T>);
+size_t nd_lvl_lds_bytes(int max_nf, int kg) {
+  return (size_t)std::max(1, max_nf) * kg * sizeof(cpx<T>);
 }
 
 static size_t nd_top_lds_bytes(size_t ts, int max_ntop, int kg) {
@@ -506,31 +861,36 @@ template <typename T>
 int nd_kg(int max_nf, int kg, size_t lds_cap) {
   int k = 16;
   while (k > kg && k > 1) k >>= 1;
-  while (k > 1 && nd_sub_lds_bytes<T>(max_nf, k) > lds_cap) k >>= 1;
-  return nd_sub_lds_bytes<T>(max_nf, k) <= lds_cap ? k : 0;
+  while (k > 1 && nd_lvl_lds_bytes<T>(max_nf, k) > lds_cap) k >>= 1;
+  return nd_lvl_lds_bytes<T>(max_nf, k) <= lds_cap ? k : 0;
 }
 
 static unsigned nd_grid(long long tasks) { return (unsigned)(((tasks + 7) / 8) * 8); }
 
+// shape: tt <= 0: one node per wave, eight nodes per workgroup; else one node
+// per workgroup of tt row tiles x cg column groups of waves.
 template <typename T, int KG>
-static void launch_fwd_k(const NdSubJob* jobs, int njobs, const NdNodeDev* nodes, const int* lev,
-                         const int* levnodes, const int* cells, const int* maps, const cpx<T>* fac,
-                         cpx<T>* rpool, cpx<T>* upool, long long ps, int nrhs, int kmax,
-                         int max_nf, hipStream_t s) {
+static void launch_lvl_fwd_k(int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
+                             const int* umaps, const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool,
+                             long long ps, int nrhs, int kmax, int max_nf, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  hipLaunchKernelGGL((k_nd_fwd<T, KG>), dim3(nd_grid((long long)njobs * G)), dim3(64 * ND_W),
-                     nd_sub_lds_bytes<T>(max_nf, KG), s, jobs, njobs, G, nodes, lev, levnodes,
-                     cells, maps, fac, rpool, upool, ps, nrhs, kmax, max_nf * KG);
+  const int npw = tt <= 0 ? 8 : 1, wv = tt <= 0 ? 8 : tt * cg;
+  const int region = std::max(1, max_nf) * KG;
+  const long long groups = (njobs + npw - 1) / npw;
+  const size_t lds = tt <= 0 ? (size_t)npw * region
+                             : (size_t)region + (size_t)std::max(cg - 1, 1) * tt * 64 * KG;
+  hipLaunchKernelGGL((k_nd_lvl_fwd<T, KG>), dim3(nd_grid(groups * G)), dim3(64 * wv),
+                     lds * sizeof(cpx<T>), s, jobs, njobs, G, npw, region, std::max(1, tt),
+                     std::max(1, cg), cells, umaps, fac, rpool, upool, ps, nrhs, kmax);
 }
 
 template <typename T>
-void launch_nd_fwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nodes,
-                   const int* lev, const int* levnodes, const int* cells, const int* maps,
-                   const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool, long long pool_stride,
-                   int nrhs, int kmax, int max_nf, hipStream_t s) {
+void launch_nd_lvl_fwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
+                       const int* umaps, const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool,
+                       long long pool_stride, int nrhs, int kmax, int max_nf, hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0) return;
-#define ND_FWD(K) launch_fwd_k<T, K>(jobs, njobs, nodes, lev, levnodes, cells, maps, fac, rpool, \
-                                     upool, pool_stride, nrhs, kmax, max_nf, s)
+#define ND_FWD(K) launch_lvl_fwd_k<T, K>(tt, cg, jobs, njobs, cells, umaps, fac, rpool, upool, \
+                                         pool_stride, nrhs, kmax, max_nf, s)
   switch (kg) {
     case 16: ND_FWD(16); break;
     case 8: ND_FWD(8); break;
@@ -542,24 +902,27 @@ void launch_nd_fwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nod
 }
 
 template <typename T, int KG>
-static void launch_bwd_k(const NdSubJob* jobs, int njobs, const NdNodeDev* nodes, const int* lev,
-                         const int* levnodes, const int* cells, const cpx<T>* fac,
-                         const cpx<T>* rpool, cpx<T>* xpool, long long ps, int nrhs, int kmax,
-                         int max_nf, hipStream_t s) {
+static void launch_lvl_bwd_k(int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
+                             const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long ps,
+                             int nrhs, int max_nf, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  hipLaunchKernelGGL((k_nd_bwd<T, KG>), dim3(nd_grid((long long)njobs * G)), dim3(64 * ND_W),
-                     nd_sub_lds_bytes<T>(max_nf, KG), s, jobs, njobs, G, nodes, lev, levnodes,
-                     cells, fac, rpool, xpool, ps, nrhs, kmax, max_nf * KG);
+  const int npw = tt <= 0 ? 8 : 1, wv = tt <= 0 ? 8 : tt * cg;
+  const int region = std::max(1, max_nf) * KG;
+  const long long groups = (njobs + npw - 1) / npw;
+  const size_t lds = tt <= 0 ? (size_t)npw * region
+                             : (size_t)region + (size_t)std::max(cg - 1, 1) * tt * 64 * KG;
+  hipLaunchKernelGGL((k_nd_lvl_bwd<T, KG>), dim3(nd_grid(groups * G)), dim3(64 * wv),
+                     lds * sizeof(cpx<T>), s, jobs, njobs, G, npw, region, std::max(1, tt),
+                     std::max(1, cg), cells, fac, rpool, xpool, ps, nrhs);
 }
 
 template <typename T>
-void launch_nd_bwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nodes,
-                   const int* lev, const int* levnodes, const int* cells, const cpx<T>* fac,
-                   const cpx<T>* rpool, cpx<T>* xpool, long long pool_stride, int nrhs, int kmax,
-                   int max_nf, hipStream_t s) {
+void launch_nd_lvl_bwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
+                       const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool,
+                       long long pool_stride, int nrhs, int max_nf, hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0) return;
-#define ND_BWD(K) launch_bwd_k<T, K>(jobs, njobs, nodes, lev, levnodes, cells, fac, rpool, xpool, \
-                                     pool_stride, nrhs, kmax, max_nf, s)
+#define ND_BWD(K) launch_lvl_bwd_k<T, K>(tt, cg, jobs, njobs, cells, fac, rpool, xpool, pool_stride, \
+                                         nrhs, max_nf, s)
   switch (kg) {
     case 16: ND_BWD(16); break;
     case 8: ND_BWD(8); break;
@@ -571,30 +934,29 @@ void launch_nd_bwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nod
 }
 
 template <typename T, int KG>
-static void launch_top_k(const NdTopJob* jobs, int njobs, const NdNodeDev* nodes, const int* cells,
-                         const int* src, const cpx<T>* fac, const cpx<T>* rpool,
-                         const cpx<T>* upool, cpx<T>* xpool, long long ps, int nrhs, int kmax,
-                         int max_ntop, hipStream_t s) {
+static void launch_top_k(const NdTopJob* jobs, int njobs, const int* cells, const int* usrc,
+                         const cpx<T>* fac, const cpx<T>* rpool, const cpx<T>* upool,
+                         cpx<T>* xpool, long long ps, int nrhs, int kmax, int max_ntop,
+                         hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
   const int ntiles = (max_ntop + 63) / 64;
   const int cwmax = (max_ntop + ND_TW - 1) / ND_TW;
   hipLaunchKernelGGL((k_nd_top<T, KG>), dim3(nd_grid((long long)njobs * G * ntiles)),
                      dim3(64 * ND_TW), nd_top_lds_bytes(sizeof(cpx<T>), max_ntop, KG), s, jobs,
-                     njobs, G, ntiles, nodes, cells, src, fac, rpool, upool, xpool, ps, nrhs, kmax,
+                     njobs, G, ntiles, cells, usrc, fac, rpool, upool, xpool, ps, nrhs, kmax,
                      cwmax);
 }
 
 template <typename T>
-void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const NdNodeDev* nodes,
-                   const int* cells, const int* src, const cpx<T>* fac, const cpx<T>* rpool,
-                   const cpx<T>* upool, cpx<T>* xpool, long long pool_stride, int nrhs, int kmax,
-                   int max_ntop, hipStream_t s) {
+void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const int* cells, const int* usrc,
+                   const cpx<T>* fac, const cpx<T>* rpool, const cpx<T>* upool, cpx<T>* xpool,
+                   long long pool_stride, int nrhs, int kmax, int max_ntop, hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0 || max_ntop <= 0) return;
   // the largest RHS group (<= kg) whose gathered columns fit the LDS
   int k = 16;
   while (k > kg && k > 1) k >>= 1;
   while (k > 1 && nd_top_lds_bytes(sizeof(cpx<T>), max_ntop, k) > 160 * 1024) k >>= 1;
-#define ND_TOP(K) launch_top_k<T, K>(jobs, njobs, nodes, cells, src, fac, rpool, upool, xpool, \
+#define ND_TOP(K) launch_top_k<T, K>(jobs, njobs, cells, usrc, fac, rpool, upool, xpool, \
                                      pool_stride, nrhs, kmax, max_ntop, s)
   switch (k) {
     case 16: ND_TOP(16); break;
@@ -769,16 +1131,16 @@ void launch_nd_gemm(const NdGemmJob* jobs, int njobs, int max_m, int max_n, cpx<
 }
 
 #define ND_INST(T)                                                                              \
-  template void launch_nd_fwd<T>(int, const NdSubJob*, int, const NdNodeDev*, const int*,        \
-                                 const int*, const int*, const int*, const cpx<T>*, cpx<T>*,      \
-                                 cpx<T>*, long long, int, int, int, hipStream_t);                \
-  template void launch_nd_bwd<T>(int, const NdSubJob*, int, const NdNodeDev*, const int*,        \
-                                 const int*, const int*, const cpx<T>*, const cpx<T>*, cpx<T>*,   \
-                                 long long, int, int, int, hipStream_t);                         \
-  template void launch_nd_top<T>(int, const NdTopJob*, int, const NdNodeDev*, const int*,        \
-                                 const int*, const cpx<T>*, const cpx<T>*, const cpx<T>*,         \
-                                 cpx<T>*, long long, int, int, int, hipStream_t);                \
-  template size_t nd_sub_lds_bytes<T>(int, int);                                                 \
+  template void launch_nd_lvl_fwd<T>(int, int, int, const NdLvlJob*, int, const int*,           \
+                                     const int*, const cpx<T>*, cpx<T>*, cpx<T>*, long long, int, \
+                                     int, int, hipStream_t);                                     \
+  template void launch_nd_lvl_bwd<T>(int, int, int, const NdLvlJob*, int, const int*,           \
+                                     const cpx<T>*, const cpx<T>*, cpx<T>*, long long, int, int,  \
+                                     hipStream_t);                                               \
+  template void launch_nd_top<T>(int, const NdTopJob*, int, const int*, const int*,              \
+                                 const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*, long long, \
+                                 int, int, int, hipStream_t);                                    \
+  template size_t nd_lvl_lds_bytes<T>(int, int);                                                 \
   template int nd_kg<T>(int, int, size_t);                                                       \
   template void launch_nd_copy<T>(const NdCopyJob*, int, int, int, cpx<double>*, cpx<T>*,       \
                                   hipStream_t);

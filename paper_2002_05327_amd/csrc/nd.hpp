@@ -65,15 +65,17 @@ struct NdShapeTab {
   int node0 = 0;             // first node in the node table
   int top_cell = 0;          // top cells in the cell table
   int top_src = 0;           // top update sources (2 dim pairs per top cell)
+  int top_usrc = 0;          // the same as update-vector entries (2 dim per top cell)
   std::vector<int> lev0;     // per subtree: first entry in the level-pointer table
   std::vector<int> nlev;     // per subtree: levels
 };
 // Append one shape to the device tables (node, cell, gather-map, top-source,
-// level-pointer and level-node tables).  False if the analysis is
+// level-pointer, level-size and level-node tables).  False if the analysis is
 // inconsistent (a boundary outside its parent's front or the top).
 bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>& nodes,
-                      std::vector<int>& cells, std::vector<int>& maps, std::vector<int>& src,
-                      std::vector<int>& lev, std::vector<int>& levnodes);
+                      std::vector<int>& cells, std::vector<int>& maps, std::vector<int>& umaps,
+                      std::vector<int>& src, std::vector<int>& usrc, std::vector<int>& lev,
+                      std::vector<int>& levmax, std::vector<int>& levnodes);
 
 // ---- device tables ---------------------------------------------------------
 // Node table entry (shared by every subdomain of one shape).  The front's
@@ -83,32 +85,39 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
 struct NdNodeDev {
   int ns, nbd;
   int cell;                  // offset of the front's cells in the cell table
-  int map;                   // offset of the gather map (2 ints per front position)
+  int map;                   // offset of the gather map (2 ints per front position); the
+                             // update-map table (umaps) has the same layout, holding the
+                             // update entries (child upd + position) instead
   int ch0, ch1;              // children (node-table indices; -1 none)
   long long fac;             // factor offset within the subdomain: L (nbd x ns), then K (ns x nf)
   long long upd;             // update-vector offset within the member (entries)
 };
 
-// One (subdomain solve, subtree) of a launch: the subtree's level l holds the
-// nodes levnodes[lev[lev0 + l] .. lev[lev0 + l + 1]).
-struct NdSubJob {
-  int sub, l;                // subdomain, sweep slot
-  int lev0, nlev;            // level pointer range of this subtree
+// One node of one member in a level launch, with everything its kernels
+// need (no further descriptor loads): sizes, the front's cells, the update
+// entries its front gathers from (umap: 2 per front position, entries
+// relative to the member's base, -1 none), its factor and update offsets.
+struct NdLvlJob {
+  int ns, nbd;
+  int cell, umap;            // offsets in the cell table and the update-map table
+  int l;                     // sweep slot
+  int pad;
   long long nloc;            // local cells
-  long long fac;             // subdomain's factor base
+  long long fac;             // factor offset of the node (L, then K)
+  long long upd;             // update-vector entry of the node (within the member)
   long long vbase;           // vector-pool offset of the subdomain slice
   long long ubase;           // update-vector base of this member (entries x kmax)
 };
 
-// Dense top of one subdomain solve.  src holds, per top cell, dim2 pairs
-// (shape-local node id of a subtree root, position in its boundary) of the
-// updates that land on it (-1: none).
+// Dense top of one subdomain solve.  usrc holds, per top cell, dim2
+// update-vector entries (relative to the member's base; -1: none) of the
+// subtree-root updates that land on it.
 struct NdTopJob {
   int ntop, dim2;
-  int cell, src;             // offsets of the top cells and of their update sources
+  int cell, usrc;            // offsets of the top cells and of their update entries
   long long nloc, fac, vbase, ubase;
   int l;                     // sweep slot
-  int node0;                 // the shape's first node in the node table
+  int pad;
 };
 
 // Factorisation (FP64) jobs.
@@ -143,28 +152,30 @@ struct NdGemmJob {           // C = beta C + alpha A B  (FP64 complex, column-ma
   long long a, b, c;
 };
 
-// forward / backward subtree passes
+// One level of the forward / backward passes: one workgroup of `waves` waves
+// per (node, RHS group); max_nf = the largest front of the launch.
+// Shape (tt, cg): tt <= 0 runs one node per wave, eight per workgroup, lanes
+// over (row, RHS) pairs (the small nodes of the deep levels); otherwise one
+// node per workgroup of tt 64-row tiles x cg column groups of waves, lanes
+// over rows and the column groups summed in LDS (the large nodes).
 template <typename T>
-void launch_nd_fwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nodes,
-                   const int* lev, const int* levnodes, const int* cells, const int* maps,
-                   const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool, long long pool_stride,
-                   int nrhs, int kmax, int max_nf, hipStream_t s);
+void launch_nd_lvl_fwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
+                       const int* umaps, const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool,
+                       long long pool_stride, int nrhs, int kmax, int max_nf, hipStream_t s);
 template <typename T>
-void launch_nd_bwd(int kg, const NdSubJob* jobs, int njobs, const NdNodeDev* nodes,
-                   const int* lev, const int* levnodes, const int* cells, const cpx<T>* fac,
-                   const cpx<T>* rpool, cpx<T>* xpool, long long pool_stride, int nrhs, int kmax,
-                   int max_nf, hipStream_t s);
+void launch_nd_lvl_bwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
+                       const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool,
+                       long long pool_stride, int nrhs, int max_nf, hipStream_t s);
 // dense top: x_top = P_top (r_top + gathered updates)
 template <typename T>
-void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const NdNodeDev* nodes,
-                   const int* cells, const int* src, const cpx<T>* fac, const cpx<T>* rpool,
-                   const cpx<T>* upool, cpx<T>* xpool, long long pool_stride, int nrhs, int kmax,
-                   int max_ntop, hipStream_t s);
+void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const int* cells, const int* usrc,
+                   const cpx<T>* fac, const cpx<T>* rpool, const cpx<T>* upool, cpx<T>* xpool,
+                   long long pool_stride, int nrhs, int kmax, int max_ntop, hipStream_t s);
 // LDS the dense top needs with one right-hand side per workgroup
 size_t nd_top_lds_need(size_t ts, int max_ntop);
-// LDS of the subtree kernels, and the RHS per workgroup that fit
+// LDS of a level launch (max_nf front entries per RHS), and the RHS per workgroup that fit
 template <typename T>
-size_t nd_sub_lds_bytes(int max_nf, int kg);
+size_t nd_lvl_lds_bytes(int max_nf, int kg);
 template <typename T>
 int nd_kg(int max_nf, int kg, size_t lds_cap);
 

@@ -192,12 +192,17 @@ struct dsd_plan {
   Buf d_part_of[3], d_axparts[3];
   Buf d_subs_local, d_local_jobs;
   // nested dissection (solver 4): shapes, device tables, per launch group jobs
+  struct NdLevel {               // one level (depth below the subtree roots) of every subtree
+    int off = 0, n = 0;          // node jobs (d_nd_lvl)
+    int max_nf = 0, max_ns = 0, max_nbd = 0;
+    double fwd_bytes = 0, bwd_bytes = 0, cells = 0;   // factor bytes; front cells (vectors)
+  };
   struct NdLaunch {
-    int sub_off = 0, nsub = 0;   // subtree jobs (d_nd_sub)
+    std::vector<NdLevel> levels; // level 0 = the subtree roots
     int top_off = 0, ntop = 0;   // dense-top jobs (d_nd_top)
-    int max_nf = 0, max_ntop = 0;
-    double fwd_bytes = 0, bwd_bytes = 0, top_bytes = 0;   // factor bytes of each launch
-    double cells = 0;            // local cells of the members (vector traffic per RHS)
+    int max_ntop = 0;            // largest top
+    double top_bytes = 0;        // factor bytes of the dense-top launch
+    double top_cells = 0;        // top cells of the members
     long long upd = 0;           // update-vector entries per RHS of the members
   };
   std::vector<NdShape> nd_shapes;
@@ -205,10 +210,14 @@ struct dsd_plan {
   std::vector<int> nd_shape_of;                      // per subdomain
   std::vector<NdLaunch> nd_launch;                   // per launch group
   std::vector<NdLaunch> nd_local;                    // per subdomain (local solves)
-  Buf d_nd_nodes, d_nd_cells, d_nd_maps, d_nd_src, d_nd_lev, d_nd_levnodes;
-  Buf d_nd_sub, d_nd_top, d_upool;
+  Buf d_nd_nodes, d_nd_cells, d_nd_maps, d_nd_umaps, d_nd_src, d_nd_usrc, d_nd_lev, d_nd_levmax,
+      d_nd_levnodes;
+  Buf d_nd_lvl, d_nd_top, d_upool;
   long long nd_upd_max = 0;                          // entries per RHS of the update pool
-  int nd_max_nf = 0, nd_max_ntop = 0;
+  int nd_max_nf = 0, nd_max_ntop = 0;   // largest subtree front; largest dense top
+  std::vector<int> nd_cell_of, nd_map_of;  // per node-table entry: cell and map offsets
+  int nd_small = 4;    // levels whose largest node needs at most this many (row pass x
+                       // column) / 64 run one node per wave
   // Krylov workspace
   Buf d_V, d_Z, d_w, d_r, d_xa, d_ba, d_part, d_h1, d_h2, d_hn, d_scal, d_idx, d_coef;
   int kr_restart = 0, kr_k = 0;
@@ -1128,7 +1137,7 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs, bool loc
 // subdomain: the nodes' L and K blocks, then P_top) and the device tables.
 int nd_setup(dsd_plan* pl) {
   const dsd_params& q = pl->prm;
-  const int leaf = q.nd_leaf > 0 ? q.nd_leaf : 16;
+  const int leaf = q.nd_leaf > 0 ? q.nd_leaf : 128;
   const int ntop_max = q.nd_top_cells > 0 ? q.nd_top_cells : 1200;
   std::map<std::tuple<int, int, int>, int> shape_id;
   pl->nd_shapes.clear();
@@ -1144,12 +1153,13 @@ int nd_setup(dsd_plan* pl) {
     pl->nd_shape_of[s] = it->second;
   }
   std::vector<NdNodeDev> nodes;
-  std::vector<int> cells, maps, src, lev, levnodes;
+  std::vector<int> cells, maps, umaps, src, usrc, lev, levmax, levnodes;
   pl->nd_tabs.assign(pl->nd_shapes.size(), NdShapeTab{});
   pl->nd_max_nf = pl->nd_max_ntop = 0;
   for (size_t k = 0; k < pl->nd_shapes.size(); ++k) {
     const NdShape& sh = pl->nd_shapes[k];
-    if (!nd_append_tables(sh, pl->nd_tabs[k], nodes, cells, maps, src, lev, levnodes)) {
+    if (!nd_append_tables(sh, pl->nd_tabs[k], nodes, cells, maps, umaps, src, usrc, lev,
+                          levmax, levnodes)) {
       g_detail = "internal error: nested-dissection tables inconsistent";
       return DSD_EINVAL;
     }
@@ -1166,26 +1176,39 @@ int nd_setup(dsd_plan* pl) {
     foff += pl->nd_shapes[pl->nd_shape_of[s]].fac_entries;
   }
   pl->sum_fac = foff;
+  pl->nd_cell_of.resize(nodes.size());
+  pl->nd_map_of.resize(nodes.size());
+  for (size_t i = 0; i < nodes.size(); ++i) {
+    pl->nd_cell_of[i] = nodes[i].cell;
+    pl->nd_map_of[i] = nodes[i].map;
+  }
   CHK(upload(pl->d_nd_nodes, nodes));
   CHK(upload(pl->d_nd_cells, cells));
   CHK(upload(pl->d_nd_maps, maps));
+  CHK(upload(pl->d_nd_umaps, umaps));
   CHK(upload(pl->d_nd_src, src));
+  CHK(upload(pl->d_nd_usrc, usrc));
   CHK(upload(pl->d_nd_lev, lev));
+  CHK(upload(pl->d_nd_levmax, levmax));
   CHK(upload(pl->d_nd_levnodes, levnodes));
   return 0;
 }
 
-// Solve jobs of a set of members {subdomain, sweep slot}: every subtree of
-// every member, and every member's dense top.  Update vectors of member i
-// start at the sum of the earlier members' (entries x kmax).  With `local`
-// the vectors are addressed from offset 0 (vbase = 0) and kmax is the call's
-// right-hand-side count (passed at launch), so ubase is in entries per RHS.
+// Solve jobs of a set of members {subdomain, sweep slot}: every node of every
+// member's subtrees, grouped by level (depth below its subtree root), and
+// every member's dense top.  Update vectors of member i start at the sum of
+// the earlier members' (entries x kmax).  With `local` the vectors are
+// addressed from offset 0 (vbase = 0) and kmax is the call's right-hand-side
+// count (passed at launch), so ubase is in entries per RHS.
 void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
-                   std::vector<NdSubJob>& sj, std::vector<NdTopJob>& tj, dsd_plan::NdLaunch& L) {
+                   std::vector<NdLvlJob>& lj, std::vector<NdTopJob>& tj, dsd_plan::NdLaunch& L) {
   const double ts = (double)tsize(pl);
   L = dsd_plan::NdLaunch{};
-  L.sub_off = (int)sj.size();
   L.top_off = (int)tj.size();
+  int nlev = 0;
+  for (const int2& m : mem) nlev = std::max(nlev, pl->nd_shapes[pl->nd_shape_of[m.x]].nlev);
+  std::vector<std::vector<NdLvlJob>> per(nlev);
+  L.levels.assign(nlev, dsd_plan::NdLevel{});
   long long ubase = 0;
   for (const int2& m : mem) {
     const SubDesc& S = pl->subs[m.x];
@@ -1194,52 +1217,60 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     const NdShapeTab& tb = pl->nd_tabs[k];
     const long long vb = local ? 0 : S.vec_off * pl->kmax;
     const long long ub = local ? ubase : ubase * pl->kmax;
-    for (size_t r = 0; r < sh.roots.size(); ++r) {
-      NdSubJob J{};
-      J.sub = m.x;
+    for (size_t i = 0; i < sh.nodes.size(); ++i) {
+      const NdNode& n = sh.nodes[i];
+      if (n.top) continue;
+      const int ns = (int)n.sep.size(), nb = (int)n.bnd.size();
+      NdLvlJob J{};
+      J.ns = ns;
+      J.nbd = nb;
+      J.cell = pl->nd_cell_of[tb.node0 + i];
+      J.umap = pl->nd_map_of[tb.node0 + i];
       J.l = m.y;
-      J.lev0 = tb.lev0[r];
-      J.nlev = tb.nlev[r];
       J.nloc = S.nloc;
-      J.fac = S.fac_off;
+      J.fac = S.fac_off + n.fac;
+      J.upd = n.upd;
       J.vbase = vb;
       J.ubase = ub;
-      sj.push_back(J);
+      per[n.level].push_back(J);
+      dsd_plan::NdLevel& V = L.levels[n.level];
+      V.max_nf = std::max(V.max_nf, ns + nb);
+      V.max_ns = std::max(V.max_ns, ns);
+      V.max_nbd = std::max(V.max_nbd, nb);
+      V.fwd_bytes += (double)nb * ns * ts;
+      V.bwd_bytes += (double)ns * (ns + nb) * ts;
+      V.cells += (double)(ns + nb);
     }
     if (sh.ntop() > 0) {
       NdTopJob T{};
       T.ntop = sh.ntop();
       T.dim2 = 2 * pl->dim;
       T.cell = tb.top_cell;
-      T.src = tb.top_src;
+      T.usrc = tb.top_usrc;
       T.nloc = S.nloc;
       T.fac = S.fac_off + sh.top_fac;
       T.vbase = vb;
       T.ubase = ub;
       T.l = m.y;
-      T.node0 = tb.node0;
       tj.push_back(T);
     }
-    for (const NdNode& n : sh.nodes) {
-      if (n.top) continue;
-      const double ns = (double)n.sep.size(), nb = (double)n.bnd.size();
-      L.fwd_bytes += nb * ns * ts;
-      L.bwd_bytes += ns * (ns + nb) * ts;
-    }
     L.top_bytes += (double)sh.ntop() * sh.ntop() * ts;
-    L.cells += (double)S.nloc;
-    L.max_nf = std::max(L.max_nf, sh.max_nf);
+    L.top_cells += (double)sh.ntop();
     L.max_ntop = std::max(L.max_ntop, sh.ntop());
     ubase += sh.upd_entries;
   }
-  L.nsub = (int)sj.size() - L.sub_off;
+  for (int l = 0; l < nlev; ++l) {
+    L.levels[l].off = (int)lj.size();
+    L.levels[l].n = (int)per[l].size();
+    lj.insert(lj.end(), per[l].begin(), per[l].end());
+  }
   L.ntop = (int)tj.size() - L.top_off;
   L.upd = ubase;
 }
 
 // Job tables of every launch group and of every subdomain's local solve.
 int build_nd_jobs(dsd_plan* pl) {
-  std::vector<NdSubJob> sj;
+  std::vector<NdLvlJob> sj;
   std::vector<NdTopJob> tj;
   pl->nd_launch.assign(pl->groups.size(), dsd_plan::NdLaunch{});
   pl->nd_upd_max = 0;
@@ -1252,7 +1283,7 @@ int build_nd_jobs(dsd_plan* pl) {
     nd_group_jobs(pl, std::vector<int2>{make_int2(s, 0)}, true, sj, tj, pl->nd_local[s]);
     pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_local[s].upd);
   }
-  CHK(upload(pl->d_nd_sub, sj));
+  CHK(upload(pl->d_nd_lvl, sj));
   CHK(upload(pl->d_nd_top, tj));
   return 0;
 }
@@ -1660,34 +1691,70 @@ void time_flush(dsd_plan* pl) {
   pl->tev_used = 0;
 }
 
+int device_lds();
+
+// Shape of a level launch (rows x cols: the level's largest matrix): one
+// node per wave when its (row, RHS) passes times its columns are at most
+// `small` x 64 and eight fronts fit the LDS (tt = 0); else one node per
+// workgroup of tt 64-row tiles x cg column groups (about 24 columns or more
+// per group, at most eight waves).
+void nd_shape(int rows, int cols, int kg, int max_nf, size_t ts, int small, int& tt, int& cg) {
+  const int rpp = 64 / std::max(1, kg);
+  const int passes = (rows + rpp - 1) / rpp;
+  if ((long long)passes * cols <= (long long)small * 64 &&
+      (size_t)8 * max_nf * kg * ts <= (size_t)device_lds()) {
+    tt = 0;
+    cg = 1;
+    return;
+  }
+  tt = std::max(1, std::min(8, (rows + 63) / 64));
+  cg = std::max(1, std::min(8 / tt, (cols + 23) / 24));
+  // the column groups' partial sums must fit next to the front
+  while (cg > 1 && ((size_t)max_nf * kg + (size_t)(cg - 1) * tt * 64 * kg) * ts > (size_t)device_lds())
+    --cg;
+}
+
 // The nested-dissection solves of one launch (a launch group's members or
-// one subdomain): forward subtree passes, the dense tops, backward passes.
-// Timed launches carry their factor bytes plus the vectors (read and write of
-// the members' local cells per RHS) and 8 flops per factor entry and RHS.
+// one subdomain): the forward levels from the deepest to the subtree roots,
+// the dense tops, the backward levels.  Timed launches carry their factor
+// bytes plus their vectors (the fronts read and the rows written per RHS) and
+// 8 flops per factor entry and RHS.
 template <typename T>
 void nd_phase(dsd_plan* pl, const dsd_plan::NdLaunch& L, cpx<T>* R, cpx<T>* X, cpx<T>* U,
               long long pool_stride, int nrhs, int kmax, bool timed) {
   hipStream_t st = pl->stream;
-  const NdSubJob* sj = pl->d_nd_sub.as<NdSubJob>() + L.sub_off;
+  const NdLvlJob* lj = pl->d_nd_lvl.as<NdLvlJob>();
   const NdTopJob* tj = pl->d_nd_top.as<NdTopJob>() + L.top_off;
-  const NdNodeDev* nodes = pl->d_nd_nodes.as<NdNodeDev>();
   const cpx<T>* fac = pl->d_fac.as<cpx<T>>();
-  const double ts = (double)sizeof(cpx<T>), vec = 2.0 * L.cells * nrhs * ts;
-  if (timed) time_begin(pl);
-  launch_nd_fwd<T>(pl->kg, sj, L.nsub, nodes, pl->d_nd_lev.as<int>(), pl->d_nd_levnodes.as<int>(),
-                   pl->d_nd_cells.as<int>(), pl->d_nd_maps.as<int>(), fac, R, U, pool_stride, nrhs,
-                   kmax, L.max_nf, st);
-  if (timed) time_end(pl, L.fwd_bytes + vec, L.fwd_bytes / ts * nrhs * 8.0);
+  const double ts = (double)sizeof(cpx<T>);
+  const int nlev = (int)L.levels.size();
+  for (int l = nlev - 1; l >= 0; --l) {
+    const dsd_plan::NdLevel& V = L.levels[l];
+    if (V.n == 0) continue;
+    if (timed) time_begin(pl);
+    int tt, cg;
+    nd_shape(V.max_nbd, V.max_ns, pl->kg, V.max_nf, sizeof(cpx<T>), pl->nd_small, tt, cg);
+    launch_nd_lvl_fwd<T>(pl->kg, tt, cg, lj + V.off, V.n,
+                         pl->d_nd_cells.as<int>(), pl->d_nd_umaps.as<int>(), fac, R, U, pool_stride,
+                         nrhs, kmax, V.max_nf, st);
+    if (timed) time_end(pl, V.fwd_bytes + 2.0 * V.cells * nrhs * ts, V.fwd_bytes / ts * nrhs * 8.0);
+  }
   if (L.ntop > 0) {
     if (timed) time_begin(pl);
-    launch_nd_top<T>(pl->kg, tj, L.ntop, nodes, pl->d_nd_cells.as<int>(), pl->d_nd_src.as<int>(),
-                     fac, R, U, X, pool_stride, nrhs, kmax, L.max_ntop, st);
-    if (timed) time_end(pl, L.top_bytes + vec, L.top_bytes / ts * nrhs * 8.0);
+    launch_nd_top<T>(pl->kg, tj, L.ntop, pl->d_nd_cells.as<int>(), pl->d_nd_usrc.as<int>(), fac,
+                     R, U, X, pool_stride, nrhs, kmax, L.max_ntop, st);
+    if (timed) time_end(pl, L.top_bytes + 2.0 * L.top_cells * nrhs * ts, L.top_bytes / ts * nrhs * 8.0);
   }
-  if (timed) time_begin(pl);
-  launch_nd_bwd<T>(pl->kg, sj, L.nsub, nodes, pl->d_nd_lev.as<int>(), pl->d_nd_levnodes.as<int>(),
-                   pl->d_nd_cells.as<int>(), fac, R, X, pool_stride, nrhs, kmax, L.max_nf, st);
-  if (timed) time_end(pl, L.bwd_bytes + vec, L.bwd_bytes / ts * nrhs * 8.0);
+  for (int l = 0; l < nlev; ++l) {
+    const dsd_plan::NdLevel& V = L.levels[l];
+    if (V.n == 0) continue;
+    if (timed) time_begin(pl);
+    int tt, cg;
+    nd_shape(V.max_ns, V.max_nf, pl->kg, V.max_nf, sizeof(cpx<T>), pl->nd_small, tt, cg);
+    launch_nd_lvl_bwd<T>(pl->kg, tt, cg, lj + V.off, V.n,
+                         pl->d_nd_cells.as<int>(), fac, R, X, pool_stride, nrhs, V.max_nf, st);
+    if (timed) time_end(pl, V.bwd_bytes + 2.0 * V.cells * nrhs * ts, V.bwd_bytes / ts * nrhs * 8.0);
+  }
 }
 
 template <typename T>
@@ -1959,11 +2026,26 @@ int gmres_batch(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, do
     std::vector<int> js(na, -1);
     for (int k = 0; k < na; ++k) g[k][0] = beta0[k];
     int jmax = 0;
+    std::vector<int> live, dead;
     for (int j = 0; j < restart; ++j) {
-      bool any = false;
-      for (int k = 0; k < na; ++k) any = any || js[k] < 0;
-      if (!any) break;
-      CHK(sweep_apply_any(pl, V + j * vs, Z + j * vs, na));
+      live.clear();
+      dead.clear();
+      for (int k = 0; k < na; ++k) (js[k] < 0 ? live : dead).push_back(k);
+      if (live.empty()) break;
+      if (dead.empty()) {
+        CHK(sweep_apply_any(pl, V + j * vs, Z + j * vs, na));
+      } else {
+        // only the right-hand sides still iterating are swept (gathered into
+        // the residual and right-hand-side work rows, free inside a cycle);
+        // the others' rows of Z_j are zero, so every later row stays finite
+        const int nl = (int)live.size(), nd = (int)dead.size();
+        HIPCHK(hipMemcpyAsync(idx, live.data(), nl * sizeof(int), hipMemcpyHostToDevice, st));
+        launch_gather_rhs(V + j * vs, idx, r, nl, N, st);
+        CHK(sweep_apply_any(pl, r, ba, nl));
+        launch_scatter_rhs(ba, idx, Z + j * vs, nl, N, st);
+        HIPCHK(hipMemcpyAsync(idx, dead.data(), nd * sizeof(int), hipMemcpyHostToDevice, st));
+        launch_zero_rhs(Z + j * vs, idx, nd, N, st);
+      }
       launch_apply_op(pl->P, pl->d_gcoef[0].as<cpx<double>>(), pl->d_gcoef[1].as<cpx<double>>(),
                       pl->d_gcoef[2].as<cpx<double>>(), pl->d_gcoef[3].as<cpx<double>>(),
                       Z + j * vs, w, na, st);
@@ -1982,7 +2064,7 @@ int gmres_batch(dsd_plan* pl, const cpx<double>* b, cpx<double>* x, int nrhs, do
       for (int k = 0; k < na; ++k) {
         const double hnorm = std::sqrt(hhn[k].re);
         if (!std::isfinite(hnorm)) { g_detail = "non-finite Arnoldi norm"; return DSD_ENOTFINITE; }
-        hscal[k] = hnorm > 1e-300 ? 1.0 / hnorm : 0.0;
+        hscal[k] = hnorm > 1e-300 && js[k] < 0 ? 1.0 / hnorm : 0.0;
       }
       HIPCHK(hipMemcpyAsync(scal, hscal.data(), na * sizeof(double), hipMemcpyHostToDevice, st));
       launch_scale(w, scal, V + (j + 1) * vs, na, N, st);
