@@ -41,7 +41,7 @@ def _inputs(name):
     return w, c, F
 
 
-def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_top=0):
+def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_top=0, nd_wide=0):
     import torch
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(1.0 / c ** 2).cuda()
@@ -49,7 +49,7 @@ def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_
     t0 = time.perf_counter()
     plan = dsw.Plan(n=w.n, h=w.h, omega=w.omega, pml=w.pml, overlap=w.overlap, parts=w.parts,
                     m=m, precision=prec, max_rhs=w.nrhs, rhs_per_group=kg, local_solver=solver,
-                    nd_leaf=nd_leaf, nd_top_cells=nd_top)
+                    nd_leaf=nd_leaf, nd_top_cells=nd_top, nd_wide=nd_wide)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"# {prec} plan ready ({plan.local_solver} local solver): factorisation {dt:.2f} s",
@@ -327,6 +327,8 @@ def main():
     ap.add_argument("--solver", default="auto", help="local solver: auto, nd, bcr, chain, chain-steps")
     ap.add_argument("--nd-leaf", type=int, default=0, help="nested dissection: leaf box cells (0: library)")
     ap.add_argument("--nd-top", type=int, default=0, help="nested dissection: dense-top cells (0: library)")
+    ap.add_argument("--nd-wide", type=int, default=0,
+                    help="nested dissection: fronts of at least this many cells in wide mode (0: library)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the solve-launch shapes first (reported separately)")
     ap.add_argument("--graph", action="store_true",
@@ -354,7 +356,7 @@ def main():
     print(f"# workload {w.name}: n={w.n} parts={w.parts} nrhs={w.nrhs}", file=sys.stderr, flush=True)
 
     plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph, args.autotune, args.solver,
-                         args.nd_leaf, args.nd_top)
+                         args.nd_leaf, args.nd_top, args.nd_wide)
     print(f"# c64 factorisation {tf64:.2f} s", file=sys.stderr, flush=True)
     dt64, its64, rel64, ok64, x64, steps64 = _solve_steps(plan64, b, args.tol, args.maxit,
                                                           args.restart, args.warmup, args.steps)
@@ -368,7 +370,7 @@ def main():
     c128 = None
     if not args.no_c128:
         plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph, args.autotune, args.solver,
-                               args.nd_leaf, args.nd_top)
+                               args.nd_leaf, args.nd_top, args.nd_wide)
         n128 = max(1, min(args.steps, 5))
         dt128, its128, rel128, ok128, x128, steps128 = _solve_steps(
             plan128, b, args.tol, args.maxit, args.restart, min(args.warmup, 1), n128)

@@ -103,6 +103,11 @@ typedef struct {
   int nd_top_cells;      /* nested dissection: the separators of the shallowest depths
                             whose cells total at most this many form the dense top
                             (0: 1200; at most 5000)                                    */
+  int nd_wide;           /* nested dissection: nodes whose front (separator plus
+                            boundary) has at least this many cells apply their blocks
+                            as tiled products over all right-hand sides of a group at
+                            once, the vectors streamed through LDS (0: 1024); nodes
+                            with more than 512 rows always do                          */
 } dsd_params;
 
 /*

@@ -43,7 +43,8 @@ class Plan:
                  parts: Sequence[int], m: torch.Tensor, precision: str = "c64",
                  max_rhs: int = 1, rhs_per_group: int = 0, sigma0_delta: float = 60.0,
                  schedule: str = "dag", local_solver: str = "auto", dense_top: int = 0,
-                 sweep_order: str = "default", nd_leaf: int = 0, nd_top_cells: int = 0):
+                 sweep_order: str = "default", nd_leaf: int = 0, nd_top_cells: int = 0,
+                 nd_wide: int = 0):
         self._lib = _lib.load()
         dim = len(n)
         if dim not in (2, 3) or len(parts) != dim:
@@ -61,7 +62,7 @@ class Plan:
         p.local_solver = {"auto": 0, "chain": 1, "bcr": 2, "chain-steps": 3, "nd": 4}[local_solver]
         p.dense_top = int(dense_top)
         p.sweep_order = {"default": 0, "l1": 1}[sweep_order]
-        p.nd_leaf, p.nd_top_cells = int(nd_leaf), int(nd_top_cells)
+        p.nd_leaf, p.nd_top_cells, p.nd_wide = int(nd_leaf), int(nd_top_cells), int(nd_wide)
         self.params = p
         self.n, self.dim, self.pml, self.omega = tuple(int(k) for k in n), dim, int(pml), omega
         self.precision, self.max_rhs = precision, int(max_rhs)

@@ -847,6 +847,194 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
   }
 }
 
+// ---- wide mode: nodes whose front is too large for the LDS (or with more
+// than 512 rows) run their products as tiled matrix products over every
+// right-hand side of a group of KG (up to 32) at once, so that each factor
+// entry is read once per solve.  A workgroup of four waves takes 256 rows of
+// one node; the columns stream through LDS in chunks of ND_WCK (the vector
+// entries of the chunk for all KG right-hand sides, double-buffered), each wave
+// multiplies its 64-row tile.  The forward pass first forms f_S (k_nd_form)
+// and ends with u_B = (children's updates on B) - L f_S; the backward pass is
+// x_S = K [f_S; -x_B].  Tiles are {job, first row} entries of a table.
+constexpr int ND_WCK = 64;
+
+// f_S = r_S + children's updates on S, into R: one thread per (position, RHS)
+template <typename T>
+__global__ __launch_bounds__(256) void k_nd_form(const NdLvlJob* __restrict__ jobs,
+                                                 const int2* __restrict__ tiles, int ntiles,
+                                                 const int* __restrict__ cells,
+                                                 const int* __restrict__ umaps,
+                                                 cpx<T>* __restrict__ rpool,
+                                                 const cpx<T>* __restrict__ upool,
+                                                 long long pool_stride, int nrhs, int kmax) {
+  const int tix = nd_task(blockIdx.x, gridDim.x);
+  if (tix >= ntiles) return;
+  const int2 t = tiles[tix];
+  const NdLvlJob J = jobs[t.x];
+  cpx<T>* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  const cpx<T>* __restrict__ U = upool + J.ubase;
+  const int* fc = cells + J.cell;
+  const int* um = umaps + J.umap;
+  const int span = min(256, J.ns - t.y);
+  for (int e = threadIdx.x; e < span * nrhs; e += 256) {
+    const int p = t.y + e / nrhs, q = e - (e / nrhs) * nrhs;
+    const int i0 = um[2 * p], i1 = um[2 * p + 1];
+    cpx<T>* r = R + (long long)q * J.nloc + fc[p];
+    cpx<T> v = *r;
+    if (i0 >= 0) v = v + U[(long long)i0 * kmax + q];
+    if (i1 >= 0) v = v + U[(long long)i1 * kmax + q];
+    *r = v;
+  }
+}
+
+// Stage the vector entries of columns [c0, c0 + n) for right-hand sides
+// [q0, q0 + nq) into buf[c * KG + q] (zero beyond n or nq): column c < ns
+// from R (f_S), column c >= ns from -X (boundary, backward pass only).
+template <typename T, int KG>
+__device__ __forceinline__ void nd_wide_stage(cpx<T>* buf, const int* fc, int ns, int c0, int n,
+                                              int q0, int nq, const cpx<T>* R, const cpx<T>* X,
+                                              long long nloc) {
+  for (int e = threadIdx.x; e < ND_WCK * KG; e += blockDim.x) {
+    const int c = e / KG, q = e - (e / KG) * KG;
+    cpx<T> v = mk((T)0, (T)0);
+    if (c < n && q < nq) {
+      const int col = c0 + c;
+      const long long o = (long long)(q0 + q) * nloc + fc[col];
+      v = col < ns ? R[o] : -X[o];
+    }
+    buf[e] = v;
+  }
+}
+
+// acc (rows row0 + 64 w + lane) = A[rows, 0:ncol] y, A column-major (lda), the
+// columns staged chunk by chunk; complex64 on the FP32 matrix cores, complex128
+// with vector FMAs.  Returns the tile's values for this lane's row in out.
+template <typename T, int KG>
+__device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, long long lda,
+                                                int nrows_tile, int ncol, int ns, const int* fc,
+                                                int q0, int nq, const cpx<T>* R, const cpx<T>* X,
+                                                long long nloc, cpx<T>* lds, cpx<T> (&out)[KG]) {
+  typedef cpx<T> C;
+  const int lane = threadIdx.x & 63;
+  C* buf0 = lds;
+  C* buf1 = lds + ND_WCK * KG;
+  const int nch = (ncol + ND_WCK - 1) / ND_WCK;
+  if (nch > 0) nd_wide_stage<T, KG>(buf0, fc, ns, 0, min(ND_WCK, ncol), q0, nq, R, X, nloc);
+  __syncthreads();
+  if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
+    constexpr int JB = KG / 8;
+    nd_mf4 macc[4][JB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < nch; ++k) {
+      C* cur = (k & 1) ? buf1 : buf0;
+      C* nxt = (k & 1) ? buf0 : buf1;
+      const int c0 = k * ND_WCK, cn = min(ND_WCK, ncol - c0);
+      if (k + 1 < nch)
+        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ncol - c0 - ND_WCK), q0, nq, R,
+                             X, nloc);
+      if (nrows_tile > 0) nd_mfma_rows<JB>(macc, A + (long long)c0 * lda, lda, nrows_tile, cur, 0, cn, lane);
+      __syncthreads();
+    }
+    // the staging buffers are free now: each wave turns its tile into rows
+    float* st = reinterpret_cast<float*>(lds) + (threadIdx.x >> 6) * 64 * KG * 2;
+    nd_mfma_out<JB>(macc, st, lane, out);
+  } else {
+#pragma unroll
+    for (int q = 0; q < KG; ++q) out[q] = mk((T)0, (T)0);
+    for (int k = 0; k < nch; ++k) {
+      C* cur = (k & 1) ? buf1 : buf0;
+      C* nxt = (k & 1) ? buf0 : buf1;
+      const int c0 = k * ND_WCK, cn = min(ND_WCK, ncol - c0);
+      if (k + 1 < nch)
+        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ncol - c0 - ND_WCK), q0, nq, R,
+                             X, nloc);
+      if (lane < nrows_tile) nd_dot_rows<T, KG, false>(out, A + (long long)c0 * lda + lane, lda, cur, 0, cn);
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+constexpr size_t nd_wide_lds_entries(int kg) {
+  // two staging chunks; the MFMA output staging (4 waves x 64 x KG) reuses them
+  return (size_t)std::max(2 * ND_WCK * kg, 4 * 64 * kg);
+}
+
+// u_B = (children's updates on B) - L f_S for rows [t.y, t.y + 256) of node t.x
+template <typename T, int KG>
+__global__ __launch_bounds__(256) void k_nd_wide_fwd(
+    const NdLvlJob* __restrict__ jobs, const int2* __restrict__ tiles, int ntiles, int G,
+    const int* __restrict__ cells, const int* __restrict__ umaps, const cpx<T>* __restrict__ fac,
+    const cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ upool, long long pool_stride,
+    int nrhs, int kmax) {
+  typedef cpx<T> C;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int tix = Lg / G, g = Lg - (Lg / G) * G;
+  if (tix >= ntiles) return;
+  const int2 t = tiles[tix];
+  const NdLvlJob J = jobs[t.x];
+  const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ U = upool + J.ubase;
+  const int ns = J.ns, nbd = J.nbd;
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = t.y + 64 * w;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C out[KG];
+  nd_wide_product<T, KG>(fac + J.fac + r0, nbd, max(0, min(64, nbd - r0)), ns, ns, cells + J.cell,
+                         q0, nq, R, R, J.nloc, lds, out);
+  const int i = r0 + lane;
+  if (i < nbd) {
+    const int p = ns + i;
+    const int i0 = umaps[J.umap + 2 * p], i1 = umaps[J.umap + 2 * p + 1];
+#pragma unroll
+    for (int q = 0; q < KG; ++q) {
+      if (q < nq) {
+        C v = mk((T)0, (T)0);
+        if (i0 >= 0) v = v + U[(long long)i0 * kmax + q0 + q];
+        if (i1 >= 0) v = v + U[(long long)i1 * kmax + q0 + q];
+        U[(J.upd + i) * kmax + q0 + q] = v - out[q];
+      }
+    }
+  }
+}
+
+// x_S = K [f_S; -x_B] for rows [t.y, t.y + 256) of node t.x
+template <typename T, int KG>
+__global__ __launch_bounds__(256) void k_nd_wide_bwd(
+    const NdLvlJob* __restrict__ jobs, const int2* __restrict__ tiles, int ntiles, int G,
+    const int* __restrict__ cells, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
+    cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs) {
+  typedef cpx<T> C;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int tix = Lg / G, g = Lg - (Lg / G) * G;
+  if (tix >= ntiles) return;
+  const int2 t = tiles[tix];
+  const NdLvlJob J = jobs[t.x];
+  const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+  C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
+  const int ns = J.ns, nf = J.ns + J.nbd;
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int r0 = t.y + 64 * w;
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  C out[KG];
+  nd_wide_product<T, KG>(fac + J.fac + (long long)J.nbd * ns + r0, ns, max(0, min(64, ns - r0)), nf,
+                         ns, cells + J.cell, q0, nq, R, X, J.nloc, lds, out);
+  const int i = r0 + lane;
+  if (i < ns) {
+    const int cell = cells[J.cell + i];
+#pragma unroll
+    for (int q = 0; q < KG; ++q)
+      if (q < nq) X[(long long)(q0 + q) * J.nloc + cell] = out[q];
+  }
+}
+
 template <typename T>
 size_t nd_lvl_lds_bytes(int max_nf, int kg) {
   return (size_t)std::max(1, max_nf) * kg * sizeof(cpx<T>);
@@ -952,10 +1140,7 @@ void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const int* cells, co
                    const cpx<T>* fac, const cpx<T>* rpool, const cpx<T>* upool, cpx<T>* xpool,
                    long long pool_stride, int nrhs, int kmax, int max_ntop, hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0 || max_ntop <= 0) return;
-  // the largest RHS group (<= kg) whose gathered columns fit the LDS
-  int k = 16;
-  while (k > kg && k > 1) k >>= 1;
-  while (k > 1 && nd_top_lds_bytes(sizeof(cpx<T>), max_ntop, k) > 160 * 1024) k >>= 1;
+  const int k = kg;
 #define ND_TOP(K) launch_top_k<T, K>(jobs, njobs, cells, usrc, fac, rpool, upool, xpool, \
                                      pool_stride, nrhs, kmax, max_ntop, s)
   switch (k) {
@@ -968,8 +1153,75 @@ void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const int* cells, co
 #undef ND_TOP
 }
 
+// ---- wide-mode launchers
+template <typename T>
+void launch_nd_form(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                    const int* umaps, cpx<T>* rpool, const cpx<T>* upool, long long pool_stride,
+                    int nrhs, int kmax, hipStream_t s) {
+  if (ntiles <= 0 || nrhs <= 0) return;
+  hipLaunchKernelGGL(k_nd_form<T>, dim3(nd_grid(ntiles)), dim3(256), 0, s, jobs, tiles, ntiles,
+                     cells, umaps, rpool, upool, pool_stride, nrhs, kmax);
+}
+
+int nd_wide_kg(size_t ts, int nrhs) {
+  if (ts > sizeof(cpx<float>)) return 8;
+  return nrhs <= 8 ? 8 : nrhs <= 16 ? 16 : 32;
+}
+
+template <typename T, int KG>
+static void launch_wide_fwd_k(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                              const int* umaps, const cpx<T>* fac, const cpx<T>* rpool,
+                              cpx<T>* upool, long long ps, int nrhs, int kmax, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  hipLaunchKernelGGL((k_nd_wide_fwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(256),
+                     nd_wide_lds_entries<T>(KG) * sizeof(cpx<T>), s, jobs, tiles, ntiles, G, cells,
+                     umaps, fac, rpool, upool, ps, nrhs, kmax);
+}
+
+template <typename T, int KG>
+static void launch_wide_bwd_k(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                              const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long ps,
+                              int nrhs, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  hipLaunchKernelGGL((k_nd_wide_bwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(256),
+                     nd_wide_lds_entries<T>(KG) * sizeof(cpx<T>), s, jobs, tiles, ntiles, G, cells,
+                     fac, rpool, xpool, ps, nrhs);
+}
+
+template <typename T>
+void launch_nd_wide_fwd(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                        const int* umaps, const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* upool,
+                        long long pool_stride, int nrhs, int kmax, hipStream_t s) {
+  if (ntiles <= 0 || nrhs <= 0) return;
+  switch (nd_wide_kg(sizeof(cpx<T>), nrhs)) {
+    case 32: launch_wide_fwd_k<T, 32>(jobs, tiles, ntiles, cells, umaps, fac, rpool, upool, pool_stride, nrhs, kmax, s); break;
+    case 16: launch_wide_fwd_k<T, 16>(jobs, tiles, ntiles, cells, umaps, fac, rpool, upool, pool_stride, nrhs, kmax, s); break;
+    default: launch_wide_fwd_k<T, 8>(jobs, tiles, ntiles, cells, umaps, fac, rpool, upool, pool_stride, nrhs, kmax, s); break;
+  }
+}
+
+template <typename T>
+void launch_nd_wide_bwd(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                        const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long pool_stride,
+                        int nrhs, hipStream_t s) {
+  if (ntiles <= 0 || nrhs <= 0) return;
+  switch (nd_wide_kg(sizeof(cpx<T>), nrhs)) {
+    case 32: launch_wide_bwd_k<T, 32>(jobs, tiles, ntiles, cells, fac, rpool, xpool, pool_stride, nrhs, s); break;
+    case 16: launch_wide_bwd_k<T, 16>(jobs, tiles, ntiles, cells, fac, rpool, xpool, pool_stride, nrhs, s); break;
+    default: launch_wide_bwd_k<T, 8>(jobs, tiles, ntiles, cells, fac, rpool, xpool, pool_stride, nrhs, s); break;
+  }
+}
+
 // LDS needed by the dense top for a given RHS group (1 if even that does not fit)
 size_t nd_top_lds_need(size_t ts, int max_ntop) { return nd_top_lds_bytes(ts, max_ntop, 1); }
+
+// The largest RHS group (a power of two <= kg) whose gathered columns fit the LDS
+int nd_top_kg(size_t ts, int ntop, int kg) {
+  int k = 16;
+  while (k > kg && k > 1) k >>= 1;
+  while (k > 1 && nd_top_lds_bytes(ts, ntop, k) > 160 * 1024) k >>= 1;
+  return k;
+}
 
 // ============================================================================
 // Factorisation kernels (FP64)
@@ -1096,37 +1348,81 @@ void launch_nd_copy(const NdCopyJob* jobs, int njobs, int max_rows, int max_cols
                      dim3(256), 0, s, jobs, work, fac);
 }
 
-// C = beta C + alpha A B on 16 x 16 output tiles, 16-deep slices of A and B staged in LDS.
+// C = beta C + alpha A B (FP64 complex, column-major with leading dimensions)
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64): a 64 x 64 output tile per
+// 256-thread workgroup, K staged through LDS in panels of 16; wave w owns the
+// 32 x 32 quarter at (32 (w % 2), 32 (w / 2)) as 2 x 2 blocks of 16 x 16.
+// Operand lanes: A[row l % 16][k l / 16], B[k l / 16][col l % 16]; output j of
+// lane l is row 4 j + l / 16, column l % 16 of the block.
+typedef double nd_f64x4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_nd_gemm(const NdGemmJob* __restrict__ jobs,
                                                  cpx<double>* W) {
   const NdGemmJob J = jobs[blockIdx.z];
-  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
   if (i0 >= J.m || j0 >= J.n) return;
-  __shared__ cpx<double> As[16][17], Bs[16][17];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  cpx<double> acc = mk(0.0, 0.0);
+  __shared__ cpx<double> As[16][65];   // [k][row]
+  __shared__ cpx<double> Bs[16][65];   // [k][col]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = (w & 1) * 32, wc = (w >> 1) * 32, l16 = lane & 15, l4 = lane >> 4;
+  const cpx<double>* __restrict__ A = W + J.a;
+  const cpx<double>* __restrict__ B = W + J.b;
+  nd_f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      cr[rb][cb] = nd_f64x4{0.0, 0.0, 0.0, 0.0};
+      ci[rb][cb] = nd_f64x4{0.0, 0.0, 0.0, 0.0};
+    }
   for (int k0 = 0; k0 < J.k; k0 += 16) {
-    As[ty][tx] = (i0 + tx < J.m && k0 + ty < J.k)
-                     ? W[J.a + (i0 + tx) + (long long)(k0 + ty) * J.lda] : mk(0.0, 0.0);
-    Bs[ty][tx] = (k0 + tx < J.k && j0 + ty < J.n)
-                     ? W[J.b + (k0 + tx) + (long long)(j0 + ty) * J.ldb] : mk(0.0, 0.0);
+    for (int e = tid; e < 1024; e += 256) {
+      const int mm = e & 63, ka = e >> 6;
+      const int r = i0 + mm, ka0 = k0 + ka;
+      As[ka][mm] = (r < J.m && ka0 < J.k) ? A[r + (long long)ka0 * J.lda] : mk(0.0, 0.0);
+      const int kb = e & 15, nn = e >> 4;
+      const int cc = j0 + nn, kb0 = k0 + kb;
+      Bs[kb][nn] = (cc < J.n && kb0 < J.k) ? B[kb0 + (long long)cc * J.ldb] : mk(0.0, 0.0);
+    }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) fma_acc(acc, As[kk][tx], Bs[ty][kk]);
+    for (int kk = 0; kk < 16; kk += 4) {
+      cpx<double> av[2], bv[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) av[rb] = As[kk + l4][wr + 16 * rb + l16];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) bv[cb] = Bs[kk + l4][wc + 16 * cb + l16];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          cr[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rb].re, bv[cb].re, cr[rb][cb], 0, 0, 0);
+          cr[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[rb].im, bv[cb].im, cr[rb][cb], 0, 0, 0);
+          ci[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rb].re, bv[cb].im, ci[rb][cb], 0, 0, 0);
+          ci[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[rb].im, bv[cb].re, ci[rb][cb], 0, 0, 0);
+        }
+    }
     __syncthreads();
   }
-  const int i = i0 + tx, j = j0 + ty;
-  if (i < J.m && j < J.n) {
-    const long long o = J.c + i + (long long)j * J.ldc;
-    const cpx<double> r = J.alpha * acc;
-    W[o] = J.beta ? W[o] + r : r;
-  }
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = i0 + wr + 16 * rb + 4 * j + l4, cc = j0 + wc + 16 * cb + l16;
+        if (r < J.m && cc < J.n) {
+          const long long o = J.c + r + (long long)cc * J.ldc;
+          const cpx<double> v = mk(J.alpha * cr[rb][cb][j], J.alpha * ci[rb][cb][j]);
+          W[o] = J.beta ? W[o] + v : v;
+        }
+      }
 }
 
 void launch_nd_gemm(const NdGemmJob* jobs, int njobs, int max_m, int max_n, cpx<double>* work,
                     hipStream_t s) {
   if (njobs <= 0 || max_m <= 0 || max_n <= 0) return;
-  hipLaunchKernelGGL(k_nd_gemm, dim3(nd_cdiv(max_m, 16), nd_cdiv(max_n, 16), njobs), dim3(256), 0,
+  hipLaunchKernelGGL(k_nd_gemm, dim3(nd_cdiv(max_m, 64), nd_cdiv(max_n, 64), njobs), dim3(256), 0,
                      s, jobs, work);
 }
 
@@ -1140,6 +1436,14 @@ void launch_nd_gemm(const NdGemmJob* jobs, int njobs, int max_m, int max_n, cpx<
   template void launch_nd_top<T>(int, const NdTopJob*, int, const int*, const int*,              \
                                  const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*, long long, \
                                  int, int, int, hipStream_t);                                    \
+  template void launch_nd_form<T>(const NdLvlJob*, const int2*, int, const int*, const int*,      \
+                                 cpx<T>*, const cpx<T>*, long long, int, int, hipStream_t);      \
+  template void launch_nd_wide_fwd<T>(const NdLvlJob*, const int2*, int, const int*, const int*,  \
+                                      const cpx<T>*, const cpx<T>*, cpx<T>*, long long, int, int, \
+                                      hipStream_t);                                               \
+  template void launch_nd_wide_bwd<T>(const NdLvlJob*, const int2*, int, const int*,              \
+                                      const cpx<T>*, const cpx<T>*, cpx<T>*, long long, int,      \
+                                      hipStream_t);                                               \
   template size_t nd_lvl_lds_bytes<T>(int, int);                                                 \
   template int nd_kg<T>(int, int, size_t);                                                       \
   template void launch_nd_copy<T>(const NdCopyJob*, int, int, int, cpx<double>*, cpx<T>*,       \

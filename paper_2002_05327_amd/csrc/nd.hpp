@@ -166,13 +166,34 @@ template <typename T>
 void launch_nd_lvl_bwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
                        const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool,
                        long long pool_stride, int nrhs, int max_nf, hipStream_t s);
-// dense top: x_top = P_top (r_top + gathered updates)
+// dense top: x_top = P_top (r_top + gathered updates); kg = the RHS group
+// (nd_top_kg of the launch's largest top)
 template <typename T>
 void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const int* cells, const int* usrc,
                    const cpx<T>* fac, const cpx<T>* rpool, const cpx<T>* upool, cpx<T>* xpool,
                    long long pool_stride, int nrhs, int kmax, int max_ntop, hipStream_t s);
+// Wide mode (fronts too large for the LDS, or more than 512 rows): tiles are
+// {node job, first of 256 rows (or separator positions for the form step)}.
+// Forward: launch_nd_form (f_S = r_S + children's updates, into R), then
+// launch_nd_wide_fwd (u_B); backward: launch_nd_wide_bwd (x_S).  Every
+// right-hand side of a group of nd_wide_kg(ts, nrhs) in one pass.
+template <typename T>
+void launch_nd_form(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                    const int* umaps, cpx<T>* rpool, const cpx<T>* upool, long long pool_stride,
+                    int nrhs, int kmax, hipStream_t s);
+template <typename T>
+void launch_nd_wide_fwd(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                        const int* umaps, const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* upool,
+                        long long pool_stride, int nrhs, int kmax, hipStream_t s);
+template <typename T>
+void launch_nd_wide_bwd(const NdLvlJob* jobs, const int2* tiles, int ntiles, const int* cells,
+                        const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long pool_stride,
+                        int nrhs, hipStream_t s);
+int nd_wide_kg(size_t ts, int nrhs);
 // LDS the dense top needs with one right-hand side per workgroup
 size_t nd_top_lds_need(size_t ts, int max_ntop);
+// RHS group of a dense top of ntop cells (a power of two <= kg that fits the LDS)
+int nd_top_kg(size_t ts, int ntop, int kg);
 // LDS of a level launch (max_nf front entries per RHS), and the RHS per workgroup that fit
 template <typename T>
 size_t nd_lvl_lds_bytes(int max_nf, int kg);

@@ -193,18 +193,30 @@ struct dsd_plan {
   Buf d_subs_local, d_local_jobs;
   // nested dissection (solver 4): shapes, device tables, per launch group jobs
   struct NdLevel {               // one level (depth below the subtree roots) of every subtree
-    int off = 0, n = 0;          // node jobs (d_nd_lvl)
-    int max_nf = 0, max_ns = 0, max_nbd = 0;
-    double fwd_bytes = 0, bwd_bytes = 0, cells = 0;   // factor bytes; front cells (vectors)
+    int off = 0, n = 0;          // node jobs (d_nd_lvl), ordered: wide both ways, wide
+                                 // backward only, narrow, wide forward only
+    int nf_off = 0, nf_n = 0;    // the narrow forward products (jobs)
+    int nb_off = 0, nb_n = 0;    // the narrow backward products (jobs)
+    // wide-mode tiles (d_nd_wide): f_S forming, forward rows, backward rows
+    int fm_off = 0, fm_n = 0, wf_off = 0, wf_n = 0, wb_off = 0, wb_n = 0;
+    // factor bytes and front cells of the narrow and wide, forward and backward products
+    double nf_bytes = 0, nb_bytes = 0, nf_cells = 0, nb_cells = 0;
+    double wf_bytes = 0, wb_bytes = 0, wf_cells = 0, wb_cells = 0;
   };
   struct NdLaunch {
     std::vector<NdLevel> levels; // level 0 = the subtree roots
     int top_off = 0, ntop = 0;   // dense-top jobs (d_nd_top)
-    int max_ntop = 0;            // largest top
-    double top_bytes = 0;        // factor bytes of the dense-top launch
-    double top_cells = 0;        // top cells of the members
+    double top_bytes = 0, top_cells = 0;
     long long upd = 0;           // update-vector entries per RHS of the members
   };
+  // Per level, over every shape of the plan: the largest narrow node (forward:
+  // rows nbd, columns ns; backward: rows ns, columns nf).  A level's launch
+  // shape follows from these alone, so a node's arithmetic never depends on
+  // which other nodes share its launch.
+  struct NdLevelMax {
+    int f_rows = 0, f_cols = 0, f_nf = 0, b_rows = 0, b_cols = 0;
+  };
+  std::vector<NdLevelMax> nd_lvmax;
   std::vector<NdShape> nd_shapes;
   std::vector<NdShapeTab> nd_tabs;
   std::vector<int> nd_shape_of;                      // per subdomain
@@ -215,6 +227,9 @@ struct dsd_plan {
   Buf d_nd_lvl, d_nd_top, d_upool;
   long long nd_upd_max = 0;                          // entries per RHS of the update pool
   int nd_max_nf = 0, nd_max_ntop = 0;   // largest subtree front; largest dense top
+  int nd_wide = 1024;                   // fronts of at least this size run in wide mode
+  int nd_max_nf_narrow = 0;             // largest front below nd_wide
+  Buf d_nd_wide;                        // wide-mode tiles {job, first row}
   std::vector<int> nd_cell_of, nd_map_of;  // per node-table entry: cell and map offsets
   int nd_small = 4;    // levels whose largest node needs at most this many (row pass x
                        // column) / 64 run one node per wave
@@ -1133,6 +1148,13 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs, bool loc
 }
 
 // ------------------------------------------- nested dissection (local solver 4)
+// Whether a node's forward (rows = boundary) or backward (rows = separator)
+// product runs in wide mode: a front of at least nd_wide cells, or more rows
+// than the LDS-front kernels cover (eight 64-row tiles).
+bool nd_wide_node(const dsd_plan* pl, int ns, int nbd, bool fwd) {
+  return ns + nbd >= pl->nd_wide || (fwd ? nbd : ns) > 512;
+}
+
 // Analysis of every distinct local grid shape, the factor layout (per
 // subdomain: the nodes' L and K blocks, then P_top) and the device tables.
 int nd_setup(dsd_plan* pl) {
@@ -1155,7 +1177,9 @@ int nd_setup(dsd_plan* pl) {
   std::vector<NdNodeDev> nodes;
   std::vector<int> cells, maps, umaps, src, usrc, lev, levmax, levnodes;
   pl->nd_tabs.assign(pl->nd_shapes.size(), NdShapeTab{});
-  pl->nd_max_nf = pl->nd_max_ntop = 0;
+  pl->nd_max_nf = pl->nd_max_ntop = pl->nd_max_nf_narrow = 0;
+  pl->nd_lvmax.clear();
+  pl->nd_wide = q.nd_wide > 0 ? q.nd_wide : 1024;
   for (size_t k = 0; k < pl->nd_shapes.size(); ++k) {
     const NdShape& sh = pl->nd_shapes[k];
     if (!nd_append_tables(sh, pl->nd_tabs[k], nodes, cells, maps, umaps, src, usrc, lev,
@@ -1164,6 +1188,22 @@ int nd_setup(dsd_plan* pl) {
       return DSD_EINVAL;
     }
     pl->nd_max_nf = std::max(pl->nd_max_nf, sh.max_nf);
+    for (const NdNode& n : sh.nodes) {
+      if (n.top) continue;
+      const int ns = (int)n.sep.size(), nbd = (int)n.bnd.size(), nf = ns + nbd;
+      if (nf < pl->nd_wide) pl->nd_max_nf_narrow = std::max(pl->nd_max_nf_narrow, nf);
+      if ((int)pl->nd_lvmax.size() <= n.level) pl->nd_lvmax.resize(n.level + 1);
+      dsd_plan::NdLevelMax& M = pl->nd_lvmax[n.level];
+      if (!nd_wide_node(pl, ns, nbd, true)) {
+        M.f_rows = std::max(M.f_rows, nbd);
+        M.f_cols = std::max(M.f_cols, ns);
+        M.f_nf = std::max(M.f_nf, nf);
+      }
+      if (!nd_wide_node(pl, ns, nbd, false)) {
+        M.b_rows = std::max(M.b_rows, ns);
+        M.b_cols = std::max(M.b_cols, nf);
+      }
+    }
     pl->nd_max_ntop = std::max(pl->nd_max_ntop, sh.ntop());
   }
   if (pl->nd_max_ntop > 5000) {
@@ -1201,13 +1241,15 @@ int nd_setup(dsd_plan* pl) {
 // addressed from offset 0 (vbase = 0) and kmax is the call's right-hand-side
 // count (passed at launch), so ubase is in entries per RHS.
 void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
-                   std::vector<NdLvlJob>& lj, std::vector<NdTopJob>& tj, dsd_plan::NdLaunch& L) {
+                   std::vector<NdLvlJob>& lj, std::vector<NdTopJob>& tj, std::vector<int2>& wt,
+                   dsd_plan::NdLaunch& L) {
   const double ts = (double)tsize(pl);
   L = dsd_plan::NdLaunch{};
   L.top_off = (int)tj.size();
   int nlev = 0;
   for (const int2& m : mem) nlev = std::max(nlev, pl->nd_shapes[pl->nd_shape_of[m.x]].nlev);
   std::vector<std::vector<NdLvlJob>> per(nlev);
+  std::vector<NdTopJob> tops;
   L.levels.assign(nlev, dsd_plan::NdLevel{});
   long long ubase = 0;
   for (const int2& m : mem) {
@@ -1220,10 +1262,9 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     for (size_t i = 0; i < sh.nodes.size(); ++i) {
       const NdNode& n = sh.nodes[i];
       if (n.top) continue;
-      const int ns = (int)n.sep.size(), nb = (int)n.bnd.size();
       NdLvlJob J{};
-      J.ns = ns;
-      J.nbd = nb;
+      J.ns = (int)n.sep.size();
+      J.nbd = (int)n.bnd.size();
       J.cell = pl->nd_cell_of[tb.node0 + i];
       J.umap = pl->nd_map_of[tb.node0 + i];
       J.l = m.y;
@@ -1233,13 +1274,6 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
       J.vbase = vb;
       J.ubase = ub;
       per[n.level].push_back(J);
-      dsd_plan::NdLevel& V = L.levels[n.level];
-      V.max_nf = std::max(V.max_nf, ns + nb);
-      V.max_ns = std::max(V.max_ns, ns);
-      V.max_nbd = std::max(V.max_nbd, nb);
-      V.fwd_bytes += (double)nb * ns * ts;
-      V.bwd_bytes += (double)ns * (ns + nb) * ts;
-      V.cells += (double)(ns + nb);
     }
     if (sh.ntop() > 0) {
       NdTopJob T{};
@@ -1252,19 +1286,64 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
       T.vbase = vb;
       T.ubase = ub;
       T.l = m.y;
-      tj.push_back(T);
+      tops.push_back(T);
     }
-    L.top_bytes += (double)sh.ntop() * sh.ntop() * ts;
-    L.top_cells += (double)sh.ntop();
-    L.max_ntop = std::max(L.max_ntop, sh.ntop());
     ubase += sh.upd_entries;
   }
+  // Per level: jobs ordered wide both ways, wide backward only, narrow, wide
+  // forward only (each class by decreasing front), so that the narrow forward
+  // and the narrow backward products are contiguous ranges.
+  auto cat = [&](const NdLvlJob& J) {
+    const bool wf = nd_wide_node(pl, J.ns, J.nbd, true), wb = nd_wide_node(pl, J.ns, J.nbd, false);
+    return wf && wb ? 0 : wb ? 1 : !wf ? 2 : 3;
+  };
   for (int l = 0; l < nlev; ++l) {
-    L.levels[l].off = (int)lj.size();
-    L.levels[l].n = (int)per[l].size();
-    lj.insert(lj.end(), per[l].begin(), per[l].end());
+    std::vector<NdLvlJob>& v = per[l];
+    std::stable_sort(v.begin(), v.end(), [&](const NdLvlJob& a, const NdLvlJob& b) {
+      const int ca = cat(a), cb = cat(b);
+      if (ca != cb) return ca < cb;
+      return a.ns + a.nbd > b.ns + b.nbd;
+    });
+    dsd_plan::NdLevel& V = L.levels[l];
+    V.off = (int)lj.size();
+    V.n = (int)v.size();
+    int c[5] = {0, 0, 0, 0, 0};
+    for (const NdLvlJob& J : v) ++c[cat(J) + 1];
+    for (int k = 1; k < 5; ++k) c[k] += c[k - 1];
+    V.nf_off = V.off + c[1];
+    V.nf_n = c[3] - c[1];
+    V.nb_off = V.off + c[2];
+    V.nb_n = c[4] - c[2];
+    // wide-mode tiles: 256 separator positions (forming f_S), 256 rows
+    auto add_tiles = [&](bool fwd, bool form, int& off, int& cnt) {
+      off = (int)wt.size();
+      for (size_t j = 0; j < v.size(); ++j) {
+        const NdLvlJob& J = v[j];
+        if (!nd_wide_node(pl, J.ns, J.nbd, fwd)) continue;
+        const int rows = form ? J.ns : fwd ? J.nbd : J.ns;
+        for (int r0 = 0; r0 < rows; r0 += 256) wt.push_back(make_int2(V.off + (int)j, r0));
+      }
+      cnt = (int)wt.size() - off;
+    };
+    add_tiles(true, true, V.fm_off, V.fm_n);
+    add_tiles(true, false, V.wf_off, V.wf_n);
+    add_tiles(false, false, V.wb_off, V.wb_n);
+    for (const NdLvlJob& J : v) {
+      const double fb = (double)J.nbd * J.ns * ts, bb = (double)J.ns * (J.ns + J.nbd) * ts;
+      const double fc = (double)(J.ns + J.nbd);
+      if (nd_wide_node(pl, J.ns, J.nbd, true)) { V.wf_bytes += fb; V.wf_cells += fc; }
+      else { V.nf_bytes += fb; V.nf_cells += fc; }
+      if (nd_wide_node(pl, J.ns, J.nbd, false)) { V.wb_bytes += bb; V.wb_cells += fc; }
+      else { V.nb_bytes += bb; V.nb_cells += fc; }
+    }
+    lj.insert(lj.end(), v.begin(), v.end());
   }
-  L.ntop = (int)tj.size() - L.top_off;
+  for (const NdTopJob& T : tops) {
+    L.top_bytes += (double)T.ntop * T.ntop * ts;
+    L.top_cells += (double)T.ntop;
+  }
+  tj.insert(tj.end(), tops.begin(), tops.end());
+  L.ntop = (int)tops.size();
   L.upd = ubase;
 }
 
@@ -1272,19 +1351,22 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
 int build_nd_jobs(dsd_plan* pl) {
   std::vector<NdLvlJob> sj;
   std::vector<NdTopJob> tj;
+  std::vector<int2> wt;
   pl->nd_launch.assign(pl->groups.size(), dsd_plan::NdLaunch{});
   pl->nd_upd_max = 0;
   for (size_t g = 0; g < pl->groups.size(); ++g) {
-    nd_group_jobs(pl, pl->groups[g], false, sj, tj, pl->nd_launch[g]);
+    nd_group_jobs(pl, pl->groups[g], false, sj, tj, wt, pl->nd_launch[g]);
     pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_launch[g].upd);
   }
   pl->nd_local.assign(pl->S, dsd_plan::NdLaunch{});
   for (int s = 0; s < pl->S; ++s) {
-    nd_group_jobs(pl, std::vector<int2>{make_int2(s, 0)}, true, sj, tj, pl->nd_local[s]);
+    nd_group_jobs(pl, std::vector<int2>{make_int2(s, 0)}, true, sj, tj, wt, pl->nd_local[s]);
     pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_local[s].upd);
   }
   CHK(upload(pl->d_nd_lvl, sj));
   CHK(upload(pl->d_nd_top, tj));
+  if (wt.empty()) wt.push_back(make_int2(0, 0));
+  CHK(upload(pl->d_nd_wide, wt));
   return 0;
 }
 
@@ -1299,34 +1381,71 @@ int nd_factor(dsd_plan* pl) {
   CHK(pl->d_fac.alloc((size_t)pl->sum_fac * tsize(pl)));
   const cpx<double>* cf[4] = {pl->d_lcoef64[0].as<cpx<double>>(), pl->d_lcoef64[1].as<cpx<double>>(),
                               pl->d_lcoef64[2].as<cpx<double>>(), pl->d_lcoef64[3].as<cpx<double>>()};
-  // FP64 work per subdomain: every front, and the top matrix
-  std::vector<long long> fwork(pl->S, 0);
+  // FP64 work per subdomain.  A depth's fronts are assembled from the next
+  // depth's and are dead once their parents are, so the fronts of even and of
+  // odd depths share two regions; then the top matrix and the largest depth's
+  // S (ns x ns) and L (nbd x ns) blocks.
   int maxdepth = 0;
-  for (int s = 0; s < pl->S; ++s) {
-    const NdShape& sh = pl->nd_shapes[pl->nd_shape_of[s]];
-    for (const NdNode& n : sh.nodes) {
-      maxdepth = std::max(maxdepth, n.depth);
-      if (!n.top) fwork[s] += (long long)(n.sep.size() + n.bnd.size()) * (n.sep.size() + n.bnd.size());
+  for (const NdShape& sh : pl->nd_shapes)
+    for (const NdNode& n : sh.nodes) maxdepth = std::max(maxdepth, n.depth);
+  auto depth_entries = [&](int s, std::vector<long long>& e, std::vector<long long>& sl) {
+    e.assign(maxdepth + 2, 0);
+    sl.assign(maxdepth + 2, 0);
+    for (const NdNode& n : pl->nd_shapes[pl->nd_shape_of[s]].nodes) {
+      if (n.top) continue;
+      const long long ns = (long long)n.sep.size(), nf = ns + (long long)n.bnd.size();
+      e[n.depth] += nf * nf;
+      sl[n.depth] += ns * nf;
     }
-    fwork[s] += (long long)sh.ntop() * sh.ntop();
+  };
+  std::vector<long long> fneed(pl->S, 0);
+  {
+    std::vector<long long> e, sl;
+    for (int s = 0; s < pl->S; ++s) {
+      depth_entries(s, e, sl);
+      long long m2 = 0, ms = 0;
+      for (int d = 0; d <= maxdepth; ++d) {
+        m2 = std::max(m2, e[d] + e[d + 1]);
+        ms = std::max(ms, sl[d]);
+      }
+      const long long nt = pl->nd_shapes[pl->nd_shape_of[s]].ntop();
+      fneed[s] = m2 + nt * nt + ms;
+    }
   }
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));
   const double budget = 0.4 * (double)fr / sizeof(cpx<double>);
   int s0 = 0;
   while (s0 < pl->S) {
-    // chunk [s0, s1): fronts and tops of its subdomains, plus per-level S and L blocks
+    // chunk [s0, s1)
     int s1 = s0;
     double need = 0;
-    while (s1 < pl->S && s1 - s0 < 255 && (s1 == s0 || need + 2.0 * fwork[s1] < budget)) {
-      need += 2.0 * fwork[s1];
+    while (s1 < pl->S && s1 - s0 < 255 && (s1 == s0 || need + (double)fneed[s1] < budget)) {
+      need += (double)fneed[s1];
       ++s1;
     }
-    // offsets: fronts of (sub, node), then the tops
+    // front offsets: depth d in region d % 2
+    std::vector<long long> E(maxdepth + 2, 0), SL(maxdepth + 2, 0);
+    {
+      std::vector<long long> e, sl;
+      for (int s = s0; s < s1; ++s) {
+        depth_entries(s, e, sl);
+        for (int d = 0; d <= maxdepth; ++d) {
+          E[d] += e[d];
+          SL[d] += sl[d];
+        }
+      }
+    }
+    long long half[2] = {0, 0}, lvl_max = 0;
+    for (int d = 0; d <= maxdepth; ++d) {
+      half[d & 1] = std::max(half[d & 1], E[d]);
+      lvl_max = std::max(lvl_max, SL[d]);
+    }
+    std::vector<long long> cur(maxdepth + 1);
+    for (int d = 0; d <= maxdepth; ++d) cur[d] = (d & 1) ? half[0] : 0;
     std::vector<long long> fo;          // per (sub in chunk, node of its shape); -1 for top nodes
     std::vector<int> fo_base(s1 - s0);
     std::vector<long long> toff(s1 - s0);
-    long long w = 0;
     for (int s = s0; s < s1; ++s) {
       const NdShape& sh = pl->nd_shapes[pl->nd_shape_of[s]];
       fo_base[s - s0] = (int)fo.size();
@@ -1335,24 +1454,15 @@ int nd_factor(dsd_plan* pl) {
           fo.push_back(-1);
           continue;
         }
-        fo.push_back(w);
-        w += (long long)(n.sep.size() + n.bnd.size()) * (n.sep.size() + n.bnd.size());
+        fo.push_back(cur[n.depth]);
+        cur[n.depth] += (long long)(n.sep.size() + n.bnd.size()) * (n.sep.size() + n.bnd.size());
       }
     }
+    long long w = half[0] + half[1];
     for (int s = s0; s < s1; ++s) {
       const NdShape& sh = pl->nd_shapes[pl->nd_shape_of[s]];
       toff[s - s0] = w;
       w += (long long)sh.ntop() * sh.ntop();
-    }
-    // per-level S (ns x ns) and L (nbd x ns) blocks: the largest level of the chunk
-    long long lvl_max = 0;
-    for (int d = 0; d <= maxdepth; ++d) {
-      long long e = 0;
-      for (int s = s0; s < s1; ++s)
-        for (const NdNode& n : pl->nd_shapes[pl->nd_shape_of[s]].nodes)
-          if (!n.top && n.depth == d)
-            e += (long long)n.sep.size() * (n.sep.size() + n.bnd.size());
-      lvl_max = std::max(lvl_max, e);
     }
     const long long sl_base = w;
     w += lvl_max;
@@ -1726,35 +1836,56 @@ void nd_phase(dsd_plan* pl, const dsd_plan::NdLaunch& L, cpx<T>* R, cpx<T>* X, c
   const NdLvlJob* lj = pl->d_nd_lvl.as<NdLvlJob>();
   const NdTopJob* tj = pl->d_nd_top.as<NdTopJob>() + L.top_off;
   const cpx<T>* fac = pl->d_fac.as<cpx<T>>();
-  const double ts = (double)sizeof(cpx<T>);
-  const int nlev = (int)L.levels.size();
-  for (int l = nlev - 1; l >= 0; --l) {
-    const dsd_plan::NdLevel& V = L.levels[l];
-    if (V.n == 0) continue;
-    if (timed) time_begin(pl);
+  const size_t tsz = sizeof(cpx<T>);
+  const double ts = (double)tsz;
+  const int* cells = pl->d_nd_cells.as<int>();
+  // One level, forward (rows = boundary, columns = separator) or backward
+  // (rows = separator, columns = front): the wide nodes' tiles, then the
+  // narrow nodes in one launch of the level's plan-wide shape.
+  const int2* wt = pl->d_nd_wide.as<int2>();
+  auto level = [&](int l, const dsd_plan::NdLevel& V, bool fwd) {
+    if (fwd && V.fm_n > 0)
+      launch_nd_form<T>(lj, wt + V.fm_off, V.fm_n, cells, pl->d_nd_umaps.as<int>(), R, U, pool_stride,
+                        nrhs, kmax, st);
+    const int wn = fwd ? V.wf_n : V.wb_n;
+    if (wn > 0) {
+      if (timed) time_begin(pl);
+      if (fwd)
+        launch_nd_wide_fwd<T>(lj, wt + V.wf_off, wn, cells, pl->d_nd_umaps.as<int>(), fac, R, U,
+                              pool_stride, nrhs, kmax, st);
+      else
+        launch_nd_wide_bwd<T>(lj, wt + V.wb_off, wn, cells, fac, R, X, pool_stride, nrhs, st);
+      const double b = fwd ? V.wf_bytes : V.wb_bytes, c = fwd ? V.wf_cells : V.wb_cells;
+      if (timed) time_end(pl, b + 2.0 * c * nrhs * ts, b / ts * nrhs * 8.0);
+    }
+    const int n = fwd ? V.nf_n : V.nb_n;
+    if (n == 0) return;
+    const dsd_plan::NdLevelMax& M = pl->nd_lvmax[l];
     int tt, cg;
-    nd_shape(V.max_nbd, V.max_ns, pl->kg, V.max_nf, sizeof(cpx<T>), pl->nd_small, tt, cg);
-    launch_nd_lvl_fwd<T>(pl->kg, tt, cg, lj + V.off, V.n,
-                         pl->d_nd_cells.as<int>(), pl->d_nd_umaps.as<int>(), fac, R, U, pool_stride,
-                         nrhs, kmax, V.max_nf, st);
-    if (timed) time_end(pl, V.fwd_bytes + 2.0 * V.cells * nrhs * ts, V.fwd_bytes / ts * nrhs * 8.0);
-  }
+    if (timed) time_begin(pl);
+    if (fwd) {
+      nd_shape(M.f_rows, M.f_cols, pl->kg, M.f_nf, tsz, pl->nd_small, tt, cg);
+      launch_nd_lvl_fwd<T>(pl->kg, tt, cg, lj + V.nf_off, n, cells, pl->d_nd_umaps.as<int>(), fac, R,
+                           U, pool_stride, nrhs, kmax, M.f_nf, st);
+    } else {
+      nd_shape(M.b_rows, M.b_cols, pl->kg, M.b_cols, tsz, pl->nd_small, tt, cg);
+      launch_nd_lvl_bwd<T>(pl->kg, tt, cg, lj + V.nb_off, n, cells, fac, R, X, pool_stride, nrhs,
+                           M.b_cols, st);
+    }
+    const double b = fwd ? V.nf_bytes : V.nb_bytes, c = fwd ? V.nf_cells : V.nb_cells;
+    if (timed) time_end(pl, b + 2.0 * c * nrhs * ts, b / ts * nrhs * 8.0);
+  };
+  const int nlev = (int)L.levels.size();
+  for (int l = nlev - 1; l >= 0; --l) level(l, L.levels[l], true);
+  // dense tops: the RHS group of the plan's largest top
   if (L.ntop > 0) {
     if (timed) time_begin(pl);
-    launch_nd_top<T>(pl->kg, tj, L.ntop, pl->d_nd_cells.as<int>(), pl->d_nd_usrc.as<int>(), fac,
-                     R, U, X, pool_stride, nrhs, kmax, L.max_ntop, st);
+    launch_nd_top<T>(nd_top_kg(tsz, pl->nd_max_ntop, pl->kg), tj, L.ntop, cells,
+                     pl->d_nd_usrc.as<int>(), fac, R, U, X, pool_stride, nrhs, kmax, pl->nd_max_ntop,
+                     st);
     if (timed) time_end(pl, L.top_bytes + 2.0 * L.top_cells * nrhs * ts, L.top_bytes / ts * nrhs * 8.0);
   }
-  for (int l = 0; l < nlev; ++l) {
-    const dsd_plan::NdLevel& V = L.levels[l];
-    if (V.n == 0) continue;
-    if (timed) time_begin(pl);
-    int tt, cg;
-    nd_shape(V.max_ns, V.max_nf, pl->kg, V.max_nf, sizeof(cpx<T>), pl->nd_small, tt, cg);
-    launch_nd_lvl_bwd<T>(pl->kg, tt, cg, lj + V.off, V.n,
-                         pl->d_nd_cells.as<int>(), fac, R, X, pool_stride, nrhs, V.max_nf, st);
-    if (timed) time_end(pl, V.bwd_bytes + 2.0 * V.cells * nrhs * ts, V.bwd_bytes / ts * nrhs * 8.0);
-  }
+  for (int l = 0; l < nlev; ++l) level(l, L.levels[l], false);
 }
 
 template <typename T>
@@ -2213,8 +2344,8 @@ int dense_blocks(const dsd_plan* pl, int req) {
 int choose_kg(const dsd_plan* pl, int want) {
   const int lds = device_lds();
   if (pl->solver == 4)
-    return pl->c64 ? nd_kg<float>(pl->nd_max_nf, want, (size_t)lds)
-                   : nd_kg<double>(pl->nd_max_nf, want, (size_t)lds);
+    return pl->c64 ? nd_kg<float>(std::max(1, pl->nd_max_nf_narrow), want, (size_t)lds)
+                   : nd_kg<double>(std::max(1, pl->nd_max_nf_narrow), want, (size_t)lds);
   if (pl->chain_steps) {
     int kg = pl->c64 ? bcr_kg<float>(pl->max_nb, want) : bcr_kg<double>(pl->max_nb, want);
     auto need = [&](int k) {
@@ -2350,10 +2481,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
       q.local_solver > 4 || q.schedule < 0 || q.schedule > 2 || q.dense_top < -1 ||
       q.dense_top > 64 || q.sweep_order < 0 || q.sweep_order > 1 ||
       (q.sweep_order == 1 && q.dim != 3) || q.nd_leaf < 0 || q.nd_top_cells < 0 ||
-      q.nd_top_cells > 5000) {
+      q.nd_top_cells > 5000 || q.nd_wide < 0) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
                "local_solver 0..4, schedule 0..2, dense_top -1..64, sweep_order 0..1 (1: 3D only), "
-               "nd_leaf >= 0, nd_top_cells 0..5000";
+               "nd_leaf >= 0, nd_top_cells 0..5000, nd_wide >= 0";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)

@@ -22,14 +22,17 @@ torch = pytest.importorskip("torch")
 
 
 def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="auto", dense_top=0):
+    """solver "nd-wide": nested dissection with every node in wide mode (tiled
+    products over all right-hand sides of a group, vectors streamed through LDS)."""
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(slowness2(c)).cuda()
+    wide = 1 if solver == "nd-wide" else 0
     return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
-                    max_rhs=k, rhs_per_group=kg, schedule=schedule, local_solver=solver,
-                    dense_top=dense_top)
+                    max_rhs=k, rhs_per_group=kg, schedule=schedule,
+                    local_solver="nd" if wide else solver, dense_top=dense_top, nd_wide=wide)
 
 
-SOLVERS = ["bcr", "chain", "chain-steps", "nd"]
+SOLVERS = ["bcr", "chain", "chain-steps", "nd", "nd-wide"]
 
 
 def _cuda(x):
