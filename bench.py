@@ -41,7 +41,8 @@ def _inputs(name):
     return w, c, F
 
 
-def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_top=0, nd_wide=0):
+def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_top=0, nd_wide=0,
+          nd_wave=0, nd_fuse=0):
     import torch
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(1.0 / c ** 2).cuda()
@@ -49,7 +50,8 @@ def _plan(w, c, prec, kg, graph=False, tune=False, solver="auto", nd_leaf=0, nd_
     t0 = time.perf_counter()
     plan = dsw.Plan(n=w.n, h=w.h, omega=w.omega, pml=w.pml, overlap=w.overlap, parts=w.parts,
                     m=m, precision=prec, max_rhs=w.nrhs, rhs_per_group=kg, local_solver=solver,
-                    nd_leaf=nd_leaf, nd_top_cells=nd_top, nd_wide=nd_wide)
+                    nd_leaf=nd_leaf, nd_top_cells=nd_top, nd_wide=nd_wide, nd_wave_steps=nd_wave,
+                    nd_fuse=nd_fuse)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"# {prec} plan ready ({plan.local_solver} local solver): factorisation {dt:.2f} s",
@@ -322,13 +324,17 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--maxit", type=int, default=60)
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=0, help="FGMRES restart (0: the workload's)")
     ap.add_argument("--kg", type=int, default=0, help="RHS per workgroup in the block solves")
     ap.add_argument("--solver", default="auto", help="local solver: auto, nd, bcr, chain, chain-steps")
     ap.add_argument("--nd-leaf", type=int, default=0, help="nested dissection: leaf box cells (0: library)")
     ap.add_argument("--nd-top", type=int, default=0, help="nested dissection: dense-top cells (0: library)")
     ap.add_argument("--nd-wide", type=int, default=0,
                     help="nested dissection: fronts of at least this many cells in wide mode (0: library)")
+    ap.add_argument("--nd-wave", type=int, default=0,
+                    help="nested dissection: 64-lane steps up to which a level runs a node per wave (0: library)")
+    ap.add_argument("--nd-fuse", type=int, default=0,
+                    help="nested dissection: front size below which subtree levels run fused (0: library; 1: off)")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time the solve-launch shapes first (reported separately)")
     ap.add_argument("--graph", action="store_true",
@@ -342,6 +348,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     w, c, F = _inputs(args.workload)
+    if args.restart <= 0:
+        args.restart = w.restart
     cpu, u_glob = None, None
     if not args.no_cpu_baseline:
         # before any GPU call: the oracle's worker processes fork from this one
@@ -356,7 +364,7 @@ def main():
     print(f"# workload {w.name}: n={w.n} parts={w.parts} nrhs={w.nrhs}", file=sys.stderr, flush=True)
 
     plan64, tf64 = _plan(w, c, "c64", args.kg, args.graph, args.autotune, args.solver,
-                         args.nd_leaf, args.nd_top, args.nd_wide)
+                         args.nd_leaf, args.nd_top, args.nd_wide, args.nd_wave, args.nd_fuse)
     print(f"# c64 factorisation {tf64:.2f} s", file=sys.stderr, flush=True)
     dt64, its64, rel64, ok64, x64, steps64 = _solve_steps(plan64, b, args.tol, args.maxit,
                                                           args.restart, args.warmup, args.steps)
@@ -370,7 +378,7 @@ def main():
     c128 = None
     if not args.no_c128:
         plan128, tf128 = _plan(w, c, "c128", args.kg, args.graph, args.autotune, args.solver,
-                               args.nd_leaf, args.nd_top, args.nd_wide)
+                               args.nd_leaf, args.nd_top, args.nd_wide, args.nd_wave, args.nd_fuse)
         n128 = max(1, min(args.steps, 5))
         dt128, its128, rel128, ok128, x128, steps128 = _solve_steps(
             plan128, b, args.tol, args.maxit, args.restart, min(args.warmup, 1), n128)

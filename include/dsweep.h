@@ -84,8 +84,9 @@ typedef struct {
                                separators stored inverted, the separators above a
                                depth applied as one dense inverse, one workgroup per
                                remaining subtree (about a quarter of the band factor);
-                            0: 2 unless its factor would exceed 45% of device memory,
-                               else 3 for blocks of 512 cells or more, else 1.          */
+                            0: 4 in 3D; in 2D 2 unless its factor would exceed 45% of
+                               device memory, else 3 for blocks of 512 cells or more,
+                               else 1.                                                  */
   int dense_top;         /* block cyclic reduction only: the reduction stops at the first
                             level that has at most this many blocks (at least 2) and
                             applies the precomputed inverse of that reduced system as one
@@ -108,6 +109,15 @@ typedef struct {
                             as tiled products over all right-hand sides of a group at
                             once, the vectors streamed through LDS (0: 1024); nodes
                             with more than 512 rows always do                          */
+  int nd_wave_steps;     /* nested dissection: a tree level whose largest narrow node
+                            needs at most this many 64-lane steps (row passes of
+                            64 / rhs_per_group rows times columns, / 64) runs one node
+                            per wave instead of one node per workgroup (0: 4)           */
+  int nd_fuse;           /* nested dissection: from the shallowest subtree level below
+                            which every node's front has at most this many cells
+                            (0: 128; at most 512), each subtree runs in one workgroup,
+                            level after level, in one launch per direction; 1 turns
+                            this off                                                    */
 } dsd_params;
 
 /*

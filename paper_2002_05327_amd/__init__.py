@@ -44,7 +44,7 @@ class Plan:
                  max_rhs: int = 1, rhs_per_group: int = 0, sigma0_delta: float = 60.0,
                  schedule: str = "dag", local_solver: str = "auto", dense_top: int = 0,
                  sweep_order: str = "default", nd_leaf: int = 0, nd_top_cells: int = 0,
-                 nd_wide: int = 0):
+                 nd_wide: int = 0, nd_wave_steps: int = 0, nd_fuse: int = 0):
         self._lib = _lib.load()
         dim = len(n)
         if dim not in (2, 3) or len(parts) != dim:
@@ -63,6 +63,7 @@ class Plan:
         p.dense_top = int(dense_top)
         p.sweep_order = {"default": 0, "l1": 1}[sweep_order]
         p.nd_leaf, p.nd_top_cells, p.nd_wide = int(nd_leaf), int(nd_top_cells), int(nd_wide)
+        p.nd_wave_steps, p.nd_fuse = int(nd_wave_steps), int(nd_fuse)
         self.params = p
         self.n, self.dim, self.pml, self.omega = tuple(int(k) for k in n), dim, int(pml), omega
         self.precision, self.max_rhs = precision, int(max_rhs)

@@ -17,7 +17,8 @@ class Params(C.Structure):
         ("precision", C.c_int), ("max_rhs", C.c_int), ("rhs_per_group", C.c_int),
         ("schedule", C.c_int), ("local_solver", C.c_int), ("dense_top", C.c_int),
         ("sweep_order", C.c_int), ("nd_leaf", C.c_int), ("nd_top_cells", C.c_int),
-        ("nd_wide", C.c_int),
+        ("nd_wide", C.c_int), ("nd_wave_steps", C.c_int),
+        ("nd_fuse", C.c_int),
     ]
 
 

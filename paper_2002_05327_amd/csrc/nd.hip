@@ -349,6 +349,10 @@ __device__ __forceinline__ void nd_dot_rows(cpx<T> (&acc)[KG], const cpx<T>* __r
 // Im(A) against [-Im y_q, Re y_q] give [Re (A y)_q, Im (A y)_q].  Output
 // acc[rb][jb][r] = row 16 rb + 4 (l / 16) + r, column n = l % 16 of block jb.
 typedef float nd_mf4 __attribute__((ext_vector_type(4)));
+// The LDS-front kernels (one node per workgroup, and the dense top) take the
+// matrix cores from this RHS group up; with fewer right-hand sides per group
+// the FP32 vector FMAs were measured faster there.
+constexpr int ND_MFMA_KG = 16;
 
 template <int JB>
 __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<float>* __restrict__ A,
@@ -512,7 +516,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
   const int c0 = min(ns, cgi * cw), c1 = min(ns, c0 + cw);
   const int i = t * 64 + lane;
   const bool live = i < nbd;
-  if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
+  if constexpr (std::is_same<T, float>::value && KG % 8 == 0 && KG >= ND_MFMA_KG) {
     constexpr int JB = KG / 8;
     nd_mf4 macc[4][JB];
 #pragma unroll
@@ -638,7 +642,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
   const int c0 = min(nf, cgi * cw), c1 = min(nf, c0 + cw);
   const int i = t * 64 + lane;
   const bool live = i < ns;
-  if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
+  if constexpr (std::is_same<T, float>::value && KG % 8 == 0 && KG >= ND_MFMA_KG) {
     constexpr int JB = KG / 8;
     nd_mf4 macc[4][JB];
 #pragma unroll
@@ -1035,6 +1039,145 @@ __global__ __launch_bounds__(256) void k_nd_wide_bwd(
   }
 }
 
+// ---- fused bottom levels: the small nodes below the fusion level run one
+// workgroup per (subtree, RHS group), level by level inside the workgroup
+// (workgroup barriers instead of launches).  The subtree's nodes come in
+// batches of one level whose fronts fit the LDS together (job.pad = the
+// node's front offset in the batch): the waves gather the batch's fronts
+// (a node per wave, lanes over front positions), then share its row passes
+// (64 / KG rows x KG right-hand sides per pass, as in the one-node-per-wave
+// kernels, so the arithmetic of a node is the same in either).  The forward
+// pass runs the batches deepest level first, the backward pass in reverse.
+template <typename T, int KG>
+__global__ __launch_bounds__(512) void k_nd_fused_fwd(
+    const int2* __restrict__ fjobs, int nfj, int G, const int2* __restrict__ batches,
+    const NdLvlJob* __restrict__ jobs, const int* __restrict__ cells, const int* __restrict__ umaps,
+    const cpx<T>* __restrict__ fac, cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ upool,
+    long long pool_stride, int nrhs, int kmax) {
+  typedef cpx<T> C;
+  constexpr int RPP = 64 / KG;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int fj = Lg / G, g = Lg - (Lg / G) * G;
+  if (fj >= nfj) return;
+  const int2 F = fjobs[fj];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int qq = lane % KG, rr = lane / KG;
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
+  const C zero = mk((T)0, (T)0);
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  for (int b = F.x; b < F.x + F.y; ++b) {
+    const int2 B = batches[b];
+    for (int k = w; k < B.y; k += 8) {
+      const NdLvlJob J = jobs[B.x + k];
+      C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+      const C* __restrict__ U = upool + J.ubase;
+      const int* fc = cells + J.cell;
+      const int* um = umaps + J.umap;
+      C* fr = lds + (long long)J.pad * KG;
+      const int ns = J.ns, nf = J.ns + J.nbd;
+      for (int p = lane; p < nf; p += 64) {
+        const int i0 = um[2 * p], i1 = um[2 * p + 1];
+        const bool own = p < ns;
+        const int cell = own ? fc[p] : 0;
+        const C* U0 = U + (long long)i0 * kmax + q0;
+        const C* U1 = U + (long long)i1 * kmax + q0;
+        C* Rc = R + (long long)q0 * J.nloc + cell;
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          C v = zero;
+          if (q < nq) {
+            if (own) v = Rc[(long long)q * J.nloc];
+            if (i0 >= 0) v = v + U0[q];
+            if (i1 >= 0) v = v + U1[q];
+            if (own) Rc[(long long)q * J.nloc] = v;
+          }
+          fr[p * KG + q] = v;
+        }
+      }
+    }
+    __syncthreads();
+    int item = 0;
+    for (int k = 0; k < B.y; ++k) {
+      const NdLvlJob J = jobs[B.x + k];
+      const int np = (J.nbd + RPP - 1) / RPP;
+      const C* fr = lds + (long long)J.pad * KG;
+      const C* __restrict__ Lf = fac + J.fac;
+      C* __restrict__ U = upool + J.ubase;
+      for (int p = (w - item % 8 + 8) % 8; p < np; p += 8) {
+        const int i = p * RPP + rr;
+        if (i >= J.nbd) continue;
+        C acc = fr[(J.ns + i) * KG + qq];
+        nd_dot<T, KG, true>(acc, Lf + i, J.nbd, fr + qq, J.ns);
+        if (qq < nq) U[(J.upd + i) * kmax + q0 + qq] = acc;
+      }
+      item += np;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int KG>
+__global__ __launch_bounds__(512) void k_nd_fused_bwd(
+    const int2* __restrict__ fjobs, int nfj, int G, const int2* __restrict__ batches,
+    const NdLvlJob* __restrict__ jobs, const int* __restrict__ cells, const cpx<T>* __restrict__ fac,
+    const cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs) {
+  typedef cpx<T> C;
+  constexpr int RPP = 64 / KG;
+  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int fj = Lg / G, g = Lg - (Lg / G) * G;
+  if (fj >= nfj) return;
+  const int2 F = fjobs[fj];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int qq = lane % KG, rr = lane / KG;
+  const int q0 = g * KG, nq = min(KG, nrhs - q0);
+  const C zero = mk((T)0, (T)0);
+  extern __shared__ unsigned char smem_raw[];
+  C* lds = reinterpret_cast<C*>(smem_raw);
+  for (int b = F.x + F.y - 1; b >= F.x; --b) {
+    const int2 B = batches[b];
+    for (int k = w; k < B.y; k += 8) {
+      const NdLvlJob J = jobs[B.x + k];
+      const C* __restrict__ R = rpool + (long long)J.l * pool_stride + J.vbase;
+      const C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
+      const int* fc = cells + J.cell;
+      C* v = lds + (long long)J.pad * KG;
+      const int ns = J.ns, nf = J.ns + J.nbd;
+      for (int p = lane; p < nf; p += 64) {
+        const bool own = p < ns;
+        const long long c = (long long)q0 * J.nloc + fc[p];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          C x = zero;
+          if (q < nq) x = own ? R[c + (long long)q * J.nloc] : -X[c + (long long)q * J.nloc];
+          v[p * KG + q] = x;
+        }
+      }
+    }
+    __syncthreads();
+    int item = 0;
+    for (int k = 0; k < B.y; ++k) {
+      const NdLvlJob J = jobs[B.x + k];
+      const int np = (J.ns + RPP - 1) / RPP;
+      const C* v = lds + (long long)J.pad * KG;
+      const C* __restrict__ K = fac + J.fac + (long long)J.nbd * J.ns;
+      C* __restrict__ X = xpool + (long long)J.l * pool_stride + J.vbase;
+      const int* fc = cells + J.cell;
+      for (int p = (w - item % 8 + 8) % 8; p < np; p += 8) {
+        const int i = p * RPP + rr;
+        if (i >= J.ns) continue;
+        C acc = zero;
+        nd_dot<T, KG, false>(acc, K + i, J.ns, v + qq, J.ns + J.nbd);
+        if (qq < nq) X[(long long)(q0 + qq) * J.nloc + fc[i]] = acc;
+      }
+      item += np;
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 size_t nd_lvl_lds_bytes(int max_nf, int kg) {
   return (size_t)std::max(1, max_nf) * kg * sizeof(cpx<T>);
@@ -1210,6 +1353,40 @@ void launch_nd_wide_bwd(const NdLvlJob* jobs, const int2* tiles, int ntiles, con
     case 16: launch_wide_bwd_k<T, 16>(jobs, tiles, ntiles, cells, fac, rpool, xpool, pool_stride, nrhs, s); break;
     default: launch_wide_bwd_k<T, 8>(jobs, tiles, ntiles, cells, fac, rpool, xpool, pool_stride, nrhs, s); break;
   }
+}
+
+// ---- fused bottom levels: launchers
+template <typename T, int KG>
+static void launch_fused_k(bool fwd, const int2* fjobs, int nfj, const int2* batches,
+                           const NdLvlJob* jobs, const int* cells, const int* umaps,
+                           const cpx<T>* fac, cpx<T>* rpool, cpx<T>* upool, cpx<T>* xpool,
+                           long long ps, int nrhs, int kmax, hipStream_t s) {
+  const int G = (nrhs + KG - 1) / KG;
+  const size_t lds = (size_t)ND_FUSE_CAP * KG * sizeof(cpx<T>);
+  if (fwd)
+    hipLaunchKernelGGL((k_nd_fused_fwd<T, KG>), dim3(nd_grid((long long)nfj * G)), dim3(512), lds, s,
+                       fjobs, nfj, G, batches, jobs, cells, umaps, fac, rpool, upool, ps, nrhs, kmax);
+  else
+    hipLaunchKernelGGL((k_nd_fused_bwd<T, KG>), dim3(nd_grid((long long)nfj * G)), dim3(512), lds, s,
+                       fjobs, nfj, G, batches, jobs, cells, fac, rpool, xpool, ps, nrhs);
+}
+
+template <typename T>
+void launch_nd_fused(bool fwd, int kg, const int2* fjobs, int nfj, const int2* batches,
+                     const NdLvlJob* jobs, const int* cells, const int* umaps, const cpx<T>* fac,
+                     cpx<T>* rpool, cpx<T>* upool, cpx<T>* xpool, long long pool_stride, int nrhs,
+                     int kmax, hipStream_t s) {
+  if (nfj <= 0 || nrhs <= 0) return;
+#define ND_FUSED(K) launch_fused_k<T, K>(fwd, fjobs, nfj, batches, jobs, cells, umaps, fac, rpool, \
+                                         upool, xpool, pool_stride, nrhs, kmax, s)
+  switch (kg) {
+    case 16: ND_FUSED(16); break;
+    case 8: ND_FUSED(8); break;
+    case 4: ND_FUSED(4); break;
+    case 2: ND_FUSED(2); break;
+    default: ND_FUSED(1); break;
+  }
+#undef ND_FUSED
 }
 
 // LDS needed by the dense top for a given RHS group (1 if even that does not fit)
@@ -1444,6 +1621,9 @@ void launch_nd_gemm(const NdGemmJob* jobs, int njobs, int max_m, int max_n, cpx<
   template void launch_nd_wide_bwd<T>(const NdLvlJob*, const int2*, int, const int*,              \
                                       const cpx<T>*, const cpx<T>*, cpx<T>*, long long, int,      \
                                       hipStream_t);                                               \
+  template void launch_nd_fused<T>(bool, int, const int2*, int, const int2*, const NdLvlJob*,     \
+                                   const int*, const int*, const cpx<T>*, cpx<T>*, cpx<T>*,       \
+                                   cpx<T>*, long long, int, int, hipStream_t);                    \
   template size_t nd_lvl_lds_bytes<T>(int, int);                                                 \
   template int nd_kg<T>(int, int, size_t);                                                       \
   template void launch_nd_copy<T>(const NdCopyJob*, int, int, int, cpx<double>*, cpx<T>*,       \

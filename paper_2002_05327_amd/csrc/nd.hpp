@@ -190,6 +190,16 @@ void launch_nd_wide_bwd(const NdLvlJob* jobs, const int2* tiles, int ntiles, con
                         const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long pool_stride,
                         int nrhs, hipStream_t s);
 int nd_wide_kg(size_t ts, int nrhs);
+// Fused bottom levels: one workgroup per (subtree below the fusion level, RHS
+// group); fjobs[i] = {first batch, batches}; a batch = {first job, jobs} of one
+// level whose fronts total at most ND_FUSE_CAP positions (job.pad = the node's
+// front offset in the batch).  Forward: batches in order; backward: reversed.
+constexpr int ND_FUSE_CAP = 512;
+template <typename T>
+void launch_nd_fused(bool fwd, int kg, const int2* fjobs, int nfj, const int2* batches,
+                     const NdLvlJob* jobs, const int* cells, const int* umaps, const cpx<T>* fac,
+                     cpx<T>* rpool, cpx<T>* upool, cpx<T>* xpool, long long pool_stride, int nrhs,
+                     int kmax, hipStream_t s);
 // LDS the dense top needs with one right-hand side per workgroup
 size_t nd_top_lds_need(size_t ts, int max_ntop);
 // RHS group of a dense top of ntop cells (a power of two <= kg that fits the LDS)

@@ -204,7 +204,9 @@ struct dsd_plan {
     double wf_bytes = 0, wb_bytes = 0, wf_cells = 0, wb_cells = 0;
   };
   struct NdLaunch {
-    std::vector<NdLevel> levels; // level 0 = the subtree roots
+    std::vector<NdLevel> levels; // level 0 = the subtree roots (levels above the fusion level)
+    int fj_off = 0, fj_n = 0;    // fused subtrees (d_nd_fj)
+    double fu_fbytes = 0, fu_bbytes = 0, fu_cells = 0;   // their factor bytes; front cells
     int top_off = 0, ntop = 0;   // dense-top jobs (d_nd_top)
     double top_bytes = 0, top_cells = 0;
     long long upd = 0;           // update-vector entries per RHS of the members
@@ -230,6 +232,8 @@ struct dsd_plan {
   int nd_wide = 1024;                   // fronts of at least this size run in wide mode
   int nd_max_nf_narrow = 0;             // largest front below nd_wide
   Buf d_nd_wide;                        // wide-mode tiles {job, first row}
+  int nd_fuse_level = 1 << 30;          // subtree levels from here down run fused
+  Buf d_nd_fj, d_nd_fb;                 // fused subtrees {first batch, batches}; batches {job, jobs}
   std::vector<int> nd_cell_of, nd_map_of;  // per node-table entry: cell and map offsets
   int nd_small = 4;    // levels whose largest node needs at most this many (row pass x
                        // column) / 64 run one node per wave
@@ -1180,6 +1184,21 @@ int nd_setup(dsd_plan* pl) {
   pl->nd_max_nf = pl->nd_max_ntop = pl->nd_max_nf_narrow = 0;
   pl->nd_lvmax.clear();
   pl->nd_wide = q.nd_wide > 0 ? q.nd_wide : 1024;
+  pl->nd_small = q.nd_wave_steps > 0 ? q.nd_wave_steps : 4;
+  // fusion level: the shallowest subtree level from which every node below
+  // (in every shape) has a front of at most nd_fuse cells
+  {
+    const int fuse_nf = std::min(ND_FUSE_CAP, q.nd_fuse > 0 ? q.nd_fuse : 128);
+    std::vector<int> mx;
+    for (const NdShape& sh : pl->nd_shapes)
+      for (const NdNode& n : sh.nodes) {
+        if (n.top) continue;
+        if ((int)mx.size() <= n.level) mx.resize(n.level + 1, 0);
+        mx[n.level] = std::max(mx[n.level], (int)(n.sep.size() + n.bnd.size()));
+      }
+    pl->nd_fuse_level = 1 << 30;
+    for (int l = (int)mx.size() - 1; l >= 0 && mx[l] <= fuse_nf; --l) pl->nd_fuse_level = l;
+  }
   for (size_t k = 0; k < pl->nd_shapes.size(); ++k) {
     const NdShape& sh = pl->nd_shapes[k];
     if (!nd_append_tables(sh, pl->nd_tabs[k], nodes, cells, maps, umaps, src, usrc, lev,
@@ -1192,6 +1211,7 @@ int nd_setup(dsd_plan* pl) {
       if (n.top) continue;
       const int ns = (int)n.sep.size(), nbd = (int)n.bnd.size(), nf = ns + nbd;
       if (nf < pl->nd_wide) pl->nd_max_nf_narrow = std::max(pl->nd_max_nf_narrow, nf);
+      if (n.level >= pl->nd_fuse_level) continue;
       if ((int)pl->nd_lvmax.size() <= n.level) pl->nd_lvmax.resize(n.level + 1);
       dsd_plan::NdLevelMax& M = pl->nd_lvmax[n.level];
       if (!nd_wide_node(pl, ns, nbd, true)) {
@@ -1242,12 +1262,14 @@ int nd_setup(dsd_plan* pl) {
 // count (passed at launch), so ubase is in entries per RHS.
 void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
                    std::vector<NdLvlJob>& lj, std::vector<NdTopJob>& tj, std::vector<int2>& wt,
-                   dsd_plan::NdLaunch& L) {
+                   std::vector<int2>& fj, std::vector<int2>& fb, dsd_plan::NdLaunch& L) {
   const double ts = (double)tsize(pl);
   L = dsd_plan::NdLaunch{};
   L.top_off = (int)tj.size();
+  L.fj_off = (int)fj.size();
   int nlev = 0;
   for (const int2& m : mem) nlev = std::max(nlev, pl->nd_shapes[pl->nd_shape_of[m.x]].nlev);
+  nlev = std::min(nlev, pl->nd_fuse_level);
   std::vector<std::vector<NdLvlJob>> per(nlev);
   std::vector<NdTopJob> tops;
   L.levels.assign(nlev, dsd_plan::NdLevel{});
@@ -1259,9 +1281,60 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     const NdShapeTab& tb = pl->nd_tabs[k];
     const long long vb = local ? 0 : S.vec_off * pl->kmax;
     const long long ub = local ? ubase : ubase * pl->kmax;
+    auto job_of = [&](size_t i) {
+      const NdNode& n = sh.nodes[i];
+      NdLvlJob J{};
+      J.ns = (int)n.sep.size();
+      J.nbd = (int)n.bnd.size();
+      J.cell = pl->nd_cell_of[tb.node0 + i];
+      J.umap = pl->nd_map_of[tb.node0 + i];
+      J.l = m.y;
+      J.nloc = S.nloc;
+      J.fac = S.fac_off + n.fac;
+      J.upd = n.upd;
+      J.vbase = vb;
+      J.ubase = ub;
+      return J;
+    };
+    // fused subtrees: the nodes below the fusion level, by their ancestor at
+    // it; per ancestor, level by level from the deepest, in batches whose
+    // fronts fit ND_FUSE_CAP positions
+    std::map<int, std::vector<std::vector<int>>> fuse;   // ancestor -> nodes per level
     for (size_t i = 0; i < sh.nodes.size(); ++i) {
       const NdNode& n = sh.nodes[i];
-      if (n.top) continue;
+      if (n.top || n.level < pl->nd_fuse_level) continue;
+      int a = (int)i;
+      while (sh.nodes[a].level > pl->nd_fuse_level) a = sh.nodes[a].parent;
+      std::vector<std::vector<int>>& lv = fuse[a];
+      const int d = n.level - pl->nd_fuse_level;
+      if ((int)lv.size() <= d) lv.resize(d + 1);
+      lv[d].push_back((int)i);
+    }
+    for (auto& kv : fuse) {
+      const int b0 = (int)fb.size();
+      for (int d = (int)kv.second.size() - 1; d >= 0; --d) {
+        int used = ND_FUSE_CAP;
+        for (int i : kv.second[d]) {
+          NdLvlJob J = job_of((size_t)i);
+          const int nf = J.ns + J.nbd;
+          if (used + nf > ND_FUSE_CAP) {
+            fb.push_back(make_int2((int)lj.size(), 0));
+            used = 0;
+          }
+          J.pad = used;
+          used += nf;
+          lj.push_back(J);
+          ++fb.back().y;
+          L.fu_fbytes += (double)J.nbd * J.ns * ts;
+          L.fu_bbytes += (double)J.ns * nf * ts;
+          L.fu_cells += (double)nf;
+        }
+      }
+      fj.push_back(make_int2(b0, (int)fb.size() - b0));
+    }
+    for (size_t i = 0; i < sh.nodes.size(); ++i) {
+      const NdNode& n = sh.nodes[i];
+      if (n.top || n.level >= pl->nd_fuse_level) continue;
       NdLvlJob J{};
       J.ns = (int)n.sep.size();
       J.nbd = (int)n.bnd.size();
@@ -1343,6 +1416,7 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     L.top_cells += (double)T.ntop;
   }
   tj.insert(tj.end(), tops.begin(), tops.end());
+  L.fj_n = (int)fj.size() - L.fj_off;
   L.ntop = (int)tops.size();
   L.upd = ubase;
 }
@@ -1351,22 +1425,26 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
 int build_nd_jobs(dsd_plan* pl) {
   std::vector<NdLvlJob> sj;
   std::vector<NdTopJob> tj;
-  std::vector<int2> wt;
+  std::vector<int2> wt, fj, fb;
   pl->nd_launch.assign(pl->groups.size(), dsd_plan::NdLaunch{});
   pl->nd_upd_max = 0;
   for (size_t g = 0; g < pl->groups.size(); ++g) {
-    nd_group_jobs(pl, pl->groups[g], false, sj, tj, wt, pl->nd_launch[g]);
+    nd_group_jobs(pl, pl->groups[g], false, sj, tj, wt, fj, fb, pl->nd_launch[g]);
     pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_launch[g].upd);
   }
   pl->nd_local.assign(pl->S, dsd_plan::NdLaunch{});
   for (int s = 0; s < pl->S; ++s) {
-    nd_group_jobs(pl, std::vector<int2>{make_int2(s, 0)}, true, sj, tj, wt, pl->nd_local[s]);
+    nd_group_jobs(pl, std::vector<int2>{make_int2(s, 0)}, true, sj, tj, wt, fj, fb, pl->nd_local[s]);
     pl->nd_upd_max = std::max(pl->nd_upd_max, pl->nd_local[s].upd);
   }
   CHK(upload(pl->d_nd_lvl, sj));
   CHK(upload(pl->d_nd_top, tj));
   if (wt.empty()) wt.push_back(make_int2(0, 0));
   CHK(upload(pl->d_nd_wide, wt));
+  if (fj.empty()) fj.push_back(make_int2(0, 0));
+  if (fb.empty()) fb.push_back(make_int2(0, 0));
+  CHK(upload(pl->d_nd_fj, fj));
+  CHK(upload(pl->d_nd_fb, fb));
   return 0;
 }
 
@@ -1876,6 +1954,15 @@ void nd_phase(dsd_plan* pl, const dsd_plan::NdLaunch& L, cpx<T>* R, cpx<T>* X, c
     if (timed) time_end(pl, b + 2.0 * c * nrhs * ts, b / ts * nrhs * 8.0);
   };
   const int nlev = (int)L.levels.size();
+  auto fused = [&](bool fwd) {
+    if (L.fj_n == 0) return;
+    if (timed) time_begin(pl);
+    launch_nd_fused<T>(fwd, pl->kg, pl->d_nd_fj.as<int2>() + L.fj_off, L.fj_n, pl->d_nd_fb.as<int2>(),
+                       lj, cells, pl->d_nd_umaps.as<int>(), fac, R, U, X, pool_stride, nrhs, kmax, st);
+    const double b = fwd ? L.fu_fbytes : L.fu_bbytes;
+    if (timed) time_end(pl, b + 2.0 * L.fu_cells * nrhs * ts, b / ts * nrhs * 8.0);
+  };
+  fused(true);
   for (int l = nlev - 1; l >= 0; --l) level(l, L.levels[l], true);
   // dense tops: the RHS group of the plan's largest top
   if (L.ntop > 0) {
@@ -1886,6 +1973,7 @@ void nd_phase(dsd_plan* pl, const dsd_plan::NdLaunch& L, cpx<T>* R, cpx<T>* X, c
     if (timed) time_end(pl, L.top_bytes + 2.0 * L.top_cells * nrhs * ts, L.top_bytes / ts * nrhs * 8.0);
   }
   for (int l = 0; l < nlev; ++l) level(l, L.levels[l], false);
+  fused(false);
 }
 
 template <typename T>
@@ -2481,10 +2569,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
       q.local_solver > 4 || q.schedule < 0 || q.schedule > 2 || q.dense_top < -1 ||
       q.dense_top > 64 || q.sweep_order < 0 || q.sweep_order > 1 ||
       (q.sweep_order == 1 && q.dim != 3) || q.nd_leaf < 0 || q.nd_top_cells < 0 ||
-      q.nd_top_cells > 5000 || q.nd_wide < 0) {
+      q.nd_top_cells > 5000 || q.nd_wide < 0 || q.nd_wave_steps < 0 || q.nd_fuse < 0) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
                "local_solver 0..4, schedule 0..2, dense_top -1..64, sweep_order 0..1 (1: 3D only), "
-               "nd_leaf >= 0, nd_top_cells 0..5000, nd_wide >= 0";
+               "nd_leaf >= 0, nd_top_cells 0..5000, nd_wide >= 0, nd_wave_steps >= 0, nd_fuse >= 0";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)
@@ -2504,13 +2592,14 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   pl->sequential = q.schedule == 1;
   pl->additive = q.schedule == 2;
   if (rc == 0) {
-    // local solver: block cyclic reduction unless its factor (about three
-    // times the chain factor) would take more than 45% of the device memory
+    // local solver: nested dissection in 3D; in 2D block cyclic reduction
+    // unless its factor (about three times the chain factor) would take more
+    // than 45% of the device memory
     std::vector<long long> toff(pl->S);
     for (int i = 0; i < pl->S; ++i) toff[i] = pl->subs[i].fac_off;
     const long long tsum = pl->sum_fac;
     pl->solver = (q.local_solver == 1 || q.local_solver == 3) ? 1 : 2;
-    if (q.local_solver == 4) {
+    if (q.local_solver == 4 || (q.local_solver == 0 && q.dim == 3)) {
       pl->solver = 4;
       rc = nd_setup(pl);
     }

@@ -123,25 +123,18 @@ def test_c3_sweep_matches_oracle_sweep():
 
 def test_c4r_solutions_and_local_solves_against_oracle():
     """C4r (80^3, 4x4x4, 32 RHS, complex64 + FP64 refinement, as bench.py
-    --workload c4r runs it): every RHS meets the FP64 true residual 1e-6 under
-    the oracle's operator, and the local solves of an interior and a corner
-    subdomain equal the oracle's local sparse LU (complex64 2e-4, complex128
-    1e-11)."""
+    --workload c4r runs it), with the nested-dissection local solver (the 3D
+    default; its top separators run in wide mode) and with the block-chain
+    solver: every RHS meets the FP64 true residual 1e-6 under the oracle's
+    operator, and the local solves of an interior and a corner subdomain equal
+    the oracle's local sparse LU (complex64 2e-4, complex128 1e-11)."""
     import scipy.sparse.linalg as spla
     from oracle.partition import Partition
     from oracle.pml import assemble
     w, c, F = _workload("c4r")
     M = _oracle_operator(w, c)
     b = torch.from_numpy(F).cuda()
-    plan = _plan(w, c, "c64")
-    sol, iters, relres, ok = plan.gmres(b, tol=1e-6, maxit=100, restart=30)
-    assert ok
-    X = sol.cpu().numpy().reshape(F.shape[0], -1)
     B = F.reshape(F.shape[0], -1)
-    rr = np.linalg.norm((M @ X.T).T - B, axis=1) / np.linalg.norm(B, axis=1)
-    print(f"c4r: iterations {min(iters)}-{max(iters)}; oracle-operator residual max {rr.max():.2e}",
-          flush=True)
-    assert rr.max() <= 1.0e-6 * 1.001
     part = Partition(w.n, w.parts, w.pml, w.overlap, w.h)
     corner, interior = 0, 1 + 4 + 16          # parts (0,0,0) and (1,1,1)
     cases = []
@@ -152,14 +145,51 @@ def test_c4r_solutions_and_local_solves_against_oracle():
         Ml = assemble(axes, 1.0 / c ** 2, w.h, w.omega, w.pml).tocsc()
         r = rng.standard_normal((2, Ml.shape[0])) + 1j * rng.standard_normal((2, Ml.shape[0]))
         cases.append((sid, shape, r, spla.splu(Ml).solve(r.T).T))
-    for prec, tol in [("c64", 2e-4), ("c128", 1e-11)]:
-        if prec == "c128":
-            plan.close()
-            plan = _plan(w, c, "c128", max_rhs=2)
-        for sid, shape, r, u_ref in cases:
-            u = plan.local_solve(sid, torch.from_numpy(r.reshape((2,) + shape)).cuda())
-            close(u.cpu().numpy().reshape(2, -1), u_ref, tol, f"c4r {prec} local solve sub {sid}")
+    for solver in ("auto", "chain-steps"):
+        plan = _plan(w, c, "c64", local_solver=solver)
+        if solver == "auto":
+            assert plan.local_solver == "nd"
+        sol, iters, relres, ok = plan.gmres(b, tol=1e-6, maxit=100, restart=30)
+        assert ok
+        X = sol.cpu().numpy().reshape(F.shape[0], -1)
+        rr = np.linalg.norm((M @ X.T).T - B, axis=1) / np.linalg.norm(B, axis=1)
+        print(f"c4r {plan.local_solver}: iterations {min(iters)}-{max(iters)}; "
+              f"oracle-operator residual max {rr.max():.2e}", flush=True)
+        assert rr.max() <= 1.0e-6 * 1.001
+        for prec, tol in [("c64", 2e-4), ("c128", 1e-11)]:
+            if prec == "c128":
+                plan.close()
+                plan = _plan(w, c, "c128", max_rhs=2, local_solver=solver)
+            for sid, shape, r, u_ref in cases:
+                u = plan.local_solve(sid, torch.from_numpy(r.reshape((2,) + shape)).cuda())
+                close(u.cpu().numpy().reshape(2, -1), u_ref, tol,
+                      f"c4r {solver} {prec} local solve sub {sid}")
+        plan.close()
+
+
+@pytest.mark.timeout(900)
+def test_c4_full_size_fits_and_converges():
+    """Full C4 (160^3, h = 1/160, omega = 2 pi 12, 4x4x4, PML 8, overlap 4, 32 RHS,
+    complex64 factors + FP64 refinement) with the nested-dissection local solver:
+    the plan fits on one device and every RHS meets the FP64 true residual 1e-6
+    under the oracle's own operator assembly."""
+    w, c, F = _workload("c4")
+    b = torch.from_numpy(F).cuda()
+    plan = _plan(w, c, "c64")
+    assert plan.local_solver == "nd"
+    info = plan.info()
+    print(f"c4: factor {info['factor_bytes'] / 1e9:.1f} GB", flush=True)
+    sol, iters, relres, ok = plan.gmres(b, tol=1e-6, maxit=100, restart=20)
+    assert ok
+    X = sol.cpu().numpy().reshape(F.shape[0], -1)
     plan.close()
+    del sol, b
+    M = _oracle_operator(w, c)
+    B = F.reshape(F.shape[0], -1)
+    rr = np.linalg.norm((M @ X.T).T - B, axis=1) / np.linalg.norm(B, axis=1)
+    print(f"c4: iterations {min(iters)}-{max(iters)}; oracle-operator residual max {rr.max():.2e}",
+          flush=True)
+    assert rr.max() <= 1.0e-6 * 1.001
 
 
 def _fwi_setup(n_cells, parts, nsrc, nrec):

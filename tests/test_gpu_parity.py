@@ -23,16 +23,25 @@ torch = pytest.importorskip("torch")
 
 def _plan(n, h, om, pml, d, parts, c, prec, k, kg=0, schedule="dag", solver="auto", dense_top=0):
     """solver "nd-wide": nested dissection with every node in wide mode (tiled
-    products over all right-hand sides of a group, vectors streamed through LDS)."""
+    products over all right-hand sides of a group, vectors streamed through LDS);
+    "nd-mfma": nested dissection with 16 right-hand sides per workgroup, where its
+    LDS-front kernels run on the matrix cores; "nd-fused": leaves of at most 16
+    cells and the subtree levels whose fronts have at most 128 cells fused into
+    one workgroup per subtree; "nd-fused-all": every subtree level fused."""
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(slowness2(c)).cuda()
     wide = 1 if solver == "nd-wide" else 0
+    if solver == "nd-mfma" and kg == 0:
+        kg = 16
+    leaf = 16 if solver.startswith("nd-fused") else 0
+    fuse = 512 if solver == "nd-fused-all" else 0
     return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
                     max_rhs=k, rhs_per_group=kg, schedule=schedule,
-                    local_solver="nd" if wide else solver, dense_top=dense_top, nd_wide=wide)
+                    local_solver="nd" if solver.startswith("nd") else solver,
+                    dense_top=dense_top, nd_wide=wide, nd_leaf=leaf, nd_fuse=fuse)
 
 
-SOLVERS = ["bcr", "chain", "chain-steps", "nd", "nd-wide"]
+SOLVERS = ["bcr", "chain", "chain-steps", "nd", "nd-wide", "nd-mfma", "nd-fused", "nd-fused-all"]
 
 
 def _cuda(x):

@@ -15,15 +15,18 @@ torch = pytest.importorskip("torch")
 
 
 def _plan(n, h, om, pml, d, parts, c, prec, k, solver):
-    """solver "nd-wide": nested dissection with every node in wide mode."""
+    """solver "nd-wide": nested dissection with every node in wide mode; "nd-fused":
+    leaves of at most 16 cells, the small subtree levels fused."""
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(slowness2(c)).cuda()
     wide = 1 if solver == "nd-wide" else 0
+    leaf = 16 if solver == "nd-fused" else 0
     return dsw.Plan(n=n, h=h, omega=om, pml=pml, overlap=d, parts=parts, m=m, precision=prec,
-                    max_rhs=k, local_solver="nd" if wide else solver, nd_wide=wide)
+                    max_rhs=k, local_solver="nd" if solver.startswith("nd") else solver,
+                    nd_wide=wide, nd_leaf=leaf)
 
 
-@pytest.mark.parametrize("solver", ["bcr", "chain", "chain-steps", "nd", "nd-wide"])
+@pytest.mark.parametrize("solver", ["bcr", "chain", "chain-steps", "nd", "nd-wide", "nd-fused"])
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_noalloc_local_solve_equals_local_solve(solver, prec):
     n, h, om, pml, d, parts = (61, 70), 1 / 61, 2 * np.pi * 4, 6, 4, (3, 4)
