@@ -84,9 +84,11 @@ typedef struct {
                                separators stored inverted, the separators above a
                                depth applied as one dense inverse, one workgroup per
                                remaining subtree (about a quarter of the band factor);
-                            0: 4 in 3D; in 2D 2 unless its factor would exceed 45% of
-                               device memory, else 3 for blocks of 512 cells or more,
-                               else 1.                                                  */
+                            0: 4 in 3D, 2 in 2D (in 2D nested dissection first
+                               eliminates closed boxes of physical medium many
+                               wavelengths wide, whose separator blocks can be near
+                               singular; it is faster on some workloads, see
+                               dsd_plan_pivots).                                          */
   int dense_top;         /* block cyclic reduction only: the reduction stops at the first
                             level that has at most this many blocks (at least 2) and
                             applies the precomputed inverse of that reduced system as one

@@ -354,11 +354,18 @@ typedef float nd_mf4 __attribute__((ext_vector_type(4)));
 // the FP32 vector FMAs were measured faster there.
 constexpr int ND_MFMA_KG = 16;
 
+// The right-hand sides y sit in LDS at entry y_off of the dynamic LDS.  All
+// loads are issued at clamped (valid) addresses and masked afterwards: a
+// conditional load `c ? p[i] : 0` becomes a load from a selected address, a
+// generic pointer, which compiles to flat loads; those wait for every global
+// load in flight and break the pipelining of the matrix loads.
 template <int JB>
 __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<float>* __restrict__ A,
-                                             long long lda, int nrows, const cpx<float>* y,
+                                             long long lda, int nrows, long long y_off,
                                              int c0, int c1, int lane) {
   typedef cpx<float> C;
+  extern __shared__ unsigned char smem_raw[];
+  const C* y = reinterpret_cast<const C*>(smem_raw) + y_off;
   constexpr int KG = 8 * JB;
   constexpr int CH = 4;                      // 4-column chunks per batch of loads
   const int lr = lane & 15, lk = lane >> 4, n = lane & 15, qn = n >> 1;
@@ -373,7 +380,8 @@ __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<flo
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb) {
         const int row = 16 * rb + lr;
-        buf[c][rb] = (cv && row < nrows) ? A[(long long)col * lda + row] : zero;
+        const C v = A[(long long)min(col, c1 - 1) * lda + min(row, nrows - 1)];
+        buf[c][rb] = (cv && row < nrows) ? v : zero;
       }
     }
   };
@@ -385,7 +393,8 @@ __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<flo
       float bre[JB], bim[JB];
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) {
-        const C yv = col < c1 ? y[col * KG + jb * 8 + qn] : zero;
+        const C y0 = y[min(col, c1 - 1) * KG + jb * 8 + qn];
+        const C yv = col < c1 ? y0 : zero;
         bre[jb] = im ? yv.im : yv.re;
         bim[jb] = im ? yv.re : -yv.im;
       }
@@ -412,12 +421,15 @@ __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<flo
 }
 
 // The complex outputs of a wave's MFMA tile: the (re, im) halves of a value sit
-// in neighbouring lanes; they meet through the wave's LDS staging area st
-// (64 x KG complex) and come back as row `lane`, all KG right-hand sides.
+// in neighbouring lanes; they meet through the wave's LDS staging area (64 x KG
+// complex, at float st_off of the dynamic LDS) and come back as row `lane`,
+// all KG right-hand sides.
 template <int JB>
-__device__ __forceinline__ void nd_mfma_out(const nd_mf4 (&acc)[4][JB], float* st, int lane,
+__device__ __forceinline__ void nd_mfma_out(const nd_mf4 (&acc)[4][JB], long long st_off, int lane,
                                             cpx<float> (&out)[8 * JB]) {
   constexpr int KG = 8 * JB;
+  extern __shared__ unsigned char smem_raw[];
+  float* st = reinterpret_cast<float*>(smem_raw) + st_off;
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -523,8 +535,8 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
-    if (t * 64 < nbd) nd_mfma_rows<JB>(macc, L + t * 64, nbd, nbd - t * 64, fr, c0, c1, lane);
-    float* pf = reinterpret_cast<float*>(fr + region);
+    if (t * 64 < nbd) nd_mfma_rows<JB>(macc, L + t * 64, nbd, nbd - t * 64, 0, c0, c1, lane);
+    float* pf = reinterpret_cast<float*>(smem_raw) + 2LL * region;
     if (CG > 1) {
       if (cgi > 0) {
 #pragma unroll
@@ -547,7 +559,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
               macc[rb][jb][r] += pf[((((o - 1) * TT + t) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
     }
     C out[KG];
-    nd_mfma_out<JB>(macc, pf + (long long)t * 64 * KG * 2, lane, out);
+    nd_mfma_out<JB>(macc, 2LL * region + (long long)t * 64 * KG * 2, lane, out);
     if (live) {
 #pragma unroll
       for (int q = 0; q < KG; ++q)
@@ -649,8 +661,8 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
-    if (t * 64 < ns) nd_mfma_rows<JB>(macc, K + t * 64, ns, ns - t * 64, v, c0, c1, lane);
-    float* pf = reinterpret_cast<float*>(v + region);
+    if (t * 64 < ns) nd_mfma_rows<JB>(macc, K + t * 64, ns, ns - t * 64, 0, c0, c1, lane);
+    float* pf = reinterpret_cast<float*>(smem_raw) + 2LL * region;
     if (CG > 1) {
       if (cgi > 0) {
 #pragma unroll
@@ -673,7 +685,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
               macc[rb][jb][r] += pf[((((o - 1) * TT + t) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
     }
     C out[KG];
-    nd_mfma_out<JB>(macc, pf + (long long)t * 64 * KG * 2, lane, out);
+    nd_mfma_out<JB>(macc, 2LL * region + (long long)t * 64 * KG * 2, lane, out);
     if (live) {
       const int cell = fc[i];
 #pragma unroll
@@ -769,9 +781,9 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
     // gl holds this wave's columns c0..c1 from its start: shift y so that y[col] = gl[col - c0]
-    nd_mfma_rows<JB>(macc, P + tile * 64 + (long long)c0 * ntop, ntop, ntop - tile * 64, gl - 0,
-                     0, c1 - c0, lane);
-    float* pf = reinterpret_cast<float*>(lds + (long long)ND_TW * cwmax * KG);
+    nd_mfma_rows<JB>(macc, P + tile * 64 + (long long)c0 * ntop, ntop, ntop - tile * 64,
+                     (long long)w * cwmax * KG, 0, c1 - c0, lane);
+    float* pf = reinterpret_cast<float*>(smem_raw) + 2LL * ND_TW * cwmax * KG;
     if (w > 0) {
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
@@ -792,7 +804,7 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
           for (int r = 0; r < 4; ++r)
             macc[rb][jb][r] += pf[(((o - 1) * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
     C out[KG];
-    nd_mfma_out<JB>(macc, pf, lane, out);
+    nd_mfma_out<JB>(macc, 2LL * ND_TW * cwmax * KG, lane, out);
     if (i < ntop) {
       const int cell = tc[i];
 #pragma unroll
@@ -854,10 +866,14 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
 // ---- wide mode: nodes whose front is too large for the LDS (or with more
 // than 512 rows) run their products as tiled matrix products over every
 // right-hand side of a group of KG (up to 32) at once, so that each factor
-// entry is read once per solve.  A workgroup of four waves takes 256 rows of
-// one node; the columns stream through LDS in chunks of ND_WCK (the vector
-// entries of the chunk for all KG right-hand sides, double-buffered), each wave
-// multiplies its 64-row tile.  The forward pass first forms f_S (k_nd_form)
+// entry is read once per solve.  A workgroup of eight waves takes 256 rows of
+// one node: four 64-row tiles x two column halves (two waves per SIMD keep the
+// matrix cores fed while the other waits for its loads).  Each half streams
+// its columns through LDS in chunks of ND_WCK (the vector entries of the chunk
+// for all KG right-hand sides, double-buffered), and the halves meet in LDS:
+// the second half's partial sums are added to the first's, so every row sums
+// its columns in the same order whatever else the launch holds.  The forward
+// pass first forms f_S (k_nd_form)
 // and ends with u_B = (children's updates on B) - L f_S; the backward pass is
 // x_S = K [f_S; -x_B].  Tiles are {job, first row} entries of a table.
 constexpr int ND_WCK = 64;
@@ -892,13 +908,14 @@ __global__ __launch_bounds__(256) void k_nd_form(const NdLvlJob* __restrict__ jo
 }
 
 // Stage the vector entries of columns [c0, c0 + n) for right-hand sides
-// [q0, q0 + nq) into buf[c * KG + q] (zero beyond n or nq): column c < ns
-// from R (f_S), column c >= ns from -X (boundary, backward pass only).
+// [q0, q0 + nq) into buf[c * KG + q] (zero beyond n or nq), by the 256
+// threads of one column half: column c < ns from R (f_S), column c >= ns from
+// -X (boundary, backward pass only).
 template <typename T, int KG>
 __device__ __forceinline__ void nd_wide_stage(cpx<T>* buf, const int* fc, int ns, int c0, int n,
                                               int q0, int nq, const cpx<T>* R, const cpx<T>* X,
                                               long long nloc) {
-  for (int e = threadIdx.x; e < ND_WCK * KG; e += blockDim.x) {
+  for (int e = threadIdx.x & 255; e < ND_WCK * KG; e += 256) {
     const int c = e / KG, q = e - (e / KG) * KG;
     cpx<T> v = mk((T)0, (T)0);
     if (c < n && q < nq) {
@@ -910,9 +927,13 @@ __device__ __forceinline__ void nd_wide_stage(cpx<T>* buf, const int* fc, int ns
   }
 }
 
-// acc (rows row0 + 64 w + lane) = A[rows, 0:ncol] y, A column-major (lda), the
-// columns staged chunk by chunk; complex64 on the FP32 matrix cores, complex128
-// with vector FMAs.  Returns the tile's values for this lane's row in out.
+// out (row `lane` of this wave's 64-row tile) = A[tile rows, 0:ncol] y, A
+// column-major (lda, already offset to the tile), the columns of this wave's
+// half staged chunk by chunk; complex64 on the FP32 matrix cores, complex128
+// with vector FMAs.  out is valid in the first half's waves (w < 4) only.
+// LDS (entries from the base): staging [0, 4 ND_WCK KG) (half h at
+// 2 h ND_WCK KG), reused for the second half's partial sums; the MFMA output
+// staging at [4 ND_WCK KG, 4 ND_WCK KG + 256 KG).
 template <typename T, int KG>
 __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, long long lda,
                                                 int nrows_tile, int ncol, int ns, const int* fc,
@@ -920,10 +941,16 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
                                                 long long nloc, cpx<T>* lds, cpx<T> (&out)[KG]) {
   typedef cpx<T> C;
   const int lane = threadIdx.x & 63;
-  C* buf0 = lds;
-  C* buf1 = lds + ND_WCK * KG;
-  const int nch = (ncol + ND_WCK - 1) / ND_WCK;
-  if (nch > 0) nd_wide_stage<T, KG>(buf0, fc, ns, 0, min(ND_WCK, ncol), q0, nq, R, X, nloc);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int h = w >> 2, t = w & 3;
+  const int half = (((ncol + 1) / 2) + 3) / 4 * 4;   // a multiple of the MFMA column step
+  const int cb = min(ncol, h * half), ce = min(ncol, cb + half);
+  const int nown = (ce - cb + ND_WCK - 1) / ND_WCK;
+  const int nch = (min(ncol, half) + ND_WCK - 1) / ND_WCK;   // the first half's chunks (>= own)
+  const long long hb = (long long)h * 2 * ND_WCK * KG;        // this half's staging
+  C* buf0 = lds + hb;
+  C* buf1 = buf0 + ND_WCK * KG;
+  if (nown > 0) nd_wide_stage<T, KG>(buf0, fc, ns, cb, min(ND_WCK, ce - cb), q0, nq, R, X, nloc);
   __syncthreads();
   if constexpr (std::is_same<T, float>::value && KG % 8 == 0) {
     constexpr int JB = KG / 8;
@@ -932,44 +959,74 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
+    // lds is the base of the dynamic LDS: this half's buffer k & 1 starts at
+    // entry hb + (k & 1) ND_WCK KG
     for (int k = 0; k < nch; ++k) {
-      C* cur = (k & 1) ? buf1 : buf0;
       C* nxt = (k & 1) ? buf0 : buf1;
-      const int c0 = k * ND_WCK, cn = min(ND_WCK, ncol - c0);
-      if (k + 1 < nch)
-        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ncol - c0 - ND_WCK), q0, nq, R,
+      const int c0 = cb + k * ND_WCK, cn = min(ND_WCK, ce - c0);
+      if (k + 1 < nown)
+        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ce - c0 - ND_WCK), q0, nq, R,
                              X, nloc);
-      if (nrows_tile > 0) nd_mfma_rows<JB>(macc, A + (long long)c0 * lda, lda, nrows_tile, cur, 0, cn, lane);
+      if (k < nown && nrows_tile > 0)
+        nd_mfma_rows<JB>(macc, A + (long long)c0 * lda, lda, nrows_tile,
+                         hb + ((k & 1) ? ND_WCK * KG : 0), 0, cn, lane);
       __syncthreads();
     }
-    // the staging buffers are free now: each wave turns its tile into rows
-    float* st = reinterpret_cast<float*>(lds) + (threadIdx.x >> 6) * 64 * KG * 2;
-    nd_mfma_out<JB>(macc, st, lane, out);
+    // the staging area is free: the second half's partial sums go there
+    float* pf = reinterpret_cast<float*>(lds);
+    if (h == 1) {
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) pf[((t * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane] = macc[rb][jb][r];
+    }
+    __syncthreads();
+    if (h == 1) return;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int jb = 0; jb < JB; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) macc[rb][jb][r] += pf[((t * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
+    nd_mfma_out<JB>(macc, 2LL * 4 * ND_WCK * KG + (long long)t * 64 * KG * 2, lane, out);
   } else {
 #pragma unroll
     for (int q = 0; q < KG; ++q) out[q] = mk((T)0, (T)0);
     for (int k = 0; k < nch; ++k) {
       C* cur = (k & 1) ? buf1 : buf0;
       C* nxt = (k & 1) ? buf0 : buf1;
-      const int c0 = k * ND_WCK, cn = min(ND_WCK, ncol - c0);
-      if (k + 1 < nch)
-        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ncol - c0 - ND_WCK), q0, nq, R,
+      const int c0 = cb + k * ND_WCK, cn = min(ND_WCK, ce - c0);
+      if (k + 1 < nown)
+        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ce - c0 - ND_WCK), q0, nq, R,
                              X, nloc);
-      if (lane < nrows_tile) nd_dot_rows<T, KG, false>(out, A + (long long)c0 * lda + lane, lda, cur, 0, cn);
+      if (k < nown && lane < nrows_tile)
+        nd_dot_rows<T, KG, false>(out, A + (long long)c0 * lda + lane, lda, cur, 0, cn);
       __syncthreads();
     }
+    C* part = lds;
+    if (h == 1) {
+#pragma unroll
+      for (int q = 0; q < KG; ++q) part[(t * KG + q) * 64 + lane] = out[q];
+    }
+    __syncthreads();
+    if (h == 1) return;
+#pragma unroll
+    for (int q = 0; q < KG; ++q) out[q] = out[q] + part[(t * KG + q) * 64 + lane];
   }
 }
 
 template <typename T>
 constexpr size_t nd_wide_lds_entries(int kg) {
-  // two staging chunks; the MFMA output staging (4 waves x 64 x KG) reuses them
-  return (size_t)std::max(2 * ND_WCK * kg, 4 * 64 * kg);
+  // two halves x two staging chunks (reused for the partial sums, 4 x 64 x KG),
+  // then the MFMA output staging (4 waves x 64 x KG)
+  return (size_t)std::max(4 * ND_WCK * kg, 4 * 64 * kg) + (size_t)4 * 64 * kg;
 }
 
 // u_B = (children's updates on B) - L f_S for rows [t.y, t.y + 256) of node t.x
 template <typename T, int KG>
-__global__ __launch_bounds__(256) void k_nd_wide_fwd(
+__global__ __launch_bounds__(512) void k_nd_wide_fwd(
     const NdLvlJob* __restrict__ jobs, const int2* __restrict__ tiles, int ntiles, int G,
     const int* __restrict__ cells, const int* __restrict__ umaps, const cpx<T>* __restrict__ fac,
     const cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ upool, long long pool_stride,
@@ -985,14 +1042,14 @@ __global__ __launch_bounds__(256) void k_nd_wide_fwd(
   const int ns = J.ns, nbd = J.nbd;
   const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = t.y + 64 * w;
+  const int r0 = t.y + 64 * (w & 3);
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C out[KG];
   nd_wide_product<T, KG>(fac + J.fac + r0, nbd, max(0, min(64, nbd - r0)), ns, ns, cells + J.cell,
                          q0, nq, R, R, J.nloc, lds, out);
   const int i = r0 + lane;
-  if (i < nbd) {
+  if (w < 4 && i < nbd) {                 // the first column half holds the sums
     const int p = ns + i;
     const int i0 = umaps[J.umap + 2 * p], i1 = umaps[J.umap + 2 * p + 1];
 #pragma unroll
@@ -1009,7 +1066,7 @@ __global__ __launch_bounds__(256) void k_nd_wide_fwd(
 
 // x_S = K [f_S; -x_B] for rows [t.y, t.y + 256) of node t.x
 template <typename T, int KG>
-__global__ __launch_bounds__(256) void k_nd_wide_bwd(
+__global__ __launch_bounds__(512) void k_nd_wide_bwd(
     const NdLvlJob* __restrict__ jobs, const int2* __restrict__ tiles, int ntiles, int G,
     const int* __restrict__ cells, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
     cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs) {
@@ -1024,14 +1081,14 @@ __global__ __launch_bounds__(256) void k_nd_wide_bwd(
   const int ns = J.ns, nf = J.ns + J.nbd;
   const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = t.y + 64 * w;
+  const int r0 = t.y + 64 * (w & 3);
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C out[KG];
   nd_wide_product<T, KG>(fac + J.fac + (long long)J.nbd * ns + r0, ns, max(0, min(64, ns - r0)), nf,
                          ns, cells + J.cell, q0, nq, R, X, J.nloc, lds, out);
   const int i = r0 + lane;
-  if (i < ns) {
+  if (w < 4 && i < ns) {                  // the first column half holds the sums
     const int cell = cells[J.cell + i];
 #pragma unroll
     for (int q = 0; q < KG; ++q)
@@ -1316,7 +1373,7 @@ static void launch_wide_fwd_k(const NdLvlJob* jobs, const int2* tiles, int ntile
                               const int* umaps, const cpx<T>* fac, const cpx<T>* rpool,
                               cpx<T>* upool, long long ps, int nrhs, int kmax, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  hipLaunchKernelGGL((k_nd_wide_fwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(256),
+  hipLaunchKernelGGL((k_nd_wide_fwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(512),
                      nd_wide_lds_entries<T>(KG) * sizeof(cpx<T>), s, jobs, tiles, ntiles, G, cells,
                      umaps, fac, rpool, upool, ps, nrhs, kmax);
 }
@@ -1326,7 +1383,7 @@ static void launch_wide_bwd_k(const NdLvlJob* jobs, const int2* tiles, int ntile
                               const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long ps,
                               int nrhs, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  hipLaunchKernelGGL((k_nd_wide_bwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(256),
+  hipLaunchKernelGGL((k_nd_wide_bwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(512),
                      nd_wide_lds_entries<T>(KG) * sizeof(cpx<T>), s, jobs, tiles, ntiles, G, cells,
                      fac, rpool, xpool, ps, nrhs);
 }

@@ -2592,31 +2592,22 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   pl->sequential = q.schedule == 1;
   pl->additive = q.schedule == 2;
   if (rc == 0) {
-    // local solver: nested dissection in 3D; in 2D block cyclic reduction
-    // unless its factor (about three times the chain factor) would take more
-    // than 45% of the device memory
-    std::vector<long long> toff(pl->S);
-    for (int i = 0; i < pl->S; ++i) toff[i] = pl->subs[i].fac_off;
-    const long long tsum = pl->sum_fac;
-    pl->solver = (q.local_solver == 1 || q.local_solver == 3) ? 1 : 2;
-    if (q.local_solver == 4 || (q.local_solver == 0 && q.dim == 3)) {
-      pl->solver = 4;
-      rc = nd_setup(pl);
-    }
+    // local solver: nested dissection in 3D, block cyclic reduction in 2D.  In
+    // 2D the subdomains span many wavelengths and nested dissection eliminates
+    // closed boxes of physical medium first, whose Dirichlet problems can sit
+    // near resonance (ill-conditioned separator blocks); the reduction
+    // eliminates thin slabs that reach the PML.
+    pl->solver = q.local_solver == 1 || q.local_solver == 3 ? 1
+               : q.local_solver == 2 || (q.local_solver == 0 && q.dim == 2) ? 2 : 4;
+    if (pl->solver == 4) rc = nd_setup(pl);
     if (pl->solver == 2) {
       pl->dense_max = dense_blocks(pl, q.dense_top);
       bcr_layout(pl);
-      size_t fr = 0, tot = 0;
-      if (q.local_solver == 0 && hipMemGetInfo(&fr, &tot) == hipSuccess &&
-          (double)pl->sum_fac * tsize(pl) > 0.45 * (double)tot) {
-        pl->solver = 1;
-        for (int i = 0; i < pl->S; ++i) pl->subs[i].fac_off = toff[i];
-        pl->sum_fac = tsum;
-      }
     }
-    // chain solves: one launch per block step for wide blocks (the 3D planes),
-    // where one workgroup per chain would leave most of the GPU idle
-    pl->chain_steps = pl->solver == 1 && (q.local_solver == 3 || (q.local_solver == 0 && pl->max_nb >= 512));
+    // chain block steps: one launch per block step, every chain of a launch
+    // group in it (for wide blocks, where one workgroup per chain would leave
+    // most of the GPU idle)
+    pl->chain_steps = q.local_solver == 3;
   }
   if (rc == 0) {
     const int kdef = pl->solver == 4 ? 8 : ((pl->solver == 2 || pl->chain_steps) ? (pl->c64 ? 8 : 4) : 2);
