@@ -79,15 +79,18 @@ typedef struct {
                                memory; every reduction level is one batched launch);
                             3: the LDL^T chains of 1 with one launch per block step,
                                every chain of a launch group in it (wide blocks);
-                            4: nested dissection (multifrontal): recursive bisection of
-                               the subdomain box, the Schur complements of the
-                               separators stored inverted, the separators above a
-                               depth applied as one dense inverse, one workgroup per
-                               remaining subtree (about a quarter of the band factor);
-                            0: 4 in 3D, 2 in 2D (in 2D nested dissection first
-                               eliminates closed boxes of physical medium many
-                               wavelengths wide, whose separator blocks can be near
-                               singular; it is faster on some workloads, see
+                            4: nested dissection (multifrontal, the local solver of
+                               Section 5's experiments): recursive bisection of the
+                               subdomain box, the Schur complements of the separators
+                               stored inverted, the separators above a depth applied
+                               as one dense inverse, one launch per tree level over
+                               every node of a launch group (in 3D about a sixth of
+                               the band factor; the only one full C4 fits in);
+                            0: 4 in 3D; in 2D 2 unless its factor would exceed 45% of
+                               device memory, else 3 for blocks of 512 cells or more,
+                               else 1 (in 2D nested dissection first eliminates closed
+                               boxes of physical medium many wavelengths wide, whose
+                               separator blocks can be near singular; see
                                dsd_plan_pivots).                                          */
   int dense_top;         /* block cyclic reduction only: the reduction stops at the first
                             level that has at most this many blocks (at least 2) and
@@ -141,6 +144,14 @@ void dsd_destroy(dsd_plan* plan);
 /* Sizes of a plan (host outputs; any pointer may be NULL). */
 int dsd_plan_info(const dsd_plan* plan, long long* n_global, int* n_subdomains,
                   long long* factor_bytes, long long* workspace_bytes);
+
+/* Pivot report of the factorisation (host outputs; either may be NULL): every
+ * dense block the local solver inverts (Gauss-Jordan with partial pivoting in
+ * FP64) records its largest and smallest pivot magnitude; *ratio is the largest
+ * max|pivot| / min|pivot| over all of them (a lower bound on that block's
+ * condition number: a large value flags a nearly singular local block, whose
+ * complex64 factor loses that many digits) and *subdomain its subdomain. */
+int dsd_plan_pivots(const dsd_plan* plan, double* ratio, int* subdomain);
 
 /* Local solver in use: 1 = twisted block LDL^T chains, 2 = block cyclic reduction,
  * 3 = LDL^T chains with one launch per block step, 4 = nested dissection

@@ -95,6 +95,13 @@ class Plan:
         return {"n_global": ng.value, "n_subdomains": ns.value, "factor_bytes": fb.value,
                 "workspace_bytes": wb.value}
 
+    def pivots(self) -> dict:
+        """dsd_plan_pivots: the largest max|pivot| / min|pivot| of the factorisation's
+        block inversions and its subdomain."""
+        r, sub = C.c_double(), C.c_int()
+        check(self._lib.dsd_plan_pivots(self._h, C.byref(r), C.byref(sub)), "dsd_plan_pivots")
+        return {"ratio": r.value, "subdomain": sub.value}
+
     def subdomain_grid(self, sub: int) -> Tuple[Tuple[int, ...], Tuple[int, ...]]:
         dims, g0 = (C.c_int * 3)(), (C.c_int * 3)()
         check(self._lib.dsd_subdomain_grid(self._h, int(sub), dims, g0), "dsd_subdomain_grid")

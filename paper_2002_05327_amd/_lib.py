@@ -29,6 +29,7 @@ EXPORTS = {
     "dsd_plan_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_longlong), C.POINTER(C.c_int),
                                 C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     "dsd_plan_local_solver": (C.c_int, [C.c_void_p]),
+    "dsd_plan_pivots": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "dsd_set_graph": (C.c_int, [C.c_void_p, C.c_int]),
     "dsd_autotune": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
                                C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double),

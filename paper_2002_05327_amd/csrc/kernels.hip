@@ -167,7 +167,8 @@ constexpr int GJ_TI = 64, GJ_TC = 64; // product tile: rows x columns
 // then, unless the panel is the whole matrix, R = the panel's pivot rows.
 // 1024 threads; returns nonzero (in thread 0) for a zero pivot.
 __device__ __forceinline__ int gj_panel(cpx<double>* a, const int n, const int j0, int* piv,
-                                        cpx<double>* R, cpx<double>* tcol, cpx<double>* rowj) {
+                                        cpx<double>* R, cpx<double>* tcol, cpx<double>* rowj,
+                                        double* pst) {
   __shared__ double red_v[16];
   __shared__ int red_i[16];
   __shared__ int s_p;
@@ -198,6 +199,10 @@ __device__ __forceinline__ int gj_panel(cpx<double>* a, const int n, const int j
       if (!(v > 0.0)) { bad = 1; p = j; }
       s_p = p;
       piv[j] = p;
+      if (pst) {                    // smallest and largest squared pivot magnitude
+        pst[0] = fmin(pst[0], v);
+        pst[1] = fmax(pst[1], v);
+      }
     }
     __syncthreads();
     const int p = s_p;
@@ -319,7 +324,7 @@ __device__ __forceinline__ void gj_unpermute(cpx<double>* a, const int n, const 
 }
 
 __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv, cpx<double>* R,
-                                          unsigned char* smem, const int max_n) {
+                                          unsigned char* smem, const int max_n, double* pst) {
   cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem);
   cpx<double>* rowj = tcol + max_n;
   cpx<double>* Pt = rowj + max_n;           // [GJ_B][GJ_TI]
@@ -327,7 +332,7 @@ __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv,
   int bad = 0;
   for (int j0 = 0; j0 < n; j0 += GJ_B) {
     const int j1 = min(n, j0 + GJ_B);
-    bad |= gj_panel(a, n, j0, piv, R, tcol, rowj);
+    bad |= gj_panel(a, n, j0, piv, R, tcol, rowj, pst);
     if (j1 >= n && j0 == 0) continue;
     const int nti = (n + GJ_TI - 1) / GJ_TI, ntc = (n + GJ_TC - 1) / GJ_TC;
     for (int tile = 0; tile < nti * ntc; ++tile) {
@@ -370,13 +375,15 @@ __device__ inline GjView gj_view(const FactorJob* jobs, const SubDesc* subs, cpx
 template <typename JOB>
 __global__ __launch_bounds__(1024) void k_gj_panel(const JOB* jobs, const SubDesc* subs,
                                                    cpx<double>* base, int* pivbuf,
-                                                   cpx<double>* rbuf, int* err, int j0, int max_n) {
+                                                   cpx<double>* rbuf, int* err, double* pstat,
+                                                   int j0, int max_n) {
   const GjView V = gj_view(jobs, subs, base, blockIdx.x);
   if (j0 >= V.n) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem_raw);
   const int bad = gj_panel(V.a, V.n, j0, pivbuf + (long long)blockIdx.x * max_n,
-                           rbuf + (long long)blockIdx.x * GJ_B * max_n, tcol, tcol + max_n);
+                           rbuf + (long long)blockIdx.x * GJ_B * max_n, tcol, tcol + max_n,
+                           pstat ? pstat + 2 * blockIdx.x : nullptr);
   if (threadIdx.x == 0 && bad) err[blockIdx.x] = V.errval;
 }
 
@@ -416,13 +423,13 @@ static inline bool gj_use_split(int njobs, int max_n) { return njobs < 256 && ma
 template <typename T, typename JOB>
 static void launch_gj_split(const JOB* d_jobs, const SubDesc* d_subs, int njobs, int max_n,
                             cpx<double>* base, cpx<T>* fac, int* d_err, int* d_piv,
-                            cpx<double>* d_rbuf, hipStream_t s) {
+                            cpx<double>* d_rbuf, double* d_pst, hipStream_t s) {
   const int nt = (max_n + GJ_TI - 1) / GJ_TI;
   const size_t lds_panel = (size_t)2 * max_n * sizeof(cpx<double>);
   const size_t lds_tile = ((size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
   for (int j0 = 0; j0 < max_n; j0 += GJ_B) {
     hipLaunchKernelGGL(k_gj_panel<JOB>, dim3(njobs), dim3(1024), lds_panel, s, d_jobs, d_subs, base,
-                       d_piv, d_rbuf, d_err, j0, max_n);
+                       d_piv, d_rbuf, d_err, d_pst, j0, max_n);
     hipLaunchKernelGGL(k_gj_update<JOB>, dim3(nt * nt, njobs), dim3(1024), lds_tile, s, d_jobs,
                        d_subs, base, d_rbuf, j0, max_n);
   }
@@ -435,14 +442,16 @@ static void launch_gj_split(const JOB* d_jobs, const SubDesc* d_subs, int njobs,
 template <typename T>
 __global__ __launch_bounds__(1024) void k_invert(const SubDesc* subs, const FactorJob* jobs,
                                                  cpx<double>* scratch, cpx<T>* fac, int* err,
-                                                 int* pivbuf, cpx<double>* rbuf, int max_nb) {
+                                                 int* pivbuf, cpx<double>* rbuf, double* pstat,
+                                                 int max_nb) {
   const FactorJob J = jobs[blockIdx.x];
   const SubDesc S = subs[J.sub];
   const int nb = S.nb;
   cpx<double>* a = scratch + J.cur;
   extern __shared__ unsigned char smem_raw[];
   const int bad = gj_blocked(a, nb, pivbuf + (long long)blockIdx.x * max_nb,
-                             rbuf + (long long)blockIdx.x * GJ_B * max_nb, smem_raw, max_nb);
+                             rbuf + (long long)blockIdx.x * GJ_B * max_nb, smem_raw, max_nb,
+                             pstat ? pstat + 2 * blockIdx.x : nullptr);
   cpx<T>* out = fac + S.fac_off + (long long)J.k * nb * nb;
   const long long ne = (long long)nb * nb;
   for (long long e = threadIdx.x; e < ne; e += blockDim.x) out[e] = cvt<T>(a[e]);
@@ -454,14 +463,15 @@ size_t gj_rbuf_entries(int max_n) { return (size_t)GJ_B * max_n; }
 template <typename T>
 void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
                    cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf,
-                   hipStream_t s) {
+                   double* d_pst, hipStream_t s) {
   if (njobs <= 0) return;
   if (gj_use_split(njobs, max_nb)) {
-    launch_gj_split<T, FactorJob>(d_jobs, d_subs, njobs, max_nb, scratch, fac, d_err, d_piv, d_rbuf, s);
+    launch_gj_split<T, FactorJob>(d_jobs, d_subs, njobs, max_nb, scratch, fac, d_err, d_piv, d_rbuf,
+                                  d_pst, s);
     return;
   }
   hipLaunchKernelGGL(k_invert<T>, dim3(njobs), dim3(1024), gj_lds_bytes(max_nb), s, d_subs, d_jobs,
-                     scratch, fac, d_err, d_piv, d_rbuf, max_nb);
+                     scratch, fac, d_err, d_piv, d_rbuf, d_pst, max_nb);
 }
 
 // ============================================================================
@@ -998,13 +1008,14 @@ void launch_bcr_assemble(const Problem& P, const SubDesc* d_subs, const BcrBlkJo
 template <typename T>
 __global__ __launch_bounds__(1024) void k_bcr_invert(const BcrInvJob* jobs, cpx<double>* work,
                                                      cpx<T>* fac, int* err, int* pivbuf,
-                                                     cpx<double>* rbuf, int max_nb) {
+                                                     cpx<double>* rbuf, double* pstat, int max_nb) {
   const BcrInvJob J = jobs[blockIdx.x];
   const int nb = J.nb;
   cpx<double>* a = work + J.src;
   extern __shared__ unsigned char smem_raw[];
   const int bad = gj_blocked(a, nb, pivbuf + (long long)blockIdx.x * max_nb,
-                             rbuf + (long long)blockIdx.x * GJ_B * max_nb, smem_raw, max_nb);
+                             rbuf + (long long)blockIdx.x * GJ_B * max_nb, smem_raw, max_nb,
+                             pstat ? pstat + 2 * blockIdx.x : nullptr);
   if (J.dst >= 0) {
     const long long ne = (long long)nb * nb;
     for (long long e = threadIdx.x; e < ne; e += blockDim.x) fac[J.dst + e] = cvt<T>(a[e]);
@@ -1014,14 +1025,16 @@ __global__ __launch_bounds__(1024) void k_bcr_invert(const BcrInvJob* jobs, cpx<
 
 template <typename T>
 void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
-                       cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, hipStream_t s) {
+                       cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, double* d_pst,
+                       hipStream_t s) {
   if (njobs <= 0) return;
   if (gj_use_split(njobs, max_nb)) {
-    launch_gj_split<T, BcrInvJob>(d_jobs, nullptr, njobs, max_nb, work, fac, d_err, d_piv, d_rbuf, s);
+    launch_gj_split<T, BcrInvJob>(d_jobs, nullptr, njobs, max_nb, work, fac, d_err, d_piv, d_rbuf,
+                                  d_pst, s);
     return;
   }
   hipLaunchKernelGGL(k_bcr_invert<T>, dim3(njobs), dim3(1024), gj_lds_bytes(max_nb), s, d_jobs,
-                     work, fac, d_err, d_piv, d_rbuf, max_nb);
+                     work, fac, d_err, d_piv, d_rbuf, d_pst, max_nb);
 }
 
 __global__ void k_bcr_diag_update(Problem P, const SubDesc* subs, const BcrDiagUpd* jobs,
@@ -2262,7 +2275,7 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
 #define DSD_INST(T)                                                                              \
   template void launch_convert<T>(const cpx<double>*, cpx<T>*, long long, hipStream_t);          \
   template void launch_invert<T>(const SubDesc*, const FactorJob*, int, int, cpx<double>*,      \
-                                 cpx<T>*, int*, int*, cpx<double>*, hipStream_t);                \
+                                 cpx<T>*, int*, int*, cpx<double>*, double*, hipStream_t);       \
   template void launch_chain<T>(int, int, const SubDesc*, const int4*, int, int, int, int,      \
                                 const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*, long long, \
                                 hipStream_t);                                                    \
@@ -2279,7 +2292,7 @@ void launch_sample(const cpx<double>* u, int nsrc, long long N, const long long*
                                      int, int, int, int, const cpx<T>*, long long, cpx<double>*, \
                                      hipStream_t);                                               \
   template void launch_bcr_invert<T>(const BcrInvJob*, int, int, cpx<double>*, cpx<T>*, int*,  \
-                                     int*, cpx<double>*, hipStream_t);                           \
+                                     int*, cpx<double>*, double*, hipStream_t);                  \
   template void launch_bcr_copy<T>(const BcrCopyJob*, int, int, const cpx<double>*, cpx<T>*,    \
                                    hipStream_t);                                                 \
   template void launch_bcr_solve<T>(int, const SubDesc*, const BcrJob*, int, int, int, int, int,\

@@ -37,11 +37,13 @@ void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jo
                   const cpx<double>* cy, const cpx<double>* cz, cpx<double>* scratch,
                   hipStream_t s);
 // Inversions (blocked Gauss-Jordan, FP64): d_piv holds max_nb ints and d_rbuf
-// gj_rbuf_entries(max_nb) complex entries per job of the launch.
+// gj_rbuf_entries(max_nb) complex entries per job of the launch; d_pst (may be
+// null) 2 doubles per job, updated to the smallest and largest squared pivot
+// magnitude (initialise to +inf and 0).
 template <typename T>
 void launch_invert(const SubDesc* d_subs, const FactorJob* d_jobs, int njobs, int max_nb,
                    cpx<double>* scratch, cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf,
-                   hipStream_t s);
+                   double* d_pst, hipStream_t s);
 size_t gj_rbuf_entries(int max_n);
 size_t gj_lds_bytes(int max_n);   // dynamic LDS of an inversion launch
 
@@ -65,7 +67,7 @@ struct BcrBlkJob {        // D := A_k (assembly of a diagonal block)
 };
 struct BcrInvJob {        // invert src in place (FP64); round the inverse into fac[dst] (dst >= 0)
   int nb;
-  int pad;
+  int sub;                // subdomain (pivot report)
   long long src, dst;
 };
 struct BcrDiagUpd {       // level 0: D_j -= c_{j-1} P_{j-1} c_{j-1} + c_j P_{j+1} c_j;
@@ -81,7 +83,8 @@ void launch_bcr_assemble(const Problem& P, const SubDesc* d_subs, const BcrBlkJo
                          const cpx<double>* cy, cpx<double>* work, hipStream_t s);
 template <typename T>
 void launch_bcr_invert(const BcrInvJob* d_jobs, int njobs, int max_nb, cpx<double>* work,
-                       cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, hipStream_t s);
+                       cpx<T>* fac, int* d_err, int* d_piv, cpx<double>* d_rbuf, double* d_pst,
+                       hipStream_t s);
 void launch_bcr_diag_update(const Problem& P, const SubDesc* d_subs, const BcrDiagUpd* d_jobs,
                             int njobs, int max_nb, const cpx<double>* cy, const cpx<double>* cz,
                             cpx<double>* work, hipStream_t s);

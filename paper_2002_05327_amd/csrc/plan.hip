@@ -112,6 +112,7 @@ int upload(Buf& b, const std::vector<U>& v) {
   return 0;
 }
 
+
 struct StepTab {
   int mem_off, nmem;           // members (subdomain ids) in d_members
   int job_off;                 // fwd/bwd jobs (2 per member) in d_jobs2; mid jobs at d_jobs1
@@ -233,6 +234,10 @@ struct dsd_plan {
   int nd_max_nf_narrow = 0;             // largest front below nd_wide
   Buf d_nd_wide;                        // wide-mode tiles {job, first row}
   int nd_fuse_level = 1 << 30;          // subtree levels from here down run fused
+  // pivot report: the largest max|pivot| / min|pivot| over the inversions of
+  // the factorisation, and its subdomain
+  double piv_ratio = 0.0;
+  int piv_sub = -1;
   Buf d_nd_fj, d_nd_fb;                 // fused subtrees {first batch, batches}; batches {job, jobs}
   std::vector<int> nd_cell_of, nd_map_of;  // per node-table entry: cell and map offsets
   int nd_small = 4;    // levels whose largest node needs at most this many (row pass x
@@ -266,6 +271,31 @@ struct dsd_plan {
     for (hipEvent_t e : tev) (void)hipEventDestroy(e);
   }
 };
+
+// Pivot report of a set of inversions: stats (2 doubles per job, the smallest
+// and largest squared pivot magnitude) start at (+inf, 0); piv_end folds them
+// into the plan's largest max|pivot| / min|pivot| and its subdomain.
+int piv_begin(Buf& d, size_t njobs) {
+  std::vector<double> h(2 * std::max<size_t>(njobs, 1), 0.0);
+  for (size_t k = 0; k < njobs; ++k) h[2 * k] = HUGE_VAL;
+  return upload(d, h);
+}
+int piv_end(dsd_plan* pl, const Buf& d, const std::vector<int>& sub_of_job) {
+  if (sub_of_job.empty()) return 0;
+  std::vector<double> h(2 * sub_of_job.size());
+  HIPCHK(hipMemcpyAsync(h.data(), d.p, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  for (size_t k = 0; k < sub_of_job.size(); ++k) {
+    if (!(h[2 * k + 1] > 0.0)) continue;
+    const double r = h[2 * k] > 0.0 ? std::sqrt(h[2 * k + 1] / h[2 * k]) : HUGE_VAL;
+    if (r > pl->piv_ratio) {
+      pl->piv_ratio = r;
+      pl->piv_sub = sub_of_job[k];
+    }
+  }
+  return 0;
+}
 
 namespace {
 
@@ -688,6 +718,9 @@ int bcr_factor(dsd_plan* pl) {
   for (const SubDesc& S : pl->subs) ninv += S.nblk + 1;
   CHK(derr.alloc((size_t)ninv * sizeof(int)));
   HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)ninv * sizeof(int), st));
+  Buf dpst;
+  CHK(piv_begin(dpst, (size_t)ninv));
+  std::vector<int> job_sub;              // subdomain of every inversion, in err_off order
   const int maxinv = std::min(batch * (int)half, 2048);   // inversions per launch
   CHK(dpiv.alloc((size_t)maxinv * pl->max_nb * sizeof(int)));
   CHK(drbuf.alloc((size_t)maxinv * gj_rbuf_entries(pl->max_nb) * sizeof(cpx<double>)));
@@ -741,6 +774,7 @@ int bcr_factor(dsd_plan* pl) {
       std::vector<ZGemmJob> gw, gd1, gd2, ge;
       std::vector<BcrCopyJob> cp;
       std::vector<BcrDenseJob> dns;
+      std::vector<int> dns_sub;
       const int rd = l & 1, wr_ = (l + 1) & 1;
       for (int sid = s0; sid < s1; ++sid) {
         const BcrSub& B = pl->bcr[sid];
@@ -762,10 +796,11 @@ int bcr_factor(dsd_plan* pl) {
           bad_off |= n > dn_max || dj_.out + n * n > (long long)batch * dn2 ||
                      B.dense < 0 || B.dense + n * n > pl->sum_fac;
           dns.push_back(dj_);
+          dns_sub.push_back(sid);
           continue;
         }
         for (int p = 0; p < len; p += 2)
-          inv.push_back(BcrInvJob{nb, 0, D(sid, c[p]), S.fac_off + (long long)c[p] * nb2});
+          inv.push_back(BcrInvJob{nb, sid, D(sid, c[p]), S.fac_off + (long long)c[p] * nb2});
         if (l == B.top) continue;
         if (l == 0) {
           for (int q = 1; q < len; q += 2) {
@@ -815,7 +850,8 @@ int bcr_factor(dsd_plan* pl) {
       if (!dns.empty()) {
         // dense top level: assemble, invert in FP64 (Gauss-Jordan), round into row blocks
         std::vector<BcrInvJob> dinv;
-        for (const BcrDenseJob& j : dns) dinv.push_back(BcrInvJob{j.nb * j.m, 0, j.out, -1});
+        for (size_t k = 0; k < dns.size(); ++k)
+          dinv.push_back(BcrInvJob{dns[k].nb * dns[k].m, dns_sub[k], dns[k].out, -1});
         std::vector<unsigned char> pack(dns.size() * sizeof(BcrDenseJob) + dinv.size() * sizeof(BcrInvJob));
         memcpy(pack.data(), dns.data(), dns.size() * sizeof(BcrDenseJob));
         memcpy(pack.data() + dns.size() * sizeof(BcrDenseJob), dinv.data(), dinv.size() * sizeof(BcrInvJob));
@@ -827,15 +863,18 @@ int bcr_factor(dsd_plan* pl) {
         launch_bcr_dense_build(ddj, (int)dns.size(), (int)dn_max, W, DW, st);
         if (pl->c64) {
           launch_bcr_invert<float>(dij, (int)dinv.size(), (int)dn_max, DW, pl->d_fac.as<cpx<float>>(),
-                                   derr.as<int>() + err_off, dpivd.as<int>(), drbufd.as<cpx<double>>(), st);
+                                   derr.as<int>() + err_off, dpivd.as<int>(), drbufd.as<cpx<double>>(),
+                                   dpst.as<double>() + 2 * err_off, st);
           launch_bcr_dense_store<float>(ddj, (int)dns.size(), (int)dn_max, DW, pl->d_fac.as<cpx<float>>(), st);
         } else {
           launch_bcr_invert<double>(dij, (int)dinv.size(), (int)dn_max, DW, pl->d_fac.as<cpx<double>>(),
-                                    derr.as<int>() + err_off, dpivd.as<int>(), drbufd.as<cpx<double>>(), st);
+                                    derr.as<int>() + err_off, dpivd.as<int>(), drbufd.as<cpx<double>>(),
+                                    dpst.as<double>() + 2 * err_off, st);
           launch_bcr_dense_store<double>(ddj, (int)dns.size(), (int)dn_max, DW,
                                          pl->d_fac.as<cpx<double>>(), st);
         }
         err_off += (long long)dinv.size();
+        job_sub.insert(job_sub.end(), dns_sub.begin(), dns_sub.end());
         HIPCHK(hipGetLastError());
       }
       // inversions of the eliminated blocks (FP64 in place; rounded copy into the factor)
@@ -844,11 +883,14 @@ int bcr_factor(dsd_plan* pl) {
         const int n = std::min(maxinv, (int)inv.size() - i0);
         if (pl->c64)
           launch_bcr_invert<float>(dj.as<BcrInvJob>() + i0, n, pl->max_nb, W, pl->d_fac.as<cpx<float>>(),
-                                   derr.as<int>() + err_off, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                                   derr.as<int>() + err_off, dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                                   dpst.as<double>() + 2 * err_off, st);
         else
           launch_bcr_invert<double>(dj.as<BcrInvJob>() + i0, n, pl->max_nb, W,
                                     pl->d_fac.as<cpx<double>>(), derr.as<int>() + err_off,
-                                    dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                                    dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                                    dpst.as<double>() + 2 * err_off, st);
+        for (int k = i0; k < i0 + n; ++k) job_sub.push_back(inv[k].sub);
         err_off += n;
       }
       HIPCHK(hipGetLastError());
@@ -891,7 +933,7 @@ int bcr_factor(dsd_plan* pl) {
       g_detail = "singular block in the cyclic reduction (inversion " + std::to_string(i) + ")";
       return DSD_EPIVOT;
     }
-  return 0;
+  return piv_end(pl, dpst, job_sub);
 }
 
 // Solve launches of one launch group (members {subdomain, sweep}): the forward
@@ -1579,7 +1621,7 @@ int nd_factor(dsd_plan* pl) {
           const long long Sb = so, Lb = so + (long long)ns * ns;
           so += (long long)ns * nf;
           cj.push_back(NdCopyJob{ns, ns, nf, ns, 0, 0, F, Sb});
-          ij.push_back(BcrInvJob{ns, 0, Sb, -1});
+          ij.push_back(BcrInvJob{ns, s, Sb, -1});
           g1.push_back(NdGemmJob{nbd, ns, ns, nf, ns, nbd, 0, 0, 1.0, F + ns, Sb, Lb});
           g2.push_back(NdGemmJob{nbd, nbd, ns, nbd, nf, nf, 1, 0, -1.0, Lb,
                                  F + (long long)ns * nf, F + ns + (long long)ns * nf});
@@ -1600,6 +1642,8 @@ int nd_factor(dsd_plan* pl) {
       CHK(upload(dj3, ij));
       CHK(derr.alloc((size_t)nj * sizeof(int)));
       HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)nj * sizeof(int), st));
+      Buf dpst;
+      CHK(piv_begin(dpst, (size_t)nj));
       // inversions in launches of at most 255 (the split form serves large orders)
       const int step = 255;
       CHK(dpiv.alloc((size_t)std::min(nj, step) * max_ns * sizeof(int)));
@@ -1608,10 +1652,12 @@ int nd_factor(dsd_plan* pl) {
         const int n = std::min(step, nj - j0);
         if (pl->c64)
           launch_bcr_invert<float>(dj3.as<BcrInvJob>() + j0, n, max_ns, W, pl->d_fac.as<cpx<float>>(),
-                                   derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                                   derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                                   dpst.as<double>() + 2 * j0, st);
         else
           launch_bcr_invert<double>(dj3.as<BcrInvJob>() + j0, n, max_ns, W, pl->d_fac.as<cpx<double>>(),
-                                    derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                                    derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                                    dpst.as<double>() + 2 * j0, st);
       }
       HIPCHK(hipGetLastError());
       CHK(upload(dj4, g1));
@@ -1631,9 +1677,14 @@ int nd_factor(dsd_plan* pl) {
       for (int j = 0; j < nj; ++j)
         if (herr[j]) {
           g_detail = "singular separator block in a nested-dissection front (depth " +
-                     std::to_string(d) + ")";
+                     std::to_string(d) + ", subdomain " + std::to_string(ij[j].sub) + ")";
           return DSD_EPIVOT;
         }
+      {
+        std::vector<int> js(nj);
+        for (int j = 0; j < nj; ++j) js[j] = ij[j].sub;
+        CHK(piv_end(pl, dpst, js));
+      }
     }
     // dense tops of the chunk
     std::vector<NdTopAsmJob> tj;
@@ -1657,7 +1708,7 @@ int nd_factor(dsd_plan* pl) {
       J.coef = S.coef_off;
       J.T = toff[s - s0];
       tj.push_back(J);
-      ti.push_back(BcrInvJob{nt, 0, toff[s - s0], -1});
+      ti.push_back(BcrInvJob{nt, s, toff[s - s0], -1});
       tc.push_back(NdCopyJob{nt, nt, nt, nt, 0, 1, toff[s - s0], S.fac_off + sh.top_fac});
       max_top = std::max(max_top, nt);
     }
@@ -1670,14 +1721,18 @@ int nd_factor(dsd_plan* pl) {
       CHK(upload(dj3, ti));
       CHK(derr.alloc((size_t)nj * sizeof(int)));
       HIPCHK(hipMemsetAsync(derr.p, 0, (size_t)nj * sizeof(int), st));
+      Buf dpst;
+      CHK(piv_begin(dpst, (size_t)nj));
       CHK(dpiv.alloc((size_t)nj * max_top * sizeof(int)));
       CHK(drbuf.alloc((size_t)nj * gj_rbuf_entries(max_top) * sizeof(cpx<double>)));
       if (pl->c64)
         launch_bcr_invert<float>(dj3.as<BcrInvJob>(), nj, max_top, W, pl->d_fac.as<cpx<float>>(),
-                                 derr.as<int>(), dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                                 derr.as<int>(), dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                                 dpst.as<double>(), st);
       else
         launch_bcr_invert<double>(dj3.as<BcrInvJob>(), nj, max_top, W, pl->d_fac.as<cpx<double>>(),
-                                  derr.as<int>(), dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                                  derr.as<int>(), dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                                  dpst.as<double>(), st);
       CHK(upload(dj2, tc));
       if (pl->c64) launch_nd_copy<float>(dj2.as<NdCopyJob>(), nj, max_top, max_top, W, pl->d_fac.as<cpx<float>>(), st);
       else launch_nd_copy<double>(dj2.as<NdCopyJob>(), nj, max_top, max_top, W, pl->d_fac.as<cpx<double>>(), st);
@@ -1687,9 +1742,15 @@ int nd_factor(dsd_plan* pl) {
       HIPCHK(hipStreamSynchronize(st));
       for (int j = 0; j < nj; ++j)
         if (herr[j]) {
-          g_detail = "singular dense top in a nested-dissection factorisation";
+          g_detail = "singular dense top in a nested-dissection factorisation (subdomain " +
+                     std::to_string(ti[j].sub) + ")";
           return DSD_EPIVOT;
         }
+      {
+        std::vector<int> js(nj);
+        for (int j = 0; j < nj; ++j) js[j] = ti[j].sub;
+        CHK(piv_end(pl, dpst, js));
+      }
     }
     HIPCHK(hipStreamSynchronize(st));
     s0 = s1;
@@ -1808,6 +1869,8 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
   CHK(upload(djobs, all));
   CHK(derr.alloc(all.size() * sizeof(int)));
   HIPCHK(hipMemsetAsync(derr.p, 0, all.size() * sizeof(int), st));
+  Buf dpst;
+  CHK(piv_begin(dpst, all.size()));
   int maxjobs = 0;
   for (int t = 0; t <= maxlen; ++t) maxjobs = std::max(maxjobs, job_off[t + 1] - job_off[t]);
   CHK(dpiv.alloc((size_t)maxjobs * pl->max_nb * sizeof(int)));
@@ -1823,11 +1886,13 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
     if (pl->c64)
       launch_invert<float>(pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
                            scratch.as<cpx<double>>(), pl->d_fac.as<cpx<float>>(),
-                           derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                           derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                           dpst.as<double>() + 2 * j0, st);
     else
       launch_invert<double>(pl->d_subs.as<SubDesc>(), jp, nj, pl->max_nb,
                             scratch.as<cpx<double>>(), pl->d_fac.as<cpx<double>>(),
-                            derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(), st);
+                            derr.as<int>() + j0, dpiv.as<int>(), drbuf.as<cpx<double>>(),
+                            dpst.as<double>() + 2 * j0, st);
     HIPCHK(hipGetLastError());
   }
   std::vector<int> herr(all.size());
@@ -1838,7 +1903,9 @@ int assemble_and_factor(dsd_plan* pl, const double* m_dev) {
       g_detail = "singular Schur block in subdomain " + std::to_string(v - 1);
       return DSD_EPIVOT;
     }
-  return 0;
+  std::vector<int> js(all.size());
+  for (size_t k = 0; k < all.size(); ++k) js[k] = all[k].sub;
+  return piv_end(pl, dpst, js);
 }
 
 int ensure_pools(dsd_plan* pl) {
@@ -2592,22 +2659,33 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
   pl->sequential = q.schedule == 1;
   pl->additive = q.schedule == 2;
   if (rc == 0) {
-    // local solver: nested dissection in 3D, block cyclic reduction in 2D.  In
-    // 2D the subdomains span many wavelengths and nested dissection eliminates
-    // closed boxes of physical medium first, whose Dirichlet problems can sit
-    // near resonance (ill-conditioned separator blocks); the reduction
-    // eliminates thin slabs that reach the PML.
+    // local solver: nested dissection in 3D; in 2D block cyclic reduction
+    // unless its factor (about three times the chain factor) would take more
+    // than 45% of the device memory, then the chains (one launch per block
+    // step for blocks of 512 cells or more).  In 2D the subdomains span many
+    // wavelengths and nested dissection eliminates closed boxes of physical
+    // medium first, whose Dirichlet problems can sit near resonance
+    // (ill-conditioned separator blocks); the reduction and the chains
+    // eliminate slabs that reach the PML.
+    std::vector<long long> toff(pl->S);
+    for (int i = 0; i < pl->S; ++i) toff[i] = pl->subs[i].fac_off;
+    const long long tsum = pl->sum_fac;
     pl->solver = q.local_solver == 1 || q.local_solver == 3 ? 1
                : q.local_solver == 2 || (q.local_solver == 0 && q.dim == 2) ? 2 : 4;
     if (pl->solver == 4) rc = nd_setup(pl);
     if (pl->solver == 2) {
       pl->dense_max = dense_blocks(pl, q.dense_top);
       bcr_layout(pl);
+      size_t fr = 0, tot = 0;
+      if (q.local_solver == 0 && hipMemGetInfo(&fr, &tot) == hipSuccess &&
+          (double)pl->sum_fac * tsize(pl) > 0.45 * (double)tot) {
+        pl->solver = 1;
+        for (int i = 0; i < pl->S; ++i) pl->subs[i].fac_off = toff[i];
+        pl->sum_fac = tsum;
+      }
     }
-    // chain block steps: one launch per block step, every chain of a launch
-    // group in it (for wide blocks, where one workgroup per chain would leave
-    // most of the GPU idle)
-    pl->chain_steps = q.local_solver == 3;
+    pl->chain_steps = pl->solver == 1 &&
+                      (q.local_solver == 3 || (q.local_solver == 0 && pl->max_nb >= 512));
   }
   if (rc == 0) {
     const int kdef = pl->solver == 4 ? 8 : ((pl->solver == 2 || pl->chain_steps) ? (pl->c64 ? 8 : 4) : 2);
@@ -2669,6 +2747,13 @@ int dsd_plan_info(const dsd_plan* pl, long long* n_global, int* n_subdomains,
     for (const Buf* b : bs) w += (long long)b->bytes;
     *workspace_bytes = w;
   }
+  return DSD_OK;
+}
+
+int dsd_plan_pivots(const dsd_plan* pl, double* ratio, int* subdomain) {
+  if (!pl) return DSD_EINVAL;
+  if (ratio) *ratio = pl->piv_ratio;
+  if (subdomain) *subdomain = pl->piv_sub;
   return DSD_OK;
 }
 

@@ -136,6 +136,28 @@ def test_singular_block_is_reported_as_epivot(solver):
     plan.close()
 
 
+@pytest.mark.parametrize("solver", ["bcr", "chain", "nd"])
+def test_pivot_report_flags_nearly_singular_blocks(solver):
+    """The 2 x 1 Dirichlet grid of the test above, with m = 3 - delta: the
+    operator [[delta - 1, 1], [1, delta - 1]] (up to sign) has eigenvalues delta
+    and delta - 2, so elimination's second pivot is about 2 delta while the
+    first is about 1: dsd_plan_pivots reports max|pivot| / min|pivot| ~ 1 / (2
+    delta) for subdomain 0.  At m = 2.5 the ratio is a small number."""
+    import paper_2002_05327_amd as dsw
+    out = {}
+    for m0 in (3.0 - 1e-6, 2.5):
+        plan = dsw.Plan(n=(2, 1), h=1.0, omega=1.0, pml=0, overlap=3, parts=(1, 1),
+                        m=torch.full((1, 2), m0, dtype=torch.float64, device="cuda"),
+                        precision="c128", max_rhs=1, local_solver=solver)
+        out[m0] = plan.pivots()
+        plan.close()
+    print(out)
+    near, far = out[3.0 - 1e-6], out[2.5]
+    assert near["subdomain"] == 0 and far["subdomain"] == 0
+    assert 2e5 < near["ratio"] < 2e6
+    assert 1.0 <= far["ratio"] < 10.0
+
+
 def test_fwi_refuses_unconverged_gradients():
     import synth
     import paper_2002_05327_amd as dsw

@@ -37,8 +37,10 @@ def _oracle_operator(w, c):
     return assemble(global_axes(w.n, w.pml, w.h), 1.0 / c ** 2, w.h, w.omega, w.pml)
 
 
-def test_c2_solutions_against_oracle_operator_and_global_lu():
-    """C2 (1024^2, 8x8, 16 RHS), both paths as bench.py runs them: every RHS meets
+@pytest.mark.parametrize("solver", ["nd", "auto"])
+def test_c2_solutions_against_oracle_operator_and_global_lu(solver):
+    """C2 (1024^2, 8x8, 16 RHS), both paths, with the nested dissection bench.py
+    runs and with the 2D default (cyclic reduction): every RHS meets
     the FP64 true residual 1e-6 under the oracle's operator; the GPU operator
     equals the oracle's; RHS 0 refined further equals the global sparse LU
     solution to 1e-6 (complex64 + FP64 refinement) and 1e-10 (complex128)."""
@@ -51,7 +53,8 @@ def test_c2_solutions_against_oracle_operator_and_global_lu():
     x = rng.standard_normal((2,) + shape[1:]) + 1j * rng.standard_normal((2,) + shape[1:])
     u_ref = global_solve(M, F[0].ravel())
     for prec, tol_err in [("c64", 1e-6), ("c128", 1e-10)]:
-        plan = _plan(w, c, prec)
+        plan = _plan(w, c, prec, local_solver=solver)
+        print(f"c2 {prec} {plan.local_solver}: pivot report {plan.pivots()}", flush=True)
         y = plan.apply_operator(torch.from_numpy(x).cuda()).cpu().numpy().reshape(2, -1)
         y_ref = (M @ x.reshape(2, -1).T).T
         close(y, y_ref, 1e-13, f"c2 {prec}: operator vs oracle")
