@@ -108,7 +108,7 @@ typedef struct {
                             bisected further (0: 128)                                  */
   int nd_top_cells;      /* nested dissection: the separators of the shallowest depths
                             whose cells total at most this many form the dense top
-                            (0: 1200; at most 5000)                                    */
+                            (0: 1200; at most 9000)                                    */
   int nd_wide;           /* nested dissection: nodes whose front (separator plus
                             boundary) has at least this many cells apply their blocks
                             as tiled products over all right-hand sides of a group at

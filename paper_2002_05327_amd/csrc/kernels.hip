@@ -156,7 +156,7 @@ void launch_schur(const Problem& P, const SubDesc* d_subs, const FactorJob* d_jo
 // with P the transformed panel and R the panel's pivot rows (copied to R
 // first), as 64 x 64 tiled products on the FP64 matrix cores with operands
 // staged in LDS.  The row interchanges are undone as column interchanges at
-// the end.  LDS: tcol and rowj (2 max_n entries), then the product tiles.
+// the end.  LDS: tcol (max_n entries) and rowj (GJ_B), then the product tiles.
 // Returns nonzero (in thread 0) for a zero pivot.
 typedef double gj_f64x4 __attribute__((ext_vector_type(4)));
 constexpr int GJ_B = 32;              // panel width
@@ -219,12 +219,12 @@ __device__ __forceinline__ int gj_panel(cpx<double>* a, const int n, const int j
     const cpx<double> pv = tcol[j];
     const cpx<double> pinv = (abs2(pv) > 0.0) ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
     for (int c = j0 + tid; c < j1; c += bs)
-      rowj[c] = (c == j) ? pinv : a[(long long)c * n + j] * pinv;
+      rowj[c - j0] = (c == j) ? pinv : a[(long long)c * n + j] * pinv;
     __syncthreads();
     // rank-1 update of the panel columns, one column per wave
     for (int c = j0 + wid; c < j1; c += nw) {
       cpx<double>* col = a + (long long)c * n;
-      const cpx<double> rj = rowj[c];
+      const cpx<double> rj = rowj[c - j0];
       for (int i0 = lane; i0 < n; i0 += 256) {
         cpx<double> v[4];
 #pragma unroll
@@ -326,8 +326,8 @@ __device__ __forceinline__ void gj_unpermute(cpx<double>* a, const int n, const 
 __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv, cpx<double>* R,
                                           unsigned char* smem, const int max_n, double* pst) {
   cpx<double>* tcol = reinterpret_cast<cpx<double>*>(smem);
-  cpx<double>* rowj = tcol + max_n;
-  cpx<double>* Pt = rowj + max_n;           // [GJ_B][GJ_TI]
+  cpx<double>* rowj = tcol + max_n;        // [GJ_B]
+  cpx<double>* Pt = rowj + GJ_B;            // [GJ_B][GJ_TI]
   cpx<double>* Rt = Pt + GJ_B * GJ_TI;      // [GJ_TC][GJ_B + 1]
   int bad = 0;
   for (int j0 = 0; j0 < n; j0 += GJ_B) {
@@ -346,7 +346,7 @@ __device__ __forceinline__ int gj_blocked(cpx<double>* a, const int n, int* piv,
 }
 
 size_t gj_lds_bytes(int max_n) {
-  return ((size_t)2 * max_n + (size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
+  return ((size_t)max_n + GJ_B + (size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
 }
 
 // Split form for launches with few large matrices (the fused kernel would leave
@@ -425,7 +425,7 @@ static void launch_gj_split(const JOB* d_jobs, const SubDesc* d_subs, int njobs,
                             cpx<double>* base, cpx<T>* fac, int* d_err, int* d_piv,
                             cpx<double>* d_rbuf, double* d_pst, hipStream_t s) {
   const int nt = (max_n + GJ_TI - 1) / GJ_TI;
-  const size_t lds_panel = (size_t)2 * max_n * sizeof(cpx<double>);
+  const size_t lds_panel = ((size_t)max_n + GJ_B) * sizeof(cpx<double>);
   const size_t lds_tile = ((size_t)GJ_B * GJ_TI + (size_t)GJ_TC * (GJ_B + 1)) * sizeof(cpx<double>);
   for (int j0 = 0; j0 < max_n; j0 += GJ_B) {
     hipLaunchKernelGGL(k_gj_panel<JOB>, dim3(njobs), dim3(1024), lds_panel, s, d_jobs, d_subs, base,

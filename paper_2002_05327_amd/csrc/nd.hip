@@ -927,6 +927,35 @@ __device__ __forceinline__ void nd_wide_stage(cpx<T>* buf, const int* fc, int ns
   }
 }
 
+// The same staging in two halves: load issues the loads of this thread's
+// entries into registers (at clamped addresses, masked afterwards), store
+// writes them to LDS -- so a chunk's loads are in flight while the previous
+// chunk is multiplied.
+template <typename T, int KG>
+struct NdWideStager {
+  static constexpr int PER = ND_WCK * KG / 256;
+  cpx<T> v[PER];
+  __device__ __forceinline__ void load(const int* fc, int ns, int c0, int n, int q0, int nq,
+                                       const cpx<T>* R, const cpx<T>* X, long long nloc) {
+    const int tid = threadIdx.x & 255;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + 256 * u, c = e / KG, q = e - (e / KG) * KG;
+      const int col = c0 + min(c, n - 1);
+      const bool own = col < ns;
+      const cpx<T>* src = own ? R : X;
+      const cpx<T> x = src[(long long)(q0 + min(q, nq - 1)) * nloc + fc[col]];
+      const cpx<T> y = own ? x : -x;
+      v[u] = (c < n && q < nq) ? y : mk((T)0, (T)0);
+    }
+  }
+  __device__ __forceinline__ void store(cpx<T>* buf) const {
+    const int tid = threadIdx.x & 255;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) buf[tid + 256 * u] = v[u];
+  }
+};
+
 // out (row `lane` of this wave's 64-row tile) = A[tile rows, 0:ncol] y, A
 // column-major (lda, already offset to the tile), the columns of this wave's
 // half staged chunk by chunk; complex64 on the FP32 matrix cores, complex128
@@ -960,16 +989,17 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
     // lds is the base of the dynamic LDS: this half's buffer k & 1 starts at
-    // entry hb + (k & 1) ND_WCK KG
+    // entry hb + (k & 1) ND_WCK KG.  The next chunk's vector loads are issued
+    // before this chunk's products and written to LDS after them.
+    NdWideStager<T, KG> stg;
     for (int k = 0; k < nch; ++k) {
       C* nxt = (k & 1) ? buf0 : buf1;
       const int c0 = cb + k * ND_WCK, cn = min(ND_WCK, ce - c0);
-      if (k + 1 < nown)
-        nd_wide_stage<T, KG>(nxt, fc, ns, c0 + ND_WCK, min(ND_WCK, ce - c0 - ND_WCK), q0, nq, R,
-                             X, nloc);
+      if (k + 1 < nown) stg.load(fc, ns, c0 + ND_WCK, min(ND_WCK, ce - c0 - ND_WCK), q0, nq, R, X, nloc);
       if (k < nown && nrows_tile > 0)
         nd_mfma_rows<JB>(macc, A + (long long)c0 * lda, lda, nrows_tile,
                          hb + ((k & 1) ? ND_WCK * KG : 0), 0, cn, lane);
+      if (k + 1 < nown) stg.store(nxt);
       __syncthreads();
     }
     // the staging area is free: the second half's partial sums go there

@@ -1193,6 +1193,8 @@ int bcr_check_jobs(const dsd_plan* pl, const std::vector<BcrJob>& jobs, bool loc
   return 0;
 }
 
+int device_lds();
+
 // ------------------------------------------- nested dissection (local solver 4)
 // Whether a node's forward (rows = boundary) or backward (rows = separator)
 // product runs in wide mode: a front of at least nd_wide cells, or more rows
@@ -1268,8 +1270,14 @@ int nd_setup(dsd_plan* pl) {
     }
     pl->nd_max_ntop = std::max(pl->nd_max_ntop, sh.ntop());
   }
-  if (pl->nd_max_ntop > 5000) {
-    g_detail = "nested dissection: dense top above 5000 cells (lower nd_top_cells)";
+  // the inversions run the split Gauss-Jordan form, whose panel kernel keeps
+  // one column of the matrix in LDS
+  int max_inv = pl->nd_max_ntop;
+  for (const NdShape& sh : pl->nd_shapes) max_inv = std::max(max_inv, sh.max_ns);
+  if ((size_t)(max_inv + 32) * sizeof(cpx<double>) > (size_t)device_lds()) {
+    g_detail = "nested dissection: a separator or dense top of " + std::to_string(max_inv) +
+               " cells exceeds the inversion kernel's LDS (lower nd_top_cells or use more "
+               "subdomains)";
     return DSD_EINVAL;
   }
   long long foff = 0;
@@ -2636,10 +2644,10 @@ int dsd_plan_create(const dsd_params* params, double omega, const double* m_dev,
       q.local_solver > 4 || q.schedule < 0 || q.schedule > 2 || q.dense_top < -1 ||
       q.dense_top > 64 || q.sweep_order < 0 || q.sweep_order > 1 ||
       (q.sweep_order == 1 && q.dim != 3) || q.nd_leaf < 0 || q.nd_top_cells < 0 ||
-      q.nd_top_cells > 5000 || q.nd_wide < 0 || q.nd_wave_steps < 0 || q.nd_fuse < 0) {
+      q.nd_top_cells > 9000 || q.nd_wide < 0 || q.nd_wave_steps < 0 || q.nd_fuse < 0) {
     g_detail = "dim must be 2 or 3, overlap >= 3, pml >= 0, h > 0, omega > 0, precision C64|C128, "
                "local_solver 0..4, schedule 0..2, dense_top -1..64, sweep_order 0..1 (1: 3D only), "
-               "nd_leaf >= 0, nd_top_cells 0..5000, nd_wide >= 0, nd_wave_steps >= 0, nd_fuse >= 0";
+               "nd_leaf >= 0, nd_top_cells 0..9000, nd_wide >= 0, nd_wave_steps >= 0, nd_fuse >= 0";
     return DSD_EINVAL;
   }
   for (int a = 0; a < q.dim; ++a)

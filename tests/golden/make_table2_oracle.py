@@ -44,7 +44,7 @@ def main():
                        "discrete solution (separable direct solve) with the unit-mass source as "
                        "printed; L2 error over the physical cells against the free-space solution",
            "rows": {}}
-    for mesh in (80, 96):
+    for mesh in (80, 96, 128, 160):
         dim, kappa, h, n, pml, x0, f = table2_problem(tab, mesh)
         u = solve_constant((n,) * dim, h, kappa, pml, 1.0, f.ravel())
         M = assemble(global_axes((n,) * dim, pml, h), np.ones((n,) * dim), h, kappa, pml)

@@ -64,6 +64,7 @@ def _problem(tab, mesh):
     ("table1_2d", 2240, 10, "c64"),
     ("table2_3d", 80, 4, "c64"),
     ("table2_3d", 96, 3, "c64"),
+    ("table2_3d", 128, 4, "c64"),
 ])
 def test_accuracy_table_row(table, mesh, overlap, prec):
     import paper_2002_05327_amd as dsw

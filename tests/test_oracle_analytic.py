@@ -91,9 +91,10 @@ def test_second_order_convergence_at_lower_frequency():
 
 def test_table2_oracle_values_and_printed_rate():
     """Table 2 (Section 5.1, 3D): tests/golden/table2_oracle.json holds the
-    oracle's L2 errors at 80^3 and 96^3 with the printed unit-mass source (the
-    values the GPU is held to).  They are reproduced here from oracle/ alone
-    (separable direct solve, residual under the sparse operator <= 1e-9), and
+    oracle's L2 errors at 80^3, 96^3, 128^3 and 160^3 with the printed
+    unit-mass source (the values the GPU is held to; 160^3 is not run on the
+    GPU).  The first three are reproduced here from oracle/ alone (separable
+    direct solve, residual under the sparse operator <= 1e-9, 1e-7 at 128^3), and
     their ratio equals the printed ratio 2.67e-2 / 1.82e-2 within 1%: the
     printed rate is matched, the printed level is a constant 1.77 times
     lower, so parity with the printed values is unpinned."""
@@ -105,11 +106,11 @@ def test_table2_oracle_values_and_printed_rate():
     tab = json.load(open(GOLDEN))["table2_3d"]
     stored = json.load(open(os.path.join(os.path.dirname(GOLDEN), "table2_oracle.json")))["rows"]
     errs = {}
-    for mesh in (80, 96):
+    for mesh in (80, 96, 128):
         dim, kappa, h, n, pml, x0, f = table2_problem(tab, mesh)
         u = solve_constant((n,) * dim, h, kappa, pml, 1.0, f.ravel())
         M = assemble(global_axes((n,) * dim, pml, h), np.ones((n,) * dim), h, kappa, pml)
-        assert residual(M, u, f.ravel()) < 1e-9
+        assert residual(M, u, f.ravel()) < (1e-9 if mesh < 128 else 1e-7)
         sl = (slice(pml, pml + n),) * dim
         errs[mesh] = l2_error(u.reshape(f.shape)[sl], h, x0, kappa)
         assert abs(errs[mesh] / stored[str(mesh)]["l2_error"] - 1) < 1e-10
