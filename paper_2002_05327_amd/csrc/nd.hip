@@ -866,17 +866,19 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
 // ---- wide mode: nodes whose front is too large for the LDS (or with more
 // than 512 rows) run their products as tiled matrix products over every
 // right-hand side of a group of KG (up to 32) at once, so that each factor
-// entry is read once per solve.  A workgroup of eight waves takes 256 rows of
-// one node: four 64-row tiles x two column halves (two waves per SIMD keep the
-// matrix cores fed while the other waits for its loads).  Each half streams
-// its columns through LDS in chunks of ND_WCK (the vector entries of the chunk
-// for all KG right-hand sides, double-buffered), and the halves meet in LDS:
-// the second half's partial sums are added to the first's, so every row sums
-// its columns in the same order whatever else the launch holds.  The forward
-// pass first forms f_S (k_nd_form)
+// entry is read once per solve.  A workgroup of eight waves takes ND_WROWS =
+// 128 rows of one node: ND_WRT = 2 64-row tiles x ND_WCQ = 4 column quarters
+// (more workgroups than 256-row tiles would give, so the few large nodes of a
+// launch still reach every compute unit; two waves per SIMD).  Each quarter
+// streams its columns through LDS in chunks of ND_WCK (the vector entries of
+// the chunk for all KG right-hand sides, double-buffered), and the quarters
+// meet in LDS: quarters 1..3 add their partial sums to quarter 0's in that
+// order, so every row sums its columns the same way whatever else the launch
+// holds.  The forward pass first forms f_S (k_nd_form)
 // and ends with u_B = (children's updates on B) - L f_S; the backward pass is
 // x_S = K [f_S; -x_B].  Tiles are {job, first row} entries of a table.
 constexpr int ND_WCK = 64;
+constexpr int ND_WRT = 2, ND_WCQ = 4;   // row tiles x column quarters of a workgroup
 
 // f_S = r_S + children's updates on S, into R: one thread per (position, RHS)
 template <typename T>
@@ -908,14 +910,15 @@ __global__ __launch_bounds__(256) void k_nd_form(const NdLvlJob* __restrict__ jo
 }
 
 // Stage the vector entries of columns [c0, c0 + n) for right-hand sides
-// [q0, q0 + nq) into buf[c * KG + q] (zero beyond n or nq), by the 256
-// threads of one column half: column c < ns from R (f_S), column c >= ns from
-// -X (boundary, backward pass only).
+// [q0, q0 + nq) into buf[c * KG + q] (zero beyond n or nq), by the threads of
+// one column quarter: column c < ns from R (f_S), column c >= ns from -X
+// (boundary, backward pass only).
 template <typename T, int KG>
 __device__ __forceinline__ void nd_wide_stage(cpx<T>* buf, const int* fc, int ns, int c0, int n,
                                               int q0, int nq, const cpx<T>* R, const cpx<T>* X,
                                               long long nloc) {
-  for (int e = threadIdx.x & 255; e < ND_WCK * KG; e += 256) {
+  constexpr int GT = ND_WRT * 64;
+  for (int e = threadIdx.x % GT; e < ND_WCK * KG; e += GT) {
     const int c = e / KG, q = e - (e / KG) * KG;
     cpx<T> v = mk((T)0, (T)0);
     if (c < n && q < nq) {
@@ -933,14 +936,15 @@ __device__ __forceinline__ void nd_wide_stage(cpx<T>* buf, const int* fc, int ns
 // chunk is multiplied.
 template <typename T, int KG>
 struct NdWideStager {
-  static constexpr int PER = ND_WCK * KG / 256;
+  static constexpr int GT = ND_WRT * 64;            // threads of one column quarter
+  static constexpr int PER = ND_WCK * KG / GT;
   cpx<T> v[PER];
   __device__ __forceinline__ void load(const int* fc, int ns, int c0, int n, int q0, int nq,
                                        const cpx<T>* R, const cpx<T>* X, long long nloc) {
-    const int tid = threadIdx.x & 255;
+    const int tid = threadIdx.x % GT;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int e = tid + 256 * u, c = e / KG, q = e - (e / KG) * KG;
+      const int e = tid + GT * u, c = e / KG, q = e - (e / KG) * KG;
       const int col = c0 + min(c, n - 1);
       const bool own = col < ns;
       const cpx<T>* src = own ? R : X;
@@ -950,19 +954,19 @@ struct NdWideStager {
     }
   }
   __device__ __forceinline__ void store(cpx<T>* buf) const {
-    const int tid = threadIdx.x & 255;
+    const int tid = threadIdx.x % GT;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) buf[tid + 256 * u] = v[u];
+    for (int u = 0; u < PER; ++u) buf[tid + GT * u] = v[u];
   }
 };
 
 // out (row `lane` of this wave's 64-row tile) = A[tile rows, 0:ncol] y, A
 // column-major (lda, already offset to the tile), the columns of this wave's
-// half staged chunk by chunk; complex64 on the FP32 matrix cores, complex128
-// with vector FMAs.  out is valid in the first half's waves (w < 4) only.
-// LDS (entries from the base): staging [0, 4 ND_WCK KG) (half h at
-// 2 h ND_WCK KG), reused for the second half's partial sums; the MFMA output
-// staging at [4 ND_WCK KG, 4 ND_WCK KG + 256 KG).
+// quarter staged chunk by chunk; complex64 on the FP32 matrix cores,
+// complex128 with vector FMAs.  out is valid in quarter 0's waves (w <
+// ND_WRT) only.  LDS (entries from the base): staging [0, ND_WCQ 2 ND_WCK KG)
+// (quarter h at 2 h ND_WCK KG), reused for the other quarters' partial sums;
+// the MFMA output staging after it (ND_WRT x 64 x KG).
 template <typename T, int KG>
 __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, long long lda,
                                                 int nrows_tile, int ncol, int ns, const int* fc,
@@ -971,12 +975,13 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
   typedef cpx<T> C;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int h = w >> 2, t = w & 3;
-  const int half = (((ncol + 1) / 2) + 3) / 4 * 4;   // a multiple of the MFMA column step
-  const int cb = min(ncol, h * half), ce = min(ncol, cb + half);
+  const int h = w / ND_WRT, t = w % ND_WRT;
+  const int part = ((ncol + ND_WCQ - 1) / ND_WCQ + 3) / 4 * 4;   // a multiple of the MFMA column step
+  const int cb = min(ncol, h * part), ce = min(ncol, cb + part);
   const int nown = (ce - cb + ND_WCK - 1) / ND_WCK;
-  const int nch = (min(ncol, half) + ND_WCK - 1) / ND_WCK;   // the first half's chunks (>= own)
-  const long long hb = (long long)h * 2 * ND_WCK * KG;        // this half's staging
+  const int nch = (min(ncol, part) + ND_WCK - 1) / ND_WCK;   // quarter 0's chunks (>= any other's)
+  const long long hb = (long long)h * 2 * ND_WCK * KG;        // this quarter's staging
+  constexpr long long STG = (long long)ND_WCQ * 2 * ND_WCK * KG;
   C* buf0 = lds + hb;
   C* buf1 = buf0 + ND_WCK * KG;
   if (nown > 0) nd_wide_stage<T, KG>(buf0, fc, ns, cb, min(ND_WCK, ce - cb), q0, nq, R, X, nloc);
@@ -988,7 +993,7 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
-    // lds is the base of the dynamic LDS: this half's buffer k & 1 starts at
+    // lds is the base of the dynamic LDS: this quarter's buffer k & 1 starts at
     // entry hb + (k & 1) ND_WCK KG.  The next chunk's vector loads are issued
     // before this chunk's products and written to LDS after them.
     NdWideStager<T, KG> stg;
@@ -1002,25 +1007,29 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
       if (k + 1 < nown) stg.store(nxt);
       __syncthreads();
     }
-    // the staging area is free: the second half's partial sums go there
+    // the staging area is free: the other quarters' partial sums go there
     float* pf = reinterpret_cast<float*>(lds);
-    if (h == 1) {
+    constexpr int PW = 16 * JB * 64;                          // floats per wave
+    if (h > 0) {
 #pragma unroll
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) pf[((t * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane] = macc[rb][jb][r];
+          for (int r = 0; r < 4; ++r)
+            pf[((h - 1) * ND_WRT + t) * PW + ((rb * JB + jb) * 4 + r) * 64 + lane] = macc[rb][jb][r];
     }
     __syncthreads();
-    if (h == 1) return;
+    if (h > 0) return;
+    for (int o = 1; o < ND_WCQ; ++o)
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+      for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int jb = 0; jb < JB; ++jb)
+        for (int jb = 0; jb < JB; ++jb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) macc[rb][jb][r] += pf[((t * 4 + rb) * JB * 4 + jb * 4 + r) * 64 + lane];
-    nd_mfma_out<JB>(macc, 2LL * 4 * ND_WCK * KG + (long long)t * 64 * KG * 2, lane, out);
+          for (int r = 0; r < 4; ++r)
+            macc[rb][jb][r] += pf[((o - 1) * ND_WRT + t) * PW + ((rb * JB + jb) * 4 + r) * 64 + lane];
+    nd_mfma_out<JB>(macc, 2 * STG + (long long)t * 64 * KG * 2, lane, out);
   } else {
 #pragma unroll
     for (int q = 0; q < KG; ++q) out[q] = mk((T)0, (T)0);
@@ -1035,26 +1044,28 @@ __device__ __forceinline__ void nd_wide_product(const cpx<T>* __restrict__ A, lo
         nd_dot_rows<T, KG, false>(out, A + (long long)c0 * lda + lane, lda, cur, 0, cn);
       __syncthreads();
     }
-    C* part = lds;
-    if (h == 1) {
+    C* part_s = lds;
+    if (h > 0) {
 #pragma unroll
-      for (int q = 0; q < KG; ++q) part[(t * KG + q) * 64 + lane] = out[q];
+      for (int q = 0; q < KG; ++q) part_s[(((h - 1) * ND_WRT + t) * KG + q) * 64 + lane] = out[q];
     }
     __syncthreads();
-    if (h == 1) return;
+    if (h > 0) return;
+    for (int o = 1; o < ND_WCQ; ++o)
 #pragma unroll
-    for (int q = 0; q < KG; ++q) out[q] = out[q] + part[(t * KG + q) * 64 + lane];
+      for (int q = 0; q < KG; ++q) out[q] = out[q] + part_s[(((o - 1) * ND_WRT + t) * KG + q) * 64 + lane];
   }
 }
 
 template <typename T>
 constexpr size_t nd_wide_lds_entries(int kg) {
-  // two halves x two staging chunks (reused for the partial sums, 4 x 64 x KG),
-  // then the MFMA output staging (4 waves x 64 x KG)
-  return (size_t)std::max(4 * ND_WCK * kg, 4 * 64 * kg) + (size_t)4 * 64 * kg;
+  // the quarters' staging chunks (reused for the partial sums of quarters 1..3),
+  // then the MFMA output staging (ND_WRT waves x 64 x KG)
+  return (size_t)std::max(ND_WCQ * 2 * ND_WCK * kg, (ND_WCQ - 1) * ND_WRT * 64 * kg) +
+         (size_t)ND_WRT * 64 * kg;
 }
 
-// u_B = (children's updates on B) - L f_S for rows [t.y, t.y + 256) of node t.x
+// u_B = (children's updates on B) - L f_S for rows [t.y, t.y + ND_WROWS) of node t.x
 template <typename T, int KG>
 __global__ __launch_bounds__(512) void k_nd_wide_fwd(
     const NdLvlJob* __restrict__ jobs, const int2* __restrict__ tiles, int ntiles, int G,
@@ -1072,14 +1083,14 @@ __global__ __launch_bounds__(512) void k_nd_wide_fwd(
   const int ns = J.ns, nbd = J.nbd;
   const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = t.y + 64 * (w & 3);
+  const int r0 = t.y + 64 * (w % ND_WRT);
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C out[KG];
   nd_wide_product<T, KG>(fac + J.fac + r0, nbd, max(0, min(64, nbd - r0)), ns, ns, cells + J.cell,
                          q0, nq, R, R, J.nloc, lds, out);
   const int i = r0 + lane;
-  if (w < 4 && i < nbd) {                 // the first column half holds the sums
+  if (w < ND_WRT && i < nbd) {            // column quarter 0 holds the sums
     const int p = ns + i;
     const int i0 = umaps[J.umap + 2 * p], i1 = umaps[J.umap + 2 * p + 1];
 #pragma unroll
@@ -1094,7 +1105,7 @@ __global__ __launch_bounds__(512) void k_nd_wide_fwd(
   }
 }
 
-// x_S = K [f_S; -x_B] for rows [t.y, t.y + 256) of node t.x
+// x_S = K [f_S; -x_B] for rows [t.y, t.y + ND_WROWS) of node t.x
 template <typename T, int KG>
 __global__ __launch_bounds__(512) void k_nd_wide_bwd(
     const NdLvlJob* __restrict__ jobs, const int2* __restrict__ tiles, int ntiles, int G,
@@ -1111,14 +1122,14 @@ __global__ __launch_bounds__(512) void k_nd_wide_bwd(
   const int ns = J.ns, nf = J.ns + J.nbd;
   const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int r0 = t.y + 64 * (w & 3);
+  const int r0 = t.y + 64 * (w % ND_WRT);
   extern __shared__ unsigned char smem_raw[];
   C* lds = reinterpret_cast<C*>(smem_raw);
   C out[KG];
   nd_wide_product<T, KG>(fac + J.fac + (long long)J.nbd * ns + r0, ns, max(0, min(64, ns - r0)), nf,
                          ns, cells + J.cell, q0, nq, R, X, J.nloc, lds, out);
   const int i = r0 + lane;
-  if (w < 4 && i < ns) {                  // the first column half holds the sums
+  if (w < ND_WRT && i < ns) {             // column quarter 0 holds the sums
     const int cell = cells[J.cell + i];
 #pragma unroll
     for (int q = 0; q < KG; ++q)

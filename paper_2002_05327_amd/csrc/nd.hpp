@@ -173,7 +173,8 @@ void launch_nd_top(int kg, const NdTopJob* jobs, int njobs, const int* cells, co
                    const cpx<T>* fac, const cpx<T>* rpool, const cpx<T>* upool, cpx<T>* xpool,
                    long long pool_stride, int nrhs, int kmax, int max_ntop, hipStream_t s);
 // Wide mode (fronts too large for the LDS, or more than 512 rows): tiles are
-// {node job, first of 256 rows (or separator positions for the form step)}.
+// {node job, first of ND_WROWS rows (or of 256 separator positions for the
+// form step)}.
 // Forward: launch_nd_form (f_S = r_S + children's updates, into R), then
 // launch_nd_wide_fwd (u_B); backward: launch_nd_wide_bwd (x_S).  Every
 // right-hand side of a group of nd_wide_kg(ts, nrhs) in one pass.
@@ -195,6 +196,7 @@ int nd_wide_kg(size_t ts, int nrhs);
 // level whose fronts total at most ND_FUSE_CAP positions (job.pad = the node's
 // front offset in the batch).  Forward: batches in order; backward: reversed.
 constexpr int ND_FUSE_CAP = 512;
+constexpr int ND_WROWS = 128;      // rows of a wide-mode tile
 template <typename T>
 void launch_nd_fused(bool fwd, int kg, const int2* fjobs, int nfj, const int2* batches,
                      const NdLvlJob* jobs, const int* cells, const int* umaps, const cpx<T>* fac,

@@ -1437,14 +1437,15 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     V.nf_n = c[3] - c[1];
     V.nb_off = V.off + c[2];
     V.nb_n = c[4] - c[2];
-    // wide-mode tiles: 256 separator positions (forming f_S), 256 rows
+    // wide-mode tiles: 256 separator positions (forming f_S), ND_WROWS rows
     auto add_tiles = [&](bool fwd, bool form, int& off, int& cnt) {
       off = (int)wt.size();
       for (size_t j = 0; j < v.size(); ++j) {
         const NdLvlJob& J = v[j];
         if (!nd_wide_node(pl, J.ns, J.nbd, fwd)) continue;
         const int rows = form ? J.ns : fwd ? J.nbd : J.ns;
-        for (int r0 = 0; r0 < rows; r0 += 256) wt.push_back(make_int2(V.off + (int)j, r0));
+        const int step = form ? 256 : ND_WROWS;
+        for (int r0 = 0; r0 < rows; r0 += step) wt.push_back(make_int2(V.off + (int)j, r0));
       }
       cnt = (int)wt.size() - off;
     };

@@ -26,10 +26,12 @@ def _workload(name):
 
 
 def _plan(w, c, prec, **kw):
+    """The workload's plan, with the local solver bench.py uses unless one is given."""
     import paper_2002_05327_amd as dsw
     m = torch.from_numpy(1.0 / c ** 2).cuda()
     return dsw.Plan(n=w.n, h=w.h, omega=w.omega, pml=w.pml, overlap=w.overlap, parts=w.parts,
-                    m=m, precision=prec, max_rhs=kw.pop("max_rhs", w.nrhs), **kw)
+                    m=m, precision=prec, max_rhs=kw.pop("max_rhs", w.nrhs),
+                    local_solver=kw.pop("local_solver", w.solver), **kw)
 
 
 def _oracle_operator(w, c):
@@ -84,30 +86,33 @@ def test_c3_solutions_against_oracle_operator():
     x = np.random.default_rng(6).standard_normal(F.shape[1:]) + 0j
     y = plan.apply_operator(torch.from_numpy(x[None]).cuda()).cpu().numpy().ravel()
     close(y, M @ x.ravel(), 1e-13, "c3 operator vs oracle")
-    sol, iters, relres, ok = plan.gmres(torch.from_numpy(F).cuda(), tol=1e-6, maxit=100, restart=30)
+    sol, iters, relres, ok = plan.gmres(torch.from_numpy(F).cuda(), tol=1e-6, maxit=100,
+                                        restart=w.restart)
     assert ok
     X = sol.cpu().numpy().reshape(F.shape[0], -1)
     B = F.reshape(F.shape[0], -1)
     rr = np.linalg.norm((M @ X.T).T - B, axis=1) / np.linalg.norm(B, axis=1)
-    print(f"c3: iterations {min(iters)}-{max(iters)}; oracle-operator residual max {rr.max():.2e}",
-          flush=True)
+    print(f"c3 ({plan.local_solver}, restart {w.restart}): iterations {min(iters)}-{max(iters)}; "
+          f"oracle-operator residual max {rr.max():.2e}; pivot report {plan.pivots()}", flush=True)
     assert rr.max() <= 1.0e-6 * 1.001
     plan.close()
 
 
 def test_c2_sweep_matches_oracle_sweep():
-    """One application of the diagonal sweeps at C2 size (RHS 0), against the
-    oracle's sequential sweep with real local PML solves."""
+    """One application of the diagonal sweeps at C2 size (RHS 0), with the nested
+    dissection bench.py uses and the 2D default, against the oracle's sequential
+    sweep with real local PML solves."""
     from oracle.sweep import DiagonalSweepDDM
     w, c, F = _workload("c2")
     ddm = DiagonalSweepDDM(w.n, w.h, w.omega, w.pml, w.overlap, w.parts, 1.0 / c ** 2)
     u_ref = ddm.apply(F[0].ravel())
     f = torch.from_numpy(F[:2].copy()).cuda()
-    for prec, tol in [("c128", 1e-10), ("c64", 1e-4)]:
-        plan = _plan(w, c, prec)
-        u = plan.sweep_apply(f).cpu().numpy().reshape(2, -1)
-        close(u[0], u_ref, tol, f"c2 sweep {prec} vs oracle")
-        plan.close()
+    for solver in ("nd", "auto"):
+        for prec, tol in [("c128", 1e-10), ("c64", 1e-4)]:
+            plan = _plan(w, c, prec, local_solver=solver)
+            u = plan.sweep_apply(f).cpu().numpy().reshape(2, -1)
+            close(u[0], u_ref, tol, f"c2 sweep {plan.local_solver} {prec} vs oracle")
+            plan.close()
 
 
 def test_c3_sweep_matches_oracle_sweep():
