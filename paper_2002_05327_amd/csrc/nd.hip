@@ -244,6 +244,16 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
 // so the small separators of the deep levels still fill the wave; gathers
 // take one front position per lane (index loads once, then KG data loads).
 
+// Load through a global-address-space pointer: a pointer selected between two
+// arrays would otherwise be generic and compile to flat loads, whose wait
+// also covers every other load in flight.
+template <typename T>
+__device__ __forceinline__ cpx<T> nd_gload(const cpx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
+  return mk(v.x, v.y);
+}
+
 __device__ __forceinline__ void nd_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -299,12 +309,23 @@ __device__ __forceinline__ void nd_dot(cpx<T>& acc, const cpx<T>* __restrict__ A
 // Lanes over rows: acc[q] -= (or +=) sum_{j in [c0, c1)} A[j * lda] y[j * KG + q]
 // for all KG right-hand sides; the column loads (64 consecutive rows, one
 // load per column) issued eight at a time, one batch ahead of their FMAs.
+// The first batch (nd_rows_first, c1 > c0) can be issued early by the caller,
+// so that it travels with the loads of the front gather.
+template <typename T>
+__device__ __forceinline__ void nd_rows_first(cpx<T> (&a)[8], const cpx<T>* __restrict__ A,
+                                              long long lda, int c0, int c1) {
+  const int n = c1 - c0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = A[(long long)(c0 + min(u, n - 1)) * lda];
+}
+
 template <typename T, int KG, bool SUB>
-__device__ __forceinline__ void nd_dot_rows(cpx<T> (&acc)[KG], const cpx<T>* __restrict__ A,
-                                            long long lda, const cpx<T>* y, int c0, int c1) {
+__device__ __forceinline__ void nd_dot_rows_pre(cpx<T> (&acc)[KG], cpx<T> (&a)[8],
+                                                const cpx<T>* __restrict__ A, long long lda,
+                                                const cpx<T>* y, int c0, int c1) {
   typedef cpx<T> C;
   constexpr int B = 8;
-  C a[B], b[B];
+  C b[B];
   const int n = c1 - c0;
   if (n <= 0) return;
   auto load = [&](C (&buf)[B], int j0) {
@@ -331,7 +352,6 @@ __device__ __forceinline__ void nd_dot_rows(cpx<T> (&acc)[KG], const cpx<T>* __r
       }
     }
   };
-  load(a, 0);
   for (int j0 = 0; j0 < n; j0 += 2 * B) {
     if (j0 + B < n) load(b, j0 + B);
     use(a, j0);
@@ -340,6 +360,15 @@ __device__ __forceinline__ void nd_dot_rows(cpx<T> (&acc)[KG], const cpx<T>* __r
       use(b, j0 + B);
     }
   }
+}
+
+template <typename T, int KG, bool SUB>
+__device__ __forceinline__ void nd_dot_rows(cpx<T> (&acc)[KG], const cpx<T>* __restrict__ A,
+                                            long long lda, const cpx<T>* y, int c0, int c1) {
+  if (c1 <= c0) return;
+  cpx<T> a[8];
+  nd_rows_first(a, A, lda, c0, c1);
+  nd_dot_rows_pre<T, KG, SUB>(acc, a, A, lda, y, c0, c1);
 }
 
 // ---- complex64 on the FP32 matrix cores (v_mfma_f32_16x16x4f32): a wave
@@ -352,14 +381,16 @@ typedef float nd_mf4 __attribute__((ext_vector_type(4)));
 // The LDS-front kernels (one node per workgroup, and the dense top) take the
 // matrix cores from this RHS group up; with fewer right-hand sides per group
 // the FP32 vector FMAs were measured faster there.
-constexpr int ND_MFMA_KG = 16;
+constexpr int ND_MFMA_KG = 8;
 
 // The right-hand sides y sit in LDS at entry y_off of the dynamic LDS.  All
 // loads are issued at clamped (valid) addresses and masked afterwards: a
 // conditional load `c ? p[i] : 0` becomes a load from a selected address, a
 // generic pointer, which compiles to flat loads; those wait for every global
 // load in flight and break the pipelining of the matrix loads.
-template <int JB>
+// CH 4-column chunks per batch of loads: 4 where few waves share a compute unit
+// (loads in flight), 2 in the level kernels (registers: more waves).
+template <int JB, int CH = 4>
 __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<float>* __restrict__ A,
                                              long long lda, int nrows, long long y_off,
                                              int c0, int c1, int lane) {
@@ -367,7 +398,6 @@ __device__ __forceinline__ void nd_mfma_rows(nd_mf4 (&acc)[4][JB], const cpx<flo
   extern __shared__ unsigned char smem_raw[];
   const C* y = reinterpret_cast<const C*>(smem_raw) + y_off;
   constexpr int KG = 8 * JB;
-  constexpr int CH = 4;                      // 4-column chunks per batch of loads
   const int lr = lane & 15, lk = lane >> 4, n = lane & 15, qn = n >> 1;
   const bool im = n & 1;
   const C zero = mk(0.0f, 0.0f);
@@ -483,25 +513,44 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
   const C zero = mk((T)0, (T)0);
   const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int ns = J.ns, nbd = J.nbd, nf = ns + nbd;
+  // lanes over rows (vector FMAs): wave w takes row tile w % TT and column
+  // group w / TT; its first batch of matrix columns is issued before the
+  // front gather, so that the two travel together
+  constexpr bool VEC = !(std::is_same<T, float>::value && KG % 8 == 0 && KG >= ND_MFMA_KG);
+  const int t = w % TT, cgi = w / TT;
+  const int cw = (ns + CG - 1) / CG;
+  const int c0 = min(ns, cgi * cw), c1 = min(ns, c0 + cw);
+  C pre[8];
+  if (VEC && npw == 1 && t * 64 < nbd && c1 > c0)
+    nd_rows_first(pre, fac + J.fac + min(t * 64 + lane, nbd - 1), nbd, c0, c1);
   {
     const int* fc = cells + J.cell;
     const int* um = umaps + J.umap;
     for (int p = tid; p < nf; p += nt) {
       const int i0 = um[2 * p], i1 = um[2 * p + 1];
-      const bool own = p < ns;
-      const int cell = own ? fc[p] : 0;
-      const C* U0 = U + (long long)i0 * kmax + q0;
-      const C* U1 = U + (long long)i1 * kmax + q0;
-      C* Rc = R + (long long)q0 * nloc + cell;
+      const bool own = p < ns, h0 = i0 >= 0, h1 = i1 >= 0;
+      C* Rc = R + (long long)q0 * nloc + fc[p];
+      // every load at a valid address (an absent update reads the R entry)
+      // and the terms selected afterwards: a position's loads go out together
+      // instead of one branch, and one wait, per term and RHS
+      const C* U0 = h0 ? U + (long long)i0 * kmax + q0 : Rc;
+      const C* U1 = h1 ? U + (long long)i1 * kmax + q0 : Rc;
+      const long long s0 = h0 ? 1 : nloc, s1 = h1 ? 1 : nloc;
+      C r[KG], a[KG], b[KG];
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
-        C v = zero;
-        if (q < nq) {
-          if (own) v = Rc[(long long)q * nloc];
-          if (i0 >= 0) v = v + U0[q];
-          if (i1 >= 0) v = v + U1[q];
-          if (own) Rc[(long long)q * nloc] = v;
-        }
+        const long long qc = min(q, nq - 1);
+        r[q] = Rc[qc * nloc];
+        a[q] = nd_gload(U0 + qc * s0);
+        b[q] = nd_gload(U1 + qc * s1);
+      }
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        C v = own ? r[q] : zero;
+        v = h0 ? v + a[q] : v;
+        v = h1 ? v + b[q] : v;
+        v = q < nq ? v : zero;
+        if (own && (h0 || h1) && q < nq) Rc[(long long)q * nloc] = v;
         fr[p * KG + q] = v;
       }
     }
@@ -522,10 +571,6 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
     return;
   }
   (void)W;
-  // lanes over rows: wave w takes row tile w % TT and column group w / TT
-  const int t = w % TT, cgi = w / TT;
-  const int cw = (ns + CG - 1) / CG;
-  const int c0 = min(ns, cgi * cw), c1 = min(ns, c0 + cw);
   const int i = t * 64 + lane;
   const bool live = i < nbd;
   if constexpr (std::is_same<T, float>::value && KG % 8 == 0 && KG >= ND_MFMA_KG) {
@@ -535,7 +580,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
-    if (t * 64 < nbd) nd_mfma_rows<JB>(macc, L + t * 64, nbd, nbd - t * 64, 0, c0, c1, lane);
+    if (t * 64 < nbd) nd_mfma_rows<JB, 2>(macc, L + t * 64, nbd, nbd - t * 64, 0, c0, c1, lane);
     float* pf = reinterpret_cast<float*>(smem_raw) + 2LL * region;
     if (CG > 1) {
       if (cgi > 0) {
@@ -568,9 +613,13 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
     return;
   }
   C acc[KG];
+  const int ri = live ? ns + i : 0;    // LDS read at a valid position, selected after
 #pragma unroll
-  for (int q = 0; q < KG; ++q) acc[q] = (cgi == 0 && live) ? fr[(ns + i) * KG + q] : zero;
-  if (live) nd_dot_rows<T, KG, true>(acc, L + i, nbd, fr, c0, c1);
+  for (int q = 0; q < KG; ++q) {
+    const C f = fr[ri * KG + q];
+    acc[q] = (cgi == 0 && live) ? f : zero;
+  }
+  if (live) nd_dot_rows_pre<T, KG, true>(acc, pre, L + i, nbd, fr, c0, c1);
   C* part = fr + region;
   if (CG > 1) {
     if (cgi > 0) {
@@ -591,12 +640,15 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
 }
 
 // One level of the backward pass: x_S = K [f_S; -x_B] with K = [P | L^T]
-// (ns x nf), f_S from R, x_B from X (ancestors, or the dense top).
+// (ns x nf), f_S from R, x_B from X (ancestors, or the dense top).  For a
+// leaf L^T x_B = P A_SB x_B with A_SB the operator's face couplings of the
+// box, so the front is v = f_S - A_SB x_B (ns entries) and x_S = P v.
 template <typename T, int KG>
 __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
     const NdLvlJob* __restrict__ jobs, int njobs, int G, int npw, int region, int TT, int CG,
     const int* __restrict__ cells, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
-    cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs) {
+    cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs, const cpx<T>* __restrict__ cx,
+    const cpx<T>* __restrict__ cy, const cpx<T>* __restrict__ cz) {
   typedef cpx<T> C;
   constexpr int RPP = 64 / KG;
   const int Lg = nd_task(blockIdx.x, gridDim.x);
@@ -624,15 +676,53 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
   const int q0 = g * KG, nq = min(KG, nrhs - q0);
   const int ns = J.ns, nbd = J.nbd, nf = ns + nbd;
   const int* fc = cells + J.cell;
-  for (int p = tid; p < nf; p += nt) {
+  const int ncol = J.leaf ? ns : nf;
+  constexpr bool VEC = !(std::is_same<T, float>::value && KG % 8 == 0 && KG >= ND_MFMA_KG);
+  const int t = w % TT, cgi = w / TT;
+  const int cw = (ncol + CG - 1) / CG;
+  const int c0 = min(ncol, cgi * cw), c1 = min(ncol, c0 + cw);
+  C pre[8];
+  if (VEC && npw == 1 && t * 64 < ns && c1 > c0)
+    nd_rows_first(pre, fac + J.fac + (long long)nbd * ns + min(t * 64 + lane, ns - 1), ns, c0, c1);
+  for (int p = tid; p < ncol; p += nt) {
     const bool own = p < ns;
-    const long long c = (long long)q0 * nloc + fc[p];
+    const int cell = fc[p];
+    // loads at valid addresses, selected afterwards (see the forward gather)
+    const C* xs = (own ? R : X) + (long long)q0 * nloc + cell;
+    C x[KG];
 #pragma unroll
-    for (int q = 0; q < KG; ++q) {
-      C x = zero;
-      if (q < nq) x = own ? R[c + (long long)q * nloc] : -X[c + (long long)q * nloc];
-      v[p * KG + q] = x;
+    for (int q = 0; q < KG; ++q) x[q] = nd_gload(xs + (long long)min(q, nq - 1) * nloc);
+#pragma unroll
+    for (int q = 0; q < KG; ++q) x[q] = q < nq ? (own ? x[q] : -x[q]) : zero;
+    if (J.leaf) {
+      // the box's faces, in a fixed order: -x, +x, -y, +y, -z, +z (one at a
+      // time: the kernel's registers are set by its largest live set)
+      const int nx = J.dims[0], ny = J.dims[1], nz = J.dims[2], nxy = nx * ny;
+      const int px = cell % nx, py = (cell / nx) % ny, pz = cell / nxy;
+      const int nd2 = nz > 1 ? 6 : 4;
+#pragma unroll 1
+      for (int d = 0; d < nd2; ++d) {
+        const int a = d >> 1;
+        const bool lo = (d & 1) == 0;
+        const int pa = a == 0 ? px : a == 1 ? py : pz;
+        const int ea = a == 0 ? nx : a == 1 ? ny : nz;
+        const int sa = a == 0 ? 1 : a == 1 ? nx : nxy;
+        const int la = a == 0 ? J.lo[0] : a == 1 ? J.lo[1] : J.lo[2];
+        const int ha = a == 0 ? J.hi[0] : a == 1 ? J.hi[1] : J.hi[2];
+        const C* __restrict__ ca = (a == 0 ? cx : a == 1 ? cy : cz) + J.coef;
+        const bool face = lo ? pa == la && la > 0 : pa == ha - 1 && ha < ea;
+        const int nb = face ? (lo ? cell - sa : cell + sa) : cell;
+        const C cpl = nd_gload(ca + (face && !lo ? cell : nb));
+        const C* xb = X + (long long)q0 * nloc + nb;
+        C xn[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) xn[q] = xb[(long long)min(q, nq - 1) * nloc];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) x[q] = face && q < nq ? x[q] - cpl * xn[q] : x[q];
+      }
     }
+#pragma unroll
+    for (int q = 0; q < KG; ++q) v[p * KG + q] = x[q];
   }
   if (npw > 1) nd_wave_sync();
   else __syncthreads();
@@ -643,15 +733,12 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
       const int i = i0 + rr;
       if (i >= ns) continue;
       C acc = zero;
-      nd_dot<T, KG, false>(acc, K + i, ns, v + qq, nf);
+      nd_dot<T, KG, false>(acc, K + i, ns, v + qq, ncol);
       if (qq < nq) X[(long long)(q0 + qq) * nloc + fc[i]] = acc;
     }
     return;
   }
   (void)W;
-  const int t = w % TT, cgi = w / TT;
-  const int cw = (nf + CG - 1) / CG;
-  const int c0 = min(nf, cgi * cw), c1 = min(nf, c0 + cw);
   const int i = t * 64 + lane;
   const bool live = i < ns;
   if constexpr (std::is_same<T, float>::value && KG % 8 == 0 && KG >= ND_MFMA_KG) {
@@ -661,7 +748,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int jb = 0; jb < JB; ++jb) macc[rb][jb] = nd_mf4{0.f, 0.f, 0.f, 0.f};
-    if (t * 64 < ns) nd_mfma_rows<JB>(macc, K + t * 64, ns, ns - t * 64, 0, c0, c1, lane);
+    if (t * 64 < ns) nd_mfma_rows<JB, 2>(macc, K + t * 64, ns, ns - t * 64, 0, c0, c1, lane);
     float* pf = reinterpret_cast<float*>(smem_raw) + 2LL * region;
     if (CG > 1) {
       if (cgi > 0) {
@@ -697,7 +784,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
   C acc[KG];
 #pragma unroll
   for (int q = 0; q < KG; ++q) acc[q] = zero;
-  if (live) nd_dot_rows<T, KG, false>(acc, K + i, ns, v, c0, c1);
+  if (live) nd_dot_rows_pre<T, KG, false>(acc, pre, K + i, ns, v, c0, c1);
   C* part = v + region;
   if (CG > 1) {
     if (cgi > 0) {
@@ -757,19 +844,27 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
   for (int j = c0 + lane; j < c1; j += 64) {
     int o[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) o[k] = k < J.dim2 ? us[j * J.dim2 + k] : -1;
+    for (int k = 0; k < 6; ++k) o[k] = k < J.dim2 ? us[j * J.dim2 + min(k, J.dim2 - 1)] : -1;
     const C* Rc = R + (long long)q0 * nloc + tc[j];
+    // loads at valid addresses, selected afterwards (an absent update reads
+    // the R entry): the loads of a column go out together
+    C v[KG];
 #pragma unroll
-    for (int q = 0; q < KG; ++q) {
-      C v = zero;
-      if (q < nq) {
-        v = Rc[(long long)q * nloc];
+    for (int q = 0; q < KG; ++q) v[q] = Rc[(long long)min(q, nq - 1) * nloc];
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-          if (o[k] >= 0) v = v + U[(long long)o[k] * kmax + q0 + q];
-      }
-      gl[(j - c0) * KG + q] = v;
+    for (int k = 0; k < 6; ++k) {
+      if (k >= J.dim2) break;
+      const bool h = o[k] >= 0;
+      const C* Uk = h ? U + (long long)o[k] * kmax + q0 : Rc;
+      const long long sk = h ? 1 : nloc;
+      C u[KG];
+#pragma unroll
+      for (int q = 0; q < KG; ++q) u[q] = nd_gload(Uk + (long long)min(q, nq - 1) * sk);
+#pragma unroll
+      for (int q = 0; q < KG; ++q) v[q] = h ? v[q] + u[q] : v[q];
     }
+#pragma unroll
+    for (int q = 0; q < KG; ++q) gl[(j - c0) * KG + q] = q < nq ? v[q] : zero;
   }
   nd_wave_sync();
   const int i = tile * 64 + lane;
@@ -1189,7 +1284,7 @@ __global__ __launch_bounds__(512) void k_nd_fused_fwd(
             if (own) v = Rc[(long long)q * J.nloc];
             if (i0 >= 0) v = v + U0[q];
             if (i1 >= 0) v = v + U1[q];
-            if (own) Rc[(long long)q * J.nloc] = v;
+            if (own && (i0 >= 0 || i1 >= 0)) Rc[(long long)q * J.nloc] = v;
           }
           fr[p * KG + q] = v;
         }
@@ -1333,7 +1428,7 @@ void launch_nd_lvl_fwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, 
 template <typename T, int KG>
 static void launch_lvl_bwd_k(int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
                              const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long ps,
-                             int nrhs, int max_nf, hipStream_t s) {
+                             int nrhs, int max_nf, const cpx<T>* const* coef, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
   const int npw = tt <= 0 ? 8 : 1, wv = tt <= 0 ? 8 : tt * cg;
   const int region = std::max(1, max_nf) * KG;
@@ -1342,16 +1437,17 @@ static void launch_lvl_bwd_k(int tt, int cg, const NdLvlJob* jobs, int njobs, co
                              : (size_t)region + (size_t)std::max(cg - 1, 1) * tt * 64 * KG;
   hipLaunchKernelGGL((k_nd_lvl_bwd<T, KG>), dim3(nd_grid(groups * G)), dim3(64 * wv),
                      lds * sizeof(cpx<T>), s, jobs, njobs, G, npw, region, std::max(1, tt),
-                     std::max(1, cg), cells, fac, rpool, xpool, ps, nrhs);
+                     std::max(1, cg), cells, fac, rpool, xpool, ps, nrhs, coef[0], coef[1], coef[2]);
 }
 
 template <typename T>
 void launch_nd_lvl_bwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
                        const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool,
-                       long long pool_stride, int nrhs, int max_nf, hipStream_t s) {
+                       long long pool_stride, int nrhs, int max_nf, const cpx<T>* const* coef,
+                       hipStream_t s) {
   if (njobs <= 0 || nrhs <= 0) return;
 #define ND_BWD(K) launch_lvl_bwd_k<T, K>(tt, cg, jobs, njobs, cells, fac, rpool, xpool, pool_stride, \
-                                         nrhs, max_nf, s)
+                                         nrhs, max_nf, coef, s)
   switch (kg) {
     case 16: ND_BWD(16); break;
     case 8: ND_BWD(8); break;
@@ -1707,7 +1803,7 @@ void launch_nd_gemm(const NdGemmJob* jobs, int njobs, int max_m, int max_n, cpx<
                                      int, int, hipStream_t);                                     \
   template void launch_nd_lvl_bwd<T>(int, int, int, const NdLvlJob*, int, const int*,           \
                                      const cpx<T>*, const cpx<T>*, cpx<T>*, long long, int, int,  \
-                                     hipStream_t);                                               \
+                                     const cpx<T>* const*, hipStream_t);                         \
   template void launch_nd_top<T>(int, const NdTopJob*, int, const int*, const int*,              \
                                  const cpx<T>*, const cpx<T>*, const cpx<T>*, cpx<T>*, long long, \
                                  int, int, int, hipStream_t);                                    \

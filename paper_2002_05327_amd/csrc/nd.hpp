@@ -107,6 +107,13 @@ struct NdLvlJob {
   long long upd;             // update-vector entry of the node (within the member)
   long long vbase;           // vector-pool offset of the subdomain slice
   long long ubase;           // update-vector base of this member (entries x kmax)
+  // Leaves (no children): the separator is the whole box [lo, hi) of the local
+  // grid and its couplings to the boundary are the operator's own face
+  // couplings, so the backward product forms f_S - A_SB x_B from the
+  // coefficients and multiplies it by P alone (the first ns columns of K).
+  int leaf;
+  int lo[3], hi[3], dims[3];
+  long long coef;            // first cell of the subdomain in the coefficient arrays
 };
 
 // Dense top of one subdomain solve.  usrc holds, per top cell, dim2
@@ -165,7 +172,8 @@ void launch_nd_lvl_fwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, 
 template <typename T>
 void launch_nd_lvl_bwd(int kg, int tt, int cg, const NdLvlJob* jobs, int njobs, const int* cells,
                        const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool,
-                       long long pool_stride, int nrhs, int max_nf, hipStream_t s);
+                       long long pool_stride, int nrhs, int max_nf, const cpx<T>* const* coef,
+                       hipStream_t s);
 // dense top: x_top = P_top (r_top + gathered updates); kg = the RHS group
 // (nd_top_kg of the launch's largest top)
 template <typename T>

@@ -1264,8 +1264,10 @@ int nd_setup(dsd_plan* pl) {
         M.f_nf = std::max(M.f_nf, nf);
       }
       if (!nd_wide_node(pl, ns, nbd, false)) {
+        // a leaf's backward product runs over its separator only
+        const bool leaf = n.child[0] < 0 && n.child[1] < 0;
         M.b_rows = std::max(M.b_rows, ns);
-        M.b_cols = std::max(M.b_cols, nf);
+        M.b_cols = std::max(M.b_cols, leaf ? ns : nf);
       }
     }
     pl->nd_max_ntop = std::max(pl->nd_max_ntop, sh.ntop());
@@ -1344,6 +1346,13 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
       J.upd = n.upd;
       J.vbase = vb;
       J.ubase = ub;
+      J.leaf = n.child[0] < 0 && n.child[1] < 0;
+      for (int a = 0; a < 3; ++a) {
+        J.lo[a] = n.lo[a];
+        J.hi[a] = n.hi[a];
+        J.dims[a] = S.dims[a];
+      }
+      J.coef = S.coef_off;
       return J;
     };
     // fused subtrees: the nodes below the fusion level, by their ancestor at
@@ -1385,18 +1394,7 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     for (size_t i = 0; i < sh.nodes.size(); ++i) {
       const NdNode& n = sh.nodes[i];
       if (n.top || n.level >= pl->nd_fuse_level) continue;
-      NdLvlJob J{};
-      J.ns = (int)n.sep.size();
-      J.nbd = (int)n.bnd.size();
-      J.cell = pl->nd_cell_of[tb.node0 + i];
-      J.umap = pl->nd_map_of[tb.node0 + i];
-      J.l = m.y;
-      J.nloc = S.nloc;
-      J.fac = S.fac_off + n.fac;
-      J.upd = n.upd;
-      J.vbase = vb;
-      J.ubase = ub;
-      per[n.level].push_back(J);
+      per[n.level].push_back(job_of(i));
     }
     if (sh.ntop() > 0) {
       NdTopJob T{};
@@ -1453,11 +1451,13 @@ void nd_group_jobs(const dsd_plan* pl, const std::vector<int2>& mem, bool local,
     add_tiles(true, false, V.wf_off, V.wf_n);
     add_tiles(false, false, V.wb_off, V.wb_n);
     for (const NdLvlJob& J : v) {
-      const double fb = (double)J.nbd * J.ns * ts, bb = (double)J.ns * (J.ns + J.nbd) * ts;
+      const bool wb = nd_wide_node(pl, J.ns, J.nbd, false);
+      const double fb = (double)J.nbd * J.ns * ts,
+                   bb = (double)J.ns * (J.leaf && !wb ? J.ns : J.ns + J.nbd) * ts;
       const double fc = (double)(J.ns + J.nbd);
       if (nd_wide_node(pl, J.ns, J.nbd, true)) { V.wf_bytes += fb; V.wf_cells += fc; }
       else { V.nf_bytes += fb; V.nf_cells += fc; }
-      if (nd_wide_node(pl, J.ns, J.nbd, false)) { V.wb_bytes += bb; V.wb_cells += fc; }
+      if (wb) { V.wb_bytes += bb; V.wb_cells += fc; }
       else { V.nb_bytes += bb; V.nb_cells += fc; }
     }
     lj.insert(lj.end(), v.begin(), v.end());
@@ -2023,8 +2023,10 @@ void nd_phase(dsd_plan* pl, const dsd_plan::NdLaunch& L, cpx<T>* R, cpx<T>* X, c
                            U, pool_stride, nrhs, kmax, M.f_nf, st);
     } else {
       nd_shape(M.b_rows, M.b_cols, pl->kg, M.b_cols, tsz, pl->nd_small, tt, cg);
+      const cpx<T>* coef[3] = {pl->d_lcoefT[1].as<cpx<T>>(), pl->d_lcoefT[2].as<cpx<T>>(),
+                               pl->d_lcoefT[3].as<cpx<T>>()};
       launch_nd_lvl_bwd<T>(pl->kg, tt, cg, lj + V.nb_off, n, cells, fac, R, X, pool_stride, nrhs,
-                           M.b_cols, st);
+                           M.b_cols, coef, st);
     }
     const double b = fwd ? V.nf_bytes : V.nb_bytes, c = fwd ? V.nf_cells : V.nb_cells;
     if (timed) time_end(pl, b + 2.0 * c * nrhs * ts, b / ts * nrhs * 8.0);
