@@ -526,32 +526,55 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
   {
     const int* fc = cells + J.cell;
     const int* um = umaps + J.umap;
+    // Lanes over positions: the separator's R entries (RHS q at q * nloc, so
+    // neighbouring cells share cache lines), 0 on the boundary; every load at
+    // a valid address and selected afterwards, so they go out together.
     for (int p = tid; p < nf; p += nt) {
-      const int i0 = um[2 * p], i1 = um[2 * p + 1];
-      const bool own = p < ns, h0 = i0 >= 0, h1 = i1 >= 0;
-      C* Rc = R + (long long)q0 * nloc + fc[p];
-      // every load at a valid address (an absent update reads the R entry)
-      // and the terms selected afterwards: a position's loads go out together
-      // instead of one branch, and one wait, per term and RHS
-      const C* U0 = h0 ? U + (long long)i0 * kmax + q0 : Rc;
-      const C* U1 = h1 ? U + (long long)i1 * kmax + q0 : Rc;
-      const long long s0 = h0 ? 1 : nloc, s1 = h1 ? 1 : nloc;
-      C r[KG], a[KG], b[KG];
+      const C* Rc = R + (long long)q0 * nloc + fc[p];
+      C r[KG];
 #pragma unroll
-      for (int q = 0; q < KG; ++q) {
-        const long long qc = min(q, nq - 1);
-        r[q] = Rc[qc * nloc];
-        a[q] = nd_gload(U0 + qc * s0);
-        b[q] = nd_gload(U1 + qc * s1);
-      }
+      for (int q = 0; q < KG; ++q) r[q] = Rc[(long long)min(q, nq - 1) * nloc];
 #pragma unroll
-      for (int q = 0; q < KG; ++q) {
-        C v = own ? r[q] : zero;
-        v = h0 ? v + a[q] : v;
-        v = h1 ? v + b[q] : v;
-        v = q < nq ? v : zero;
-        if (own && (h0 || h1) && q < nq) Rc[(long long)q * nloc] = v;
-        fr[p * KG + q] = v;
+      for (int q = 0; q < KG; ++q) fr[p * KG + q] = p < ns && q < nq ? r[q] : zero;
+    }
+    if (!J.leaf) {
+      if (npw > 1) nd_wave_sync();
+      else __syncthreads();
+      // Lanes over (position, RHS) pairs, RHS fastest: a child's update entry
+      // holds the KG right-hand sides of a position contiguously, read whole
+      // by KG neighbouring lanes; the sum goes back to R on the separator.
+      // Four pairs per thread per pass, every load at a valid address (an
+      // absent child reads the position's R entry) so that all go out together.
+      constexpr int PP = 4;
+      for (int e0 = tid; e0 < nf * KG; e0 += PP * nt) {
+        int i0[PP], i1[PP], cl[PP];
+#pragma unroll
+        for (int k = 0; k < PP; ++k) {
+          const int e = min(e0 + k * nt, nf * KG - 1), p = e / KG;
+          i0[k] = um[2 * p];
+          i1[k] = um[2 * p + 1];
+          cl[k] = fc[p];
+        }
+        C a[PP], b[PP];
+#pragma unroll
+        for (int k = 0; k < PP; ++k) {
+          const int e = min(e0 + k * nt, nf * KG - 1), q = e - (e / KG) * KG;
+          const C* rq = R + (long long)(q0 + min(q, nq - 1)) * nloc + cl[k];
+          a[k] = nd_gload(i0[k] >= 0 ? U + (long long)i0[k] * kmax + q0 + q : rq);
+          b[k] = nd_gload(i1[k] >= 0 ? U + (long long)i1[k] * kmax + q0 + q : rq);
+        }
+#pragma unroll
+        for (int k = 0; k < PP; ++k) {
+          const int e = e0 + k * nt;
+          if (e >= nf * KG) break;
+          const int p = e / KG, q = e - (e / KG) * KG;
+          if (q >= nq || (i0[k] < 0 && i1[k] < 0)) continue;
+          C v = fr[e];
+          v = i0[k] >= 0 ? v + a[k] : v;
+          v = i1[k] >= 0 ? v + b[k] : v;
+          fr[e] = v;
+          if (p < ns) R[(long long)(q0 + q) * nloc + cl[k]] = v;
+        }
       }
     }
   }
@@ -841,30 +864,52 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
   const int cw = (ntop + ND_TW - 1) / ND_TW;
   const int c0 = min(ntop, w * cw), c1 = min(ntop, c0 + cw);
   C* gl = lds + (long long)w * cwmax * KG;
+  // lanes over columns: r_top (RHS q at q * nloc: neighbouring cells share
+  // cache lines), loads at valid addresses and selected afterwards
   for (int j = c0 + lane; j < c1; j += 64) {
-    int o[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) o[k] = k < J.dim2 ? us[j * J.dim2 + min(k, J.dim2 - 1)] : -1;
     const C* Rc = R + (long long)q0 * nloc + tc[j];
-    // loads at valid addresses, selected afterwards (an absent update reads
-    // the R entry): the loads of a column go out together
     C v[KG];
 #pragma unroll
     for (int q = 0; q < KG; ++q) v[q] = Rc[(long long)min(q, nq - 1) * nloc];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      if (k >= J.dim2) break;
-      const bool h = o[k] >= 0;
-      const C* Uk = h ? U + (long long)o[k] * kmax + q0 : Rc;
-      const long long sk = h ? 1 : nloc;
-      C u[KG];
+    for (int q = 0; q < KG; ++q) gl[(j - c0) * KG + q] = q < nq ? v[q] : zero;
+  }
+  nd_wave_sync();
+  // lanes over (column, RHS) pairs, RHS fastest: a subtree root's update entry
+  // holds the KG right-hand sides contiguously, read whole by KG lanes
+  // (two pairs per lane per pass; every load at a valid address, an absent
+  // update reading the column's R entry, so that all go out together)
+  const int ne = (c1 - c0) * KG, d2 = J.dim2;
+  for (int e0 = lane; e0 < ne; e0 += 128) {
+    int o[2][6], cl[2];
 #pragma unroll
-      for (int q = 0; q < KG; ++q) u[q] = nd_gload(Uk + (long long)min(q, nq - 1) * sk);
+    for (int h = 0; h < 2; ++h) {
+      const int e = min(e0 + 64 * h, ne - 1), j = c0 + e / KG;
+      cl[h] = tc[j];
 #pragma unroll
-      for (int q = 0; q < KG; ++q) v[q] = h ? v[q] + u[q] : v[q];
+      for (int k = 0; k < 6; ++k) o[h][k] = k < d2 ? us[j * d2 + min(k, d2 - 1)] : -1;
+    }
+    C u[2][6];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = min(e0 + 64 * h, ne - 1), q = e - (e / KG) * KG;
+      const C* rq = R + (long long)(q0 + min(q, nq - 1)) * nloc + cl[h];
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < d2) u[h][k] = nd_gload(o[h][k] >= 0 ? U + (long long)o[h][k] * kmax + q0 + q : rq);
     }
 #pragma unroll
-    for (int q = 0; q < KG; ++q) gl[(j - c0) * KG + q] = q < nq ? v[q] : zero;
+    for (int h = 0; h < 2; ++h) {
+      const int e = e0 + 64 * h;
+      if (e >= ne) break;
+      const int q = e - (e / KG) * KG;
+      if (q >= nq) continue;
+      C v = gl[e];
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (k < d2) v = o[h][k] >= 0 ? v + u[h][k] : v;
+      gl[e] = v;
+    }
   }
   nd_wave_sync();
   const int i = tile * 64 + lane;
