@@ -249,9 +249,16 @@ bool nd_append_tables(const NdShape& S, NdShapeTab& tab, std::vector<NdNodeDev>&
 // also covers every other load in flight.
 template <typename T>
 __device__ __forceinline__ cpx<T> nd_gload(const cpx<T>* p) {
-  typedef T v2 __attribute__((ext_vector_type(2)));
-  const v2 v = *(const __attribute__((address_space(1))) v2*)p;
-  return mk(v.x, v.y);
+  const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)p;
+  return mk(g[0], g[1]);
+}
+
+// Select between two complex values by component: a conditional between two
+// complex lvalues selects an address, which keeps the arrays in memory
+// (scratch, or flat loads when one side is in LDS).
+template <typename T>
+__device__ __forceinline__ cpx<T> nd_sel(bool c, cpx<T> a, cpx<T> b) {
+  return mk(c ? a.re : b.re, c ? a.im : b.im);
 }
 
 __device__ __forceinline__ void nd_wave_sync() {
@@ -520,8 +527,10 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
   const int t = w % TT, cgi = w / TT;
   const int cw = (ns + CG - 1) / CG;
   const int c0 = min(ns, cgi * cw), c1 = min(ns, c0 + cw);
+  // (complex128 keeps its registers for occupancy and loads after the gather)
+  constexpr bool PRE = VEC && sizeof(T) == 4;
   C pre[8];
-  if (VEC && npw == 1 && t * 64 < nbd && c1 > c0)
+  if (PRE && npw == 1 && t * 64 < nbd && c1 > c0)
     nd_rows_first(pre, fac + J.fac + min(t * 64 + lane, nbd - 1), nbd, c0, c1);
   {
     const int* fc = cells + J.cell;
@@ -535,7 +544,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
 #pragma unroll
       for (int q = 0; q < KG; ++q) r[q] = Rc[(long long)min(q, nq - 1) * nloc];
 #pragma unroll
-      for (int q = 0; q < KG; ++q) fr[p * KG + q] = p < ns && q < nq ? r[q] : zero;
+      for (int q = 0; q < KG; ++q) fr[p * KG + q] = nd_sel(p < ns && q < nq, r[q], zero);
     }
     if (!J.leaf) {
       if (npw > 1) nd_wave_sync();
@@ -545,7 +554,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
       // by KG neighbouring lanes; the sum goes back to R on the separator.
       // Four pairs per thread per pass, every load at a valid address (an
       // absent child reads the position's R entry) so that all go out together.
-      constexpr int PP = 4;
+      constexpr int PP = sizeof(T) == 4 ? 4 : 2;
       for (int e0 = tid; e0 < nf * KG; e0 += PP * nt) {
         int i0[PP], i1[PP], cl[PP];
 #pragma unroll
@@ -566,14 +575,14 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
 #pragma unroll
         for (int k = 0; k < PP; ++k) {
           const int e = e0 + k * nt;
-          if (e >= nf * KG) break;
           const int p = e / KG, q = e - (e / KG) * KG;
-          if (q >= nq || (i0[k] < 0 && i1[k] < 0)) continue;
-          C v = fr[e];
-          v = i0[k] >= 0 ? v + a[k] : v;
-          v = i1[k] >= 0 ? v + b[k] : v;
-          fr[e] = v;
-          if (p < ns) R[(long long)(q0 + q) * nloc + cl[k]] = v;
+          if (e < nf * KG && q < nq && (i0[k] >= 0 || i1[k] >= 0)) {
+            C v = fr[e];
+            v = i0[k] >= 0 ? v + a[k] : v;
+            v = i1[k] >= 0 ? v + b[k] : v;
+            fr[e] = v;
+            if (p < ns) R[(long long)(q0 + q) * nloc + cl[k]] = v;
+          }
         }
       }
     }
@@ -640,9 +649,12 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
 #pragma unroll
   for (int q = 0; q < KG; ++q) {
     const C f = fr[ri * KG + q];
-    acc[q] = (cgi == 0 && live) ? f : zero;
+    acc[q] = nd_sel(cgi == 0 && live, f, zero);
   }
-  if (live) nd_dot_rows_pre<T, KG, true>(acc, pre, L + i, nbd, fr, c0, c1);
+  if (live) {
+    if constexpr (PRE) nd_dot_rows_pre<T, KG, true>(acc, pre, L + i, nbd, fr, c0, c1);
+    else nd_dot_rows<T, KG, true>(acc, L + i, nbd, fr, c0, c1);
+  }
   C* part = fr + region;
   if (CG > 1) {
     if (cgi > 0) {
@@ -704,8 +716,9 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
   const int t = w % TT, cgi = w / TT;
   const int cw = (ncol + CG - 1) / CG;
   const int c0 = min(ncol, cgi * cw), c1 = min(ncol, c0 + cw);
+  constexpr bool PRE = VEC && sizeof(T) == 4;
   C pre[8];
-  if (VEC && npw == 1 && t * 64 < ns && c1 > c0)
+  if (PRE && npw == 1 && t * 64 < ns && c1 > c0)
     nd_rows_first(pre, fac + J.fac + (long long)nbd * ns + min(t * 64 + lane, ns - 1), ns, c0, c1);
   for (int p = tid; p < ncol; p += nt) {
     const bool own = p < ns;
@@ -716,32 +729,54 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
 #pragma unroll
     for (int q = 0; q < KG; ++q) x[q] = nd_gload(xs + (long long)min(q, nq - 1) * nloc);
 #pragma unroll
-    for (int q = 0; q < KG; ++q) x[q] = q < nq ? (own ? x[q] : -x[q]) : zero;
+    for (int q = 0; q < KG; ++q) x[q] = nd_sel(q < nq, nd_sel(own, x[q], -x[q]), zero);
     if (J.leaf) {
       // the box's faces, in a fixed order: -x, +x, -y, +y, -z, +z (one at a
       // time: the kernel's registers are set by its largest live set)
       const int nx = J.dims[0], ny = J.dims[1], nz = J.dims[2], nxy = nx * ny;
       const int px = cell % nx, py = (cell / nx) % ny, pz = cell / nxy;
-      const int nd2 = nz > 1 ? 6 : 4;
+      const int na = nz > 1 ? 3 : 2;
+      // complex128: one face at a time (registers); complex64: both faces of
+      // an axis, their loads going out together
+      constexpr bool PAIR = sizeof(T) == 4;
 #pragma unroll 1
-      for (int d = 0; d < nd2; ++d) {
-        const int a = d >> 1;
-        const bool lo = (d & 1) == 0;
+      for (int a = 0; a < na; ++a) {
         const int pa = a == 0 ? px : a == 1 ? py : pz;
         const int ea = a == 0 ? nx : a == 1 ? ny : nz;
         const int sa = a == 0 ? 1 : a == 1 ? nx : nxy;
         const int la = a == 0 ? J.lo[0] : a == 1 ? J.lo[1] : J.lo[2];
         const int ha = a == 0 ? J.hi[0] : a == 1 ? J.hi[1] : J.hi[2];
         const C* __restrict__ ca = (a == 0 ? cx : a == 1 ? cy : cz) + J.coef;
-        const bool face = lo ? pa == la && la > 0 : pa == ha - 1 && ha < ea;
-        const int nb = face ? (lo ? cell - sa : cell + sa) : cell;
-        const C cpl = nd_gload(ca + (face && !lo ? cell : nb));
-        const C* xb = X + (long long)q0 * nloc + nb;
-        C xn[KG];
+        const bool f0 = pa == la && la > 0, f1 = pa == ha - 1 && ha < ea;
+        const int n0 = f0 ? cell - sa : cell, n1 = f1 ? cell + sa : cell;
+        const C c0v = nd_gload(ca + n0), c1v = nd_gload(ca + cell);
+        const C* x0 = X + (long long)q0 * nloc + n0;
+        const C* x1 = X + (long long)q0 * nloc + n1;
+        if constexpr (PAIR) {
+          C y0[KG], y1[KG];
 #pragma unroll
-        for (int q = 0; q < KG; ++q) xn[q] = xb[(long long)min(q, nq - 1) * nloc];
+          for (int q = 0; q < KG; ++q) {
+            y0[q] = x0[(long long)min(q, nq - 1) * nloc];
+            y1[q] = x1[(long long)min(q, nq - 1) * nloc];
+          }
 #pragma unroll
-        for (int q = 0; q < KG; ++q) x[q] = face && q < nq ? x[q] - cpl * xn[q] : x[q];
+          for (int q = 0; q < KG; ++q) {
+            x[q] = f0 && q < nq ? x[q] - c0v * y0[q] : x[q];
+            x[q] = f1 && q < nq ? x[q] - c1v * y1[q] : x[q];
+          }
+        } else {
+#pragma unroll 1
+          for (int side = 0; side < 2; ++side) {
+            const C* xs_ = side == 0 ? x0 : x1;
+            const C cv = side == 0 ? c0v : c1v;
+            const bool f = side == 0 ? f0 : f1;
+            C y[KG];
+#pragma unroll
+            for (int q = 0; q < KG; ++q) y[q] = nd_gload(xs_ + (long long)min(q, nq - 1) * nloc);
+#pragma unroll
+            for (int q = 0; q < KG; ++q) x[q] = f && q < nq ? x[q] - cv * y[q] : x[q];
+          }
+        }
       }
     }
 #pragma unroll
@@ -807,7 +842,10 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
   C acc[KG];
 #pragma unroll
   for (int q = 0; q < KG; ++q) acc[q] = zero;
-  if (live) nd_dot_rows_pre<T, KG, false>(acc, pre, K + i, ns, v, c0, c1);
+  if (live) {
+    if constexpr (PRE) nd_dot_rows_pre<T, KG, false>(acc, pre, K + i, ns, v, c0, c1);
+    else nd_dot_rows<T, KG, false>(acc, K + i, ns, v, c0, c1);
+  }
   C* part = v + region;
   if (CG > 1) {
     if (cgi > 0) {
@@ -872,26 +910,28 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
 #pragma unroll
     for (int q = 0; q < KG; ++q) v[q] = Rc[(long long)min(q, nq - 1) * nloc];
 #pragma unroll
-    for (int q = 0; q < KG; ++q) gl[(j - c0) * KG + q] = q < nq ? v[q] : zero;
+    for (int q = 0; q < KG; ++q) gl[(j - c0) * KG + q] = nd_sel(q < nq, v[q], zero);
   }
   nd_wave_sync();
   // lanes over (column, RHS) pairs, RHS fastest: a subtree root's update entry
   // holds the KG right-hand sides contiguously, read whole by KG lanes
-  // (two pairs per lane per pass; every load at a valid address, an absent
-  // update reading the column's R entry, so that all go out together)
+  // (two pairs per lane per pass in complex64, one in complex128 for
+  // registers; every load at a valid address, an absent update reading the
+  // column's R entry, so that all go out together)
+  constexpr int HH = sizeof(T) == 4 ? 2 : 1;
   const int ne = (c1 - c0) * KG, d2 = J.dim2;
-  for (int e0 = lane; e0 < ne; e0 += 128) {
-    int o[2][6], cl[2];
+  for (int e0 = lane; e0 < ne; e0 += 64 * HH) {
+    int o[HH][6], cl[HH];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < HH; ++h) {
       const int e = min(e0 + 64 * h, ne - 1), j = c0 + e / KG;
       cl[h] = tc[j];
 #pragma unroll
       for (int k = 0; k < 6; ++k) o[h][k] = k < d2 ? us[j * d2 + min(k, d2 - 1)] : -1;
     }
-    C u[2][6];
+    C u[HH][6];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < HH; ++h) {
       const int e = min(e0 + 64 * h, ne - 1), q = e - (e / KG) * KG;
       const C* rq = R + (long long)(q0 + min(q, nq - 1)) * nloc + cl[h];
 #pragma unroll
@@ -899,16 +939,16 @@ __global__ __launch_bounds__(64 * ND_TW) void k_nd_top(
         if (k < d2) u[h][k] = nd_gload(o[h][k] >= 0 ? U + (long long)o[h][k] * kmax + q0 + q : rq);
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < HH; ++h) {
       const int e = e0 + 64 * h;
-      if (e >= ne) break;
       const int q = e - (e / KG) * KG;
-      if (q >= nq) continue;
-      C v = gl[e];
+      if (e < ne && q < nq) {
+        C v = gl[e];
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if (k < d2) v = o[h][k] >= 0 ? v + u[h][k] : v;
-      gl[e] = v;
+        for (int k = 0; k < 6; ++k)
+          if (k < d2) v = o[h][k] >= 0 ? v + u[h][k] : v;
+        gl[e] = v;
+      }
     }
   }
   nd_wave_sync();
