@@ -539,7 +539,9 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
     // neighbouring cells share cache lines), 0 on the boundary; every load at
     // a valid address and selected afterwards, so they go out together.
     for (int p = tid; p < nf; p += nt) {
-      const C* Rc = R + (long long)q0 * nloc + fc[p];
+      // (a boundary position reads its separator's last cell, selected out:
+      // the boundary's own cells would pull extra cache lines)
+      const C* Rc = R + (long long)q0 * nloc + fc[min(p, ns - 1)];
       C r[KG];
 #pragma unroll
       for (int q = 0; q < KG; ++q) r[q] = Rc[(long long)min(q, nq - 1) * nloc];
@@ -555,6 +557,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
       // Four pairs per thread per pass, every load at a valid address (an
       // absent child reads the position's R entry) so that all go out together.
       constexpr int PP = sizeof(T) == 4 ? 4 : 2;
+      const int cell0 = fc[0];
       for (int e0 = tid; e0 < nf * KG; e0 += PP * nt) {
         int i0[PP], i1[PP], cl[PP];
 #pragma unroll
@@ -568,9 +571,13 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
 #pragma unroll
         for (int k = 0; k < PP; ++k) {
           const int e = min(e0 + k * nt, nf * KG - 1), q = e - (e / KG) * KG;
-          const C* rq = R + (long long)(q0 + min(q, nq - 1)) * nloc + cl[k];
-          a[k] = nd_gload(i0[k] >= 0 ? U + (long long)i0[k] * kmax + q0 + q : rq);
-          b[k] = nd_gload(i1[k] >= 0 ? U + (long long)i1[k] * kmax + q0 + q : rq);
+          // an absent child reads the other child's entry, or with neither
+          // the separator's first cell (one shared line): no extra lines
+          const C* rq = R + (long long)(q0 + min(q, nq - 1)) * nloc + cell0;
+          const C* u0 = i0[k] >= 0 ? U + (long long)i0[k] * kmax + q0 + q : nullptr;
+          const C* u1 = i1[k] >= 0 ? U + (long long)i1[k] * kmax + q0 + q : nullptr;
+          a[k] = nd_gload(u0 ? u0 : u1 ? u1 : rq);
+          b[k] = nd_gload(u1 ? u1 : u0 ? u0 : rq);
         }
 #pragma unroll
         for (int k = 0; k < PP; ++k) {
@@ -750,14 +757,17 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
         const bool f0 = pa == la && la > 0, f1 = pa == ha - 1 && ha < ea;
         const int n0 = f0 ? cell - sa : cell, n1 = f1 ? cell + sa : cell;
         const C c0v = nd_gload(ca + n0), c1v = nd_gload(ca + cell);
-        const C* x0 = X + (long long)q0 * nloc + n0;
-        const C* x1 = X + (long long)q0 * nloc + n1;
+        // off the face: the cell's own R entries (already read above), not
+        // X's, so that no extra cache lines are pulled
+        const C* rs = R + (long long)q0 * nloc + cell;
+        const C* x0 = f0 ? X + (long long)q0 * nloc + n0 : rs;
+        const C* x1 = f1 ? X + (long long)q0 * nloc + n1 : rs;
         if constexpr (PAIR) {
           C y0[KG], y1[KG];
 #pragma unroll
           for (int q = 0; q < KG; ++q) {
-            y0[q] = x0[(long long)min(q, nq - 1) * nloc];
-            y1[q] = x1[(long long)min(q, nq - 1) * nloc];
+            y0[q] = nd_gload(x0 + (long long)min(q, nq - 1) * nloc);
+            y1[q] = nd_gload(x1 + (long long)min(q, nq - 1) * nloc);
           }
 #pragma unroll
           for (int q = 0; q < KG; ++q) {
