@@ -273,6 +273,17 @@ __device__ __forceinline__ int nd_task(int b, int total) {
   return (b & 7) * per + (b >> 3);
 }
 
+// XCD-aware order of the level kernels (grid 8 ceil(groups / 8) G): node
+// groups dealt round-robin to the eight XCDs, a contiguous share per XCD would
+// give some XCDs the larger nodes of a level (jobs are sorted by size); the G
+// RHS groups of a node run on one XCD one after another and share its matrix
+// through that XCD's L2.
+__device__ __forceinline__ int nd_task_rr(int b, int G) {
+  const int x = b & 7, k = b >> 3;
+  return (x + 8 * (k / G)) * G + k % G;
+}
+static unsigned nd_grid_rr(long long groups, int G) { return (unsigned)(8 * ((groups + 7) / 8) * G); }
+
 // Dot products of the node kernels: acc -= (or +=) sum_j A[j * lda] y[j * KG],
 // the matrix column loads issued eight at a time and one batch ahead of the
 // FMAs that use them (so a row's loads are in flight together).
@@ -496,7 +507,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_fwd(
     int kmax) {
   typedef cpx<T> C;
   constexpr int RPP = 64 / KG;
-  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int Lg = nd_task_rr(blockIdx.x, G);
   const int grp = Lg / G, g = Lg - (Lg / G) * G;
   int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63;
@@ -693,7 +704,7 @@ __global__ __launch_bounds__(512) void k_nd_lvl_bwd(
     const cpx<T>* __restrict__ cy, const cpx<T>* __restrict__ cz) {
   typedef cpx<T> C;
   constexpr int RPP = 64 / KG;
-  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int Lg = nd_task_rr(blockIdx.x, G);
   const int grp = Lg / G, g = Lg - (Lg / G) * G;
   int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63;
@@ -1498,7 +1509,7 @@ static void launch_lvl_fwd_k(int tt, int cg, const NdLvlJob* jobs, int njobs, co
   const long long groups = (njobs + npw - 1) / npw;
   const size_t lds = tt <= 0 ? (size_t)npw * region
                              : (size_t)region + (size_t)std::max(cg - 1, 1) * tt * 64 * KG;
-  hipLaunchKernelGGL((k_nd_lvl_fwd<T, KG>), dim3(nd_grid(groups * G)), dim3(64 * wv),
+  hipLaunchKernelGGL((k_nd_lvl_fwd<T, KG>), dim3(nd_grid_rr(groups, G)), dim3(64 * wv),
                      lds * sizeof(cpx<T>), s, jobs, njobs, G, npw, region, std::max(1, tt),
                      std::max(1, cg), cells, umaps, fac, rpool, upool, ps, nrhs, kmax);
 }
@@ -1530,7 +1541,7 @@ static void launch_lvl_bwd_k(int tt, int cg, const NdLvlJob* jobs, int njobs, co
   const long long groups = (njobs + npw - 1) / npw;
   const size_t lds = tt <= 0 ? (size_t)npw * region
                              : (size_t)region + (size_t)std::max(cg - 1, 1) * tt * 64 * KG;
-  hipLaunchKernelGGL((k_nd_lvl_bwd<T, KG>), dim3(nd_grid(groups * G)), dim3(64 * wv),
+  hipLaunchKernelGGL((k_nd_lvl_bwd<T, KG>), dim3(nd_grid_rr(groups, G)), dim3(64 * wv),
                      lds * sizeof(cpx<T>), s, jobs, njobs, G, npw, region, std::max(1, tt),
                      std::max(1, cg), cells, fac, rpool, xpool, ps, nrhs, coef[0], coef[1], coef[2]);
 }
