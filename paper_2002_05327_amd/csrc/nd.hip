@@ -273,7 +273,7 @@ __device__ __forceinline__ int nd_task(int b, int total) {
   return (b & 7) * per + (b >> 3);
 }
 
-// XCD-aware order of the level kernels (grid 8 ceil(groups / 8) G): node
+// XCD-aware order of the level and wide kernels (grid 8 ceil(groups / 8) G): node
 // groups dealt round-robin to the eight XCDs, a contiguous share per XCD would
 // give some XCDs the larger nodes of a level (jobs are sorted by size); the G
 // RHS groups of a node run on one XCD one after another and share its matrix
@@ -1090,7 +1090,9 @@ __global__ __launch_bounds__(256) void k_nd_form(const NdLvlJob* __restrict__ jo
                                                  cpx<T>* __restrict__ rpool,
                                                  const cpx<T>* __restrict__ upool,
                                                  long long pool_stride, int nrhs, int kmax) {
-  const int tix = nd_task(blockIdx.x, gridDim.x);
+  // tiles in launch order: consecutive workgroups go to different XCDs, so the
+  // tiles of the large and the small nodes spread over all of them
+  const int tix = blockIdx.x;
   if (tix >= ntiles) return;
   const int2 t = tiles[tix];
   const NdLvlJob J = jobs[t.x];
@@ -1274,7 +1276,9 @@ __global__ __launch_bounds__(512) void k_nd_wide_fwd(
     const cpx<T>* __restrict__ rpool, cpx<T>* __restrict__ upool, long long pool_stride,
     int nrhs, int kmax) {
   typedef cpx<T> C;
-  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  // tiles dealt round-robin to the XCDs (the tiles of large and small nodes
+  // spread over all of them), a tile's RHS groups on one XCD
+  const int Lg = nd_task_rr(blockIdx.x, G);
   const int tix = Lg / G, g = Lg - (Lg / G) * G;
   if (tix >= ntiles) return;
   const int2 t = tiles[tix];
@@ -1313,7 +1317,7 @@ __global__ __launch_bounds__(512) void k_nd_wide_bwd(
     const int* __restrict__ cells, const cpx<T>* __restrict__ fac, const cpx<T>* __restrict__ rpool,
     cpx<T>* __restrict__ xpool, long long pool_stride, int nrhs) {
   typedef cpx<T> C;
-  const int Lg = nd_task(blockIdx.x, gridDim.x);
+  const int Lg = nd_task_rr(blockIdx.x, G);   // as in the forward kernel
   const int tix = Lg / G, g = Lg - (Lg / G) * G;
   if (tix >= ntiles) return;
   const int2 t = tiles[tix];
@@ -1616,7 +1620,7 @@ static void launch_wide_fwd_k(const NdLvlJob* jobs, const int2* tiles, int ntile
                               const int* umaps, const cpx<T>* fac, const cpx<T>* rpool,
                               cpx<T>* upool, long long ps, int nrhs, int kmax, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  hipLaunchKernelGGL((k_nd_wide_fwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(512),
+  hipLaunchKernelGGL((k_nd_wide_fwd<T, KG>), dim3(nd_grid_rr(ntiles, G)), dim3(512),
                      nd_wide_lds_entries<T>(KG) * sizeof(cpx<T>), s, jobs, tiles, ntiles, G, cells,
                      umaps, fac, rpool, upool, ps, nrhs, kmax);
 }
@@ -1626,7 +1630,7 @@ static void launch_wide_bwd_k(const NdLvlJob* jobs, const int2* tiles, int ntile
                               const cpx<T>* fac, const cpx<T>* rpool, cpx<T>* xpool, long long ps,
                               int nrhs, hipStream_t s) {
   const int G = (nrhs + KG - 1) / KG;
-  hipLaunchKernelGGL((k_nd_wide_bwd<T, KG>), dim3(nd_grid((long long)ntiles * G)), dim3(512),
+  hipLaunchKernelGGL((k_nd_wide_bwd<T, KG>), dim3(nd_grid_rr(ntiles, G)), dim3(512),
                      nd_wide_lds_entries<T>(KG) * sizeof(cpx<T>), s, jobs, tiles, ntiles, G, cells,
                      fac, rpool, xpool, ps, nrhs);
 }
